@@ -1,0 +1,112 @@
+"""The paper's matrix form of the linearized OSB-PD operator, assembled densely.
+
+TEST INFRASTRUCTURE ONLY (tiny grids).  This is a second, independent route
+to the internal force: instead of the bond loops of ``pd_oracle.c`` it builds
+the global matrices of the matrix-based scheme from their per-bond blocks and
+multiplies them,
+
+    E      = C_e U                 (Eqs. 2.4, 2.7)
+    Theta  = C_theta E             (Eqs. 2.6, 2.10)
+    F_int  = K_theta Theta + K_e E (Eqs. 2.5, 2.8, 2.9)
+    F_int  = (K^v + K^d) U,  K^v = K_theta C_theta C_e,  K^d = K_e C_e   (Eq. 2.14)
+
+with its own brute-force horizon search.  F_int here is the restoring force
+(the peridynamic force of the solver listing), so the positive semi-definite
+stiffness is -(K^v + K^d).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .oracle import constants
+
+
+def bonds_bruteforce(w):
+    """Unique bonds (i < j) with 0 < |xi| <= delta inside one specimen."""
+    lat = np.zeros((w.n, 3), dtype=np.int64)
+    lat[:, : w.dim] = w.lat
+    d = lat[None, :, :] - lat[:, None, :]
+    xi = d.astype(np.float64) * w.dx
+    r = np.sqrt((xi * xi).sum(-1))
+    same = w.specimen[:, None] == w.specimen[None, :]
+    ok = (r <= w.delta) & (r > 0) & same
+    bi, bj = np.nonzero(np.triu(ok, 1))
+    return bi, bj, xi[bi, bj], r[bi, bj]
+
+
+def matrices(w, rho_bond=None, bonds=None):
+    """Global C_e (Nb x 3N), C_theta (N x Nb), K_theta (3N x N), K_e (3N x Nb).
+
+    rho_bond: bond status per unique bond (None = all intact); a broken bond
+    contributes to none of the four matrices.
+    """
+    if bonds is None:
+        bi, bj, xi, x = bonds_bruteforce(w)
+    else:
+        bi, bj = bonds
+        lat = np.zeros((w.n, 3), dtype=np.int64)
+        lat[:, : w.dim] = w.lat
+        xi = (lat[bj] - lat[bi]).astype(np.float64) * w.dx
+        x = np.sqrt((xi * xi).sum(-1))
+    n, nb = w.n, len(bi)
+    M = xi / x[:, None]
+    V = np.asarray(w.vol, dtype=np.float64)
+    # weighted volume, Eq. 1.9 (w = 1), full geometric family
+    m = np.zeros(n)
+    np.add.at(m, bi, x * x * V[bj])
+    np.add.at(m, bj, x * x * V[bi])
+    rho = np.ones(nb) if rho_bond is None else np.asarray(rho_bond, dtype=np.float64)
+    CE = np.zeros((nb, 3 * n))
+    CTH = np.zeros((n, nb))
+    KTH = np.zeros((3 * n, n))
+    KE = np.zeros((3 * n, nb))
+    for b in range(nb):
+        if rho[b] == 0:
+            continue
+        i, j = bi[b], bj[b]
+        mat = w.materials[w.specimen[i]]
+        k = constants(w.mode_id(), mat.E, mat.nu)
+        A, Kc, G = k["A"], k["K"], k["G"]
+        Mb = M[b]
+        # Eq. 2.7
+        CE[b, 3 * i:3 * i + 3] = -Mb
+        CE[b, 3 * j:3 * j + 3] = Mb
+        # Eq. 2.10
+        CTH[i, b] = A * x[b] * V[j] / m[i]
+        CTH[j, b] = A * x[b] * V[i] / m[j]
+        # Eq. 2.8
+        c = (Kc - G / 3.0) * x[b] * V[i] * V[j]
+        KTH[3 * i:3 * i + 3, i] += c * Mb / m[i]
+        KTH[3 * j:3 * j + 3, i] += -c * Mb / m[i]
+        KTH[3 * i:3 * i + 3, j] += c * Mb / m[j]
+        KTH[3 * j:3 * j + 3, j] += -c * Mb / m[j]
+        # Eq. 2.9
+        g = G * V[i] * V[j] * (1.0 / m[i] + 1.0 / m[j])
+        KE[3 * i:3 * i + 3, b] = g * Mb
+        KE[3 * j:3 * j + 3, b] = -g * Mb
+    return dict(CE=CE, CTH=CTH, KTH=KTH, KE=KE, bi=bi, bj=bj, x=x, M=M, m=m)
+
+
+def internal_force_operator(w, rho_bond=None, bonds=None):
+    """F_int = (K^v + K^d) U as a dense 3N x 3N matrix (Eq. 2.14)."""
+    mats = matrices(w, rho_bond, bonds)
+    Kv = mats["KTH"] @ mats["CTH"] @ mats["CE"]
+    Kd = mats["KE"] @ mats["CE"]
+    return Kv + Kd, mats
+
+
+def mass_vector(w):
+    """Diagonal of the lumped mass matrix, 3 entries per node (rho V)."""
+    rho = np.array([w.materials[s].rho for s in w.specimen])
+    return np.repeat(rho * np.asarray(w.vol), 3)
+
+
+def free_dofs(w):
+    """Indices of the unconstrained degrees of freedom (active components only)."""
+    idx = []
+    for p in range(w.n):
+        for c in range(w.dim):
+            if not (int(w.bc[p]) >> c) & 1:
+                idx.append(3 * p + c)
+    return np.array(idx, dtype=np.int64)

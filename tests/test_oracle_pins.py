@@ -1,0 +1,528 @@
+"""Pins of the CPU reference (oracle) against facts fixed by the paper and by
+the mathematics, independent of the oracle's own formulas.
+
+Each test names what it pins; a plausible mistake in the oracle (a dropped
+term, a wrong sign, a transposed index, a wrong constant) fails at least one.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.linalg as sl
+
+import oracle
+from oracle import Oracle, dense
+from pd_inputs import workloads as W
+from pd_inputs.workloads import Material, Workload
+
+MODES = {"3d": 0, "plane_stress": 1, "plane_strain": 2}
+
+
+def small_box(shape, dx=1e-3, mode=None, E=70e9, nu=0.25, rho=2000.0, delta_ratio=3.015,
+              G0=None, bc=None, dt=1e-8):
+    lat = W._box(shape)
+    n = lat.shape[0]
+    dim = len(shape)
+    if mode is None:
+        mode = "3d" if dim == 3 else "plane_stress"
+    vol = np.full(n, dx ** dim)
+    return Workload(name="box", dim=dim, mode=mode, lat=lat, dx=dx, origin=np.zeros(3),
+                    delta=delta_ratio * dx, vol=vol, specimen=np.zeros(n, np.int32),
+                    materials=[Material(E, nu, rho, G0)],
+                    bc=np.zeros(n, np.uint8) if bc is None else bc,
+                    v0=np.zeros((n, 3)), fext=np.zeros((n, 3)), ramp_steps=0, cuts=[],
+                    steps=1, dt=np.array([dt]))
+
+
+# ---------------------------------------------------------------------------
+# family (horizon) -- Sec. 2.1, Sec. 3.3
+# ---------------------------------------------------------------------------
+
+def test_bond_count_10x10_mratio3():
+    """Sec. 3.3: a 10x10 2D grid with m-ratio 3 has 1058 bonds."""
+    w = small_box((10, 10), dx=1.0, delta_ratio=3.0)
+    assert Oracle(w).nb == 1058
+    assert Oracle(w, search="cells").nb == 1058
+
+
+@pytest.mark.parametrize("shape,count", [((15, 15), 28), ((15, 15, 15), 122)])
+def test_interior_family_size(shape, count):
+    """Lattice points within 3.015 lattice units of the origin: 28 (2D), 122 (3D)."""
+    w = small_box(shape)
+    o = Oracle(w)
+    bi, bj = o.bonds()
+    deg = np.bincount(bi, minlength=w.n) + np.bincount(bj, minlength=w.n)
+    centre = np.all(w.lat == np.array(shape) // 2, axis=1)
+    assert deg[centre][0] == count
+    # brute-force enumeration of integer offsets
+    d = len(shape)
+    rng = range(-4, 5)
+    offs = [o_ for o_ in np.array(np.meshgrid(*[rng] * d)).reshape(d, -1).T
+            if 0 < (o_ ** 2).sum() <= 3.015 ** 2]
+    assert len(offs) == count
+
+
+def test_cell_search_equals_brute_force():
+    """The cell-list search returns exactly the brute-force family, also
+    across specimens (which never bond to each other)."""
+    w = W.batch2d(n_plates=2, dt=np.ones(2))
+    keep = np.isin(w.specimen, [0, 1]) & (w.lat[:, 0] < 30)
+    sub = small_box((1, 1))
+    sub.lat = w.lat[keep]
+    sub.vol = w.vol[keep]
+    sub.specimen = w.specimen[keep]
+    sub.materials = w.materials
+    sub.bc = w.bc[keep]
+    sub.v0 = w.v0[keep]
+    sub.fext = w.fext[keep]
+    sub.dx, sub.delta, sub.dim, sub.mode = w.dx, w.delta, 2, w.mode
+    sub.dt = np.ones(2)
+    a = Oracle(sub, search="brute")
+    b = Oracle(sub, search="cells")
+    assert a.nb == b.nb > 0
+    for x, y in zip(a.bonds(), b.bonds()):
+        np.testing.assert_array_equal(x, y)
+    bi, bj = a.bonds()
+    assert np.all(sub.specimen[bi] == sub.specimen[bj])
+    w3 = small_box((9, 7, 6))
+    a3, b3 = Oracle(w3, search="brute"), Oracle(w3, search="cells")
+    for x, y in zip(a3.bonds(), b3.bonds()):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_bond_geometry_and_weighted_volume():
+    """xi, x, M (Eqs. 1.2-1.5, 1.13) and m (Eq. 1.9) against direct numpy."""
+    w = small_box((7, 6, 5))
+    o = Oracle(w)
+    bi, bj = o.bonds()
+    xl, M = o.bond_geom()
+    X = w.positions()
+    xi = X[bj] - X[bi]
+    np.testing.assert_allclose(xl, np.linalg.norm(xi, axis=1), rtol=1e-15)
+    np.testing.assert_allclose(M * xl[:, None], xi, rtol=1e-14, atol=1e-18)
+    m = np.zeros(w.n)
+    np.add.at(m, bi, xl ** 2 * w.vol[bj])
+    np.add.at(m, bj, xl ** 2 * w.vol[bi])
+    np.testing.assert_allclose(o.m(), m, rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# operator invariants -- Eqs. 2.2, 2.3
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,mode", [((8, 5, 4), "3d"), ((12, 9), "plane_stress"),
+                                        ((11, 10), "plane_strain")])
+def test_rigid_motion_gives_zero_force(shape, mode):
+    """Rigid translation and infinitesimal rigid rotation give e = 0 on every
+    bond, hence theta = 0 and f = 0 (to round-off)."""
+    w = small_box(shape, mode=mode)
+    o = Oracle(w)
+    X = w.positions()
+    rng = np.random.default_rng(3)
+    scale = 1e-6
+    c = rng.standard_normal(3) * scale
+    Wm = rng.standard_normal((3, 3)) * scale
+    Wm = Wm - Wm.T
+    if w.dim == 2:
+        c[2] = 0
+        Wm[2, :] = 0
+        Wm[:, 2] = 0
+    for u in (np.tile(c, (w.n, 1)), X @ Wm.T):
+        f, th = o.force(u)
+        fref = o.force(rng.standard_normal((w.n, 3)) * scale)[0]
+        assert np.abs(f).max() <= 1e-12 * np.abs(fref).max()
+        assert np.abs(th).max() <= 1e-12
+
+
+@pytest.mark.parametrize("shape,mode", [((8, 5, 4), "3d"), ((12, 9), "plane_stress")])
+def test_momentum_balance(shape, mode):
+    """Forces come in equal and opposite central pairs (Eq. 2.2 with
+    M<xi_ij> = -M<xi_ji>): sum f = 0 and sum x_i x f_i = 0 for any u."""
+    w = small_box(shape, mode=mode)
+    o = Oracle(w)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((w.n, 3)) * 1e-6
+    if w.dim == 2:
+        u[:, 2] = 0
+    rho = o.rho()
+    rho[rng.random(o.nb) < 0.2] = 0
+    o.set_rho(rho)
+    f, _ = o.force(u)
+    X = w.positions()
+    fmax = np.abs(f).max()
+    assert np.abs(f.sum(0)).max() <= 1e-12 * fmax * w.n
+    L = np.cross(X, f).sum(0)
+    assert np.abs(L).max() <= 1e-12 * fmax * w.n * np.abs(X).max()
+
+
+@pytest.mark.parametrize("shape,mode", [((13, 13, 13), "3d"), ((21, 21), "plane_stress"),
+                                        ((21, 21), "plane_strain")])
+def test_uniform_dilatation(shape, mode):
+    """u = eps x: every bond has e = eps x, so theta_i = A eps at every node
+    (the weighted volume cancels, Eqs. 1.6, 1.9) and f_i = 0 wherever the
+    whole 2-delta neighbourhood is symmetric (interior)."""
+    w = small_box(shape, mode=mode, nu=0.27)
+    o = Oracle(w)
+    eps = 1e-5
+    u = w.positions() * eps
+    if w.dim == 2:
+        u[:, 2] = 0
+    f, th = o.force(u)
+    A = oracle.constants(MODES[mode], 70e9, 0.27)["A"]
+    np.testing.assert_allclose(th, A * eps, rtol=1e-12)
+    lo, hi = 6, np.array(shape) - 7
+    inner = np.all((w.lat >= lo) & (w.lat <= hi), axis=1)
+    assert inner.sum() > 0
+    fscale = np.abs(f).max()
+    assert fscale > 0
+    assert np.abs(f[inner]).max() <= 1e-10 * fscale
+
+
+@pytest.mark.parametrize("mode,E,nu", [("3d", 200e9, 0.3), ("3d", 30e9, 0.2),
+                                       ("plane_stress", 72e9, 0.22),
+                                       ("plane_stress", 72e9, 1 / 3),
+                                       ("plane_strain", 190e9, 0.25)])
+def test_equibiaxial_energy_is_classical(mode, E, nu):
+    """Uniform strain eps*I gives theta = A eps and sum_j e^2 V_j = eps^2 m at
+    every node, so W = [(K-G/3) A/2 + G/2] eps^2 at every node.  Eqs. 1.8,
+    1.15, 1.16 must make this the classical strain energy density:
+    9 kappa/2 (3D), E/(1-nu) (plane stress), 2(lambda+mu) (plane strain)."""
+    shape = (7, 7, 7) if mode == "3d" else (15, 15)
+    w = small_box(shape, mode=mode, E=E, nu=nu)
+    o = Oracle(w)
+    eps = 1e-4
+    u = w.positions() * eps
+    if w.dim == 2:
+        u[:, 2] = 0
+    Wtot = o.strain_energy(u)
+    coeff = Wtot / (w.vol.sum() * eps * eps)
+    kappa = E / (3 * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    classical = {"3d": 4.5 * kappa, "plane_stress": E / (1 - nu),
+                 "plane_strain": 2 * (lam + mu)}[mode]
+    assert coeff == pytest.approx(classical, rel=1e-12)
+
+
+def test_uniaxial_energy_close_to_classical():
+    """Uniaxial strain u = (eps x, 0, 0) in 3D: the discrete family is not
+    isotropic, so only approximate agreement with (lambda + 2 mu) eps^2 / 2
+    is expected (this separates G from K, which equibiaxial strain cannot)."""
+    E, nu = 200e9, 0.3
+    w = small_box((13, 13, 13), E=E, nu=nu)
+    o = Oracle(w)
+    eps = 1e-4
+    u = np.zeros((w.n, 3))
+    u[:, 0] = w.positions()[:, 0] * eps
+    centre = np.all(w.lat == 6, axis=1)
+    # energy density at an interior node from the local expression: use a
+    # body where only the centre node's neighbourhood matters by differencing
+    Wtot = o.strain_energy(u)
+    coeff = Wtot / (w.vol.sum() * eps * eps)
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    assert coeff == pytest.approx((lam + 2 * mu) / 2, rel=0.08)
+    assert centre.sum() == 1
+
+
+@pytest.mark.parametrize("shape,mode", [((6, 4, 4), "3d"), ((9, 8), "plane_stress")])
+def test_energy_identity(shape, mode):
+    """f = -grad E for E = sum V_i W_i (the energy from which Eq. 2.2
+    follows), hence 1/2 u.(-f) = E for this quadratic energy, and a finite
+    difference of E along a random direction equals -f.d."""
+    w = small_box(shape, mode=mode, nu=0.21)
+    o = Oracle(w)
+    rng = np.random.default_rng(11)
+    rho = o.rho()
+    rho[rng.random(o.nb) < 0.15] = 0
+    o.set_rho(rho)
+    u = rng.standard_normal((w.n, 3)) * 1e-6
+    d = rng.standard_normal((w.n, 3)) * 1e-6
+    if w.dim == 2:
+        u[:, 2] = 0
+        d[:, 2] = 0
+    f, _ = o.force(u)
+    E = o.strain_energy(u)
+    assert 0.5 * (-(u * f).sum()) == pytest.approx(E, rel=1e-11)
+    h = 1e-3
+    dE = (o.strain_energy(u + h * d) - o.strain_energy(u - h * d)) / (2 * h)
+    assert dE == pytest.approx(-(f * d).sum(), rel=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# matrix form of the paper (Eqs. 2.4-2.10, 2.14) vs the loop form
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["cantilever", "plate_notched", "plane_strain"])
+def test_matrix_form_equals_loop_form(case):
+    if case == "cantilever":
+        w = W.cantilever3d(dt=1e-7)
+    elif case == "plate_notched":
+        w = W.plate2d(nx=14, ny=10, dt=1e-8, notch_row=4, notch_tip=6.37)
+    else:
+        w = small_box((9, 9), mode="plane_strain", nu=0.25)
+    o = Oracle(w)
+    bi, bj = o.bonds()
+    rho = o.rho()
+    rng = np.random.default_rng(7)
+    rho[rng.random(o.nb) < 0.1] = 0
+    o.set_rho(rho)
+    L, mats = dense.internal_force_operator(w, rho_bond=rho)
+    # the dense form's own brute-force search finds the same bonds
+    np.testing.assert_array_equal(mats["bi"], bi)
+    np.testing.assert_array_equal(mats["bj"], bj)
+    u = rng.standard_normal((w.n, 3)) * 1e-6
+    if w.dim == 2:
+        u[:, 2] = 0
+    f, th = o.force(u)
+    scale = np.abs(f).max()
+    np.testing.assert_allclose(L @ u.ravel(), f.ravel(), rtol=0, atol=1e-13 * scale)
+    theta_mat = mats["CTH"] @ (mats["CE"] @ u.ravel())
+    A = oracle.constants(w.mode_id(), w.materials[0].E, w.materials[0].nu)["A"]
+    np.testing.assert_allclose(A * 0 + theta_mat, th, rtol=0, atol=1e-13 * np.abs(th).max())
+
+
+@pytest.mark.parametrize("shape,mode,nullity", [((5, 4, 3), "3d", 6), ((7, 6), "plane_stress", 3)])
+def test_stiffness_symmetric_psd_with_rigid_null_space(shape, mode, nullity):
+    """-(K^v + K^d) is symmetric positive semi-definite; for a free body its
+    null space is exactly the rigid motions (6 in 3D, 3 in 2D)."""
+    w = small_box(shape, mode=mode, nu=0.2)
+    L, _ = dense.internal_force_operator(w)
+    dofs = np.array([3 * p + c for p in range(w.n) for c in range(w.dim)])
+    K = -L[np.ix_(dofs, dofs)]
+    assert np.abs(K - K.T).max() <= 1e-14 * np.abs(K).max()
+    ev = np.linalg.eigvalsh(K)
+    tol = 1e-10 * ev[-1]
+    assert ev[0] > -tol
+    assert (np.abs(ev) < tol).sum() == nullity
+
+
+# ---------------------------------------------------------------------------
+# critical stretch -- Eqs. 1.21-1.29
+# ---------------------------------------------------------------------------
+
+def _varpi3d(z, delta):
+    """m_l / m for the part of the sphere beyond a plane at distance z,
+    integrated numerically (w = 1)."""
+    m = 4 * math.pi * delta ** 5 / 5
+    # points at radius r beyond the plane: polar angle below acos(z/r)
+    ml = si.quad(lambda r: r ** 4 * 2 * math.pi * (1 - z / r), z, delta, epsabs=0, epsrel=1e-13)[0]
+    return ml / m
+
+
+def _varpi2d(z, delta):
+    m = math.pi * delta ** 4 / 2
+    ml = si.quad(lambda r: r ** 3 * 2 * math.acos(min(1.0, z / r)), z, delta, epsabs=0,
+                 epsrel=1e-13)[0]
+    return ml / m
+
+
+def test_beta_constants_by_quadrature():
+    """Eqs. 1.25, 1.27, 1.29 for w = 1: beta_3D = 125 delta/1848 exactly,
+    beta'_3D = 5 delta/24 (the printed 5 delta/(24 pi) carries a spurious
+    pi), beta'_2D = 4 delta/(5 pi) exactly, beta_2D = 1087 delta/(1250 pi^2)
+    to the four digits printed."""
+    d = 1.0
+    b3 = si.quad(lambda z: _varpi3d(z, d) ** 2, 0, d, epsrel=1e-12)[0]
+    bp3 = si.quad(lambda z: _varpi3d(z, d), 0, d, epsrel=1e-12)[0]
+    b2 = si.quad(lambda z: _varpi2d(z, d) ** 2, 0, d, epsrel=1e-12)[0]
+    bp2 = si.quad(lambda z: _varpi2d(z, d), 0, d, epsrel=1e-12)[0]
+    assert b3 == pytest.approx(125 / 1848, rel=1e-9)
+    assert bp3 == pytest.approx(5 / 24, rel=1e-9)
+    assert bp3 != pytest.approx(5 / (24 * math.pi), rel=1e-2)
+    assert bp2 == pytest.approx(4 / (5 * math.pi), rel=1e-9)
+    assert b2 == pytest.approx(1087 / (1250 * math.pi ** 2), rel=5e-4)
+
+
+@pytest.mark.parametrize("E,nu,G0,delta", [(191e9, 0.3, 22170.0, 3.015e-3),
+                                           (30e9, 0.2, 100.0, 1.809e-3)])
+def test_critical_stretch_3d_from_energy_release(E, nu, G0, delta):
+    """3D: integrating the energy released per unit crack area (Eqs. 1.21-
+    1.24) with the quadrature varpi gives s_c of Eq. 1.26 with the
+    re-derived beta' (variant 1); variant 0 uses the printed beta'."""
+    kappa = E / (3 * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+
+    def Wz(z):
+        v = _varpi3d(z, delta)
+        return 1.5 * ((3 * kappa - 5 * mu) * v * v + 5 * mu * v)
+
+    per_s2 = 2 * si.quad(Wz, 0, delta, epsrel=1e-12)[0]
+    s_direct = math.sqrt(G0 / per_s2)
+    assert oracle.critical_stretch(0, E, nu, G0, delta, 1) == pytest.approx(s_direct, rel=1e-8)
+    beta = 125 * delta / 1848
+    betap_printed = 5 * delta / (24 * math.pi)
+    s_printed = math.sqrt(G0 / ((9 * kappa - 15 * mu) * beta + 15 * mu * betap_printed))
+    assert oracle.critical_stretch(0, E, nu, G0, delta, 0) == pytest.approx(s_printed, rel=1e-14)
+
+
+def test_critical_stretch_values_and_no_break_sentinel():
+    """Spot values of s_c for the workloads (Eqs. 1.26-1.29), and G0 = None
+    gives an unbreakable material."""
+    s2 = oracle.critical_stretch(1, 72e9, 0.22, 3.8, 1.5075e-3, 0)
+    assert s2 == pytest.approx(1.9549e-4, rel=2e-4)
+    s3p = oracle.critical_stretch(0, 191e9, 0.3, 22170.0, 3.015e-3, 0)
+    s3d = oracle.critical_stretch(0, 191e9, 0.3, 22170.0, 3.015e-3, 1)
+    assert s3p == pytest.approx(8.778e-3, rel=2e-4)
+    assert s3d == pytest.approx(5.403e-3, rel=2e-4)
+    assert math.isinf(oracle.critical_stretch(0, 200e9, 0.3, None, 3e-3, 0))
+
+
+# ---------------------------------------------------------------------------
+# dynamics -- Eqs. 2.11, 2.12, 1.30
+# ---------------------------------------------------------------------------
+
+def two_nodes(mode="3d", E=200e9, nu=0.3, rho=7850.0, dx=1e-3, off=(1, 0, 0), dt=1e-8,
+              bc=None, v0=None, G0=None):
+    dim = 3 if mode == "3d" else 2
+    lat = np.array([[0] * dim, list(off[:dim])], dtype=np.int32)
+    vol = np.full(2, dx ** dim)
+    w = Workload(name="pair", dim=dim, mode=mode, lat=lat, dx=dx, origin=np.zeros(3),
+                 delta=3.015 * dx, vol=vol, specimen=np.zeros(2, np.int32),
+                 materials=[Material(E, nu, rho, G0)],
+                 bc=np.zeros(2, np.uint8) if bc is None else np.asarray(bc, np.uint8),
+                 v0=np.zeros((2, 3)) if v0 is None else np.asarray(v0, float),
+                 fext=np.zeros((2, 3)), ramp_steps=0, cuts=[], steps=1, dt=np.array([dt]))
+    return w
+
+
+@pytest.mark.parametrize("mode,off", [("3d", (1, 0, 0)), ("3d", (1, 2, 2)),
+                                      ("plane_stress", (2, 1, 0))])
+def test_two_node_oscillator_closed_form(mode, off):
+    """Two free nodes joined by one bond: the extension obeys
+    e'' = -omega^2 e with omega^2 = 4[(K-G/3)A + G]/(rho x^2) (m = x^2 V).
+    The explicit update of Eq. 2.11 then has the exact discrete solution
+    e_n = e_0 cos(n phi) + B sin(n phi), cos(phi) = 1 - (omega dt)^2 / 2."""
+    E, nu, rho = 200e9, 0.3, 7850.0
+    w = two_nodes(mode=mode, E=E, nu=nu, rho=rho, off=off)
+    k = oracle.constants(MODES[mode], E, nu)
+    x = w.dx * math.sqrt(sum(o_ * o_ for o_ in off[:w.dim]))
+    omega = math.sqrt(4 * ((k["K"] - k["G"] / 3) * k["A"] + k["G"]) / (rho * x * x))
+    dt = 0.05 / omega
+    w.dt = np.array([dt])
+    o = Oracle(w)
+    Mv = np.zeros(3)
+    Mv[: w.dim] = np.array(off[: w.dim], float)
+    Mv /= np.linalg.norm(Mv)
+    u = np.zeros((2, 3))
+    v = np.zeros((2, 3))
+    e0 = 1e-7
+    u[1] = e0 * Mv
+    v[1] = 3e-3 * Mv
+    v[0] = -1e-3 * Mv
+    ex = []
+    for _ in range(600):
+        ex.append(Mv @ (u[1] - u[0]))
+        o.run(1, u, v)
+    ex = np.array(ex)
+    phi = math.acos(1 - (omega * dt) ** 2 / 2)
+    ev0 = Mv @ (v[1] - v[0])  # unused; B from the first step below
+    e1 = e0 + dt * (4e-3 - dt * omega ** 2 * e0)
+    B = (e1 - e0 * math.cos(phi)) / math.sin(phi)
+    nn = np.arange(len(ex))
+    ref = e0 * np.cos(nn * phi) + B * np.sin(nn * phi)
+    assert np.abs(ex - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert ev0 == ev0
+
+
+def test_break_step_closed_form():
+    """Node 0 fixed, node 1 driven at constant velocity along the bond: the
+    bond breaks (Eq. 1.30, s >= s_c) at the first step n with
+    n dt vbar / x >= s_c, and carries no force afterwards."""
+    dt, vbar, dx = 1e-8, 2.0, 1e-3
+    k = 37
+    s0 = (k + 0.5) * dt * vbar / dx  # breaks when n = k + 1
+    w = two_nodes(off=(1, 0, 0), dt=dt, bc=[7, 7], v0=[[0, 0, 0], [vbar, 0, 0]])
+    o = Oracle(w, s0=np.array([s0]))
+    u, v = o.initial_state()
+    o.run(k + 1, u, v)
+    assert o.rho()[0] == 1
+    o.run(1, u, v)
+    assert o.rho()[0] == 0
+    assert o.break_step()[0] == k + 1
+    f, th = o.force(u)
+    assert np.all(f == 0) and np.all(th == 0)
+    # damage (Eq. 1.31): both nodes lost their only bond
+    np.testing.assert_array_equal(o.damage(), [1.0, 1.0])
+
+
+def test_discrete_energy_invariant_cantilever():
+    """For constant external force and no breaking, the update of Eq. 2.11
+    conserves H_n = 1/2 sum rho V v^n . v^{n+1} - 1/2 u^n . f(u^n) - F.u^n
+    exactly (up to round-off)."""
+    w = W.cantilever3d(dt=2.25e-7, ramp_steps=0, steps=1)
+    o = Oracle(w)
+    u, v = o.initial_state()
+    rho = w.materials[0].rho
+    mass = (rho * w.vol)[:, None]
+    H = []
+    for _ in range(600):
+        f, _ = o.force(u)
+        vn = v.copy()
+        un = u.copy()
+        o.run(1, u, v)
+        H.append(0.5 * (mass * vn * v).sum() - 0.5 * (un * f).sum() - (w.fext * un).sum())
+    H = np.array(H[1:])
+    scale = np.abs(w.fext).sum() * np.abs(u).max()
+    assert np.ptp(H) <= 1e-9 * scale
+
+
+def test_cantilever_first_bending_frequency():
+    """Tip vibration of the 20x4x4 cantilever (after the 50-step ramp): its
+    angular frequency equals the first generalized eigenvalue of the
+    paper's stiffness matrix (Eq. 2.14) with the lumped mass (within 1%), and
+    is within 15% of Euler-Bernoulli for L = 17 mm, 4 x 4 mm."""
+    w = W.cantilever3d()
+    assert np.isfinite(w.dt[0])
+    o = Oracle(w)
+    u, v = o.initial_state()
+    tip = np.where(w.lat[:, 0] == 19)[0]
+    z = []
+    for _ in range(2000):
+        o.run(1, u, v)
+        z.append(u[tip, 2].mean())
+    z = np.array(z[150:])
+    t = np.arange(len(z)) * w.dt[0]
+
+    def resid(om):
+        Amat = np.stack([np.cos(om * t), np.sin(om * t), np.ones_like(t)], 1)
+        c, *_ = np.linalg.lstsq(Amat, z, rcond=None)
+        return np.sum((Amat @ c - z) ** 2)
+
+    grid = np.linspace(3e4, 1.2e5, 901)
+    om = grid[np.argmin([resid(g) for g in grid])]
+    import scipy.optimize as so
+    om = so.minimize_scalar(resid, bracket=(om - 200, om, om + 200)).x
+    L, _ = dense.internal_force_operator(w)
+    fd = dense.free_dofs(w)
+    Mv = dense.mass_vector(w)
+    ev = sl.eigh(-L[np.ix_(fd, fd)], np.diag(Mv[fd]), eigvals_only=True, subset_by_index=[0, 3])
+    om1 = math.sqrt(ev[0])
+    assert om1 == pytest.approx(6.3853e4, rel=1e-4)
+    assert om == pytest.approx(om1, rel=1e-2)
+    E, rho_m, Lb, b = 200e9, 7850.0, 17e-3, 4e-3
+    I = b ** 4 / 12
+    om_eb = 1.875104 ** 2 * math.sqrt(E * I / (rho_m * b * b * Lb ** 4))
+    assert om == pytest.approx(om_eb, rel=0.15)
+
+
+def test_stable_dt_table_matches_power_iteration():
+    """The time steps in the parameter table follow the stated rule (0.8 of
+    2/omega_max, four significant digits rounded down) and the power
+    iteration agrees with the dense eigenvalue on the cantilever."""
+    w = W.cantilever3d()
+    o = Oracle(w, apply_cuts=False)
+    lam = o.lambda_max(500, 0)
+    L, _ = dense.internal_force_operator(w)
+    fd = dense.free_dofs(w)
+    Mv = dense.mass_vector(w)
+    lam_dense = sl.eigh(-L[np.ix_(fd, fd)], np.diag(Mv[fd]), eigvals_only=True)[-1]
+    assert lam == pytest.approx(lam_dense, rel=1e-6)
+    dt = 0.8 * 2 / math.sqrt(1.001 * lam)
+    assert w.dt[0] <= dt
+    assert w.dt[0] >= dt * (1 - 1e-3)
+    p = W.load_params()
+    for key in ("cantilever3d", "plate2d"):
+        assert key in p
