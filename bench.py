@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of the explicit linearized OSB-PD step on one MI355X.
+
+A step is one pass of the whole hot path over the workload: breaking check
+and dilatation (pass 1), pair force and explicit update (pass 2).  The value
+is unique bonds x steps / wall time of K timed steps (inputs resident in
+HBM, steps replayed from a captured hipGraph), in bond-updates/s.
+
+Beside it the JSON line carries
+  roofline     -- the dominant kernel's algorithmic bytes per launch divided
+                  by its average duration (HIP events on the launch stream),
+                  against the 8 TB/s HBM peak of MI355X;
+  cpu_baseline -- the CPU reference timed on a bounded sample of the same
+                  workload on this host's cores;
+  fp64         -- the same workload with the double-precision force path.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (generator kwargs, description)
+    "cylinder3d": (dict(), "3D notched cylinder under end twist, r=25 mm, L=100 mm, dx=0.6 mm, "
+                           "delta=3.015 dx, helical notch, 911,319 nodes"),
+    "cylinder3d_dx05": (dict(dx=0.5e-3), "3D notched cylinder, dx=0.5 mm, 1,572,000 nodes"),
+    "impact3d": (dict(), "3D double-notched plate 200x200x9, 16.5 m/s edge impact, 360,000 nodes"),
+    "plate2d": (dict(), "2D plane-stress edge-notched plate 200x80, 1 MPa, 16,000 nodes"),
+    "batch2d": (dict(), "256 random 2D plane-stress notched plates (seed 2309), 5,800,669 nodes"),
+    "cantilever3d": (dict(), "3D cantilever 20x4x4, 320 nodes"),
+}
+
+
+def make_workload(name):
+    from pd_inputs import workloads as W
+    kw, desc = WORKLOADS[name]
+    gen = name.split("_")[0] if name.startswith("cylinder") else name
+    return W.workload(gen, **kw), desc
+
+
+def algorithmic_bytes(kernel: str, precision: str, nnz: int, n: int, n_loaded: int) -> int:
+    """Bytes one launch must move between HBM and the chip (each array read
+    or written once; neighbour gathers are served by the caches).
+
+    Per directed bond: 4 B bond word + 1 bit of bond status (1/8 B).
+    Per node (FP64 path):
+      pass 1: u,V 32 read; aux 4; (theta/m, 1/m) 16 read + 8 write
+      pass 2: u,V 32 read; (theta/m, 1/m) 16; aux 4; v 32 read + 32 write;
+              u,V 32 write
+    Per node (FP32 path):
+      pass 1: shadow 16; aux 4; (theta/m, 1/m) float 8 read + 4 write
+      pass 2: shadow 16; float (theta/m, 1/m) 8; aux 4; u,V 32 read;
+              v 32 + 32; u,V 32 write; next shadow 16 write
+    Loaded nodes read their external force (32 B) in pass 2."""
+    bond = nnz * 4.125
+    if precision == "fp64":
+        node = {"pass1": 60, "pass2": 148}[kernel]
+    else:
+        node = {"pass1": 32, "pass2": 172}[kernel]
+    extra = 32 * n_loaded if kernel == "pass2" else 0
+    return int(bond + node * n + extra)
+
+
+def traffic_from_profiles(kernel_name: str, src_hash: str):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/
+    traffic.json), or None if absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(kernel_name)
+    if not e or e.get("source_sha") != src_hash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def kernel_source_hash(precision: str) -> str:
+    src = os.path.join(ROOT, "paper_2309_11273_amd", "csrc",
+                       "kernels_f32.hip" if precision == "fp32" else "kernels.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def time_gpu(s, steps, warmup, precision, form, chunk):
+    import torch
+    s.step(warmup, precision=precision, form=form, graph_chunk=chunk, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, precision=precision, form=form, graph_chunk=chunk, report=False)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(w, budget_s: float):
+    from oracle import Oracle
+    from oracle.oracle import num_threads
+    o = Oracle(w)
+    u, v = o.initial_state()
+    o.run(1, u, v)  # first touch
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.run(1, u, v)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 1000:
+            break
+    return dict(value=o.nb * n / el, unit="bond-updates/s", cores=num_threads(), kind="oracle",
+                sample=f"{w.name}: {n} explicit steps of the full workload ({o.nb} unique bonds) "
+                       f"after one untimed step, FP64 loop reference with OpenMP over nodes")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="cylinder3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--form", default="mf", choices=["mf", "bsr"])
+    ap.add_argument("--graph-chunk", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: only a single GPU is supported (asked for {max(args.gpus, world)}); the "
+              "solver runs one GPU's share of the workload per process and has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2309_11273_amd.solver import Solver
+
+    w, desc = make_workload(args.workload)
+    t_setup = time.perf_counter()
+    s = Solver(w, device=0)
+    setup_s = time.perf_counter() - t_setup
+    sz = s.fam.sizes
+    n_bonds, nnz = int(sz.n_bonds), int(sz.nnz)
+    n_loaded = int(np.count_nonzero(np.abs(w.fext).sum(1)))
+    if args.form == "bsr":
+        s.build_K(fp32=(args.precision == "fp32"))
+        s.assemble_K()
+
+    el = time_gpu(s, args.steps, args.warmup, args.precision, args.form, args.graph_chunk)
+    ms_per_step = 1e3 * el / args.steps
+    value = n_bonds * args.steps / el
+
+    # kernel durations with HIP events on the launch stream
+    s.profile_read(reset=True)
+    s.step(args.profile_steps, precision=args.precision, form=args.form, profile=True, report=False)
+    prof = s.profile_read(reset=True)
+    ps = max(1, prof["steps"])
+    ms1, ms2 = prof["ms_pass1"] / ps, prof["ms_pass2"] / ps
+    dom = "pass2" if ms2 >= ms1 else "pass1"
+    ms_dom = max(ms1, ms2)
+    alg = algorithmic_bytes(dom, args.precision, nnz, int(sz.n), n_loaded) if args.form == "mf" else None
+    kname = f"k_{dom}_{args.precision}"
+    if alg is not None:
+        achieved = alg / (ms_dom * 1e-3) / 1e9
+        traffic = traffic_from_profiles(f"{kname}_{args.workload}", kernel_source_hash(args.precision))
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                    "kernel_ms": round(ms_dom, 5), "algorithmic_bytes": alg,
+                    "pass1_ms": round(ms1, 5), "pass2_ms": round(ms2, 5)}
+    else:
+        roofline = None
+
+    st = s.step(0, precision=args.precision, form=args.form)
+    out = {
+        "metric": "bond-updates/s per explicit step",
+        "value": value,
+        "unit": "bond-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "nodes": int(sz.n), "unique_bonds": n_bonds, "directed_bonds": nnz,
+                   "form": "matrix-free" if args.form == "mf" else "block-sparse K",
+                   "state_dtype": "f64", "graph_chunk": args.graph_chunk, "setup_s": round(setup_s, 2),
+                   "broken_bonds_after_run": int(st["broken_total"]) // 2,
+                   "fp64_rechecks": int(st["rechecks"])},
+        "roofline": roofline,
+    }
+    if not args.no_fp64 and args.precision == "fp32":
+        s.reset()
+        el64 = time_gpu(s, args.steps, args.warmup, "fp64", args.form if args.form == "mf" else "mf",
+                        args.graph_chunk)
+        s.profile_read(reset=True)
+        s.step(args.profile_steps, precision="fp64", profile=True, report=False)
+        p64 = s.profile_read(reset=True)
+        ps = max(1, p64["steps"])
+        out["fp64"] = {"value": n_bonds * args.steps / el64, "ms_per_step": 1e3 * el64 / args.steps,
+                       "pass1_ms": p64["ms_pass1"] / ps, "pass2_ms": p64["ms_pass2"] / ps}
+        out["fp32_speedup_vs_fp64"] = value / out["fp64"]["value"]
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

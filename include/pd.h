@@ -1,0 +1,392 @@
+/*
+ * pd.h -- C ABI of the MI355X (gfx950) linearized ordinary state-based
+ * peridynamics (OSB-PD) explicit solver.
+ *
+ * The operation the library performs is the explicit time stepping of the
+ * discretized OSB-PD equation of motion of Ni, Zaccariotto, Zhu, Galvanetto,
+ * "Matrix-based implementation and GPU acceleration of linearized ordinary
+ * state-based peridynamic models in MATLAB": per step, bond stretch and the
+ * critical-stretch breaking rule (Eqs. 1.17, 1.30), the nodal dilatation
+ * (Eqs. 1.6, 2.3), the pair forces (Eq. 2.2) and the explicit update
+ * (Eqs. 2.11, 2.12).  The internal force is available in two forms: a
+ * matrix-free two-pass kernel over a bond list, and the block-sparse global
+ * stiffness matrix of Eq. 2.14 applied to the displacement.
+ *
+ * Conventions
+ *  - Every function returns a pd_status; PD_OK = 0, errors are negative.
+ *    No exception, abort or exit crosses the ABI.  On error a message is
+ *    kept in the context (pd_last_error).  Argument errors are detected
+ *    before any device work is enqueued.
+ *  - Host pointers are marked [host], device pointers [device].  The caller
+ *    owns every buffer it passes; the library owns only the pd_ctx object
+ *    (stream handle, captured graphs, a small pinned report buffer and a
+ *    small device scratch block) and frees it in pd_ctx_destroy.
+ *  - Device work is enqueued on the stream given to pd_ctx_create and is
+ *    asynchronous unless stated otherwise.
+ *  - Nodes are given in the caller's order; pd_build_family chooses an
+ *    internal row order (tile-major) and returns the permutation.  All
+ *    device arrays are in internal row order and padded to n_pad rows
+ *    (a multiple of 64); padding rows carry no bonds and no mass.
+ *  - Units are SI.  2D problems use a thickness of 1 m (volumes dx^2 * 1).
+ *  - The influence function is w = 1 (the paper's choice, Sec. 2.3).
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PD_OK = 0,
+    PD_ERR_ARG = -1,         /* invalid argument (null pointer, bad value)       */
+    PD_ERR_SIZE = -2,        /* size mismatch or a size above a stated maximum   */
+    PD_ERR_HIP = -3,         /* a HIP runtime call failed                        */
+    PD_ERR_UNSTABLE = -4,    /* non-finite displacement detected                 */
+    PD_ERR_UNSUPPORTED = -5, /* option combination not implemented              */
+    PD_ERR_STATE = -6        /* call out of order (e.g. K not assembled)         */
+} pd_status;
+
+typedef enum { PD_3D = 0, PD_PLANE_STRESS = 1, PD_PLANE_STRAIN = 2 } pd_mode;
+typedef enum { PD_FP64 = 0, PD_FP32_RECHECK = 1 } pd_precision;
+typedef enum { PD_MATRIX_FREE = 0, PD_BSR = 1 } pd_form;
+
+/* Largest supported sizes. */
+#define PD_MAX_NODES (1LL << 25)  /* node index is stored in 25 bits            */
+#define PD_MAX_STENCIL 127        /* distinct bond offsets; id 127 = padding    */
+#define PD_MAX_SPECIMENS 65535
+#define PD_MAX_CUTS 65536
+
+typedef struct pd_ctx pd_ctx;
+
+/* ------------------------------------------------------------------------ */
+/* context                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Create a context bound to HIP device 'device' and stream 'hip_stream'
+ * (a hipStream_t; NULL = the default stream).  Returns PD_ERR_HIP if the
+ * device cannot be selected or is not gfx950. */
+pd_status pd_ctx_create(pd_ctx **ctx, int device, void *hip_stream);
+pd_status pd_ctx_destroy(pd_ctx *ctx);
+/* Last error message of the context ("" if none); valid until the next call. */
+const char *pd_last_error(const pd_ctx *ctx);
+/* Library version string. */
+const char *pd_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* material constants (host)                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Critical stretch s_c.  3D: Eq. 1.26 with beta = 125 delta / 1848 and
+ * beta' of Eq. 1.27 (variant 0: as printed, 5 delta / (24 pi); variant 1:
+ * 5 delta / 24, the value the varpi quadrature gives).  Plane stress and
+ * plane strain: Eq. 1.28 with Eq. 1.29.  G0 <= 0, NaN or inf gives
+ * *s0 = +inf (bonds never break).  PD_ERR_ARG for nu outside (-1, 0.5),
+ * E <= 0, delta <= 0 or s0 == NULL. */
+pd_status pd_critical_stretch(pd_mode mode, double E, double nu, double G0, double delta,
+                              int variant, double *s0);
+
+/* Per-specimen constants as the kernels read them (64 bytes, device table
+ * of n_specimens entries, built with pd_specimen_params). */
+typedef struct pd_spec {
+    double kp;   /* K - G/3 with K of Eq. 1.15, G of Eq. 1.16          */
+    double G;    /* G of Eq. 1.16                                       */
+    double A;    /* A of Eq. 1.8                                        */
+    double rho;  /* mass density                                        */
+    double s0;   /* critical stretch (Eq. 1.30 threshold; inf = never)  */
+    double dt;   /* time step of this specimen                          */
+    double pad[2];
+} pd_spec;
+
+/* Fill *out from (mode, E, nu, rho, s0, dt): kp, G, A from Eqs. 1.8,
+ * 1.15, 1.16 with kappa = E/(3(1-2nu)), mu = E/(2(1+nu)).  PD_ERR_ARG on
+ * E <= 0, nu outside (-1, 0.5), rho <= 0, dt <= 0 or NaN s0. */
+pd_status pd_specimen_params(pd_mode mode, double E, double nu, double rho, double s0,
+                             double dt, pd_spec *out);
+
+/* ------------------------------------------------------------------------ */
+/* family (host, set-up)                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* The body: nodes on a uniform lattice (all examples of the paper use
+ * uniform grids, Sec. 4).  Node p sits at origin + dx * lat[p]. */
+typedef struct pd_body {
+    int64_t n;                 /* number of nodes (1 .. PD_MAX_NODES)                  */
+    int32_t dim;               /* 2 or 3                                               */
+    int32_t pad0;
+    const int32_t *lat;        /* [host] n*dim integer lattice coordinates             */
+    double dx;                 /* lattice spacing > 0                                   */
+    double origin[3];          /* position of lattice point (0,0,0)                     */
+    double delta;              /* horizon radius > 0 (family: 0 < |xi| <= delta, Sec. 2.1) */
+    const double *vol;         /* [host] n node volumes > 0                            */
+    const int32_t *specimen;   /* [host] n specimen ids in [0, PD_MAX_SPECIMENS) or NULL (all 0);
+                                  bonds never join different specimens               */
+} pd_body;
+
+/* A notch: bonds whose straight segment properly crosses the patch start
+ * broken (bond status 0 of Eq. 1.30).
+ *   kind 0 segment (2D):    p = {ax, ay, bx, by}
+ *   kind 1 parallelogram:   p = {c(3), a(3), b(3)}, patch {c + s a + t b : 0 < s,t < 1}
+ *   kind 2 helicoidal strip about the z axis: p = {zc, pitch, r_in, r_out, th0, th1};
+ *          crossing of psi = (z - zc) - pitch * atan2(y, x) along the bond, with
+ *          the linearly interpolated crossing inside r_in < r < r_out, th0 < theta < th1.
+ * specimen >= 0 restricts the notch to that specimen. */
+typedef struct pd_cut {
+    int32_t kind;
+    int32_t specimen;
+    double p[10];
+} pd_cut;
+
+typedef struct pd_family_sizes {
+    int64_t n;          /* nodes                                                  */
+    int64_t n_pad;      /* rows incl. padding (multiple of 64)                    */
+    int64_t n_slices;   /* n_pad / 64                                              */
+    int64_t n_words;    /* bond words incl. padding                                */
+    int64_t n_mask;     /* 64-bit bond-status words = n_words / 64                 */
+    int64_t nnz;        /* directed bonds                                          */
+    int64_t n_bonds;    /* unique bonds = nnz / 2                                  */
+    int64_t n_cut;      /* unique bonds removed by notches                         */
+    int32_t n_stencil;  /* distinct bond offsets                                   */
+    int32_t max_row;    /* largest family size                                     */
+    int32_t dim;
+    int32_t n_specimens;/* 1 + largest specimen id                                 */
+} pd_family_sizes;
+
+/* Output arrays of pd_build_family, all [host], allocated by the caller
+ * with the sizes from the query call. */
+typedef struct pd_family_host {
+    int32_t *perm;        /* [n_pad] caller node of internal row r, -1 for padding   */
+    int32_t *row_of;      /* [n] internal row of caller node p                       */
+    int64_t *slice_ptr;   /* [n_slices+1] first bond word of each 64-row slice       */
+    uint32_t *words;      /* [n_words] (j << 7) | stencil id; id 127 = padding       */
+    uint64_t *mask;       /* [n_mask] initial bond status, bit lane of word k of a
+                             slice = status of bond k of row 64*slice + lane         */
+    double *stencil;      /* [n_stencil*4] M1, M2, M3, x per bond offset (Eqs. 1.5, 1.13) */
+    int32_t *stencil_off; /* [n_stencil*3] lattice offset of each stencil entry      */
+    double *vol;          /* [n_pad] node volume (0 for padding)                     */
+    double *inv_m;        /* [n_pad] 1 / m, m of Eq. 1.9 over the full family        */
+    int32_t *spec;        /* [n_pad] specimen id (0 for padding)                     */
+    int32_t *lat4;        /* [n_pad*4] lattice coordinates x,y,z,0 per row           */
+} pd_family_host;
+
+/* Horizon search and bond-list construction (Sec. 2.1 family; Eqs. 1.2-1.5,
+ * 1.9, 1.13 per bond; notch cuts).  Two-phase: with bufs == NULL only
+ * *sizes is filled; call again with every array of bufs allocated.
+ * Internal rows are ordered by specimen, then by 4x4x4 (3D) or 8x8 (2D)
+ * lattice tiles, so a 64-row slice is one tile.  Bonds of a row are
+ * sorted by neighbour row.  Within a slice the words are interleaved
+ * (word k of every row of the slice is contiguous), so 64 lanes read 256
+ * consecutive bytes.  Errors: PD_ERR_ARG (null/invalid body, duplicate
+ * lattice points, unknown cut kind), PD_ERR_SIZE (n or stencil above the
+ * maxima). */
+pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, int32_t ncuts,
+                          pd_family_sizes *sizes, pd_family_host *bufs);
+
+/* ------------------------------------------------------------------------ */
+/* device descriptors                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* The problem: family arrays uploaded by the caller, plus per-row data. */
+typedef struct pd_problem_dev {
+    int64_t n_pad;
+    int64_t n_slices;
+    int32_t dim;
+    int32_t n_stencil;
+    int32_t n_specimens;
+    int32_t pad0;
+    const int64_t *slice_ptr; /* [device] n_slices+1                              */
+    const uint32_t *words;    /* [device] n_words                                 */
+    const double *stencil;    /* [device] n_stencil*4                             */
+    const double *vol;        /* [device] n_pad                                   */
+    const double *inv_m;      /* [device] n_pad                                   */
+    const int32_t *lat4;      /* [device] n_pad*4 (needed by pd_assemble_K only)   */
+    const pd_spec *spec;      /* [device] n_specimens                             */
+    const uint32_t *aux;      /* [device] n_pad, written by pd_state_init          */
+    const double *fext;       /* [device] n_pad*4 external force at full load      */
+    int64_t ramp_steps;       /* load factor r(n) = min(1, n / ramp_steps); 0: r = 1 */
+} pd_problem_dev;
+
+/* Device control block (step counter, diagnostics).  Size in bytes: */
+#define PD_CTL_BYTES 256
+
+/* Solver state, [device] arrays in internal row order. */
+typedef struct pd_state_dev {
+    double *uv[2];      /* n_pad*4: (u_x, u_y, u_z, V) ping-pong                   */
+    double *vel;        /* n_pad*4: (v_x, v_y, v_z, 0)                              */
+    double *qr;         /* n_pad*2: (theta/m, 1/m)                                  */
+    uint64_t *mask;     /* n_mask bond status bits (mutable: bonds break)           */
+    int32_t *ush[2];    /* n_pad*4 fixed-point displacement shadow (FP32 path)      */
+    float *qr32;        /* n_pad*2 (theta/m, 1/m) in FP32 (FP32 path)               */
+    double *dsum;       /* n_pad*4 sum over intact bonds of x M V_j (FP32 path)      */
+    void *ctl;          /* PD_CTL_BYTES control block                               */
+    int32_t cur;        /* index of uv (and ush) holding the current state          */
+    int32_t pad0;
+} pd_state_dev;
+
+/* Initialise a state and the per-row aux/fext arrays from caller-order
+ * inputs [device]: u0, v0, fext0 (n*3 doubles each, any may be NULL = 0),
+ * bc (n bytes: bit c set = displacement component c prescribed: zero
+ * acceleration, velocity held at v0), perm (n_pad, from pd_build_family).
+ * aux and fext are the arrays later referenced by prob->aux / prob->fext
+ * (passed here as writable pointers).  Sets the step counter to
+ * 'start_step'.  The mask is not touched (copy the initial mask in). */
+pd_status pd_state_init(pd_ctx *ctx, const pd_problem_dev *prob, const int32_t *perm,
+                        int64_t n, const double *u0, const double *v0, const uint8_t *bc,
+                        const double *fext0, const int32_t *spec_rows, uint32_t *aux_out,
+                        double *fext_out, pd_state_dev *st, int64_t start_step);
+
+/* Copy the current displacement and velocity back to caller order [device]
+ * (n*3 doubles each; either may be NULL). */
+pd_status pd_state_read(pd_ctx *ctx, const pd_problem_dev *prob, const int32_t *perm,
+                        int64_t n, const pd_state_dev *st, double *u_out, double *v_out);
+
+/* Read the step counter (synchronises the stream). */
+pd_status pd_get_step(pd_ctx *ctx, const pd_state_dev *st, int64_t *step);
+
+/* ------------------------------------------------------------------------ */
+/* the force operator                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Internal force f = F(u) (Eqs. 2.3 then 2.2) for the current displacement
+ * of 'st' and bond status 'mask', without breaking and without updating.
+ * Outputs [device], internal order: f (n_pad*4, f_x f_y f_z 0) and theta
+ * (n_pad, dilatation of Eq. 1.6); theta may be NULL.  precision selects
+ * the double kernels or the single-precision force kernels of the
+ * FP32_RECHECK path (which then also rebuild the shadow state st->ush,
+ * st->qr32 and st->dsum from the double displacement).  Uses st->qr (or
+ * st->qr32) as scratch. */
+pd_status pd_force(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, int32_t precision,
+                   double *f, double *theta);
+
+/* ------------------------------------------------------------------------ */
+/* explicit stepping                                                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct pd_step_opts {
+    int32_t precision;   /* pd_precision                                             */
+    int32_t form;        /* pd_form                                                  */
+    int32_t graph_chunk; /* >0: capture this many steps in a hipGraph and replay it   */
+    int32_t block;       /* threads per block (64, 128 or 256) or 0 = 256           */
+    int32_t check_every; /* >0: check the non-finite flag every this many steps (sync) */
+    int32_t profile;     /* 1: time every kernel with HIP events on the stream (eager
+                            launches, one synchronisation per step); see pd_profile_read */
+} pd_step_opts;
+
+/* Kernel timings gathered by pd_step with opts->profile = 1 (milliseconds,
+ * summed over the profiled steps).  pass1: breaking + dilatation kernel
+ * (breaking-only kernel in the block form); pass2: force + update kernel
+ * (block product + update in the block form); extra: everything else the
+ * steps launched (block re-assembly). */
+typedef struct pd_profile_stats {
+    int64_t steps;
+    double ms_pass1;
+    double ms_pass2;
+    double ms_extra;
+} pd_profile_stats;
+
+/* Read (and with reset != 0 clear) the context's accumulated timings. */
+pd_status pd_profile_read(pd_ctx *ctx, pd_profile_stats *out, int32_t reset);
+
+typedef struct pd_step_report {
+    int64_t step;           /* step counter after the call                           */
+    int64_t broken_total;   /* directed bond-status bits cleared by breaking so far   */
+    int64_t rechecks;       /* FP64 rechecks performed by the FP32 path so far        */
+    int32_t nonfinite;      /* 1 if a non-finite displacement was produced            */
+    int32_t pad0;
+    double umax;            /* max |u| component at the end                           */
+} pd_step_report;
+
+/* Advance 'nsteps' explicit steps.  Each step n (t_n = n dt):
+ *   1. breaking: for every intact bond, e = M.(u_j - u_i) (Eqs. 2.4, 2.7),
+ *      s = e/x (Eq. 1.17); s >= s0 clears the bond status (Eq. 1.30) for
+ *      good.  FP64: decided in double with e evaluated as
+ *      (M1 eta1 + M2 eta2) + M3 eta3 without contraction.  FP32_RECHECK:
+ *      decided in float outside a proven error band around s0, by the same
+ *      double expression inside it.
+ *   2. dilatation theta_i (Eq. 2.3 summed over intact bonds);
+ *   3. force f_i (Eq. 2.2), or with PD_BSR f = K u with K of Eq. 2.14
+ *      (assembled by pd_assemble_K, re-assembled on rows near new breaks);
+ *   4. update (Eqs. 2.11, 2.12): a = (f + F_ext r(n)) / (rho V), zero on
+ *      prescribed components; v += dt a; u += dt v.
+ * 'rep' (may be NULL) is filled after synchronising the stream; with
+ * rep == NULL and check_every == 0 the call is fully asynchronous.
+ * Errors: PD_ERR_ARG, PD_ERR_UNSUPPORTED (PD_BSR without K, unknown
+ * option), PD_ERR_UNSTABLE (non-finite state seen at a check), PD_ERR_HIP. */
+struct pd_bsr_dev;
+pd_status pd_step(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, int64_t nsteps,
+                  const pd_step_opts *opts, struct pd_bsr_dev *K, pd_step_report *rep);
+
+/* ------------------------------------------------------------------------ */
+/* block-sparse stiffness (Eq. 2.14)                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Block pattern of K (host): row i holds a block for every node q != i that
+ * is reachable through at most two bonds (the dilatation of a neighbour
+ * couples nodes up to 2 delta apart, Eqs. 2.8, 2.10, 2.14).  Two-phase like
+ * pd_build_family: with col == NULL only *sizes is set.  row_ptr [n_pad+1],
+ * col [nnzb] (sorted per row), both [host]. */
+typedef struct pd_bsr_sizes {
+    int64_t nnzb;            /* blocks                                               */
+    int32_t max_row_blocks;  /* largest row                                          */
+    int32_t reach;           /* largest |lattice offset component| of a block        */
+} pd_bsr_sizes;
+
+pd_status pd_bsr_pattern(const pd_family_sizes *sizes, const pd_family_host *fam,
+                         pd_bsr_sizes *out, int64_t *row_ptr, int32_t *col);
+
+typedef struct pd_bsr_dev {
+    int64_t nnzb;
+    int32_t dim;            /* block size (2 or 3)                                     */
+    int32_t fp32;           /* values stored as float (1) or double (0)                */
+    int32_t max_row_blocks; /* from pd_bsr_pattern                                     */
+    int32_t reach;          /* from pd_bsr_pattern                                     */
+    const int64_t *row_ptr; /* [device] n_pad+1                                        */
+    const int32_t *col;     /* [device] nnzb                                           */
+    void *vals;             /* [device] nnzb*dim*dim, row-major blocks                 */
+    double *bc;             /* [device] n_pad*8 scratch: per-node sums B_i, C_i        */
+    uint32_t *dirty;        /* [device] n_pad flags of rows to re-assemble (zeroed)     */
+    int32_t assembled;      /* set by pd_assemble_K                                    */
+    int32_t pad0;
+} pd_bsr_dev;
+
+/* Assemble the off-diagonal blocks Kt_iq of the restoring operator in
+ * difference form, f_i = sum_{q != i} Kt_iq (u_q - u_i), which equals
+ * F_int = (K^v + K^d) U of Eq. 2.14 (K^v from Eqs. 2.8, 2.10, 2.7 and K^d
+ * from Eqs. 2.9, 2.7) for the bond status 'mask'.  Every row is assembled.
+ * Device-side and asynchronous; K->vals etc. caller-allocated. */
+pd_status pd_assemble_K(pd_ctx *ctx, const pd_problem_dev *prob, const uint64_t *mask,
+                        pd_bsr_dev *K);
+
+/* f = Kt u for the current displacement of st (internal order, n_pad*4). */
+pd_status pd_bsr_apply(pd_ctx *ctx, const pd_problem_dev *prob, const pd_bsr_dev *K,
+                       const pd_state_dev *st, double *f);
+
+/* ------------------------------------------------------------------------ */
+/* outputs                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Damage phi_i = 1 - sum rho w V_j / sum w V_j over the geometric family
+ * (Eq. 1.31), internal order, phi [device] n_pad (0 for padding rows). */
+pd_status pd_damage(pd_ctx *ctx, const pd_problem_dev *prob, const uint64_t *mask, double *phi);
+
+/* Energies of the current state (synchronises): kinetic 1/2 sum rho V v.v
+ * and strain 1/2 sum u.(-f(u)) (the quadratic energy whose gradient is
+ * Eq. 2.2).  f_scratch [device] n_pad*4. */
+pd_status pd_energy(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st,
+                    double *f_scratch, double *kinetic, double *strain);
+
+/* Largest stable time step 2/omega_max of the explicit update for
+ * specimen-uniform material, omega_max^2 = largest eigenvalue of
+ * M^-1 K on the free degrees of freedom, by power iteration from a
+ * seeded start (iters iterations), intact bonds 'mask'.  Uses st as
+ * scratch (u and v are overwritten).  Synchronises. */
+pd_status pd_stable_dt(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st,
+                       double *f_scratch, int32_t iters, uint64_t seed, double *dt_crit);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PD_H */

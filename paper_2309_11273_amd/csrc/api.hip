@@ -1,0 +1,551 @@
+// C ABI entry points of libpd (host side): context, constants, state set-up,
+// force evaluation, explicit stepping with optional hipGraph replay, damage,
+// energies and the stable time step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kernels.h"
+#include "pd.h"
+#include "pd_internal.h"
+
+struct pd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
+    std::string err;
+    pd_ctl *host_ctl = nullptr;        // pinned copy of the control block
+    hipGraphExec_t gexec = nullptr;
+    uint64_t gkey = 0;
+    int gsteps = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // profiling events
+    pd_profile_stats prof{};
+};
+
+namespace {
+
+pd_status fail(pd_ctx *c, pd_status s, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), PD_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+pd_status check_problem(pd_ctx *c, const pd_problem_dev *p) {
+    if (!p) return fail(c, PD_ERR_ARG, "problem is NULL");
+    if (p->dim != 2 && p->dim != 3) return fail(c, PD_ERR_ARG, "dim must be 2 or 3");
+    if (p->n_pad <= 0 || p->n_pad % 64 || p->n_slices != p->n_pad / 64)
+        return fail(c, PD_ERR_SIZE, "n_pad must be a positive multiple of 64 and n_slices = n_pad/64");
+    if (p->n_stencil < 1 || p->n_stencil > PD_MAX_STENCIL) return fail(c, PD_ERR_SIZE, "bad n_stencil");
+    if (p->n_specimens < 1 || p->n_specimens > PD_MAX_SPECIMENS) return fail(c, PD_ERR_SIZE, "bad n_specimens");
+    if (!p->slice_ptr || !p->words || !p->stencil || !p->vol || !p->inv_m || !p->spec)
+        return fail(c, PD_ERR_ARG, "problem has a NULL family array");
+    if (p->ramp_steps < 0) return fail(c, PD_ERR_ARG, "ramp_steps < 0");
+    return PD_OK;
+}
+
+pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
+    pdk::StepArgs a{};
+    a.n_pad = p->n_pad;
+    a.n_slices = p->n_slices;
+    a.dim = p->dim;
+    a.n_stencil = p->n_stencil;
+    a.ramp_steps = p->ramp_steps;
+    a.slice_ptr = p->slice_ptr;
+    a.words = p->words;
+    a.stencil = p->stencil;
+    a.spec = p->spec;
+    a.aux = p->aux;
+    a.fext = reinterpret_cast<const double4 *>(p->fext);
+    a.uv[0] = reinterpret_cast<double4 *>(st->uv[0]);
+    a.uv[1] = reinterpret_cast<double4 *>(st->uv[1]);
+    a.vel = reinterpret_cast<double4 *>(st->vel);
+    a.qr = reinterpret_cast<double2 *>(st->qr);
+    a.mask = st->mask;
+    a.ctl = reinterpret_cast<pd_ctl *>(st->ctl);
+    a.ush[0] = reinterpret_cast<int4 *>(st->ush[0]);
+    a.ush[1] = reinterpret_cast<int4 *>(st->ush[1]);
+    a.qr32 = reinterpret_cast<float2 *>(st->qr32);
+    a.dsum = reinterpret_cast<double4 *>(st->dsum);
+    return a;
+}
+
+pd_status check_state(pd_ctx *c, const pd_state_dev *st, bool need_f32) {
+    if (!st) return fail(c, PD_ERR_ARG, "state is NULL");
+    if (!st->uv[0] || !st->uv[1] || !st->vel || !st->qr || !st->mask || !st->ctl)
+        return fail(c, PD_ERR_ARG, "state has a NULL array");
+    if (st->cur != 0 && st->cur != 1) return fail(c, PD_ERR_ARG, "state cur must be 0 or 1");
+    if (need_f32 && (!st->ush[0] || !st->ush[1] || !st->qr32 || !st->dsum))
+        return fail(c, PD_ERR_ARG, "FP32 path needs ush[0], ush[1], qr32 and dsum");
+    return PD_OK;
+}
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pd_version(void) { return "pdx 0.1 (gfx950)"; }
+
+pd_status pd_ctx_create(pd_ctx **out, int device, void *stream) {
+    if (!out) return PD_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PD_ERR_HIP;
+    if (hipSetDevice(device) != hipSuccess) return PD_ERR_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PD_ERR_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PD_ERR_HIP;
+    pd_ctx *c = new pd_ctx();
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return PD_ERR_HIP;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->host_ctl), sizeof(pd_ctl), hipHostMallocDefault) != hipSuccess) {
+        (void)hipStreamDestroy(c->cap_stream);
+        delete c;
+        return PD_ERR_HIP;
+    }
+    *out = c;
+    return PD_OK;
+}
+
+pd_status pd_ctx_destroy(pd_ctx *c) {
+    if (!c) return PD_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (int k = 0; k < 4; k++)
+        if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+    delete c;
+    return PD_OK;
+}
+
+const char *pd_last_error(const pd_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+pd_status pd_profile_read(pd_ctx *c, pd_profile_stats *out, int32_t reset) {
+    if (!c || !out) return PD_ERR_ARG;
+    *out = c->prof;
+    if (reset) c->prof = pd_profile_stats{};
+    return PD_OK;
+}
+
+pd_status pd_critical_stretch(pd_mode mode, double E, double nu, double G0, double delta, int variant,
+                              double *s0) {
+    if (!s0 || !(E > 0.0) || !(nu > -1.0 && nu < 0.5) || !(delta > 0.0)) return PD_ERR_ARG;
+    if (mode < PD_3D || mode > PD_PLANE_STRAIN || (variant != 0 && variant != 1)) return PD_ERR_ARG;
+    if (!(G0 > 0.0) || !std::isfinite(G0)) {
+        *s0 = INFINITY;
+        return PD_OK;
+    }
+    const double pi = 3.14159265358979323846;
+    const double kappa = E / (3.0 * (1.0 - 2.0 * nu));
+    const double mu = E / (2.0 * (1.0 + nu));
+    if (mode == PD_3D) {
+        // Eqs. 1.26, 1.27
+        const double beta = 125.0 * delta / 1848.0;
+        const double betap = variant ? 5.0 * delta / 24.0 : 5.0 * delta / (24.0 * pi);
+        *s0 = std::sqrt(G0 / ((9.0 * kappa - 15.0 * mu) * beta + 15.0 * mu * betap));
+        return PD_OK;
+    }
+    // Eqs. 1.28, 1.29 with A of Eq. 1.8
+    const double A = mode == PD_PLANE_STRESS ? 2.0 * (1.0 - 2.0 * nu) / (1.0 - nu) : 2.0;
+    const double g = (1.0 + nu) / (1.0 - 2.0 * nu);
+    const double kp = mode == PD_PLANE_STRESS ? kappa + mu / 9.0 * g * g : kappa + mu / 9.0;
+    const double beta = 1087.0 * delta / (1250.0 * pi * pi);
+    const double betap = 4.0 * delta / (5.0 * pi);
+    *s0 = std::sqrt(G0 / (A * A * (kp - 8.0 / 9.0 * mu) * beta + 8.0 * mu * betap));
+    return PD_OK;
+}
+
+pd_status pd_specimen_params(pd_mode mode, double E, double nu, double rho, double s0, double dt, pd_spec *out) {
+    if (!out || !(E > 0.0) || !(nu > -1.0 && nu < 0.5) || !(rho > 0.0) || !(dt > 0.0) || std::isnan(s0))
+        return PD_ERR_ARG;
+    if (mode < PD_3D || mode > PD_PLANE_STRAIN) return PD_ERR_ARG;
+    const double kappa = E / (3.0 * (1.0 - 2.0 * nu));
+    const double mu = E / (2.0 * (1.0 + nu));
+    double A, K, G;
+    if (mode == PD_3D) {  // Eqs. 1.8, 1.15, 1.16
+        A = 3.0;
+        K = 3.0 * kappa;
+        G = 15.0 * mu;
+    } else if (mode == PD_PLANE_STRESS) {
+        A = 2.0 * (1.0 - 2.0 * nu) / (1.0 - nu);
+        K = 2.0 * kappa * (1.0 - 2.0 * nu) / (1.0 - nu) -
+            2.0 / 3.0 * mu * (1.0 + nu) * (1.0 - 3.0 * nu) / ((1.0 - nu) * (1.0 - 2.0 * nu));
+        G = 8.0 * mu;
+    } else {
+        A = 2.0;
+        K = 2.0 * kappa - 2.0 / 3.0 * mu;
+        G = 8.0 * mu;
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->kp = K - G / 3.0;
+    out->G = G;
+    out->A = A;
+    out->rho = rho;
+    out->s0 = s0;
+    out->dt = dt;
+    return PD_OK;
+}
+
+pd_status pd_state_init(pd_ctx *c, const pd_problem_dev *p, const int32_t *perm, int64_t n, const double *u0,
+                        const double *v0, const uint8_t *bc, const double *fext0, const int32_t *spec_rows,
+                        uint32_t *aux_out, double *fext_out, pd_state_dev *st, int64_t start_step) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!perm || !spec_rows || !aux_out || !fext_out) return fail(c, PD_ERR_ARG, "NULL perm/spec/aux/fext");
+    if (n < 1 || n > p->n_pad) return fail(c, PD_ERR_SIZE, "n out of range");
+    if (start_step < 0) return fail(c, PD_ERR_ARG, "start_step < 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pdk::InitArgs a{};
+    a.n_pad = p->n_pad;
+    a.start_step = start_step;
+    a.perm = perm;
+    a.spec_rows = spec_rows;
+    a.vol = p->vol;
+    a.inv_m = p->inv_m;
+    a.u0 = u0;
+    a.v0 = v0;
+    a.f0 = fext0;
+    a.bc = bc;
+    a.aux = aux_out;
+    a.fext = reinterpret_cast<double4 *>(fext_out);
+    a.uv = reinterpret_cast<double4 *>(st->uv[st->cur]);
+    a.vel = reinterpret_cast<double4 *>(st->vel);
+    a.qr = reinterpret_cast<double2 *>(st->qr);
+    a.qr32 = reinterpret_cast<float2 *>(st->qr32);
+    a.ctl = reinterpret_cast<pd_ctl *>(st->ctl);
+    HIP_TRY(c, pdk::launch_state_init(a, c->stream));
+    // the other displacement buffer carries the node volumes too
+    HIP_TRY(c, hipMemcpyAsync(st->uv[st->cur ^ 1], st->uv[st->cur], sizeof(double) * 4 * p->n_pad,
+                              hipMemcpyDeviceToDevice, c->stream));
+    return PD_OK;
+}
+
+pd_status pd_state_read(pd_ctx *c, const pd_problem_dev *p, const int32_t *perm, int64_t n, const pd_state_dev *st,
+                        double *u_out, double *v_out) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!perm) return fail(c, PD_ERR_ARG, "perm is NULL");
+    if (n < 1 || n > p->n_pad) return fail(c, PD_ERR_SIZE, "n out of range");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, pdk::launch_state_read(perm, p->n_pad, reinterpret_cast<const double4 *>(st->uv[st->cur]),
+                                      reinterpret_cast<const double4 *>(st->vel), u_out, v_out, c->stream));
+    return PD_OK;
+}
+
+pd_status pd_get_step(pd_ctx *c, const pd_state_dev *st, int64_t *step) {
+    if (!c || !st || !st->ctl || !step) return PD_ERR_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *step = c->host_ctl->s2;
+    return PD_OK;
+}
+
+pd_status pd_force(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int32_t precision, double *f,
+                   double *theta) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if (precision != PD_FP64 && precision != PD_FP32_RECHECK) return fail(c, PD_ERR_ARG, "unknown precision");
+    if ((s = check_state(c, st, precision == PD_FP32_RECHECK)) != PD_OK) return s;
+    if (!f) return fail(c, PD_ERR_ARG, "f is NULL");
+    if (!p->aux) return fail(c, PD_ERR_ARG, "aux is NULL (call pd_state_init first)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pdk::StepArgs a = make_args(p, st);
+    a.f_out = reinterpret_cast<double4 *>(f);
+    a.theta_out = theta;
+    if (precision == PD_FP64) {
+        HIP_TRY(c, pdk::launch_pass1_f64(a, st->cur, false, 256, c->stream));
+        a.theta_out = nullptr;
+        HIP_TRY(c, pdk::launch_pass2_f64(a, st->cur, false, 256, c->stream));
+    } else {
+        HIP_TRY(c, pdk::launch_shadow_prep(a, st->cur, c->stream));
+        HIP_TRY(c, pdk::launch_pass1_f32(a, st->cur, false, 256, c->stream));
+        a.theta_out = nullptr;
+        HIP_TRY(c, pdk::launch_pass2_f32(a, st->cur, false, 256, c->stream));
+    }
+    return PD_OK;
+}
+
+static pd_status check_bsr(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *K);
+
+// one explicit step on 'stream' starting from displacement buffer 'cur'
+static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, int cur, hipStream_t s,
+                               const pd_problem_dev *p, const pd_bsr_dev *K, hipEvent_t *ev = nullptr) {
+    hipError_t e;
+    const int block = o.block > 0 ? o.block : 256;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    if (o.form == PD_BSR) {
+        if ((e = pdk::launch_break_mark(a, p, K, cur, s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+        if ((e = pdk::launch_bsr_prep_assemble(a, p, K, false, cur, s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+        if ((e = pdk::launch_bsr_spmv(a, p, K, cur, true, s)) != hipSuccess) return e;
+    } else {
+        if (o.precision == PD_FP64) e = pdk::launch_pass1_f64(a, cur, true, block, s);
+        else e = pdk::launch_pass1_f32(a, cur, true, block, s);
+        if (e != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+        if (o.precision == PD_FP64) e = pdk::launch_pass2_f64(a, cur, true, block, s);
+        else e = pdk::launch_pass2_f32(a, cur, true, block, s);
+        if (e != hipSuccess) return e;
+    }
+    if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps, const pd_step_opts *opts,
+                  pd_bsr_dev *K, pd_step_report *rep) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    pd_step_opts o{};
+    if (opts) o = *opts;
+    if (o.precision != PD_FP64 && o.precision != PD_FP32_RECHECK) return fail(c, PD_ERR_ARG, "unknown precision");
+    if (o.form != PD_MATRIX_FREE && o.form != PD_BSR) return fail(c, PD_ERR_ARG, "unknown form");
+    if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
+        return fail(c, PD_ERR_ARG, "block must be 0, 64, 128 or 256");
+    if (o.graph_chunk < 0 || o.check_every < 0) return fail(c, PD_ERR_ARG, "negative option");
+    if (o.profile != 0 && o.profile != 1) return fail(c, PD_ERR_ARG, "profile must be 0 or 1");
+    if (o.profile && !c->ev[0]) {
+        for (int k = 0; k < 4; k++) HIP_TRY(c, hipEventCreate(&c->ev[k]));
+    }
+    if ((s = check_state(c, st, o.precision == PD_FP32_RECHECK && o.form == PD_MATRIX_FREE)) != PD_OK) return s;
+    if (!p->aux || !p->fext) return fail(c, PD_ERR_ARG, "aux/fext are NULL (call pd_state_init first)");
+    if (nsteps < 0) return fail(c, PD_ERR_ARG, "nsteps < 0");
+    if (o.form == PD_BSR) {
+        if (!K || !K->assembled) return fail(c, PD_ERR_UNSUPPORTED, "PD_BSR needs an assembled K");
+        if ((s = check_bsr(c, p, K)) != PD_OK) return s;
+        if ((o.precision == PD_FP32_RECHECK) != (K->fp32 != 0))
+            return fail(c, PD_ERR_UNSUPPORTED, "BSR precision must match the K value type");
+        if (!K->dirty || !K->bc || !p->lat4) return fail(c, PD_ERR_ARG, "BSR needs dirty, bc and lat4");
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    pdk::StepArgs a = make_args(p, st);
+    int cur = st->cur;
+    if (o.precision == PD_FP32_RECHECK && o.form == PD_MATRIX_FREE)
+        HIP_TRY(c, pdk::launch_shadow_prep(a, cur, c->stream));
+
+    int64_t done = 0;
+    const int64_t check = o.check_every > 0 ? o.check_every : nsteps;
+    while (done < nsteps) {
+        int64_t todo = std::min<int64_t>(check, nsteps - done);
+        int64_t chunk = (o.graph_chunk > 0 && !o.profile) ? ((int64_t)o.graph_chunk + 1) / 2 * 2 : 0;
+        if (chunk > 0 && todo >= chunk) {
+            uint64_t key = 1469598103934665603ull;
+            const uint64_t fields[] = {(uint64_t)(uintptr_t)p->words, (uint64_t)(uintptr_t)p->spec,
+                                       (uint64_t)(uintptr_t)p->aux, (uint64_t)(uintptr_t)st->uv[0],
+                                       (uint64_t)(uintptr_t)st->uv[1], (uint64_t)(uintptr_t)st->mask,
+                                       (uint64_t)(uintptr_t)st->ctl, (uint64_t)(uintptr_t)st->ush[0],
+                                       (uint64_t)(uintptr_t)st->vel, (uint64_t)o.precision,
+                                       (uint64_t)o.block, (uint64_t)cur, (uint64_t)chunk,
+                                       (uint64_t)p->ramp_steps, (uint64_t)(uintptr_t)p->fext,
+                                       (uint64_t)(uintptr_t)st->qr};
+            for (uint64_t f : fields) key = mix(key, f);
+            if (!c->gexec || c->gkey != key) {
+                if (c->gexec) {
+                    (void)hipGraphExecDestroy(c->gexec);
+                    c->gexec = nullptr;
+                }
+                hipGraph_t g;
+                HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                hipError_t ce = hipSuccess;
+                for (int64_t i = 0; i < chunk && ce == hipSuccess; i++)
+                    ce = enqueue_step(a, o, (cur + (int)i) & 1, c->cap_stream, p, K);
+                hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
+                if (ce != hipSuccess) return fail(c, PD_ERR_HIP, "capture launch: %s", hipGetErrorString(ce));
+                if (ee != hipSuccess) return fail(c, PD_ERR_HIP, "end capture: %s", hipGetErrorString(ee));
+                hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ie != hipSuccess) return fail(c, PD_ERR_HIP, "graph instantiate: %s", hipGetErrorString(ie));
+                c->gkey = key;
+                c->gsteps = (int)chunk;
+            }
+            while (todo >= chunk) {
+                HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+                todo -= chunk;
+                done += chunk;
+            }
+        }
+        for (int64_t i = 0; i < todo; i++) {
+            hipError_t e = enqueue_step(a, o, cur, c->stream, p, K, o.profile ? c->ev : nullptr);
+            if (e != hipSuccess) return fail(c, PD_ERR_HIP, "step launch: %s", hipGetErrorString(e));
+            if (o.profile) {
+                float t1 = 0, t2 = 0, t3 = 0;
+                HIP_TRY(c, hipEventSynchronize(c->ev[3]));
+                HIP_TRY(c, hipEventElapsedTime(&t1, c->ev[0], c->ev[1]));
+                HIP_TRY(c, hipEventElapsedTime(&t2, c->ev[1], c->ev[2]));
+                HIP_TRY(c, hipEventElapsedTime(&t3, c->ev[2], c->ev[3]));
+                c->prof.steps++;
+                c->prof.ms_pass1 += t1;
+                c->prof.ms_extra += t2;
+                c->prof.ms_pass2 += t3;
+            }
+            cur ^= 1;
+            done++;
+        }
+        if (o.check_every > 0) {
+            st->cur = cur;
+            HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (c->host_ctl->flags & PD_CTL_NONFINITE)
+                return fail(c, PD_ERR_UNSTABLE, "non-finite displacement before step %lld",
+                            (long long)c->host_ctl->s2);
+        }
+    }
+    st->cur = cur;
+    if (rep) {
+        HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        const pd_ctl *h = c->host_ctl;
+        rep->step = h->s2;
+        rep->broken_total = (int64_t)h->broken;
+        rep->rechecks = (int64_t)h->rechecks;
+        rep->nonfinite = (h->flags & PD_CTL_NONFINITE) ? 1 : 0;
+        float um;
+        unsigned int bits = h->umax_bits[cur];
+        std::memcpy(&um, &bits, 4);
+        rep->umax = (double)um;
+        if (rep->nonfinite) return fail(c, PD_ERR_UNSTABLE, "non-finite displacement");
+    }
+    return PD_OK;
+}
+
+static pd_status check_bsr(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *K) {
+    if (!K) return fail(c, PD_ERR_ARG, "K is NULL");
+    if (!K->row_ptr || !K->col || !K->vals || !K->bc || !K->dirty) return fail(c, PD_ERR_ARG, "K has a NULL array");
+    if (K->dim != p->dim) return fail(c, PD_ERR_ARG, "K dim differs from the problem");
+    if (!p->lat4) return fail(c, PD_ERR_ARG, "problem lat4 is NULL");
+    if (K->max_row_blocks < 0 || K->reach < 0 || K->reach > 64) return fail(c, PD_ERR_SIZE, "bad K pattern sizes");
+    const size_t lds = pdk::bsr_assemble_lds(p->dim, K->max_row_blocks, K->reach);
+    if (lds > 160 * 1024) return fail(c, PD_ERR_UNSUPPORTED, "a row of K does not fit in LDS (%zu bytes)", lds);
+    return PD_OK;
+}
+
+pd_status pd_assemble_K(pd_ctx *c, const pd_problem_dev *p, const uint64_t *mask, pd_bsr_dev *K) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_bsr(c, p, K)) != PD_OK) return s;
+    if (!mask || !p->aux) return fail(c, PD_ERR_ARG, "NULL mask or aux (call pd_state_init first)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pd_state_dev tmp{};
+    tmp.mask = const_cast<uint64_t *>(mask);
+    pdk::StepArgs a = make_args(p, &tmp);
+    const size_t lds = pdk::bsr_assemble_lds(p->dim, K->max_row_blocks, K->reach);
+    HIP_TRY(c, pdk::set_bsr_lds_limit(p->dim, K->fp32 != 0, lds));
+    HIP_TRY(c, pdk::launch_bsr_prep_assemble(a, p, K, true, 0, c->stream));
+    K->assembled = 1;
+    return PD_OK;
+}
+
+pd_status pd_bsr_apply(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *K, const pd_state_dev *st, double *f) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_bsr(c, p, K)) != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!K->assembled) return fail(c, PD_ERR_STATE, "K is not assembled");
+    if (!f) return fail(c, PD_ERR_ARG, "f is NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pdk::StepArgs a = make_args(p, st);
+    a.f_out = reinterpret_cast<double4 *>(f);
+    HIP_TRY(c, pdk::launch_bsr_spmv(a, p, K, st->cur, false, c->stream));
+    return PD_OK;
+}
+
+pd_status pd_damage(pd_ctx *c, const pd_problem_dev *p, const uint64_t *mask, double *phi) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if (!mask || !phi) return fail(c, PD_ERR_ARG, "NULL mask/phi");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pdk::DamageArgs a{};
+    a.n_slices = p->n_slices;
+    a.slice_ptr = p->slice_ptr;
+    a.words = p->words;
+    a.mask = mask;
+    a.vol = p->vol;
+    a.phi = phi;
+    HIP_TRY(c, pdk::launch_damage(a, c->stream));
+    return PD_OK;
+}
+
+pd_status pd_energy(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, double *f_scratch, double *kinetic,
+                    double *strain) {
+    if (!c) return PD_ERR_ARG;
+    if (!f_scratch || !kinetic || !strain) return fail(c, PD_ERR_ARG, "NULL output");
+    pd_status s = pd_force(c, p, st, PD_FP64, f_scratch, nullptr);
+    if (s != PD_OK) return s;
+    pd_ctl *ctl = reinterpret_cast<pd_ctl *>(st->ctl);
+    HIP_TRY(c, pdk::launch_energy(p->n_pad, reinterpret_cast<const double4 *>(st->uv[st->cur]),
+                                  reinterpret_cast<const double4 *>(st->vel),
+                                  reinterpret_cast<const double4 *>(f_scratch), p->aux, p->spec, ctl, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *strain = -0.5 * c->host_ctl->red[0];
+    *kinetic = 0.5 * c->host_ctl->red[1];
+    return PD_OK;
+}
+
+pd_status pd_stable_dt(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, double *f_scratch, int32_t iters,
+                       uint64_t seed, double *dt_crit) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!f_scratch || !dt_crit || iters < 1 || !p->aux) return fail(c, PD_ERR_ARG, "bad arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    double4 *x = reinterpret_cast<double4 *>(st->uv[st->cur]);
+    double4 *y = reinterpret_cast<double4 *>(st->uv[st->cur ^ 1]);
+    pd_ctl *ctl = reinterpret_cast<pd_ctl *>(st->ctl);
+    HIP_TRY(c, pdk::launch_pi_init(p->n_pad, p->dim, p->aux, x, seed, c->stream));
+    double lam = 0.0;
+    for (int it = 0; it < iters; it++) {
+        if ((s = pd_force(c, p, st, PD_FP64, f_scratch, nullptr)) != PD_OK) return s;
+        HIP_TRY(c, pdk::launch_pi_step(p->n_pad, p->dim, p->aux, p->spec, x,
+                                       reinterpret_cast<const double4 *>(f_scratch), y, ctl, c->stream));
+        if (it == iters - 1) {
+            HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            lam = c->host_ctl->red[0] / c->host_ctl->red[1];
+        }
+    }
+    if (!(lam > 0.0)) return fail(c, PD_ERR_UNSTABLE, "power iteration did not converge");
+    *dt_crit = 2.0 / std::sqrt(lam);
+    return PD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,447 @@
+// Host-side set-up of the linearized OSB-PD solver: horizon search, internal
+// row order, interleaved bond words, bond-offset stencil, weighted volume and
+// notch cuts.
+//
+// Family H_i = { j : 0 < |xi_ij| <= delta } (Sec. 2.1); bond geometry
+// xi = x_j - x_i, x = |xi|, M = xi / x (Eqs. 1.2-1.5 and the linearized
+// unit state below Eq. 1.13); weighted volume m_i = sum_j w x^2 V_j with
+// w = 1 (Eq. 1.9).  Nodes lie on a uniform lattice, so every bond is one of
+// a small set of lattice offsets: the geometry is stored once per offset
+// (the "stencil") and each bond stores the neighbour row and the offset id.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "pd.h"
+#include "pd_internal.h"
+
+namespace {
+
+struct Stencil {
+    int32_t off[3];
+    double M[3];
+    double x;
+};
+
+// Bond length of lattice offset o: xi_c = dx * o_c, x = sqrt(sum xi_c^2)
+// accumulated in component order.
+double offset_length(double dx, const int32_t *o, double xi[3]) {
+    double s = 0.0;
+    for (int c = 0; c < 3; c++) {
+        xi[c] = dx * (double)o[c];
+        s += xi[c] * xi[c];
+    }
+    return std::sqrt(s);
+}
+
+std::vector<Stencil> make_stencil(int dim, double dx, double delta) {
+    std::vector<Stencil> st;
+    int R = (int)std::floor(delta / dx) + 1;
+    int Rz = dim == 3 ? R : 0;
+    for (int a = -R; a <= R; a++)
+        for (int b = -R; b <= R; b++)
+            for (int c = -Rz; c <= Rz; c++) {
+                int32_t o[3] = {a, b, c};
+                double xi[3];
+                double x = offset_length(dx, o, xi);
+                if (!(x > 0.0) || !(x <= delta)) continue;
+                Stencil s;
+                for (int k = 0; k < 3; k++) {
+                    s.off[k] = o[k];
+                    s.M[k] = xi[k] / x;
+                }
+                s.x = x;
+                st.push_back(s);
+            }
+    return st;
+}
+
+// Lattice point -> caller node index.
+struct Lookup {
+    int32_t lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+    std::vector<int32_t> dense;
+    std::unordered_map<uint64_t, int32_t> sparse;
+    bool use_dense = true;
+
+    static uint64_t key(const int32_t *l) {
+        return ((uint64_t)(uint32_t)(l[0] + (1 << 20)) << 42) ^
+               ((uint64_t)(uint32_t)(l[1] + (1 << 20)) << 21) ^ (uint64_t)(uint32_t)(l[2] + (1 << 20));
+    }
+    bool build(const std::vector<int32_t> &lat, int64_t n) {
+        int32_t hi[3];
+        for (int c = 0; c < 3; c++) { lo[c] = INT32_MAX; hi[c] = INT32_MIN; }
+        for (int64_t p = 0; p < n; p++)
+            for (int c = 0; c < 3; c++) {
+                lo[c] = std::min(lo[c], lat[3 * p + c]);
+                hi[c] = std::max(hi[c], lat[3 * p + c]);
+            }
+        double vol = 1.0;
+        for (int c = 0; c < 3; c++) {
+            ext[c] = hi[c] - lo[c] + 1;
+            vol *= (double)ext[c];
+        }
+        use_dense = vol <= (double)(1LL << 30) && vol <= 64.0 * (double)n + (double)(1 << 24);
+        if (use_dense) {
+            dense.assign((size_t)vol, -1);
+            for (int64_t p = 0; p < n; p++) {
+                size_t k = idx(&lat[3 * p]);
+                if (dense[k] >= 0) return false;
+                dense[k] = (int32_t)p;
+            }
+        } else {
+            sparse.reserve((size_t)n * 2);
+            for (int64_t p = 0; p < n; p++) {
+                if (!sparse.emplace(key(&lat[3 * p]), (int32_t)p).second) return false;
+            }
+        }
+        return true;
+    }
+    size_t idx(const int32_t *l) const {
+        return ((size_t)(l[0] - lo[0]) * ext[1] + (size_t)(l[1] - lo[1])) * ext[2] + (size_t)(l[2] - lo[2]);
+    }
+    int32_t find(const int32_t *l) const {
+        if (use_dense) {
+            for (int c = 0; c < 3; c++)
+                if (l[c] < lo[c] || l[c] >= lo[c] + ext[c]) return -1;
+            return dense[idx(l)];
+        }
+        auto it = sparse.find(key(l));
+        return it == sparse.end() ? -1 : it->second;
+    }
+};
+
+// ---- notch tests (proper crossing, no ties by construction of the inputs)
+
+double cross2(double ax, double ay, double bx, double by) { return ax * by - ay * bx; }
+
+bool crosses_segment(const double *P, const double *Q, const double *c) {
+    double d1 = cross2(c[2] - c[0], c[3] - c[1], P[0] - c[0], P[1] - c[1]);
+    double d2 = cross2(c[2] - c[0], c[3] - c[1], Q[0] - c[0], Q[1] - c[1]);
+    double d3 = cross2(Q[0] - P[0], Q[1] - P[1], c[0] - P[0], c[1] - P[1]);
+    double d4 = cross2(Q[0] - P[0], Q[1] - P[1], c[2] - P[0], c[3] - P[1]);
+    return (d1 * d2 < 0.0) && (d3 * d4 < 0.0);
+}
+
+bool crosses_parallelogram(const double *P, const double *Q, const double *p) {
+    const double *c = p, *a = p + 3, *b = p + 6;
+    double nrm[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    double sp = 0, sq = 0;
+    for (int k = 0; k < 3; k++) {
+        sp += nrm[k] * (P[k] - c[k]);
+        sq += nrm[k] * (Q[k] - c[k]);
+    }
+    if (!(sp * sq < 0.0)) return false;
+    double t = sp / (sp - sq);
+    double r[3];
+    for (int k = 0; k < 3; k++) r[k] = P[k] + t * (Q[k] - P[k]) - c[k];
+    double aa = 0, ab = 0, bb = 0, ra = 0, rb = 0;
+    for (int k = 0; k < 3; k++) {
+        aa += a[k] * a[k]; ab += a[k] * b[k]; bb += b[k] * b[k];
+        ra += r[k] * a[k]; rb += r[k] * b[k];
+    }
+    double det = aa * bb - ab * ab;
+    double s = (ra * bb - rb * ab) / det;
+    double u = (rb * aa - ra * ab) / det;
+    return s > 0.0 && s < 1.0 && u > 0.0 && u < 1.0;
+}
+
+double helix_level(const double *X, const double *p) { return (X[2] - p[0]) - p[1] * std::atan2(X[1], X[0]); }
+
+bool crosses_helicoid(const double *P, const double *Q, const double *p) {
+    double fp = helix_level(P, p), fq = helix_level(Q, p);
+    if (!(fp * fq < 0.0)) return false;
+    double t = fp / (fp - fq);
+    double X[3];
+    for (int k = 0; k < 3; k++) X[k] = P[k] + t * (Q[k] - P[k]);
+    double r = std::sqrt(X[0] * X[0] + X[1] * X[1]);
+    double th = std::atan2(X[1], X[0]);
+    return r > p[2] && r < p[3] && th > p[4] && th < p[5];
+}
+
+template <class F>
+void parallel_for(int64_t n, F &&f) {
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 4096 || nt == 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; t++) {
+        int64_t a = t * chunk, b = std::min(n, a + chunk);
+        if (a >= b) break;
+        th.emplace_back([&, a, b] { f(a, b); });
+    }
+    for (auto &x : th) x.join();
+}
+
+}  // namespace
+
+extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, int32_t ncuts,
+                                     pd_family_sizes *sizes, pd_family_host *out) {
+    if (!body || !sizes || !body->lat || !body->vol) return PD_ERR_ARG;
+    const int64_t n = body->n;
+    const int dim = body->dim;
+    if (n < 1 || n > PD_MAX_NODES) return PD_ERR_SIZE;
+    if (dim != 2 && dim != 3) return PD_ERR_ARG;
+    if (!(body->dx > 0.0) || !(body->delta > 0.0) || !std::isfinite(body->delta)) return PD_ERR_ARG;
+    if (ncuts < 0 || ncuts > PD_MAX_CUTS || (ncuts > 0 && !cuts)) return PD_ERR_ARG;
+    for (int k = 0; k < ncuts; k++)
+        if (cuts[k].kind < 0 || cuts[k].kind > 2 || (cuts[k].kind != 0 && dim == 2) ||
+            (cuts[k].kind == 0 && dim == 3))
+            return PD_ERR_ARG;
+
+    std::vector<int32_t> lat((size_t)3 * n, 0);
+    std::vector<int32_t> spec((size_t)n, 0);
+    int32_t nspec = 1;
+    for (int64_t p = 0; p < n; p++) {
+        for (int c = 0; c < dim; c++) lat[3 * p + c] = body->lat[dim * p + c];
+        if (!(body->vol[p] > 0.0)) return PD_ERR_ARG;
+        if (body->specimen) {
+            int32_t s = body->specimen[p];
+            if (s < 0 || s >= PD_MAX_SPECIMENS) return PD_ERR_ARG;
+            spec[p] = s;
+            nspec = std::max(nspec, s + 1);
+        }
+    }
+    std::vector<Stencil> st = make_stencil(dim, body->dx, body->delta);
+    if ((int)st.size() > PD_MAX_STENCIL) return PD_ERR_SIZE;
+    if (st.empty()) return PD_ERR_ARG;
+
+    Lookup look;
+    if (!look.build(lat, n)) return PD_ERR_ARG;  // duplicate lattice point
+
+    // internal order: specimen, tile, position inside the tile
+    const int T = dim == 3 ? 4 : 8;
+    auto floordiv = [](int32_t a, int32_t b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); };
+    std::vector<int64_t> order((size_t)n);
+    std::iota(order.begin(), order.end(), 0);
+    struct Key { int32_t s, t0, t1, t2, l; };
+    std::vector<Key> keys((size_t)n);
+    for (int64_t p = 0; p < n; p++) {
+        const int32_t *l = &lat[3 * p];
+        int32_t t[3], r[3];
+        for (int c = 0; c < 3; c++) {
+            t[c] = floordiv(l[c] - look.lo[c], T);
+            r[c] = (l[c] - look.lo[c]) - t[c] * T;
+        }
+        keys[p] = {spec[p], t[2], t[1], t[0], (r[2] * T + r[1]) * T + r[0]};
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        const Key &x = keys[a], &y = keys[b];
+        if (x.s != y.s) return x.s < y.s;
+        if (x.t0 != y.t0) return x.t0 < y.t0;
+        if (x.t1 != y.t1) return x.t1 < y.t1;
+        if (x.t2 != y.t2) return x.t2 < y.t2;
+        return x.l < y.l;
+    });
+    const int64_t n_pad = (n + 63) / 64 * 64;
+    const int64_t n_slices = n_pad / 64;
+    std::vector<int32_t> row_of((size_t)n);
+    for (int64_t r = 0; r < n; r++) row_of[order[r]] = (int32_t)r;
+
+    // neighbour lists per row: (neighbour row, stencil id), sorted by row
+    std::vector<int32_t> deg((size_t)n_pad, 0);
+    std::vector<std::vector<uint32_t>> nb((size_t)n);
+    parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; r++) {
+            int64_t p = order[r];
+            std::vector<uint32_t> &v = nb[r];
+            v.reserve(st.size());
+            for (size_t s = 0; s < st.size(); s++) {
+                int32_t q[3];
+                for (int c = 0; c < 3; c++) q[c] = lat[3 * p + c] + st[s].off[c];
+                int32_t qi = look.find(q);
+                if (qi < 0 || spec[qi] != spec[p]) continue;
+                v.push_back(((uint32_t)row_of[qi] << 7) | (uint32_t)s);
+            }
+            std::sort(v.begin(), v.end());
+            deg[r] = (int32_t)v.size();
+        }
+    });
+    std::vector<int64_t> slice_ptr((size_t)n_slices + 1, 0);
+    int32_t max_row = 0;
+    int64_t nnz = 0;
+    for (int64_t s = 0; s < n_slices; s++) {
+        int32_t L = 0;
+        for (int k = 0; k < 64; k++) L = std::max(L, deg[64 * s + k]);
+        slice_ptr[s + 1] = slice_ptr[s] + (int64_t)L * 64;
+        max_row = std::max(max_row, L);
+    }
+    for (int64_t r = 0; r < n; r++) nnz += deg[r];
+    const int64_t n_words = slice_ptr[n_slices];
+
+    // weighted volume (Eq. 1.9, w = 1, full geometric family)
+    std::vector<double> m((size_t)n_pad, 0.0);
+    parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; r++) {
+            double s = 0.0;
+            for (uint32_t w : nb[r]) {
+                const Stencil &sv = st[w & 127u];
+                s += sv.x * sv.x * body->vol[order[w >> 7]];
+            }
+            m[r] = s;
+        }
+    });
+
+    // notch cuts on unique bonds, evaluated with the lower caller index first
+    std::vector<std::vector<uint8_t>> cut((size_t)n);
+    std::vector<int64_t> ncut_rows((size_t)n, 0);
+    auto pos = [&](int64_t p, double *X) {
+        for (int c = 0; c < 3; c++) X[c] = body->origin[c] + body->dx * (double)lat[3 * p + c];
+    };
+    if (ncuts > 0) {
+        parallel_for(n, [&](int64_t a, int64_t b) {
+            for (int64_t r = a; r < b; r++) {
+                int64_t p = order[r];
+                cut[r].assign(nb[r].size(), 0);
+                for (size_t k = 0; k < nb[r].size(); k++) {
+                    int64_t q = order[nb[r][k] >> 7];
+                    int64_t lo = std::min(p, q), hi = std::max(p, q);
+                    double P[3], Q[3];
+                    pos(lo, P);
+                    pos(hi, Q);
+                    for (int c = 0; c < ncuts; c++) {
+                        if (cuts[c].specimen >= 0 && spec[p] != cuts[c].specimen) continue;
+                        bool hit = false;
+                        if (cuts[c].kind == 0) hit = crosses_segment(P, Q, cuts[c].p);
+                        else if (cuts[c].kind == 1) hit = crosses_parallelogram(P, Q, cuts[c].p);
+                        else hit = crosses_helicoid(P, Q, cuts[c].p);
+                        if (hit) {
+                            cut[r][k] = 1;
+                            ncut_rows[r]++;
+                            break;
+                        }
+                    }
+                }
+            }
+        });
+    }
+    int64_t ncut_dir = 0;
+    for (int64_t r = 0; r < n; r++) ncut_dir += ncut_rows[r];
+
+    sizes->n = n;
+    sizes->n_pad = n_pad;
+    sizes->n_slices = n_slices;
+    sizes->n_words = n_words;
+    sizes->n_mask = n_words / 64;
+    sizes->nnz = nnz;
+    sizes->n_bonds = nnz / 2;
+    sizes->n_cut = ncut_dir / 2;
+    sizes->n_stencil = (int32_t)st.size();
+    sizes->max_row = max_row;
+    sizes->dim = dim;
+    sizes->n_specimens = nspec;
+    if (!out) return PD_OK;
+    if (!out->perm || !out->row_of || !out->slice_ptr || !out->words || !out->mask || !out->stencil ||
+        !out->stencil_off || !out->vol || !out->inv_m || !out->spec || !out->lat4)
+        return PD_ERR_ARG;
+
+    for (int64_t r = 0; r < n_pad; r++) out->perm[r] = r < n ? (int32_t)order[r] : -1;
+    for (int64_t p = 0; p < n; p++) out->row_of[p] = row_of[p];
+    std::memcpy(out->slice_ptr, slice_ptr.data(), sizeof(int64_t) * (n_slices + 1));
+    for (size_t s = 0; s < st.size(); s++) {
+        for (int c = 0; c < 3; c++) {
+            out->stencil[4 * s + c] = st[s].M[c];
+            out->stencil_off[3 * s + c] = st[s].off[c];
+        }
+        out->stencil[4 * s + 3] = st[s].x;
+    }
+    parallel_for(n_slices, [&](int64_t a, int64_t b) {
+        for (int64_t s = a; s < b; s++) {
+            int64_t base = slice_ptr[s];
+            int64_t L = (slice_ptr[s + 1] - base) / 64;
+            for (int64_t k = 0; k < L; k++) {
+                uint64_t bits = 0;
+                for (int lane = 0; lane < 64; lane++) {
+                    int64_t r = 64 * s + lane;
+                    uint32_t w;
+                    bool intact = false;
+                    if (r < n && k < (int64_t)nb[r].size()) {
+                        w = nb[r][k];
+                        intact = cut[r].empty() ? true : !cut[r][k];
+                    } else {
+                        w = ((uint32_t)r << 7) | 127u;
+                    }
+                    out->words[base + k * 64 + lane] = w;
+                    if (intact) bits |= (1ull << lane);
+                }
+                out->mask[base / 64 + k] = bits;
+            }
+        }
+    });
+    for (int64_t r = 0; r < n_pad; r++) {
+        bool real = r < n;
+        int64_t p = real ? order[r] : 0;
+        out->vol[r] = real ? body->vol[p] : 0.0;
+        out->inv_m[r] = (real && m[r] > 0.0) ? 1.0 / m[r] : 0.0;
+        out->spec[r] = real ? spec[p] : 0;
+        for (int c = 0; c < 3; c++) out->lat4[4 * r + c] = real ? lat[3 * p + c] : 0;
+        out->lat4[4 * r + 3] = 0;
+    }
+    return PD_OK;
+}
+
+// Block pattern of the stiffness: q is in row i iff q != i and q is a
+// neighbour of i or a neighbour of a neighbour of i (rows of real nodes).
+extern "C" pd_status pd_bsr_pattern(const pd_family_sizes *sz, const pd_family_host *fam, pd_bsr_sizes *out,
+                                    int64_t *row_ptr, int32_t *col) {
+    if (!sz || !fam || !out || !fam->slice_ptr || !fam->words || !fam->lat4) return PD_ERR_ARG;
+    const int64_t n_pad = sz->n_pad;
+    std::vector<std::vector<int32_t>> rows((size_t)n_pad);
+    auto row_len = [&](int64_t r) { return (fam->slice_ptr[r / 64 + 1] - fam->slice_ptr[r / 64]) / 64; };
+    auto word = [&](int64_t r, int64_t k) { return fam->words[fam->slice_ptr[r / 64] + k * 64 + (r % 64)]; };
+    std::vector<int32_t> reach_rows((size_t)n_pad, 0);
+    parallel_for(n_pad, [&](int64_t a, int64_t b) {
+        std::vector<int32_t> tmp;
+        for (int64_t r = a; r < b; r++) {
+            tmp.clear();
+            int64_t L = row_len(r);
+            for (int64_t k = 0; k < L; k++) {
+                uint32_t w = word(r, k);
+                if ((w & 127u) == 127u) continue;
+                int32_t j = (int32_t)(w >> 7);
+                tmp.push_back(j);
+                int64_t Lj = row_len(j);
+                for (int64_t kk = 0; kk < Lj; kk++) {
+                    uint32_t w2 = word(j, kk);
+                    if ((w2 & 127u) == 127u) continue;
+                    int32_t q = (int32_t)(w2 >> 7);
+                    if (q != r) tmp.push_back(q);
+                }
+            }
+            std::sort(tmp.begin(), tmp.end());
+            tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+            int32_t rc = 0;
+            for (int32_t q : tmp)
+                for (int c = 0; c < 3; c++)
+                    rc = std::max(rc, std::abs(fam->lat4[4 * (int64_t)q + c] - fam->lat4[4 * r + c]));
+            reach_rows[r] = rc;
+            rows[r] = tmp;
+        }
+    });
+    int64_t total = 0;
+    int32_t mx = 0, reach = 0;
+    for (int64_t r = 0; r < n_pad; r++) {
+        total += (int64_t)rows[r].size();
+        mx = std::max(mx, (int32_t)rows[r].size());
+        reach = std::max(reach, reach_rows[r]);
+    }
+    out->nnzb = total;
+    out->max_row_blocks = mx;
+    out->reach = reach;
+    if (!col) return PD_OK;
+    if (!row_ptr) return PD_ERR_ARG;
+    row_ptr[0] = 0;
+    for (int64_t r = 0; r < n_pad; r++) row_ptr[r + 1] = row_ptr[r] + (int64_t)rows[r].size();
+    parallel_for(n_pad, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; r++)
+            std::memcpy(col + row_ptr[r], rows[r].data(), sizeof(int32_t) * rows[r].size());
+    });
+    return PD_OK;
+}

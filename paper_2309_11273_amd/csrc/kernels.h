@@ -1,0 +1,90 @@
+// Kernel argument blocks and launchers (device side of libpd).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pd_internal.h"
+
+namespace pdk {
+
+struct StepArgs {
+    int64_t n_pad;
+    int64_t n_slices;
+    int32_t dim;
+    int32_t n_stencil;
+    int64_t ramp_steps;
+    const int64_t *slice_ptr;
+    const uint32_t *words;
+    const double *stencil;
+    const pd_spec *spec;
+    const uint32_t *aux;
+    const double4 *fext;
+    double4 *uv[2];
+    double4 *vel;
+    double2 *qr;
+    uint64_t *mask;
+    pd_ctl *ctl;
+    double4 *f_out;     // force-only mode
+    double *theta_out;  // optional dilatation output
+    // FP32 path
+    int4 *ush[2];
+    float2 *qr32;
+    double4 *dsum;
+    // BSR path
+    uint32_t *dirty;
+};
+
+struct InitArgs {
+    int64_t n_pad;
+    int64_t start_step;
+    const int32_t *perm;
+    const int32_t *spec_rows;
+    const double *vol;
+    const double *inv_m;
+    const double *u0;
+    const double *v0;
+    const double *f0;
+    const uint8_t *bc;
+    uint32_t *aux;
+    double4 *fext;
+    double4 *uv;
+    double4 *vel;
+    double2 *qr;
+    float2 *qr32;
+    pd_ctl *ctl;
+};
+
+struct DamageArgs {
+    int64_t n_slices;
+    const int64_t *slice_ptr;
+    const uint32_t *words;
+    const uint64_t *mask;
+    const double *vol;
+    double *phi;
+};
+
+hipError_t launch_pass1_f64(const StepArgs &a, int cur, bool brk, int block, hipStream_t s);
+hipError_t launch_pass2_f64(const StepArgs &a, int cur, bool update, int block, hipStream_t s);
+hipError_t launch_pass1_f32(const StepArgs &a, int cur, bool brk, int block, hipStream_t s);
+hipError_t launch_pass2_f32(const StepArgs &a, int cur, bool update, int block, hipStream_t s);
+hipError_t launch_shadow_prep(const StepArgs &a, int cur, hipStream_t s);
+hipError_t launch_state_init(const InitArgs &a, hipStream_t s);
+hipError_t launch_state_read(const int32_t *perm, int64_t n_pad, const double4 *uv, const double4 *vel,
+                             double *u_out, double *v_out, hipStream_t s);
+hipError_t launch_damage(const DamageArgs &a, hipStream_t s);
+hipError_t launch_energy(int64_t n_pad, const double4 *uv, const double4 *vel, const double4 *f,
+                         const uint32_t *aux, const pd_spec *spec, pd_ctl *ctl, hipStream_t s);
+hipError_t launch_pi_init(int64_t n_pad, int dim, const uint32_t *aux, double4 *uv, uint64_t seed,
+                          hipStream_t s);
+size_t bsr_assemble_lds(int dim, int max_row_blocks, int reach);
+hipError_t set_bsr_lds_limit(int dim, bool fp32, size_t lds);
+hipError_t launch_bsr_prep_assemble(const StepArgs &a, const pd_problem_dev *p, const pd_bsr_dev *K, bool all,
+                                    int par, hipStream_t s);
+hipError_t launch_break_mark(const StepArgs &a, const pd_problem_dev *p, const pd_bsr_dev *K, int cur,
+                             hipStream_t s);
+hipError_t launch_bsr_spmv(const StepArgs &a, const pd_problem_dev *p, const pd_bsr_dev *K, int cur, bool update,
+                           hipStream_t s);
+hipError_t launch_pi_step(int64_t n_pad, int dim, const uint32_t *aux, const pd_spec *spec, double4 *uv,
+                          const double4 *f, double4 *y, pd_ctl *ctl, hipStream_t s);
+
+}  // namespace pdk

@@ -1,0 +1,32 @@
+// Internal declarations shared by the host and device sources of libpd.
+#pragma once
+
+#include <stdint.h>
+
+#include "pd.h"
+
+// Device control block (PD_CTL_BYTES bytes, caller-allocated, zeroed by
+// pd_state_init).  Step counter: pass 1 of a step reads s2 and writes s1,
+// pass 2 reads s1 and writes s2 = s1 + 1, so no kernel writes a slot that
+// another wave of the same kernel reads.
+struct pd_ctl {
+    int64_t s1;
+    int64_t s2;
+    unsigned long long broken;    // directed bond-status bits cleared so far
+    unsigned long long rechecks;  // FP64 rechecks made by the FP32 path
+    unsigned int flags;           // bit 0: non-finite state, bit 1: shadow fallback used
+    unsigned int umax_bits[2];    // float bits of max |u| of shadow buffer k
+    unsigned int pad0;
+    double qs[2];                 // fixed-point scale of shadow buffer k (power of two)
+    unsigned long long fallbacks; // shadow entries that fell back to FP64
+    double red[8];                // reductions (energies, power iteration)
+    unsigned long long dirty[2];  // rows marked for re-assembly, by step parity
+    unsigned long long pad1[10];
+};
+static_assert(sizeof(pd_ctl) <= PD_CTL_BYTES, "control block too large");
+
+#define PD_CTL_NONFINITE 1u
+#define PD_CTL_FALLBACK 2u
+
+// Padding stencil id.
+#define PD_PAD_ID 127u

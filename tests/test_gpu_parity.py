@@ -1,0 +1,192 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU reference.
+
+Bars: FP64 displacement rel-L2 <= 1e-10, FP32-force path <= 1e-4, the
+broken-bond set identical to the reference at every compared step.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import Oracle  # noqa: E402
+from pd_inputs import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_11273_amd.solver import Context
+    return Context(0)
+
+
+def solver(w, ctx, **kw):
+    from paper_2309_11273_amd.solver import Solver
+    return Solver(w, ctx=ctx, **kw)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def small_workloads():
+    return {
+        "cantilever": W.cantilever3d(),
+        "plate_notched": W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37,
+                                   steps=300),
+        "plane_strain": W.plate2d(nx=30, ny=22, dt=1.2e-7, mode="plane_strain", E=190e9, nu=0.25,
+                                  rho=7800.0, G0=None, steps=100),
+        "impact": W.impact3d(nx=36, ny=36, nz=9, dt=2.6e-7, steps=200),
+        "cylinder": W.cylinder3d(dx=2.5e-3, dt=2.4e-7, twist_rate=8.0, steps=200),
+        "batch": W.batch2d(n_plates=3, steps=200, dt=np.array([1.0e-7, 1.1e-7, 0.9e-7])),
+    }
+
+
+@pytest.mark.parametrize("name", ["cantilever", "plate_notched", "plane_strain", "impact", "cylinder", "batch"])
+def test_force_matches_reference(ctx, name):
+    """One force evaluation (Eqs. 2.3, 2.2) for a random displacement and a
+    random set of broken bonds."""
+    w = small_workloads()[name]
+    o = Oracle(w)
+    rng = np.random.default_rng(42)
+    u = rng.standard_normal((w.n, 3)) * 1e-6
+    if w.dim == 2:
+        u[:, 2] = 0
+    s = solver(w, ctx, u0=u)
+    bi, bj, st = s.bond_status()
+    rho = o.rho()
+    assert np.array_equal(st, rho)
+    # break a random 10% of the bonds on both sides
+    drop = rng.random(o.nb) < 0.1
+    rho2 = rho.copy()
+    rho2[drop] = 0
+    o.set_rho(rho2)
+    mask = s.mask_host()
+    rows, ks, ci, cj, _ = s.fam.bond_table()
+    key = np.minimum(ci, cj).astype(np.int64) * w.n + np.maximum(ci, cj)
+    okey = bi.astype(np.int64) * w.n + bj
+    idx = np.searchsorted(okey, key)
+    clear = drop[idx]
+    widx = s.fam.slice_ptr[rows // 64] // 64 + ks
+    for wi, lane in zip(widx[clear], (rows % 64)[clear]):
+        mask[wi] &= ~np.uint64(1 << int(lane))
+    s.reset(u0=u, mask=mask)
+    f, th = s.force()
+    fo, tho = o.force(u)
+    scale = np.abs(fo).max()
+    assert np.abs(f - fo).max() <= 1e-12 * scale
+    assert np.abs(th - tho).max() <= 1e-12 * np.abs(tho).max()
+
+
+@pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("plane_strain", 100),
+                                        ("impact", 200), ("cylinder", 200), ("batch", 200)])
+def test_fp64_trajectory(ctx, name, steps):
+    w = small_workloads()[name]
+    o = Oracle(w)
+    s = solver(w, ctx)
+    uo, vo = o.initial_state()
+    done = 0
+    for target in (steps // 4, steps // 2, steps):
+        s.step(target - done, precision="fp64")
+        o.run(target - done, uo, vo)
+        done = target
+        u, v = s.read()
+        assert rel(u, uo) <= FP64_TOL, (name, target, rel(u, uo))
+        assert rel(v, vo) <= FP64_TOL * 10, (name, target, rel(v, vo))
+        _, _, st = s.bond_status()
+        assert np.array_equal(st, o.rho()), (name, target, int((st != o.rho()).sum()))
+    assert s.step_count() == steps
+    np.testing.assert_allclose(s.damage(), o.damage(), rtol=0, atol=1e-15)
+
+
+def test_plate_full_size_fp64(ctx):
+    """Edge-notched plane-stress plate, 200 x 80, 1 MPa, 1500 steps."""
+    w = W.plate2d()
+    o = Oracle(w)
+    s = solver(w, ctx)
+    uo, vo = o.initial_state()
+    done = 0
+    for target in (375, 750, 1500):
+        s.step(target - done, precision="fp64", graph_chunk=50)
+        o.run(target - done, uo, vo)
+        done = target
+        u, _ = s.read()
+        assert rel(u, uo) <= FP64_TOL
+        assert np.array_equal(s.bond_status()[2], o.rho())
+
+
+@pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("impact", 200),
+                                        ("cylinder", 200), ("batch", 200)])
+def test_fp32_recheck_trajectory(ctx, name, steps):
+    w = small_workloads()[name]
+    o = Oracle(w)
+    s = solver(w, ctx)
+    uo, vo = o.initial_state()
+    s.step(steps, precision="fp32")
+    o.run(steps, uo, vo)
+    u, _ = s.read()
+    assert rel(u, uo) <= FP32_TOL, (name, rel(u, uo))
+    st = s.bond_status()[2]
+    assert np.array_equal(st, o.rho()), (name, int((st != o.rho()).sum()), o.min_margin())
+
+
+def test_graph_replay_equals_eager(ctx):
+    w = small_workloads()["plate_notched"]
+    a = solver(w, ctx)
+    b = solver(w, ctx)
+    a.step(300, precision="fp64")
+    for _ in range(3):
+        b.step(100, precision="fp64", graph_chunk=20)
+    ua, _ = a.read()
+    ub, _ = b.read()
+    assert np.array_equal(ua, ub)
+    assert np.array_equal(a.mask_host(), b.mask_host())
+
+
+def test_deterministic_and_block_invariant(ctx):
+    w = small_workloads()["impact"]
+    outs = []
+    for block in (64, 128, 256, 256):
+        s = solver(w, ctx)
+        s.step(100, precision="fp64", block=block)
+        outs.append((s.read()[0], s.mask_host()))
+    for u, m in outs[1:]:
+        assert np.array_equal(u, outs[0][0])
+        assert np.array_equal(m, outs[0][1])
+
+
+def test_bsr_apply_matches_matrix_free(ctx):
+    for name in ("cantilever", "plate_notched", "impact"):
+        w = small_workloads()[name]
+        rng = np.random.default_rng(3)
+        u = rng.standard_normal((w.n, 3)) * 1e-6
+        if w.dim == 2:
+            u[:, 2] = 0
+        s = solver(w, ctx, u0=u)
+        s.build_K(fp32=False)
+        s.assemble_K()
+        f_mf, _ = s.force()
+        f_k = s.bsr_apply()
+        assert rel(f_k, f_mf) <= 1e-12, (name, rel(f_k, f_mf))
+
+
+@pytest.mark.parametrize("name,steps", [("plate_notched", 300), ("impact", 200)])
+def test_bsr_trajectory(ctx, name, steps):
+    w = small_workloads()[name]
+    o = Oracle(w)
+    s = solver(w, ctx)
+    s.build_K(fp32=False)
+    s.assemble_K()
+    uo, vo = o.initial_state()
+    s.step(steps, precision="fp64", form="bsr")
+    o.run(steps, uo, vo)
+    u, _ = s.read()
+    assert rel(u, uo) <= FP64_TOL, rel(u, uo)
+    assert np.array_equal(s.bond_status()[2], o.rho())

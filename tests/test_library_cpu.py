@@ -1,0 +1,244 @@
+"""CPU-side checks of libpd: it loads, exports every declared entry point,
+and its host-side set-up (family search, notch cuts, weighted volume,
+constants, block pattern, argument checks) agrees with the CPU reference.
+No GPU compute call is made here."""
+
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from pd_inputs import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2309_11273_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2309_11273_amd import build
+        build.build()
+    return _abi.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    hdr = open(os.path.join(ROOT, "include", "pd.h")).read()
+    names = set(re.findall(r"\b(pd_[a-z_A-Z0-9]+)\s*\(", hdr))
+    assert len(names) >= 19
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    from paper_2309_11273_amd import _abi
+    assert names == set(_abi.SIGNATURES), names ^ set(_abi.SIGNATURES)
+
+
+def _family(w):
+    from paper_2309_11273_amd.solver import FamilyHost
+    return FamilyHost(w.lat, w.dx, w.origin, w.delta, w.vol, w.specimen, w.cuts)
+
+
+CASES = {
+    "cantilever": lambda: W.cantilever3d(),
+    "plate": lambda: W.plate2d(),
+    "impact_small": lambda: W.impact3d(nx=40, ny=40, dt=1e-7),
+    "cylinder_small": lambda: W.cylinder3d(dx=2e-3, dt=1e-7, twist_rate=1.0),
+    "batch3": lambda: W.batch2d(n_plates=3, dt=np.ones(3)),
+    "plane_strain": lambda: W.plate2d(nx=30, ny=20, dt=1e-7, mode="plane_strain", notch_row=9,
+                                      notch_tip=14.37),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_family_matches_reference(lib, case):
+    """Same unique bonds, same notch-cut bonds, same weighted volume (Eq. 1.9)."""
+    w = CASES[case]()
+    f = _family(w)
+    o = Oracle(w)
+    bi, bj, st = f.bond_status(f.mask)
+    obi, obj = o.bonds()
+    np.testing.assert_array_equal(bi, obi)
+    np.testing.assert_array_equal(bj, obj)
+    np.testing.assert_array_equal(st, o.rho())
+    assert int(f.sizes.n_cut) == o.n_cut
+    assert int(f.sizes.n_bonds) == o.nb
+    real = f.perm >= 0
+    m = np.empty(w.n)
+    m[f.perm[real]] = 1.0 / f.inv_m[real]
+    np.testing.assert_allclose(m, o.m(), rtol=1e-14)
+    # per-bond geometry from the stencil equals the reference's xi/x and x
+    rows, ks, ci, cj, sid = f.bond_table()
+    sten = f.stencil.reshape(-1, 4)
+    xl, M = o.bond_geom()
+    key = np.minimum(ci, cj).astype(np.int64) * w.n + np.maximum(ci, cj)
+    idx = np.searchsorted(obi.astype(np.int64) * w.n + obj, key)
+    sign = np.where(ci < cj, 1.0, -1.0)
+    assert np.array_equal(sten[sid, 3], xl[idx])
+    assert np.array_equal(sten[sid, :3], M[idx] * sign[:, None])
+    # interleaved layout: a slice's word k for all lanes is contiguous
+    assert f.slice_ptr[-1] == f.sizes.n_words
+    assert np.all(np.diff(f.slice_ptr) % 64 == 0)
+
+
+def test_internal_order_is_tile_major(lib):
+    w = W.impact3d(nx=16, ny=16, nz=8, dt=1e-7)
+    f = _family(w)
+    lat = w.lat[f.perm[: w.n]]
+    for s in range(w.n // 64):
+        tile = lat[64 * s: 64 * s + 64] // 4
+        assert np.all(tile == tile[0])
+
+
+def test_constants_match_reference(lib):
+    from paper_2309_11273_amd.solver import critical_stretch, specimen_params
+    for mode, mid in (("3d", 0), ("plane_stress", 1), ("plane_strain", 2)):
+        for E, nu in ((200e9, 0.3), (72e9, 0.22), (30e9, 0.2), (190e9, 0.25)):
+            k = oracle.constants(mid, E, nu)
+            sp = specimen_params(mode, E, nu, 2000.0, 1.0, 1e-8)
+            assert sp.kp == pytest.approx(k["K"] - k["G"] / 3, rel=1e-14)
+            assert sp.G == pytest.approx(k["G"], rel=1e-14)
+            assert sp.A == pytest.approx(k["A"], rel=1e-14)
+            for var in (0, 1):
+                a = critical_stretch(mode, E, nu, 50.0, 1.5e-3, var)
+                b = oracle.critical_stretch(mid, E, nu, 50.0, 1.5e-3, var)
+                assert a == pytest.approx(b, rel=1e-14)
+    assert math.isinf(critical_stretch("3d", 200e9, 0.3, None, 1e-3))
+
+
+def test_bsr_pattern_is_two_hop_closure(lib):
+    """Row i of K holds exactly the nodes q != i joined to i by one or two
+    bonds (Eq. 2.14: the dilatation of a neighbour reaches 2 delta)."""
+    from paper_2309_11273_amd import _abi as A
+    for w in (W.plate2d(nx=20, ny=12, dt=1e-8, notch_row=5, notch_tip=8.37), W.cantilever3d()):
+        f = _family(w)
+        o = Oracle(w)
+        bi, bj = o.bonds()
+        n = w.n
+        adj = [set() for _ in range(n)]
+        for a, b in zip(bi, bj):
+            adj[a].add(b)
+            adj[b].add(a)
+        bs = A.pd_bsr_sizes()
+        A.check("pd_bsr_pattern", lib.pd_bsr_pattern(C.byref(f.sizes), C.byref(f._hb), C.byref(bs), None, None))
+        rp = np.empty(f.sizes.n_pad + 1, np.int64)
+        col = np.empty(bs.nnzb, np.int32)
+        A.check("pd_bsr_pattern", lib.pd_bsr_pattern(C.byref(f.sizes), C.byref(f._hb), C.byref(bs),
+                                                     rp.ctypes.data_as(C.c_void_p),
+                                                     col.ctypes.data_as(C.c_void_p)))
+        total = 0
+        for r in range(n):
+            p = f.perm[r]
+            want = set(adj[p])
+            for j in adj[p]:
+                want |= adj[j]
+            want.discard(p)
+            got = set(f.perm[col[rp[r]:rp[r + 1]]].tolist())
+            assert got == want
+            total += len(want)
+        assert total == bs.nnzb
+
+
+def test_argument_errors(lib):
+    from paper_2309_11273_amd import _abi as A
+    s0 = C.c_double()
+    assert lib.pd_critical_stretch(0, -1.0, 0.3, 1.0, 1e-3, 0, C.byref(s0)) == -1
+    assert lib.pd_critical_stretch(0, 1e9, 0.5, 1.0, 1e-3, 0, C.byref(s0)) == -1
+    assert lib.pd_critical_stretch(0, 1e9, 0.3, 1.0, 1e-3, 2, C.byref(s0)) == -1
+    assert lib.pd_critical_stretch(0, 1e9, 0.3, 1.0, 1e-3, 0, None) == -1
+    sp = A.pd_spec()
+    assert lib.pd_specimen_params(0, 1e9, 0.3, 0.0, 1.0, 1e-8, C.byref(sp)) == -1
+    assert lib.pd_specimen_params(0, 1e9, 0.3, 1.0, float("nan"), 1e-8, C.byref(sp)) == -1
+    sizes = A.pd_family_sizes()
+    assert lib.pd_build_family(None, None, 0, C.byref(sizes), None) == -1
+    lat = np.zeros((2, 2), np.int32)  # duplicate lattice point
+    vol = np.ones(2)
+    body = A.pd_body(n=2, dim=2, lat=lat.ctypes.data_as(C.c_void_p), dx=1.0, delta=3.0,
+                     vol=vol.ctypes.data_as(C.c_void_p))
+    assert lib.pd_build_family(C.byref(body), None, 0, C.byref(sizes), None) == -1
+    body.n = 0
+    assert lib.pd_build_family(C.byref(body), None, 0, C.byref(sizes), None) == -2
+    lat2 = np.array([[0, 0], [1, 0]], np.int32)
+    body = A.pd_body(n=2, dim=2, lat=lat2.ctypes.data_as(C.c_void_p), dx=1.0, delta=3.0,
+                     vol=vol.ctypes.data_as(C.c_void_p))
+    bad = A.pd_cut(kind=1)  # a 3D patch in 2D
+    assert lib.pd_build_family(C.byref(body), C.byref(bad), 1, C.byref(sizes), None) == -1
+    assert lib.pd_build_family(C.byref(body), None, 0, C.byref(sizes), None) == 0
+    assert sizes.n_bonds == 1 and sizes.n_pad == 64
+    # calls without a context are rejected before any device work
+    st = A.pd_state_dev()
+    pr = A.pd_problem_dev()
+    assert lib.pd_step(None, C.byref(pr), C.byref(st), 1, None, None, None) == -1
+    assert lib.pd_force(None, C.byref(pr), C.byref(st), 0, None, None) == -1
+    assert lib.pd_damage(None, C.byref(pr), None, None) == -1
+    ps = A.pd_profile_stats()
+    assert lib.pd_profile_read(None, C.byref(ps), 0) == -1
+
+
+# --------------------------------------------------------------------------
+# inputs: grid conventions and notch geometry
+# --------------------------------------------------------------------------
+
+def test_table1_node_counts_vertex_lattice_plus_three_layers():
+    """Node counts of the 2D cantilever grids (Sec. 4.1 table): a vertex
+    lattice of the 48 x 12 m beam plus 3 constrained layers beyond the
+    clamped end; and 386,984 nodes for the 3D beam (48 x 12 x 5 m)."""
+    counts = []
+    for delta in (2.4, 1.2, 0.6, 0.3, 0.15, 0.075):
+        dx = delta / 3
+        counts.append((round(48 / dx) + 1 + 3) * (round(12 / dx) + 1))
+    assert counts == [1024, 3844, 14884, 58564, 232324, 925444]
+    dx = 0.2
+    assert (round(48 / dx) + 1 + 3) * (round(12 / dx) + 1) * (round(5 / dx) + 1) == 386984
+
+
+def test_workload_sizes():
+    assert W.cantilever3d().n == 320
+    assert W.plate2d().n == 16000
+    assert W.cylinder_lattice(25e-3, 100e-3, 0.6e-3).shape[0] == 911319
+    assert W.cylinder_lattice(25e-3, 100e-3, 0.5e-3).shape[0] == 1572000
+    d = W.batch_draws(256)
+    assert len(d) == 256
+    assert sum(x["nx"] * x["ny"] for x in d) == 5800669
+    p = W.load_params()
+    for k in ("cantilever3d", "plate2d", "impact3d", "cylinder3d", "cylinder3d_dx05"):
+        assert p[k] > 0
+    assert len(p["batch2d_dt"]) == 256
+
+
+def _min_node_distance_to_segment(P, A, B):
+    AB = B - A
+    t = np.clip(((P - A) @ AB) / (AB @ AB), 0, 1)
+    return np.linalg.norm(P - (A + t[:, None] * AB), axis=1)
+
+
+@pytest.mark.parametrize("name", ["plate2d", "impact3d", "batch2d"])
+def test_notches_have_no_ties(name):
+    """No node lies on a notch and no lattice bond passes within 1e-6 dx of
+    a notch tip: every cut decision is far from a floating-point tie."""
+    if name == "plate2d":
+        w = W.plate2d()
+    elif name == "impact3d":
+        w = W.impact3d(nx=40, ny=40, dt=1e-7)
+    else:
+        w = W.batch2d(n_plates=8, dt=np.ones(8))
+    X = w.positions()
+    for c in w.cuts:
+        if c.kind == "segment2d":
+            A, B = np.array(c.p[:2]), np.array(c.p[2:4])
+            d = _min_node_distance_to_segment(X[:, :2], A, B)
+            assert d.min() > 1e-6 * w.dx
+            tip = B
+        else:
+            cc, a = np.array(c.p[:3]), np.array(c.p[3:6])
+            assert np.all(np.abs(X[:, 1] - cc[1]) > 1e-6 * w.dx)
+            tip = (cc + a)[:2]
+        # bonds crossing the notch line near the tip: crossing abscissae lie on
+        # multiples of dx/k (k <= 6) from a node; the tip sits at 0.37 dx
+        frac = (tip[0] / w.dx) % 1.0
+        for k in range(1, 7):
+            for q in range(0, k + 1):
+                assert abs(frac - q / k) > 1e-6
