@@ -50,25 +50,27 @@ def make_workload(name):
     return W.workload(gen, **kw), desc
 
 
-def algorithmic_bytes(kernel: str, precision: str, nnz: int, n: int, n_loaded: int) -> int:
+def algorithmic_bytes(kernel: str, precision: str, nnz: int, n: int, n_loaded: int, tiled: bool) -> int:
     """Bytes one launch must move between HBM and the chip (each array read
-    or written once; neighbour gathers are served by the caches).
+    or written once; neighbour data is served by the caches or LDS).
 
-    Per directed bond: 4 B bond word + 1 bit of bond status (1/8 B).
+    Per directed bond: 4 B bond word + 1 bit of bond status (1/8 B); the
+    LDS-staged tile kernels read no bond word (the stencil position of a
+    bond gives its neighbour), only the status bit.
     Per node (FP64 path):
       pass 1: u,V 32 read; aux 4; (theta/m, 1/m) 16 read + 8 write
       pass 2: u,V 32 read; (theta/m, 1/m) 16; aux 4; v 32 read + 32 write;
               u,V 32 write
     Per node (FP32 path):
       pass 1: shadow 16; aux 4; (theta/m, 1/m) float 8 read + 4 write
-      pass 2: shadow 16; float (theta/m, 1/m) 8; aux 4; u,V 32 read;
+      pass 2: shadow 16; float (theta/m, 1/m) 8; aux 4; D 32; u,V 32 read;
               v 32 + 32; u,V 32 write; next shadow 16 write
     Loaded nodes read their external force (32 B) in pass 2."""
-    bond = nnz * 4.125
+    bond = nnz * (0.125 if tiled else 4.125)
     if precision == "fp64":
         node = {"pass1": 60, "pass2": 148}[kernel]
     else:
-        node = {"pass1": 32, "pass2": 172}[kernel]
+        node = {"pass1": 32, "pass2": 204}[kernel]
     extra = 32 * n_loaded if kernel == "pass2" else 0
     return int(bond + node * n + extra)
 
@@ -87,19 +89,18 @@ def traffic_from_profiles(kernel_name: str, src_hash: str):
     return e.get("bytes_per_launch")
 
 
-def kernel_source_hash(precision: str) -> str:
-    src = os.path.join(ROOT, "paper_2309_11273_amd", "csrc",
-                       "kernels_f32.hip" if precision == "fp32" else "kernels.hip")
+def kernel_source_hash(fname: str) -> str:
+    src = os.path.join(ROOT, "paper_2309_11273_amd", "csrc", fname)
     with open(src, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def time_gpu(s, steps, warmup, precision, form, chunk):
+def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto"):
     import torch
-    s.step(warmup, precision=precision, form=form, graph_chunk=chunk, report=False)
+    s.step(warmup, precision=precision, form=form, graph_chunk=chunk, report=False, kernel=kernel)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.step(steps, precision=precision, form=form, graph_chunk=chunk, report=False)
+    s.step(steps, precision=precision, form=form, graph_chunk=chunk, report=False, kernel=kernel)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 
@@ -130,6 +131,7 @@ def main():
     ap.add_argument("--workload", default="cylinder3d", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--form", default="mf", choices=["mf", "bsr"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tiled"])
     ap.add_argument("--graph-chunk", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -160,23 +162,26 @@ def main():
         s.build_K(fp32=(args.precision == "fp32"))
         s.assemble_K()
 
-    el = time_gpu(s, args.steps, args.warmup, args.precision, args.form, args.graph_chunk)
+    el = time_gpu(s, args.steps, args.warmup, args.precision, args.form, args.graph_chunk, args.kernel)
     ms_per_step = 1e3 * el / args.steps
     value = n_bonds * args.steps / el
 
     # kernel durations with HIP events on the launch stream
     s.profile_read(reset=True)
-    s.step(args.profile_steps, precision=args.precision, form=args.form, profile=True, report=False)
+    s.step(args.profile_steps, precision=args.precision, form=args.form, profile=True, report=False,
+           kernel=args.kernel)
     prof = s.profile_read(reset=True)
     ps = max(1, prof["steps"])
     ms1, ms2 = prof["ms_pass1"] / ps, prof["ms_pass2"] / ps
     dom = "pass2" if ms2 >= ms1 else "pass1"
     ms_dom = max(ms1, ms2)
-    alg = algorithmic_bytes(dom, args.precision, nnz, int(sz.n), n_loaded) if args.form == "mf" else None
-    kname = f"k_{dom}_{args.precision}"
+    tiled = args.precision == "fp32" and args.kernel != "gather" and s.tiled_supported()
+    alg = algorithmic_bytes(dom, args.precision, nnz, int(sz.n), n_loaded, tiled) if args.form == "mf" else None
+    kname = f"k_{'t' if tiled else ''}{dom}_{args.precision}"
     if alg is not None:
         achieved = alg / (ms_dom * 1e-3) / 1e9
-        traffic = traffic_from_profiles(f"{kname}_{args.workload}", kernel_source_hash(args.precision))
+        src = "kernels_tiled.hip" if tiled else ("kernels_f32.hip" if args.precision == "fp32" else "kernels.hip")
+        traffic = traffic_from_profiles(f"{kname}_{args.workload}", kernel_source_hash(src))
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                     "kernel_ms": round(ms_dom, 5), "algorithmic_bytes": alg,

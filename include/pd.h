@@ -152,6 +152,11 @@ typedef struct pd_family_sizes {
     int32_t max_row;    /* largest family size                                     */
     int32_t dim;
     int32_t n_specimens;/* 1 + largest specimen id                                 */
+    int64_t n_tiles;    /* lattice tiles = n_slices                                */
+    int32_t tile[3];    /* tile edge lengths in lattice units (product 64)         */
+    int32_t words_per_row; /* bond words per row = n_stencil rounded up to 4      */
+    int32_t reach;      /* largest |component| of a stencil offset                 */
+    int32_t pad1;
 } pd_family_sizes;
 
 /* Output arrays of pd_build_family, all [host], allocated by the caller
@@ -169,18 +174,26 @@ typedef struct pd_family_host {
     double *inv_m;        /* [n_pad] 1 / m, m of Eq. 1.9 over the full family        */
     int32_t *spec;        /* [n_pad] specimen id (0 for padding)                     */
     int32_t *lat4;        /* [n_pad*4] lattice coordinates x,y,z,0 per row           */
+    int32_t *tile_org;    /* [n_tiles*4] lattice origin x,y,z of each tile, specimen */
+    int32_t *tile_nbr;    /* [n_tiles*27] tile at offset (dx,dy,dz) in {-1,0,1}^3,
+                             index (dz+1)*9 + (dy+1)*3 + (dx+1); -1 if absent        */
 } pd_family_host;
 
 /* Horizon search and bond-list construction (Sec. 2.1 family; Eqs. 1.2-1.5,
  * 1.9, 1.13 per bond; notch cuts).  Two-phase: with bufs == NULL only
  * *sizes is filled; call again with every array of bufs allocated.
- * Internal rows are ordered by specimen, then by 4x4x4 (3D) or 8x8 (2D)
- * lattice tiles, so a 64-row slice is one tile.  Bonds of a row are
- * sorted by neighbour row.  Within a slice the words are interleaved
- * (word k of every row of the slice is contiguous), so 64 lanes read 256
- * consecutive bytes.  Errors: PD_ERR_ARG (null/invalid body, duplicate
- * lattice points, unknown cut kind), PD_ERR_SIZE (n or stencil above the
- * maxima). */
+ * The lattice of each specimen is cut into tiles of 64 lattice points
+ * (tile[0] x tile[1] x tile[2], chosen among a few shapes to leave the
+ * fewest empty points); every tile holding a node is one 64-row slice,
+ * row 64*t + (x + tile[0]*(y + tile[1]*z)) for local lattice position
+ * (x, y, z), so a wave64 owns one tile and lanes sit on lattice points.
+ * Empty points are padding rows.  Bond k of every row is stencil entry k
+ * (a fixed lattice offset), present or not: absent neighbours are padding
+ * words (status bit 0).  Within a slice the words are interleaved in
+ * groups of four per lane (see the kernels), so a wave reads 1 KiB of
+ * consecutive memory per group.  Errors: PD_ERR_ARG (null/invalid body,
+ * duplicate lattice points, unknown cut kind), PD_ERR_SIZE (n, stencil or
+ * lattice extent above the maxima). */
 pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, int32_t ncuts,
                           pd_family_sizes *sizes, pd_family_host *bufs);
 
@@ -206,6 +219,11 @@ typedef struct pd_problem_dev {
     const uint32_t *aux;      /* [device] n_pad, written by pd_state_init          */
     const double *fext;       /* [device] n_pad*4 external force at full load      */
     int64_t ramp_steps;       /* load factor r(n) = min(1, n / ramp_steps); 0: r = 1 */
+    /* tile description for the LDS-staged kernels (NULL tile_nbr: not used) */
+    const int32_t *stencil_off; /* [device] n_stencil*3 lattice offsets            */
+    const int32_t *tile_nbr;    /* [device] n_slices*27 neighbour tiles            */
+    int32_t tile[3];            /* tile edge lengths (pd_family_sizes.tile)        */
+    int32_t reach;              /* pd_family_sizes.reach                           */
 } pd_problem_dev;
 
 /* Device control block (step counter, diagnostics).  Size in bytes: */
@@ -272,6 +290,11 @@ typedef struct pd_step_opts {
     int32_t check_every; /* >0: check the non-finite flag every this many steps (sync) */
     int32_t profile;     /* 1: time every kernel with HIP events on the stream (eager
                             launches, one synchronisation per step); see pd_profile_read */
+    int32_t kernel;      /* FP32 matrix-free kernels: 0 = LDS-staged tile kernels when
+                            the family allows them (tile edges >= stencil reach), else
+                            gather kernels; 1 = gather kernels; 2 = tile kernels (error
+                            if not possible)                                           */
+    int32_t pad1;
 } pd_step_opts;
 
 /* Kernel timings gathered by pd_step with opts->profile = 1 (milliseconds,

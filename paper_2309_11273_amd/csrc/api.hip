@@ -83,6 +83,10 @@ pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
     a.ush[1] = reinterpret_cast<int4 *>(st->ush[1]);
     a.qr32 = reinterpret_cast<float2 *>(st->qr32);
     a.dsum = reinterpret_cast<double4 *>(st->dsum);
+    a.stencil_off = p->stencil_off;
+    a.tile_nbr = p->tile_nbr;
+    for (int c = 0; c < 3; c++) a.tile[c] = p->tile[c];
+    a.reach = p->reach;
     return a;
 }
 
@@ -290,10 +294,13 @@ pd_status pd_force(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int32_t
         a.theta_out = nullptr;
         HIP_TRY(c, pdk::launch_pass2_f64(a, st->cur, false, 256, c->stream));
     } else {
+        const bool tiled = pdk::tiled_supported(a);
         HIP_TRY(c, pdk::launch_shadow_prep(a, st->cur, c->stream));
-        HIP_TRY(c, pdk::launch_pass1_f32(a, st->cur, false, 256, c->stream));
+        if (tiled) HIP_TRY(c, pdk::launch_tpass1_f32(a, st->cur, false, c->stream));
+        else HIP_TRY(c, pdk::launch_pass1_f32(a, st->cur, false, 256, c->stream));
         a.theta_out = nullptr;
-        HIP_TRY(c, pdk::launch_pass2_f32(a, st->cur, false, 256, c->stream));
+        if (tiled) HIP_TRY(c, pdk::launch_tpass2_f32(a, st->cur, false, c->stream));
+        else HIP_TRY(c, pdk::launch_pass2_f32(a, st->cur, false, 256, c->stream));
     }
     return PD_OK;
 }
@@ -313,12 +320,16 @@ static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, in
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
         if ((e = pdk::launch_bsr_spmv(a, p, K, cur, true, s)) != hipSuccess) return e;
     } else {
+        // FP32: LDS-staged tile kernels unless the gather kernels are asked for
+        const bool tiled = o.precision == PD_FP32_RECHECK && o.kernel != 1 && pdk::tiled_supported(a);
         if (o.precision == PD_FP64) e = pdk::launch_pass1_f64(a, cur, true, block, s);
+        else if (tiled) e = pdk::launch_tpass1_f32(a, cur, true, s);
         else e = pdk::launch_pass1_f32(a, cur, true, block, s);
         if (e != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
         if (o.precision == PD_FP64) e = pdk::launch_pass2_f64(a, cur, true, block, s);
+        else if (tiled) e = pdk::launch_tpass2_f32(a, cur, true, s);
         else e = pdk::launch_pass2_f32(a, cur, true, block, s);
         if (e != hipSuccess) return e;
     }
@@ -339,6 +350,12 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
         return fail(c, PD_ERR_ARG, "block must be 0, 64, 128 or 256");
     if (o.graph_chunk < 0 || o.check_every < 0) return fail(c, PD_ERR_ARG, "negative option");
     if (o.profile != 0 && o.profile != 1) return fail(c, PD_ERR_ARG, "profile must be 0 or 1");
+    if (o.kernel < 0 || o.kernel > 2) return fail(c, PD_ERR_ARG, "kernel must be 0, 1 or 2");
+    if (o.kernel == 2 && o.precision == PD_FP32_RECHECK && o.form == PD_MATRIX_FREE) {
+        pd_state_dev tmp = *st;
+        if (!pdk::tiled_supported(make_args(p, &tmp)))
+            return fail(c, PD_ERR_UNSUPPORTED, "tile kernels need tile edges >= the stencil reach");
+    }
     if (o.profile && !c->ev[0]) {
         for (int k = 0; k < 4; k++) HIP_TRY(c, hipEventCreate(&c->ev[k]));
     }

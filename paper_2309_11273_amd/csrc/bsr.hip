@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_bsr_prep(StepArgs a, BsrArgs b, int all
     for (int64_t k = 0; k < L; k++) {
         const uint64_t m64 = uni64(a.mask[(base >> 6) + k]);
         if (!((m64 >> lane) & 1ull)) continue;
-        const uint32_t w = a.words[base + k * 64 + lane];
+        const uint32_t w = a.words[pd_widx(base, k, lane)];
         const int64_t j = w >> 7;
         const double *st = a.stencil + 4 * (w & 127u);
         const double x = st[3], Vj = b.vol[j];
@@ -128,7 +128,7 @@ __global__ void k_bsr_assemble(StepArgs a, BsrArgs b, int all, int par) {
     const int64_t Li = (a.slice_ptr[si + 1] - base_i) >> 6;
     // one-bond terms
     for (int64_t k = tid; k < Li; k += nt) {
-        const uint32_t w = a.words[base_i + k * 64 + li_lane];
+        const uint32_t w = a.words[pd_widx(base_i, k, li_lane)];
         if ((w & 127u) == PD_PAD_ID) continue;
         if (!((a.mask[(base_i >> 6) + k] >> li_lane) & 1ull)) continue;
         const int64_t q = w >> 7;
@@ -149,7 +149,7 @@ __global__ void k_bsr_assemble(StepArgs a, BsrArgs b, int all, int par) {
     __syncthreads();
     // two-bond terms, one neighbour j at a time
     for (int64_t k = 0; k < Li; k++) {
-        const uint32_t w = a.words[base_i + k * 64 + li_lane];
+        const uint32_t w = a.words[pd_widx(base_i, k, li_lane)];
         const bool use = ((w & 127u) != PD_PAD_ID) && ((a.mask[(base_i >> 6) + k] >> li_lane) & 1ull);
         if (use) {
             const int64_t j = w >> 7;
@@ -161,7 +161,7 @@ __global__ void k_bsr_assemble(StepArgs a, BsrArgs b, int all, int par) {
             const int64_t base_j = a.slice_ptr[sj];
             const int64_t Lj = (a.slice_ptr[sj + 1] - base_j) >> 6;
             for (int64_t kk = tid; kk < Lj; kk += nt) {
-                const uint32_t w2 = a.words[base_j + kk * 64 + lj];
+                const uint32_t w2 = a.words[pd_widx(base_j, kk, lj)];
                 if ((w2 & 127u) == PD_PAD_ID) continue;
                 const int64_t q = w2 >> 7;
                 if (q == i) continue;
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_break_mark(StepArgs a, BsrArgs b, int c
     for (int64_t k = 0; k < L; k++) {
         const uint64_t m64 = uni64(a.mask[(base >> 6) + k]);
         if (m64 == 0) continue;
-        const uint32_t w = a.words[base + k * 64 + lane];
+        const uint32_t w = a.words[pd_widx(base, k, lane)];
         const double4 st = sst[w & 127u];
         const double4 uj = uv[w >> 7];
         double e;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_break_mark(StepArgs a, BsrArgs b, int c
     if (any) {
         b.dirty[row] = 1u;
         for (int64_t k = 0; k < L; k++) {
-            const uint32_t w = a.words[base + k * 64 + lane];
+            const uint32_t w = a.words[pd_widx(base, k, lane)];
             if ((w & 127u) != PD_PAD_ID) b.dirty[w >> 7] = 1u;
         }
         atomicAdd(&a.ctl->dirty[cur], 1ull);

@@ -216,114 +216,138 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
     Lookup look;
     if (!look.build(lat, n)) return PD_ERR_ARG;  // duplicate lattice point
 
-    // internal order: specimen, tile, position inside the tile
-    const int T = dim == 3 ? 4 : 8;
-    auto floordiv = [](int32_t a, int32_t b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); };
-    std::vector<int64_t> order((size_t)n);
-    std::iota(order.begin(), order.end(), 0);
-    struct Key { int32_t s, t0, t1, t2, l; };
-    std::vector<Key> keys((size_t)n);
-    for (int64_t p = 0; p < n; p++) {
-        const int32_t *l = &lat[3 * p];
-        int32_t t[3], r[3];
+    // ---- tiles of 64 lattice points, per specimen --------------------------
+    std::vector<int32_t> slo((size_t)3 * nspec, INT32_MAX), shi((size_t)3 * nspec, INT32_MIN);
+    for (int64_t p = 0; p < n; p++)
         for (int c = 0; c < 3; c++) {
-            t[c] = floordiv(l[c] - look.lo[c], T);
-            r[c] = (l[c] - look.lo[c]) - t[c] * T;
+            slo[3 * spec[p] + c] = std::min(slo[3 * spec[p] + c], lat[3 * p + c]);
+            shi[3 * spec[p] + c] = std::max(shi[3 * spec[p] + c], lat[3 * p + c]);
         }
-        keys[p] = {spec[p], t[2], t[1], t[0], (r[2] * T + r[1]) * T + r[0]};
+    for (int s = 0; s < nspec; s++)
+        for (int c = 0; c < 3; c++)
+            if (slo[3 * s + c] != INT32_MAX && (int64_t)shi[3 * s + c] - slo[3 * s + c] >= (1 << 20))
+                return PD_ERR_SIZE;
+    auto tile_key = [&](int64_t p, const int *T, int32_t *t, int32_t *r) {
+        for (int c = 0; c < 3; c++) {
+            const int32_t rel = lat[3 * p + c] - slo[3 * spec[p] + c];
+            t[c] = rel / T[c];
+            r[c] = rel - t[c] * T[c];
+        }
+        return ((uint64_t)spec[p] << 48) | ((uint64_t)t[2] << 32) | ((uint64_t)t[1] << 16) | (uint64_t)t[0];
+    };
+    static const int shapes3[][3] = {{4, 4, 4}, {8, 4, 2}, {8, 8, 1}, {16, 4, 1}};
+    static const int shapes2[][3] = {{8, 8, 1}, {16, 4, 1}, {32, 2, 1}};
+    const int nshape = dim == 3 ? 4 : 3;
+    int T[3] = {0, 0, 0};
+    std::vector<uint64_t> tkeys;
+    int reach = 0;
+    for (const Stencil &sv : st)
+        for (int c = 0; c < dim; c++) reach = std::max(reach, std::abs(sv.off[c]));
+    {
+        size_t best = SIZE_MAX;
+        std::vector<uint64_t> keys((size_t)n);
+        for (int k = 0; k < 2 * nshape; k++) {
+            // first pass: shapes whose every edge is at least the largest
+            // stencil offset component (a tile's family then lies in its
+            // 3^dim neighbour tiles); second pass only if none qualifies
+            if (k == nshape && best != SIZE_MAX) break;
+            const int *Tk = dim == 3 ? shapes3[k % nshape] : shapes2[k % nshape];
+            bool fits = true;
+            if (k < nshape)
+                for (int c = 0; c < dim; c++)
+                    if (Tk[c] < reach) fits = false;
+            // tiles per axis must fit in 16 bits
+            for (int s = 0; s < nspec && fits; s++)
+                for (int c = 0; c < 3; c++)
+                    if (slo[3 * s + c] != INT32_MAX && (shi[3 * s + c] - slo[3 * s + c]) / Tk[c] >= 65535) fits = false;
+            if (!fits) continue;
+            parallel_for(n, [&](int64_t a, int64_t b) {
+                int32_t t[3], r[3];
+                for (int64_t p = a; p < b; p++) keys[p] = tile_key(p, Tk, t, r);
+            });
+            std::vector<uint64_t> u = keys;
+            std::sort(u.begin(), u.end());
+            u.erase(std::unique(u.begin(), u.end()), u.end());
+            if (u.size() < best) {
+                best = u.size();
+                for (int c = 0; c < 3; c++) T[c] = Tk[c];
+                tkeys.swap(u);
+            }
+        }
+        if (best == SIZE_MAX) return PD_ERR_SIZE;
     }
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-        const Key &x = keys[a], &y = keys[b];
-        if (x.s != y.s) return x.s < y.s;
-        if (x.t0 != y.t0) return x.t0 < y.t0;
-        if (x.t1 != y.t1) return x.t1 < y.t1;
-        if (x.t2 != y.t2) return x.t2 < y.t2;
-        return x.l < y.l;
-    });
-    const int64_t n_pad = (n + 63) / 64 * 64;
-    const int64_t n_slices = n_pad / 64;
+    const int64_t n_tiles = (int64_t)tkeys.size();
+    const int64_t n_pad = n_tiles * 64;
+    const int64_t n_slices = n_tiles;
+    if (n_pad >= PD_MAX_NODES) return PD_ERR_SIZE;
+    std::vector<int64_t> node_of_row((size_t)n_pad, -1);
     std::vector<int32_t> row_of((size_t)n);
-    for (int64_t r = 0; r < n; r++) row_of[order[r]] = (int32_t)r;
-
-    // neighbour lists per row: (neighbour row, stencil id), sorted by row
-    std::vector<int32_t> deg((size_t)n_pad, 0);
-    std::vector<std::vector<uint32_t>> nb((size_t)n);
     parallel_for(n, [&](int64_t a, int64_t b) {
-        for (int64_t r = a; r < b; r++) {
-            int64_t p = order[r];
-            std::vector<uint32_t> &v = nb[r];
-            v.reserve(st.size());
-            for (size_t s = 0; s < st.size(); s++) {
-                int32_t q[3];
-                for (int c = 0; c < 3; c++) q[c] = lat[3 * p + c] + st[s].off[c];
-                int32_t qi = look.find(q);
-                if (qi < 0 || spec[qi] != spec[p]) continue;
-                v.push_back(((uint32_t)row_of[qi] << 7) | (uint32_t)s);
-            }
-            std::sort(v.begin(), v.end());
-            deg[r] = (int32_t)v.size();
+        int32_t t[3], r[3];
+        for (int64_t p = a; p < b; p++) {
+            const uint64_t key = tile_key(p, T, t, r);
+            const int64_t tid = std::lower_bound(tkeys.begin(), tkeys.end(), key) - tkeys.begin();
+            const int64_t row = tid * 64 + r[0] + T[0] * (r[1] + T[1] * r[2]);
+            row_of[p] = (int32_t)row;
+            node_of_row[row] = p;
         }
     });
-    std::vector<int64_t> slice_ptr((size_t)n_slices + 1, 0);
-    int32_t max_row = 0;
-    int64_t nnz = 0;
-    for (int64_t s = 0; s < n_slices; s++) {
-        int32_t L = 0;
-        for (int k = 0; k < 64; k++) L = std::max(L, deg[64 * s + k]);
-        slice_ptr[s + 1] = slice_ptr[s] + (int64_t)L * 64;
-        max_row = std::max(max_row, L);
-    }
-    for (int64_t r = 0; r < n; r++) nnz += deg[r];
-    const int64_t n_words = slice_ptr[n_slices];
 
-    // weighted volume (Eq. 1.9, w = 1, full geometric family)
+    // ---- per row: neighbours in stencil order, weighted volume, notch cuts ---
+    const int ns = (int)st.size();
+    const int L4 = (ns + 3) / 4 * 4;
     std::vector<double> m((size_t)n_pad, 0.0);
-    parallel_for(n, [&](int64_t a, int64_t b) {
-        for (int64_t r = a; r < b; r++) {
-            double s = 0.0;
-            for (uint32_t w : nb[r]) {
-                const Stencil &sv = st[w & 127u];
-                s += sv.x * sv.x * body->vol[order[w >> 7]];
-            }
-            m[r] = s;
-        }
-    });
-
-    // notch cuts on unique bonds, evaluated with the lower caller index first
-    std::vector<std::vector<uint8_t>> cut((size_t)n);
-    std::vector<int64_t> ncut_rows((size_t)n, 0);
+    std::vector<uint64_t> cutbits((size_t)n_pad * 2, 0);  // one bit per stencil entry (<= 127)
+    std::vector<int32_t> deg((size_t)n_pad, 0), ncutr((size_t)n_pad, 0);
     auto pos = [&](int64_t p, double *X) {
         for (int c = 0; c < 3; c++) X[c] = body->origin[c] + body->dx * (double)lat[3 * p + c];
     };
-    if (ncuts > 0) {
-        parallel_for(n, [&](int64_t a, int64_t b) {
-            for (int64_t r = a; r < b; r++) {
-                int64_t p = order[r];
-                cut[r].assign(nb[r].size(), 0);
-                for (size_t k = 0; k < nb[r].size(); k++) {
-                    int64_t q = order[nb[r][k] >> 7];
-                    int64_t lo = std::min(p, q), hi = std::max(p, q);
+    auto neighbour = [&](int64_t p, int s) -> int64_t {
+        int32_t q[3];
+        for (int c = 0; c < 3; c++) q[c] = lat[3 * p + c] + st[s].off[c];
+        const int32_t qi = look.find(q);
+        return (qi < 0 || spec[qi] != spec[p]) ? -1 : qi;
+    };
+    parallel_for(n_pad, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; r++) {
+            const int64_t p = node_of_row[r];
+            if (p < 0) continue;
+            double msum = 0.0;
+            for (int s = 0; s < ns; s++) {
+                const int64_t q = neighbour(p, s);
+                if (q < 0) continue;
+                deg[r]++;
+                msum += st[s].x * st[s].x * body->vol[q];
+                if (ncuts > 0) {
+                    const int64_t lo = std::min(p, q), hi = std::max(p, q);
                     double P[3], Q[3];
                     pos(lo, P);
                     pos(hi, Q);
                     for (int c = 0; c < ncuts; c++) {
                         if (cuts[c].specimen >= 0 && spec[p] != cuts[c].specimen) continue;
-                        bool hit = false;
+                        bool hit;
                         if (cuts[c].kind == 0) hit = crosses_segment(P, Q, cuts[c].p);
                         else if (cuts[c].kind == 1) hit = crosses_parallelogram(P, Q, cuts[c].p);
                         else hit = crosses_helicoid(P, Q, cuts[c].p);
                         if (hit) {
-                            cut[r][k] = 1;
-                            ncut_rows[r]++;
+                            cutbits[2 * r + (s >> 6)] |= 1ull << (s & 63);
+                            ncutr[r]++;
                             break;
                         }
                     }
                 }
             }
-        });
+            m[r] = msum;
+        }
+    });
+    int32_t max_row = 0;
+    int64_t nnz = 0, ncut_dir = 0;
+    for (int64_t r = 0; r < n_pad; r++) {
+        nnz += deg[r];
+        ncut_dir += ncutr[r];
+        max_row = std::max(max_row, deg[r]);
     }
-    int64_t ncut_dir = 0;
-    for (int64_t r = 0; r < n; r++) ncut_dir += ncut_rows[r];
+    const int64_t n_words = n_pad * L4;
 
     sizes->n = n;
     sizes->n_pad = n_pad;
@@ -333,19 +357,25 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
     sizes->nnz = nnz;
     sizes->n_bonds = nnz / 2;
     sizes->n_cut = ncut_dir / 2;
-    sizes->n_stencil = (int32_t)st.size();
+    sizes->n_stencil = ns;
     sizes->max_row = max_row;
     sizes->dim = dim;
     sizes->n_specimens = nspec;
+    sizes->n_tiles = n_tiles;
+    for (int c = 0; c < 3; c++) sizes->tile[c] = T[c];
+    sizes->words_per_row = L4;
+    sizes->reach = reach;
+    sizes->pad1 = 0;
     if (!out) return PD_OK;
     if (!out->perm || !out->row_of || !out->slice_ptr || !out->words || !out->mask || !out->stencil ||
-        !out->stencil_off || !out->vol || !out->inv_m || !out->spec || !out->lat4)
+        !out->stencil_off || !out->vol || !out->inv_m || !out->spec || !out->lat4 || !out->tile_org ||
+        !out->tile_nbr)
         return PD_ERR_ARG;
 
-    for (int64_t r = 0; r < n_pad; r++) out->perm[r] = r < n ? (int32_t)order[r] : -1;
+    for (int64_t r = 0; r < n_pad; r++) out->perm[r] = (int32_t)node_of_row[r];
     for (int64_t p = 0; p < n; p++) out->row_of[p] = row_of[p];
-    std::memcpy(out->slice_ptr, slice_ptr.data(), sizeof(int64_t) * (n_slices + 1));
-    for (size_t s = 0; s < st.size(); s++) {
+    for (int64_t s = 0; s <= n_slices; s++) out->slice_ptr[s] = s * 64 * L4;
+    for (int s = 0; s < ns; s++) {
         for (int c = 0; c < 3; c++) {
             out->stencil[4 * s + c] = st[s].M[c];
             out->stencil_off[3 * s + c] = st[s].off[c];
@@ -353,36 +383,55 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
         out->stencil[4 * s + 3] = st[s].x;
     }
     parallel_for(n_slices, [&](int64_t a, int64_t b) {
-        for (int64_t s = a; s < b; s++) {
-            int64_t base = slice_ptr[s];
-            int64_t L = (slice_ptr[s + 1] - base) / 64;
-            for (int64_t k = 0; k < L; k++) {
+        for (int64_t sl = a; sl < b; sl++) {
+            const int64_t base = sl * 64 * L4;
+            for (int k = 0; k < L4; k++) {
                 uint64_t bits = 0;
                 for (int lane = 0; lane < 64; lane++) {
-                    int64_t r = 64 * s + lane;
-                    uint32_t w;
-                    bool intact = false;
-                    if (r < n && k < (int64_t)nb[r].size()) {
-                        w = nb[r][k];
-                        intact = cut[r].empty() ? true : !cut[r][k];
-                    } else {
-                        w = ((uint32_t)r << 7) | 127u;
+                    const int64_t r = 64 * sl + lane;
+                    const int64_t p = node_of_row[r];
+                    uint32_t w = ((uint32_t)r << 7) | 127u;
+                    if (p >= 0 && k < ns) {
+                        const int64_t q = neighbour(p, k);
+                        if (q >= 0) {
+                            w = ((uint32_t)row_of[q] << 7) | (uint32_t)k;
+                            if (!((cutbits[2 * r + (k >> 6)] >> (k & 63)) & 1ull)) bits |= 1ull << lane;
+                        }
                     }
-                    out->words[base + k * 64 + lane] = w;
-                    if (intact) bits |= (1ull << lane);
+                    out->words[pd_widx(base, k, lane)] = w;
                 }
                 out->mask[base / 64 + k] = bits;
             }
         }
     });
     for (int64_t r = 0; r < n_pad; r++) {
-        bool real = r < n;
-        int64_t p = real ? order[r] : 0;
+        const int64_t p = node_of_row[r];
+        const bool real = p >= 0;
         out->vol[r] = real ? body->vol[p] : 0.0;
         out->inv_m[r] = (real && m[r] > 0.0) ? 1.0 / m[r] : 0.0;
         out->spec[r] = real ? spec[p] : 0;
         for (int c = 0; c < 3; c++) out->lat4[4 * r + c] = real ? lat[3 * p + c] : 0;
         out->lat4[4 * r + 3] = 0;
+    }
+    for (int64_t t = 0; t < n_tiles; t++) {
+        const uint64_t key = tkeys[t];
+        const int32_t sp = (int32_t)(key >> 48);
+        const int32_t tc[3] = {(int32_t)(key & 0xffff), (int32_t)((key >> 16) & 0xffff), (int32_t)((key >> 32) & 0xffff)};
+        for (int c = 0; c < 3; c++) out->tile_org[4 * t + c] = slo[3 * sp + c] + tc[c] * T[c];
+        out->tile_org[4 * t + 3] = sp;
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    const int32_t q[3] = {tc[0] + dx, tc[1] + dy, tc[2] + dz};
+                    int32_t id = -1;
+                    if (q[0] >= 0 && q[1] >= 0 && q[2] >= 0) {
+                        const uint64_t k2 = ((uint64_t)sp << 48) | ((uint64_t)q[2] << 32) | ((uint64_t)q[1] << 16) |
+                                            (uint64_t)q[0];
+                        auto it = std::lower_bound(tkeys.begin(), tkeys.end(), k2);
+                        if (it != tkeys.end() && *it == k2) id = (int32_t)(it - tkeys.begin());
+                    }
+                    out->tile_nbr[27 * t + (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] = id;
+                }
     }
     return PD_OK;
 }
@@ -395,7 +444,7 @@ extern "C" pd_status pd_bsr_pattern(const pd_family_sizes *sz, const pd_family_h
     const int64_t n_pad = sz->n_pad;
     std::vector<std::vector<int32_t>> rows((size_t)n_pad);
     auto row_len = [&](int64_t r) { return (fam->slice_ptr[r / 64 + 1] - fam->slice_ptr[r / 64]) / 64; };
-    auto word = [&](int64_t r, int64_t k) { return fam->words[fam->slice_ptr[r / 64] + k * 64 + (r % 64)]; };
+    auto word = [&](int64_t r, int64_t k) { return fam->words[pd_widx(fam->slice_ptr[r / 64], k, (int)(r % 64))]; };
     std::vector<int32_t> reach_rows((size_t)n_pad, 0);
     parallel_for(n_pad, [&](int64_t a, int64_t b) {
         std::vector<int32_t> tmp;

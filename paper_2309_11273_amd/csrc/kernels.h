@@ -32,6 +32,11 @@ struct StepArgs {
     double4 *dsum;
     // BSR path
     uint32_t *dirty;
+    // tile description (LDS-staged kernels)
+    const int32_t *stencil_off;
+    const int32_t *tile_nbr;
+    int32_t tile[3];
+    int32_t reach;
 };
 
 struct InitArgs {
@@ -68,6 +73,9 @@ hipError_t launch_pass2_f64(const StepArgs &a, int cur, bool update, int block, 
 hipError_t launch_pass1_f32(const StepArgs &a, int cur, bool brk, int block, hipStream_t s);
 hipError_t launch_pass2_f32(const StepArgs &a, int cur, bool update, int block, hipStream_t s);
 hipError_t launch_shadow_prep(const StepArgs &a, int cur, hipStream_t s);
+bool tiled_supported(const StepArgs &a);
+hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s);
+hipError_t launch_tpass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s);
 hipError_t launch_state_init(const InitArgs &a, hipStream_t s);
 hipError_t launch_state_read(const int32_t *perm, int64_t n_pad, const double4 *uv, const double4 *vel,
                              double *u_out, double *v_out, hipStream_t s);

@@ -70,31 +70,45 @@ __global__ __launch_bounds__(256) void k_pass1_f64(StepArgs a, int cur) {
     const double thr_scale = s0 * (1.0 - 1e-9);  // cheap pre-filter, exact test below
     double acc = 0.0;
     uint32_t nbroken = 0;
-    for (int64_t k = 0; k < L; k++) {
-        const uint64_t m64 = uniform64(a.mask[(base >> 6) + k]);
-        if (m64 == 0) continue;
-        const uint32_t w = a.words[base + k * 64 + lane];
-        const int64_t j = w >> 7;
-        const double4 st = sst[w & 127u];
-        const double4 uj = uv[j];
-        const double e = ext_canonical(st.x, st.y, DIM == 3 ? st.z : 0.0, uj.x - ui.x, uj.y - ui.y,
-                                       DIM == 3 ? uj.z - ui.z : 0.0);
-        bool intact = (m64 >> lane) & 1ull;
-        bool broke = false;
-        if (BREAK && intact && e >= thr_scale * st.w) {
-            if (e / st.w >= s0) {
-                intact = false;
-                broke = true;
+    // groups of four bond words per lane: one 16-byte load per group, the next
+    // group's words are requested before this group's neighbours are gathered
+    const uint4 *__restrict__ wg = reinterpret_cast<const uint4 *>(a.words + base) + lane;
+    const uint4 *__restrict__ mg = reinterpret_cast<const uint4 *>(a.mask + (base >> 6));
+    const int64_t G = L >> 2;
+    uint4 wn = G > 0 ? wg[0] : make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t g = 0; g < G; g++) {
+        const uint4 w4 = wn;
+        if (g + 1 < G) wn = wg[(g + 1) * 64];
+        const uint4 ma = mg[2 * g], mb = mg[2 * g + 1];
+        uint64_t m[4] = {uniform64(((uint64_t)ma.y << 32) | ma.x), uniform64(((uint64_t)ma.w << 32) | ma.z),
+                         uniform64(((uint64_t)mb.y << 32) | mb.x), uniform64(((uint64_t)mb.w << 32) | mb.z)};
+        if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
+        const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
+        double4 uj[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) uj[c] = uv[ws[c] >> 7];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const double4 st = sst[ws[c] & 127u];
+            const double e = ext_canonical(st.x, st.y, DIM == 3 ? st.z : 0.0, uj[c].x - ui.x, uj[c].y - ui.y,
+                                           DIM == 3 ? uj[c].z - ui.z : 0.0);
+            bool intact = (m[c] >> lane) & 1ull;
+            bool broke = false;
+            if (BREAK && intact && e >= thr_scale * st.w) {
+                if (e / st.w >= s0) {
+                    intact = false;
+                    broke = true;
+                }
             }
-        }
-        if (BREAK) {
-            const uint64_t bb = __ballot(broke);
-            if (bb) {
-                if (lane == 0) a.mask[(base >> 6) + k] = m64 & ~bb;
-                nbroken += __popcll(bb);
+            if (BREAK) {
+                const uint64_t bb = __ballot(broke);
+                if (bb) {
+                    if (lane == 0) a.mask[(base >> 6) + 4 * g + c] = m[c] & ~bb;
+                    nbroken += __popcll(bb);
+                }
             }
+            if (intact) acc += st.w * uj[c].w * e;  // w x V_j e, w = 1
         }
-        if (intact) acc += st.w * uj.w * e;  // w x V_j e, w = 1
     }
     const double2 qri = a.qr[row];
     // theta_i = A / m_i * acc; store theta_i / m_i
@@ -124,22 +138,37 @@ __global__ __launch_bounds__(256) void k_pass2_f64(StepArgs a, int cur) {
     const uint32_t aux = a.aux[row];
     const pd_spec sp = a.spec[aux >> 8];
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int64_t k = 0; k < L; k++) {
-        const uint64_t m64 = uniform64(a.mask[(base >> 6) + k]);
-        if (m64 == 0) continue;
-        const uint32_t w = a.words[base + k * 64 + lane];
-        const int64_t j = w >> 7;
-        const double4 st = sst[w & 127u];
-        const double4 uj = uv[j];
-        const double2 qrj = qr[j];
-        double e = st.x * (uj.x - ui.x) + st.y * (uj.y - ui.y);
-        if (DIM == 3) e += st.z * (uj.z - ui.z);
-        // [(K - G/3) x (theta_i/m_i + theta_j/m_j) + G e (1/m_i + 1/m_j)] V_j
-        const double t = (sp.kp * st.w * (qri.x + qrj.x) + sp.G * e * (qri.y + qrj.y)) * uj.w;
-        if ((m64 >> lane) & 1ull) {
-            fx += t * st.x;
-            fy += t * st.y;
-            if (DIM == 3) fz += t * st.z;
+    const uint4 *__restrict__ wg = reinterpret_cast<const uint4 *>(a.words + base) + lane;
+    const uint4 *__restrict__ mg = reinterpret_cast<const uint4 *>(a.mask + (base >> 6));
+    const int64_t G = L >> 2;
+    uint4 wn = G > 0 ? wg[0] : make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t g = 0; g < G; g++) {
+        const uint4 w4 = wn;
+        if (g + 1 < G) wn = wg[(g + 1) * 64];
+        const uint4 ma = mg[2 * g], mb = mg[2 * g + 1];
+        const uint64_t m[4] = {uniform64(((uint64_t)ma.y << 32) | ma.x), uniform64(((uint64_t)ma.w << 32) | ma.z),
+                               uniform64(((uint64_t)mb.y << 32) | mb.x), uniform64(((uint64_t)mb.w << 32) | mb.z)};
+        if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
+        const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
+        double4 uj[4];
+        double2 qrj[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            uj[c] = uv[ws[c] >> 7];
+            qrj[c] = qr[ws[c] >> 7];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const double4 st = sst[ws[c] & 127u];
+            double e = st.x * (uj[c].x - ui.x) + st.y * (uj[c].y - ui.y);
+            if (DIM == 3) e += st.z * (uj[c].z - ui.z);
+            // [(K - G/3) x (theta_i/m_i + theta_j/m_j) + G e (1/m_i + 1/m_j)] V_j
+            const double t = (sp.kp * st.w * (qri.x + qrj[c].x) + sp.G * e * (qri.y + qrj[c].y)) * uj[c].w;
+            if ((m[c] >> lane) & 1ull) {
+                fx += t * st.x;
+                fy += t * st.y;
+                if (DIM == 3) fz += t * st.z;
+            }
         }
     }
     fx *= ui.w;
@@ -250,7 +279,7 @@ __global__ __launch_bounds__(256) void k_damage(DamageArgs a) {
     double num = 0.0, den = 0.0;
     for (int64_t k = 0; k < L; k++) {
         const uint64_t m64 = uniform64(a.mask[(base >> 6) + k]);
-        const uint32_t w = a.words[base + k * 64 + lane];
+        const uint32_t w = a.words[pd_widx(base, k, lane)];
         if ((w & 127u) == PD_PAD_ID) continue;
         const double Vj = a.vol[w >> 7];
         den += Vj;

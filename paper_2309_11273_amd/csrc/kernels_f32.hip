@@ -56,12 +56,15 @@ __device__ __forceinline__ uint64_t uniform64b(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Power-of-two scale for a shadow of displacements bounded by m.
+// Power-of-two scale for a shadow of displacements bounded by m.  The
+// scale is kept >= 2^-100 so that the float table M*Q and the float force
+// accumulated along M*Q stay normal numbers; displacements beyond 2^30 Q
+// then fall back to the double state.
 __device__ __forceinline__ double shadow_scale(unsigned int mbits) {
     const float m = __uint_as_float(mbits);
     if (!(m > 0.0f) || !isfinite(m)) return ldexp(1.0, -100);
     const int e = ilogb((double)m);
-    return ldexp(1.0, e - 27);
+    return ldexp(1.0, max(e - 27, -100));
 }
 
 __device__ __forceinline__ int quantise(double u, double invQ, bool &bad) {
@@ -73,9 +76,16 @@ __device__ __forceinline__ int quantise(double u, double invQ, bool &bad) {
     return (int)rint(t);
 }
 
+// Wave maximum of a non-negative float, merged into *dst.  The atomic is
+// issued only when the wave's value exceeds what is already there (a plain
+// read that may be stale, which only costs an extra atomic), so tens of
+// thousands of waves do not serialise on one address.
 __device__ __forceinline__ void wave_max_atomic(float v, unsigned int *dst) {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(dst, __float_as_uint(v));
+    if ((threadIdx.x & 63) == 0) {
+        const unsigned int bits = __float_as_uint(v);
+        if (bits > __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMax(dst, bits);
+    }
 }
 
 __device__ __forceinline__ void load_stencil_scaled(float4 *sst, const double *stencil, int n_stencil, double Q) {
@@ -140,7 +150,7 @@ __global__ __launch_bounds__(256) void k_dsum(StepArgs a, int cur) {
     for (int64_t k = 0; k < L; k++) {
         const uint64_t m64 = uniform64b(a.mask[(base >> 6) + k]);
         if (!((m64 >> lane) & 1ull)) continue;
-        const uint32_t w = a.words[base + k * 64 + lane];
+        const uint32_t w = a.words[pd_widx(base, k, lane)];
         const double4 sd = sten[w & 127u];
         const double xv = sd.w * uv[w >> 7].w;
         d0 += xv * sd.x;
@@ -185,13 +195,29 @@ __global__ __launch_bounds__(256) void k_pass1_f32(StepArgs a, int cur) {
     float acc = 0.0f;
     uint32_t nbroken = 0, nrecheck = 0, nfall = 0;
     double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;  // x M V_j of the bonds this row breaks now
-    for (int64_t k = 0; k < L; k++) {
-        const uint64_t m64 = uniform64b(a.mask[(base >> 6) + k]);
-        if (m64 == 0) continue;
-        const uint32_t w = a.words[base + k * 64 + lane];
+    const uint4 *__restrict__ wg = reinterpret_cast<const uint4 *>(a.words + base) + lane;
+    const uint4 *__restrict__ mg = reinterpret_cast<const uint4 *>(a.mask + (base >> 6));
+    const int64_t G = L >> 2;
+    uint4 wn = G > 0 ? wg[0] : make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t g = 0; g < G; g++) {
+      const uint4 w4 = wn;
+      if (g + 1 < G) wn = wg[(g + 1) * 64];
+      const uint4 ma = mg[2 * g], mb = mg[2 * g + 1];
+      const uint64_t mm[4] = {uniform64b(((uint64_t)ma.y << 32) | ma.x), uniform64b(((uint64_t)ma.w << 32) | ma.z),
+                              uniform64b(((uint64_t)mb.y << 32) | mb.x), uniform64b(((uint64_t)mb.w << 32) | mb.z)};
+      if ((mm[0] | mm[1] | mm[2] | mm[3]) == 0) continue;
+      const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
+      int4 sjs[4];
+#pragma unroll
+      for (int c = 0; c < 4; c++) sjs[c] = sh[ws[c] >> 7];
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const int64_t k = 4 * g + c;
+        const uint64_t m64 = mm[c];
+        const uint32_t w = ws[c];
         const int64_t j = w >> 7;
         const float4 st = sst[w & 127u];
-        const int4 sj = sh[j];
+        const int4 sj = sjs[c];
         bool intact = (m64 >> lane) & 1ull;
         bool broke = false;
         float e;
@@ -246,6 +272,7 @@ __global__ __launch_bounds__(256) void k_pass1_f32(StepArgs a, int cur) {
             }
         }
         if (intact) acc += st.w * __int_as_float(sj.w) * e;
+      }
     }
     // (M Q) . (du / Q) is the physical extension: theta_i / m_i = A r_i^2 acc
     const float2 qri = a.qr32[row];
@@ -297,14 +324,33 @@ __global__ __launch_bounds__(256) void k_pass2_f32(StepArgs a, int cur) {
     const pd_spec sp = a.spec[aux >> 8];
     const float kp = (float)sp.kp, G = (float)sp.G;
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int64_t k = 0; k < L; k++) {
-        const uint64_t m64 = uniform64b(a.mask[(base >> 6) + k]);
-        if (m64 == 0) continue;
-        const uint32_t w = a.words[base + k * 64 + lane];
+    const uint4 *__restrict__ wg = reinterpret_cast<const uint4 *>(a.words + base) + lane;
+    const uint4 *__restrict__ mg = reinterpret_cast<const uint4 *>(a.mask + (base >> 6));
+    const int64_t G4 = L >> 2;
+    uint4 wn = G4 > 0 ? wg[0] : make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t g = 0; g < G4; g++) {
+      const uint4 w4 = wn;
+      if (g + 1 < G4) wn = wg[(g + 1) * 64];
+      const uint4 ma = mg[2 * g], mb = mg[2 * g + 1];
+      const uint64_t mm[4] = {uniform64b(((uint64_t)ma.y << 32) | ma.x), uniform64b(((uint64_t)ma.w << 32) | ma.z),
+                              uniform64b(((uint64_t)mb.y << 32) | mb.x), uniform64b(((uint64_t)mb.w << 32) | mb.z)};
+      if ((mm[0] | mm[1] | mm[2] | mm[3]) == 0) continue;
+      const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
+      int4 sjs[4];
+      float2 qrjs[4];
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        sjs[c] = sh[ws[c] >> 7];
+        qrjs[c] = qr[ws[c] >> 7];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const uint64_t m64 = mm[c];
+        const uint32_t w = ws[c];
         const int64_t j = w >> 7;
         const float4 st = sst[w & 127u];
-        const int4 sj = sh[j];
-        const float2 qrj = qr[j];
+        const int4 sj = sjs[c];
+        const float2 qrj = qrjs[c];
         float e, Vj;
         if (__builtin_expect(si.x == PD_SENTINEL || sj.x == PD_SENTINEL, 0)) {
             e = 0.0f;
@@ -329,6 +375,7 @@ __global__ __launch_bounds__(256) void k_pass2_f32(StepArgs a, int cur) {
             fy += t * st.y;
             if (DIM == 3) fz += t * st.z;
         }
+      }
     }
     const double4 ui = uv[row];
     const double4 D = a.dsum[row];

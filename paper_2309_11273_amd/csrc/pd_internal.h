@@ -30,3 +30,18 @@ static_assert(sizeof(pd_ctl) <= PD_CTL_BYTES, "control block too large");
 
 // Padding stencil id.
 #define PD_PAD_ID 127u
+
+#ifdef __HIPCC__
+#define PD_HD __host__ __device__
+#else
+#define PD_HD
+#endif
+
+// Bond word layout inside a 64-row slice whose words start at 'base' (a
+// multiple of 256): words come in groups of four per lane, so that lane
+// 'lane' reads words 4g..4g+3 of its row with one 16-byte load and the 64
+// lanes of a wave read 1 KiB of consecutive memory.  Row lengths inside a
+// slice are padded to a multiple of four.
+PD_HD inline int64_t pd_widx(int64_t base, int64_t k, int lane) {
+    return base + ((k >> 2) << 8) + ((int64_t)lane << 2) + (k & 3);
+}

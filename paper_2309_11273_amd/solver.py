@@ -104,9 +104,12 @@ class FamilyHost:
         self.inv_m = np.empty(s.n_pad, np.float64)
         self.spec = np.empty(s.n_pad, np.int32)
         self.lat4 = np.empty(s.n_pad * 4, np.int32)
+        self.tile_org = np.empty(s.n_tiles * 4, np.int32)
+        self.tile_nbr = np.empty(s.n_tiles * 27, np.int32)
         hb = A.pd_family_host(_np(self.perm), _np(self.row_of), _np(self.slice_ptr), _np(self.words),
                               _np(self.mask), _np(self.stencil), _np(self.stencil_off), _np(self.vol),
-                              _np(self.inv_m), _np(self.spec), _np(self.lat4))
+                              _np(self.inv_m), _np(self.spec), _np(self.lat4), _np(self.tile_org),
+                              _np(self.tile_nbr))
         self._hb = hb
         A.check("pd_build_family", L.pd_build_family(C.byref(body), C.cast(carr, C.c_void_p), len(cuts),
                                                      C.byref(sizes), C.byref(hb)))
@@ -124,11 +127,13 @@ class FamilyHost:
             L = (b1 - b0) // 64
             if L == 0:
                 continue
-            w = self.words[b0:b1].reshape(L, 64)
-            k, lane = np.nonzero((w & 127) != 127)
+            # groups of four words per lane: index (k // 4, lane, k % 4)
+            w = self.words[b0:b1].reshape(L // 4, 64, 4)
+            g, lane, c = np.nonzero((w & 127) != 127)
+            k = 4 * g + c
             rows.append(sl * 64 + lane)
             ks.append(k)
-            wi.append(b0 + k * 64 + lane)
+            wi.append(b0 + g * 256 + lane * 4 + c)
         rows = np.concatenate(rows) if rows else np.zeros(0, np.int64)
         ks = np.concatenate(ks) if ks else np.zeros(0, np.int64)
         wi = np.concatenate(wi) if wi else np.zeros(0, np.int64)
@@ -205,6 +210,12 @@ class Solver:
         P.vol, P.inv_m, P.lat4, P.spec = _tp(self.vol), _tp(self.inv_m), _tp(self.lat4), _tp(self.spec)
         P.aux, P.fext = _tp(self.aux), _tp(self.fext)
         P.ramp_steps = int(w.ramp_steps)
+        self.stencil_off = t(self.fam.stencil_off)
+        self.tile_nbr = t(self.fam.tile_nbr)
+        P.stencil_off, P.tile_nbr = _tp(self.stencil_off), _tp(self.tile_nbr)
+        for c in range(3):
+            P.tile[c] = int(s.tile[c])
+        P.reach = int(s.reach)
         self.P = P
         # state
         self.uv = [torch.zeros(self.n_pad * 4, dtype=torch.float64, device=d) for _ in range(2)]
@@ -296,18 +307,27 @@ class Solver:
         torch.cuda.synchronize(self.dev)
         return self._to_caller(f), self._rows_to_caller(th)
 
+    def tiled_supported(self) -> bool:
+        """Whether the LDS-staged tile kernels apply (tile edges >= stencil reach)."""
+        s = self.fam.sizes
+        T = list(s.tile)
+        R = int(s.reach)
+        return T[0] * T[1] * T[2] == 64 and min(T[: int(s.dim)]) >= R and R >= 1
+
     def profile_read(self, reset: bool = True) -> dict:
         p = A.pd_profile_stats()
         self.ctx.check("pd_profile_read", A.load().pd_profile_read(self.ctx.h, C.byref(p), 1 if reset else 0))
         return dict(steps=p.steps, ms_pass1=p.ms_pass1, ms_pass2=p.ms_pass2, ms_extra=p.ms_extra)
 
     def step(self, nsteps: int, precision: str = "fp64", form: str = "mf", graph_chunk: int = 0,
-             block: int = 0, check_every: int = 0, report: bool = True, profile: bool = False):
+             block: int = 0, check_every: int = 0, report: bool = True, profile: bool = False,
+             kernel: str = "auto"):
         o = A.pd_step_opts()
         o.precision = {"fp64": A.PD_FP64, "fp32": A.PD_FP32_RECHECK}[precision]
         o.form = {"mf": A.PD_MATRIX_FREE, "bsr": A.PD_BSR}[form]
         o.graph_chunk, o.block, o.check_every = int(graph_chunk), int(block), int(check_every)
         o.profile = 1 if profile else 0
+        o.kernel = {"auto": 0, "gather": 1, "tiled": 2}[kernel]
         rep = A.pd_step_report()
         Kp = C.byref(self.K) if self.K is not None else None
         self.ctx.check("pd_step", A.load().pd_step(self.ctx.h, C.byref(self.P), C.byref(self.S), int(nsteps),

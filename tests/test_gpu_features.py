@@ -1,0 +1,159 @@
+"""GPU checks of the solver's other behaviours through the C ABI: batching,
+resume, graph replay of every path, energies, the stable time step, damage,
+failure detection and full-size short runs against the CPU reference."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import Oracle  # noqa: E402
+from pd_inputs import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_11273_amd.solver import Context
+    return Context(0)
+
+
+def solver(w, ctx, **kw):
+    from paper_2309_11273_amd.solver import Solver
+    return Solver(w, ctx=ctx, **kw)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def test_batch_member_equals_single_specimen(ctx):
+    """Plate k of a batch advances exactly as the same plate alone (double
+    path, bitwise): specimens share no bonds and each row's sum order depends
+    only on its own family."""
+    dts = np.array([1.0e-7, 1.1e-7, 0.9e-7])
+    wb = W.batch2d(n_plates=3, steps=150, dt=dts)
+    sb = solver(wb, ctx)
+    sb.step(150, precision="fp64")
+    ub, _ = sb.read()
+    for k in range(3):
+        w1 = W.batch2d(n_plates=1, first=k, steps=150, dt=dts[k:k + 1])
+        s1 = solver(w1, ctx)
+        s1.step(150, precision="fp64")
+        u1, _ = s1.read()
+        uk = ub[wb.specimen == k]
+        assert np.array_equal(uk[:, :2], u1[:, :2]), k
+
+
+def test_resume_equals_uninterrupted(ctx):
+    """Stopping after n1 steps and restarting a new state from (u, v, bond
+    status, step counter) gives bitwise the uninterrupted trajectory."""
+    w = W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37, steps=200)
+    a = solver(w, ctx)
+    a.step(200, precision="fp64")
+    ua, va = a.read()
+    b = solver(w, ctx)
+    b.step(120, precision="fp64")
+    u1, v1 = b.read()
+    m1 = b.mask_host()
+    c = solver(w, ctx, u0=u1)
+    c.reset(u0=u1, v0=v1, start_step=120, mask=m1)
+    c.step(80, precision="fp64")
+    uc, vc = c.read()
+    assert np.array_equal(ua, uc)
+    assert np.array_equal(va, vc)
+    assert np.array_equal(a.mask_host(), c.mask_host())
+    assert c.step_count() == 200
+
+
+@pytest.mark.parametrize("precision,form", [("fp32", "mf"), ("fp64", "bsr")])
+def test_graph_replay_equals_eager_all_paths(ctx, precision, form):
+    w = W.impact3d(nx=36, ny=36, nz=9, dt=2.6e-7, steps=120)
+    a = solver(w, ctx)
+    b = solver(w, ctx)
+    if form == "bsr":
+        for s in (a, b):
+            s.build_K(fp32=False)
+            s.assemble_K()
+    a.step(120, precision=precision, form=form)
+    for _ in range(3):
+        b.step(40, precision=precision, form=form, graph_chunk=10)
+    ua, _ = a.read()
+    ub, _ = b.read()
+    if precision == "fp64":
+        assert np.array_equal(ua, ub)
+    else:
+        # each pd_step call re-quantises the shadow from the double state
+        assert rel(ub, ua) <= 1e-6
+    assert np.array_equal(a.mask_host(), b.mask_host())
+
+
+def test_energy_matches_reference(ctx):
+    w = W.cantilever3d(steps=300)
+    s = solver(w, ctx)
+    o = Oracle(w)
+    s.step(300, precision="fp64")
+    u, v = s.read()
+    kin, strain = s.energy()
+    rho = w.materials[0].rho
+    kin_ref = 0.5 * (rho * w.vol[:, None] * v * v).sum()
+    strain_ref = o.strain_energy(u)
+    assert kin == pytest.approx(kin_ref, rel=1e-12)
+    assert strain == pytest.approx(strain_ref, rel=1e-10)
+
+
+def test_stable_dt_matches_reference(ctx):
+    """pd_stable_dt (power iteration on the GPU operator) agrees with the
+    CPU reference's power iteration and the dense eigenvalue."""
+    w = W.cantilever3d()
+    s = solver(w, ctx)
+    dt_gpu = s.stable_dt(iters=500, seed=0)
+    o = Oracle(w, apply_cuts=False)
+    lam = o.lambda_max(500, 0)
+    assert dt_gpu == pytest.approx(2 / np.sqrt(lam), rel=1e-6)
+    assert w.dt[0] < 0.8 * dt_gpu * 1.0001
+
+
+def test_nonfinite_state_is_reported(ctx):
+    """A non-finite displacement is caught at the next check and reported
+    as PD_ERR_UNSTABLE (forced from the host: NaN in the initial state)."""
+    from paper_2309_11273_amd._abi import PDError
+    w = W.plate2d(nx=24, ny=12, dt=1.0e-7, notch_row=5, notch_tip=10.37, steps=20)
+    u0 = np.zeros((w.n, 3))
+    u0[7, 0] = np.nan
+    s = solver(w, ctx, u0=u0)
+    with pytest.raises(PDError) as ei:
+        s.step(10, precision="fp64", check_every=5)
+    assert ei.value.status == -4
+
+
+def test_damage_matches_reference(ctx):
+    w = W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37, steps=250)
+    s = solver(w, ctx)
+    o = Oracle(w)
+    s.step(250, precision="fp64")
+    uo, vo = o.initial_state()
+    o.run(250, uo, vo)
+    phi = s.damage()
+    np.testing.assert_allclose(phi, o.damage(), rtol=0, atol=1e-15)
+    assert phi.max() > 0.3
+
+
+@pytest.mark.parametrize("name,steps", [("impact3d", 6), ("cylinder3d", 4), ("batch2d", 6)])
+def test_full_size_short_run(ctx, name, steps):
+    """The full workloads in the launch configuration the benchmark times
+    (FP32 force path, graph replay) for a few steps: displacement within the
+    FP32 bar of the CPU reference, broken-bond set identical."""
+    w = W.workload(name)
+    s = solver(w, ctx)
+    s.step(steps, precision="fp32", graph_chunk=2)
+    u, _ = s.read()
+    o = Oracle(w)
+    uo, vo = o.initial_state()
+    o.run(steps, uo, vo)
+    assert rel(u, uo) <= 1e-4
+    assert np.array_equal(s.bond_status()[2], o.rho())

@@ -122,14 +122,15 @@ def test_plate_full_size_fp64(ctx):
         assert np.array_equal(s.bond_status()[2], o.rho())
 
 
+@pytest.mark.parametrize("kernel", ["gather", "tiled"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("impact", 200),
                                         ("cylinder", 200), ("batch", 200)])
-def test_fp32_recheck_trajectory(ctx, name, steps):
+def test_fp32_recheck_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
     o = Oracle(w)
     s = solver(w, ctx)
     uo, vo = o.initial_state()
-    s.step(steps, precision="fp32")
+    s.step(steps, precision="fp32", kernel=kernel)
     o.run(steps, uo, vo)
     u, _ = s.read()
     assert rel(u, uo) <= FP32_TOL, (name, rel(u, uo))

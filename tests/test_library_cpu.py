@@ -84,6 +84,64 @@ def test_family_matches_reference(lib, case):
     assert np.all(np.diff(f.slice_ptr) % 64 == 0)
 
 
+def _halo_rows(f, tile):
+    """Emulation of the LDS-staged kernels' halo gather: global row of every
+    slot of the (T0+2R)(T1+2R)(T2+2R) box around 'tile' (-1 = no tile)."""
+    s = f.sizes
+    T0, T1, T2 = list(s.tile)
+    R = int(s.reach)
+    dim = int(s.dim)
+    Bx, By = T0 + 2 * R, T1 + 2 * R
+    Bz = T2 + 2 * R if dim == 3 else 1
+    tn = f.tile_nbr[27 * tile: 27 * tile + 27]
+    out = np.full(Bx * By * Bz, -1, np.int64)
+    for slot in range(Bx * By * Bz):
+        bx, byz = slot % Bx, slot // Bx
+        by, bz = byz % By, byz // By
+        p = [bx - R, by - R, (bz - R) if dim == 3 else 0]
+        T = [T0, T1, T2]
+        d = [(-1 if p[c] < 0 else (1 if p[c] >= T[c] else 0)) for c in range(3)]
+        nt = tn[(d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1)]
+        if nt >= 0:
+            loc = [p[c] - d[c] * T[c] for c in range(3)]
+            out[slot] = nt * 64 + loc[0] + T0 * (loc[1] + T1 * loc[2])
+    return out, (Bx, By, Bz)
+
+
+@pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate"])
+def test_tile_halo_addressing_matches_bond_words(lib, case):
+    """The tile kernels find neighbour k of lane l at halo slot
+    slot(l) + soff[k]; that slot must hold exactly the row the bond word
+    names, for every present bond (and stay inside the halo box)."""
+    w = CASES[case]()
+    f = _family(w)
+    s = f.sizes
+    T0, T1, T2 = list(s.tile)
+    R = int(s.reach)
+    assert min(T0, T1) >= R and (s.dim == 2 or T2 >= R)
+    off = f.stencil_off.reshape(-1, 3)
+    L4 = int(s.words_per_row)
+    rng = np.random.default_rng(0)
+    tiles = rng.choice(int(s.n_tiles), size=min(40, int(s.n_tiles)), replace=False)
+    for t in tiles:
+        rows, (Bx, By, Bz) = _halo_rows(f, int(t))
+        soff = off[:, 0] + Bx * (off[:, 1] + By * off[:, 2])
+        base = f.slice_ptr[t]
+        for lane in range(64):
+            l0, l1, l2 = lane % T0, (lane // T0) % T1, lane // (T0 * T1)
+            my = (l0 + R) + Bx * ((l1 + R) + By * ((l2 + R) if s.dim == 3 else 0))
+            assert rows[my] == t * 64 + lane
+            for k in range(int(s.n_stencil)):
+                wd = f.words[base + (k // 4) * 256 + lane * 4 + (k % 4)]
+                slot = my + soff[k]
+                assert 0 <= slot < Bx * By * Bz
+                if (wd & 127) != 127:
+                    assert (wd & 127) == k
+                    assert rows[slot] == (wd >> 7)
+            for k in range(int(s.n_stencil), L4):
+                assert (f.words[base + (k // 4) * 256 + lane * 4 + (k % 4)] & 127) == 127
+
+
 def test_internal_order_is_tile_major(lib):
     w = W.impact3d(nx=16, ny=16, nz=8, dt=1e-7)
     f = _family(w)
@@ -130,7 +188,7 @@ def test_bsr_pattern_is_two_hop_closure(lib):
                                                      rp.ctypes.data_as(C.c_void_p),
                                                      col.ctypes.data_as(C.c_void_p)))
         total = 0
-        for r in range(n):
+        for r in np.nonzero(f.perm >= 0)[0]:
             p = f.perm[r]
             want = set(adj[p])
             for j in adj[p]:
@@ -186,13 +244,18 @@ def test_table1_node_counts_vertex_lattice_plus_three_layers():
     """Node counts of the 2D cantilever grids (Sec. 4.1 table): a vertex
     lattice of the 48 x 12 m beam plus 3 constrained layers beyond the
     clamped end; and 386,984 nodes for the 3D beam (48 x 12 x 5 m)."""
+    import json
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))
+    t1 = gold["table1_cantilever_2d"]
     counts = []
-    for delta in (2.4, 1.2, 0.6, 0.3, 0.15, 0.075):
+    for delta in t1["horizon_m"]:
         dx = delta / 3
-        counts.append((round(48 / dx) + 1 + 3) * (round(12 / dx) + 1))
-    assert counts == [1024, 3844, 14884, 58564, 232324, 925444]
-    dx = 0.2
-    assert (round(48 / dx) + 1 + 3) * (round(12 / dx) + 1) * (round(5 / dx) + 1) == 386984
+        counts.append((round(t1["beam_m"]["L"] / dx) + 1 + 3) * (round(t1["beam_m"]["H"] / dx) + 1))
+    assert counts == t1["nodes"]
+    c3 = gold["cantilever_3d_nodes"]
+    dx = c3["dx_m"]
+    b = c3["beam_m"]
+    assert (round(b["L"] / dx) + 1 + 3) * (round(b["H"] / dx) + 1) * (round(b["W"] / dx) + 1) == c3["value"]
 
 
 def test_workload_sizes():

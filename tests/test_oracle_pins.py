@@ -42,9 +42,13 @@ def small_box(shape, dx=1e-3, mode=None, E=70e9, nu=0.25, rho=2000.0, delta_rati
 
 def test_bond_count_10x10_mratio3():
     """Sec. 3.3: a 10x10 2D grid with m-ratio 3 has 1058 bonds."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    want = gold["bond_count_10x10_mratio3"]["value"]
     w = small_box((10, 10), dx=1.0, delta_ratio=3.0)
-    assert Oracle(w).nb == 1058
-    assert Oracle(w, search="cells").nb == 1058
+    assert Oracle(w).nb == want
+    assert Oracle(w, search="cells").nb == want
 
 
 @pytest.mark.parametrize("shape,count", [((15, 15), 28), ((15, 15, 15), 122)])
