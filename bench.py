@@ -137,6 +137,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the run, launch a plain read+write kernel over this many MiB (a known-size "
+                         "reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -223,6 +226,15 @@ def main():
         out["fp32_speedup_vs_fp64"] = value / out["fp64"]["value"]
     del s
     torch.cuda.empty_cache()
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        out["copy_reference_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -177,6 +177,10 @@ typedef struct pd_family_host {
     int32_t *tile_org;    /* [n_tiles*4] lattice origin x,y,z of each tile, specimen */
     int32_t *tile_nbr;    /* [n_tiles*27] tile at offset (dx,dy,dz) in {-1,0,1}^3,
                              index (dz+1)*9 + (dy+1)*3 + (dx+1); -1 if absent        */
+    uint32_t *ktab;       /* [128*8] per-entry table of the LDS-staged kernels: words
+                             0-3 M1, M2, M3, x as float, word 4 the int32 offset of
+                             the entry's neighbour in the tile's LDS halo box, words
+                             5-7 x M1, x M2, x M3 as float; all zero beyond n_stencil */
 } pd_family_host;
 
 /* Horizon search and bond-list construction (Sec. 2.1 family; Eqs. 1.2-1.5,
@@ -224,6 +228,7 @@ typedef struct pd_problem_dev {
     const int32_t *tile_nbr;    /* [device] n_slices*27 neighbour tiles            */
     int32_t tile[3];            /* tile edge lengths (pd_family_sizes.tile)        */
     int32_t reach;              /* pd_family_sizes.reach                           */
+    const uint32_t *ktab;       /* [device] 128*8 words, pd_family_host.ktab       */
 } pd_problem_dev;
 
 /* Device control block (step counter, diagnostics).  Size in bytes: */
@@ -238,6 +243,8 @@ typedef struct pd_state_dev {
     int32_t *ush[2];    /* n_pad*4 fixed-point displacement shadow (FP32 path)      */
     float *qr32;        /* n_pad*2 (theta/m, 1/m) in FP32 (FP32 path)               */
     double *dsum;       /* n_pad*4 sum over intact bonds of x M V_j (FP32 path)      */
+    float *fe32;        /* n_pad*4 deviatoric part of the pair force of the step,
+                           carried from pass 1 to pass 2 (FP32 LDS-staged path)      */
     void *ctl;          /* PD_CTL_BYTES control block                               */
     int32_t cur;        /* index of uv (and ush) holding the current state          */
     int32_t pad0;
@@ -311,6 +318,29 @@ typedef struct pd_profile_stats {
 
 /* Read (and with reset != 0 clear) the context's accumulated timings. */
 pd_status pd_profile_read(pd_ctx *ctx, pd_profile_stats *out, int32_t reset);
+
+/* Launch-shape tuning of the matrix-free step.  Candidates: for
+ * PD_FP32_RECHECK the LDS-staged tile kernels (when the family allows them)
+ * and the gather kernels at 64, 128 and 256 threads per block; for PD_FP64
+ * the gather kernels at the three block sizes.  Each candidate runs 2
+ * untimed and 'trial_steps' timed steps (HIP events on the stream) on the
+ * given state, which therefore advances by 3 + trial_steps per candidate
+ * (reset it afterwards).  Results are bitwise independent of the block size
+ * in FP64; the tile and gather kernels differ in the order of the float
+ * sums.  out->kernel / out->block are the pd_step_opts values to use. */
+typedef struct pd_tune_result {
+    int32_t kernel;            /* best pd_step_opts.kernel                        */
+    int32_t block;             /* best pd_step_opts.block                         */
+    int32_t n_candidates;
+    int32_t pad0;
+    double ms_per_step;        /* best time                                       */
+    int32_t cand_kernel[8];
+    int32_t cand_block[8];
+    double cand_ms[8];         /* time per step of each candidate                 */
+} pd_tune_result;
+
+pd_status pd_autotune(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, int32_t precision,
+                      int32_t trial_steps, pd_tune_result *out);
 
 typedef struct pd_step_report {
     int64_t step;           /* step counter after the call                           */

@@ -39,7 +39,7 @@ class pd_family_sizes(C.Structure):
 class pd_family_host(C.Structure):
     _fields_ = [("perm", P), ("row_of", P), ("slice_ptr", P), ("words", P), ("mask", P), ("stencil", P),
                 ("stencil_off", P), ("vol", P), ("inv_m", P), ("spec", P), ("lat4", P), ("tile_org", P),
-                ("tile_nbr", P)]
+                ("tile_nbr", P), ("ktab", P)]
 
 
 class pd_spec(C.Structure):
@@ -51,12 +51,13 @@ class pd_problem_dev(C.Structure):
     _fields_ = [("n_pad", i64), ("n_slices", i64), ("dim", i32), ("n_stencil", i32),
                 ("n_specimens", i32), ("pad0", i32), ("slice_ptr", P), ("words", P), ("stencil", P),
                 ("vol", P), ("inv_m", P), ("lat4", P), ("spec", P), ("aux", P), ("fext", P),
-                ("ramp_steps", i64), ("stencil_off", P), ("tile_nbr", P), ("tile", i32 * 3), ("reach", i32)]
+                ("ramp_steps", i64), ("stencil_off", P), ("tile_nbr", P), ("tile", i32 * 3), ("reach", i32),
+                ("ktab", P)]
 
 
 class pd_state_dev(C.Structure):
     _fields_ = [("uv", P * 2), ("vel", P), ("qr", P), ("mask", P), ("ush", P * 2), ("qr32", P),
-                ("dsum", P), ("ctl", P), ("cur", i32), ("pad0", i32)]
+                ("dsum", P), ("fe32", P), ("ctl", P), ("cur", i32), ("pad0", i32)]
 
 
 class pd_step_opts(C.Structure):
@@ -66,6 +67,11 @@ class pd_step_opts(C.Structure):
 
 class pd_profile_stats(C.Structure):
     _fields_ = [("steps", i64), ("ms_pass1", dbl), ("ms_pass2", dbl), ("ms_extra", dbl)]
+
+
+class pd_tune_result(C.Structure):
+    _fields_ = [("kernel", i32), ("block", i32), ("n_candidates", i32), ("pad0", i32), ("ms_per_step", dbl),
+                ("cand_kernel", i32 * 8), ("cand_block", i32 * 8), ("cand_ms", dbl * 8)]
 
 
 class pd_step_report(C.Structure):
@@ -90,6 +96,8 @@ SIGNATURES = {
     "pd_ctx_destroy": (i32, [P]),
     "pd_last_error": (C.c_char_p, [P]),
     "pd_profile_read": (i32, [P, C.POINTER(pd_profile_stats), i32]),
+    "pd_autotune": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i32, i32,
+                          C.POINTER(pd_tune_result)]),
     "pd_critical_stretch": (i32, [i32, dbl, dbl, dbl, dbl, i32, C.POINTER(dbl)]),
     "pd_specimen_params": (i32, [i32, dbl, dbl, dbl, dbl, dbl, C.POINTER(pd_spec)]),
     "pd_build_family": (i32, [C.POINTER(pd_body), P, i32, C.POINTER(pd_family_sizes),

@@ -83,10 +83,12 @@ pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
     a.ush[1] = reinterpret_cast<int4 *>(st->ush[1]);
     a.qr32 = reinterpret_cast<float2 *>(st->qr32);
     a.dsum = reinterpret_cast<double4 *>(st->dsum);
+    a.fe32 = reinterpret_cast<float4 *>(st->fe32);
     a.stencil_off = p->stencil_off;
     a.tile_nbr = p->tile_nbr;
     for (int c = 0; c < 3; c++) a.tile[c] = p->tile[c];
     a.reach = p->reach;
+    a.ktab = p->ktab;
     return a;
 }
 
@@ -95,8 +97,8 @@ pd_status check_state(pd_ctx *c, const pd_state_dev *st, bool need_f32) {
     if (!st->uv[0] || !st->uv[1] || !st->vel || !st->qr || !st->mask || !st->ctl)
         return fail(c, PD_ERR_ARG, "state has a NULL array");
     if (st->cur != 0 && st->cur != 1) return fail(c, PD_ERR_ARG, "state cur must be 0 or 1");
-    if (need_f32 && (!st->ush[0] || !st->ush[1] || !st->qr32 || !st->dsum))
-        return fail(c, PD_ERR_ARG, "FP32 path needs ush[0], ush[1], qr32 and dsum");
+    if (need_f32 && (!st->ush[0] || !st->ush[1] || !st->qr32 || !st->dsum || !st->fe32))
+        return fail(c, PD_ERR_ARG, "FP32 path needs ush[0], ush[1], qr32, dsum and fe32");
     return PD_OK;
 }
 
@@ -500,6 +502,68 @@ pd_status pd_bsr_apply(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *K, 
     pdk::StepArgs a = make_args(p, st);
     a.f_out = reinterpret_cast<double4 *>(f);
     HIP_TRY(c, pdk::launch_bsr_spmv(a, p, K, st->cur, false, c->stream));
+    return PD_OK;
+}
+
+pd_status pd_autotune(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int32_t precision, int32_t trial_steps,
+                      pd_tune_result *out) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if (precision != PD_FP64 && precision != PD_FP32_RECHECK) return fail(c, PD_ERR_ARG, "unknown precision");
+    if ((s = check_state(c, st, precision == PD_FP32_RECHECK)) != PD_OK) return s;
+    if (!out || trial_steps < 1 || trial_steps > 10000) return fail(c, PD_ERR_ARG, "bad tuning arguments");
+    if (!p->aux || !p->fext) return fail(c, PD_ERR_ARG, "aux/fext are NULL (call pd_state_init first)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    std::memset(out, 0, sizeof(*out));
+    int nc = 0;
+    int ck[8], cb[8];
+    {
+        pdk::StepArgs a = make_args(p, st);
+        if (precision == PD_FP32_RECHECK && pdk::tiled_supported(a)) {
+            ck[nc] = 2;
+            cb[nc++] = 0;
+        }
+    }
+    for (int b : {64, 128, 256}) {
+        ck[nc] = precision == PD_FP32_RECHECK ? 1 : 0;
+        cb[nc++] = b;
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    double best = 1e300;
+    for (int i = 0; i < nc; i++) {
+        pd_step_opts o{};
+        o.precision = precision;
+        o.form = PD_MATRIX_FREE;
+        o.kernel = ck[i];
+        o.block = cb[i];
+        s = pd_step(c, p, st, 2, &o, nullptr, nullptr);
+        if (s == PD_OK && hipEventRecord(e0, c->stream) != hipSuccess) s = PD_ERR_HIP;
+        if (s == PD_OK) s = pd_step(c, p, st, trial_steps, &o, nullptr, nullptr);
+        if (s == PD_OK && hipEventRecord(e1, c->stream) != hipSuccess) s = PD_ERR_HIP;
+        float ms = 0.0f;
+        if (s == PD_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            s = PD_ERR_HIP;
+        if (s != PD_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return s;
+        }
+        out->cand_kernel[i] = ck[i];
+        out->cand_block[i] = cb[i];
+        out->cand_ms[i] = (double)ms / trial_steps;
+        if (out->cand_ms[i] < best) {
+            best = out->cand_ms[i];
+            out->kernel = ck[i];
+            out->block = cb[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    out->n_candidates = nc;
+    out->ms_per_step = best;
     return PD_OK;
 }
 

@@ -369,18 +369,32 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
     if (!out) return PD_OK;
     if (!out->perm || !out->row_of || !out->slice_ptr || !out->words || !out->mask || !out->stencil ||
         !out->stencil_off || !out->vol || !out->inv_m || !out->spec || !out->lat4 || !out->tile_org ||
-        !out->tile_nbr)
+        !out->tile_nbr || !out->ktab)
         return PD_ERR_ARG;
 
     for (int64_t r = 0; r < n_pad; r++) out->perm[r] = (int32_t)node_of_row[r];
     for (int64_t p = 0; p < n; p++) out->row_of[p] = row_of[p];
     for (int64_t s = 0; s <= n_slices; s++) out->slice_ptr[s] = s * 64 * L4;
+    int32_t box[3];
+    pd_tile_box(T, reach, dim, box);
+    for (int q = 0; q < 8 * 128; q++) out->ktab[q] = 0u;
+    auto fbits = [](double v) {
+        const float f = (float)v;
+        uint32_t b;
+        std::memcpy(&b, &f, 4);
+        return b;
+    };
     for (int s = 0; s < ns; s++) {
         for (int c = 0; c < 3; c++) {
             out->stencil[4 * s + c] = st[s].M[c];
+            out->ktab[8 * s + c] = fbits(st[s].M[c]);
             out->stencil_off[3 * s + c] = st[s].off[c];
         }
         out->stencil[4 * s + 3] = st[s].x;
+        out->ktab[8 * s + 3] = fbits(st[s].x);
+        const int32_t so = st[s].off[0] + box[0] * (st[s].off[1] + box[1] * st[s].off[2]);
+        out->ktab[8 * s + 4] = (uint32_t)so;
+        for (int c = 0; c < 3; c++) out->ktab[8 * s + 5 + c] = fbits(st[s].x * st[s].M[c]);
     }
     parallel_for(n_slices, [&](int64_t a, int64_t b) {
         for (int64_t sl = a; sl < b; sl++) {

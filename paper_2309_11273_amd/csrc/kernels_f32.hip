@@ -105,16 +105,25 @@ __global__ void k_zero_umax(pd_ctl *ctl, int k) {
     if (threadIdx.x == 0) ctl->umax_bits[k] = 0u;
 }
 
+// grid-stride maximum: one block maximum (and at most one atomic) per block
 __global__ __launch_bounds__(256) void k_umax(int64_t n_pad, const double4 *uv, pd_ctl *ctl, int k) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float wm[4];
     float m = 0.0f;
-    if (r < n_pad) {
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n_pad; r += (int64_t)gridDim.x * 256) {
         const double4 u = uv[r];
-        m = (float)fmax(fabs(u.x), fmax(fabs(u.y), fabs(u.z)));
+        float v = (float)fmax(fabs(u.x), fmax(fabs(u.y), fabs(u.z)));
         // round up so that the float bound is not below the double value
-        m = __uint_as_float(__float_as_uint(m) + 1u);
+        v = __uint_as_float(__float_as_uint(v) + 1u);
+        m = fmaxf(m, v);
     }
-    wave_max_atomic(m, &ctl->umax_bits[k]);
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+        const unsigned int bits = __float_as_uint(m);
+        if (bits > __atomic_load_n(&ctl->umax_bits[k], __ATOMIC_RELAXED)) atomicMax(&ctl->umax_bits[k], bits);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_shadow_write(int64_t n_pad, const double4 *uv, int4 *ush, pd_ctl *ctl,
@@ -436,9 +445,11 @@ __global__ __launch_bounds__(256) void k_pass2_f32(StepArgs a, int cur) {
 hipError_t launch_shadow_prep(const StepArgs &a, int cur, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_umax, dim3(1), dim3(64), 0, s, a.ctl, cur);
     const int64_t nb = (a.n_pad + 255) / 256;
-    hipLaunchKernelGGL(k_umax, dim3((unsigned)nb), dim3(256), 0, s, a.n_pad, a.uv[cur], a.ctl, cur);
+    hipLaunchKernelGGL(k_umax, dim3((unsigned)(nb < 1024 ? nb : 1024)), dim3(256), 0, s, a.n_pad, a.uv[cur], a.ctl,
+                       cur);
     hipLaunchKernelGGL(k_shadow_write, dim3((unsigned)nb), dim3(256), 0, s, a.n_pad, a.uv[cur], a.ush[cur], a.ctl,
                        cur);
+    if (tiled_supported(a)) return launch_tdsum(a, cur, s);
     const dim3 g((unsigned)((a.n_slices + 3) / 4));
     if (a.dim == 3) hipLaunchKernelGGL((k_dsum<3>), g, dim3(256), 0, s, a, cur);
     else hipLaunchKernelGGL((k_dsum<2>), g, dim3(256), 0, s, a, cur);

@@ -6,23 +6,36 @@
 // the tile sits on local lattice position (l % T0, (l / T0) % T1,
 // l / (T0 T1)).  Bond k of every row is stencil entry k.  A workgroup of
 // four waves takes one tile:
-//   1. stages the fixed-point displacement shadow (and, in pass 2, theta/m
-//      and 1/m) of the tile plus an R-wide halo -- a (T0+2R)(T1+2R)(T2+2R)
-//      box gathered from the tile and its 3^dim neighbour tiles -- into LDS;
-//   2. every wave sweeps a quarter of the stencil for all 64 rows: the
-//      neighbour of row l through stencil entry k is LDS slot
-//      slot(l) + soff[k], with soff[k] the same for every lane, and the bond
-//      geometry (M Q, x) is one broadcast LDS read per k;
+//   1. stages what the pass needs of the tile plus an R-wide halo -- a box
+//      gathered from the tile and its 3^dim neighbour tiles -- into LDS
+//      (pass 1: the fixed-point displacement shadow, V and G Q V / m; pass 2:
+//      (K - G/3) theta/m and V), all of a thread's slot loads issued before
+//      any is consumed, together with the tile's bond-status words;
+//   2. every wave sweeps a quarter of the stencil for all 64 rows, four
+//      entries at a time: the neighbour of row l through entry k is LDS slot
+//      slot(l) + soff[k], soff[k] the same for every lane, and the float bond
+//      geometry, soff and status word of entry k are wave-uniform (scalar)
+//      values, the status word used directly as the lane mask;
 //   3. the four partial sums of each row are added in wave order and wave 0
 //      writes the row's result (and, in pass 2, the explicit update).
-// The arithmetic per bond is that of the gather kernels of kernels_f32.hip
-// (same shadow, same error band, same double recheck of near-threshold
-// bonds and same difference form of the dilatation term); only the source
-// of the neighbour data changes: LDS instead of L2 gathers, and no bond
-// word stream (the word is read only on the rare fallback paths).
+//
+// The arithmetic follows the gather kernels of kernels_f32.hip (same
+// fixed-point shadow and error band, same double recheck of near-threshold
+// bonds, same difference form of the dilatation term) with the shadow scale
+// Q factored out of the per-bond work: the float extension is carried in
+// units of Q, e' = M . (s_j - s_i), and Q enters once per row (the breaking
+// threshold becomes s_c x / Q, the deviatoric modulus G Q), and with the
+// pair force split between the passes: pass 1, which has the extension,
+// sums the deviatoric part; pass 2 only the dilatational part.  Rows next
+// to a shadow sentinel (a displacement too large for the fixed-point range)
+// take the double gather path bond by bond; the per-bond test is compiled
+// only into the sweep used when the tile's halo holds a sentinel.  Every row
+// of a tile belongs to one specimen, so the material constants are
+// wave-uniform and folded into the staged values.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -30,6 +43,14 @@ namespace pdk {
 
 #define PD_SENTINEL_T ((int)0x80000000)
 #define PD_TILE_WAVES 4
+#define PD_TILE_THREADS (64 * PD_TILE_WAVES)
+
+// one row of the per-entry table (pd_family_host.ktab)
+struct KEnt {
+    float m0, m1, m2, x;
+    int soff, z0, z1, z2;
+};
+static_assert(sizeof(KEnt) == 32, "ktab row is 8 words");
 
 __device__ __forceinline__ double ext_canonical_t(double m1, double m2, double m3, double e1, double e2,
                                                   double e3) {
@@ -56,29 +77,56 @@ __device__ __forceinline__ int quantise_t(double u, double invQ, bool &bad) {
     return (int)rint(t);
 }
 
-struct TileShape {
-    int T0, T1, T2, R, Bx, By, Bz, nslot;
-};
-
-template <int DIM>
-__device__ __forceinline__ TileShape tile_shape(const StepArgs &a) {
-    TileShape t;
-    t.T0 = a.tile[0];
-    t.T1 = a.tile[1];
-    t.T2 = a.tile[2];
-    t.R = a.reach;
-    t.Bx = t.T0 + 2 * t.R;
-    t.By = t.T1 + 2 * t.R;
-    t.Bz = DIM == 3 ? t.T2 + 2 * t.R : 1;
-    t.nslot = t.Bx * t.By * t.Bz;
-    return t;
+__device__ __forceinline__ uint64_t uni64_t(uint64_t v) {
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// global row of halo slot s of tile 'tile' (-1: no tile there)
+// lane's bit of a wave-uniform 64-bit word, used as the condition mask as is
+__device__ __forceinline__ bool lane_bit(uint64_t uniform_word) {
+    return __builtin_amdgcn_inverse_ballot_w64(uniform_word);
+}
+
+// specimen of a tile: every row of a tile belongs to one specimen, padding
+// rows carry id 0
+__device__ __forceinline__ uint32_t tile_specimen(uint32_t aux) {
+    const uint64_t b = __ballot((aux >> 8) != 0u);
+    return b ? ((uint32_t)__builtin_amdgcn_readlane((int)aux, (int)__builtin_ctzll(b)) >> 8) : 0u;
+}
+
+struct Box {
+    int T0, T1, T2, R, Bx, By, nslot;
+    float iBx, iBy;
+};
+
+__device__ __forceinline__ Box make_box(const StepArgs &a, int dim) {
+    Box b;
+    int32_t B[3];
+    pd_tile_box(a.tile, a.reach, dim, B);
+    b.T0 = a.tile[0];
+    b.T1 = a.tile[1];
+    b.T2 = a.tile[2];
+    b.R = a.reach;
+    b.Bx = B[0];
+    b.By = B[1];
+    b.nslot = B[0] * B[1] * B[2];
+    b.iBx = 1.0f / (float)B[0];
+    b.iBy = 1.0f / (float)B[1];
+    return b;
+}
+
+// floor(s / d) for 0 <= s < 2^16, d <= 64: the float quotient of s + 1/2 is
+// at least 1/(2d) away from an integer and its rounding error is below 1e-4/d
+__device__ __forceinline__ int small_div(int s, float inv_d) { return (int)(((float)s + 0.5f) * inv_d); }
+
+// global row of halo slot s (-1: no tile there, or x-pitch padding)
 template <int DIM>
-__device__ __forceinline__ int64_t halo_row(const TileShape &g, const int32_t *tn, int s) {
-    const int bx = s % g.Bx, byz = s / g.Bx, by = byz % g.By, bz = byz / g.By;
+__device__ __forceinline__ int64_t halo_row(const Box &g, const int *tn, int s) {
+    const int q = small_div(s, g.iBx), bx = s - q * g.Bx;
+    const int bz = DIM == 3 ? small_div(q, g.iBy) : 0, by = q - bz * g.By;
     const int p0 = bx - g.R, p1 = by - g.R, p2 = DIM == 3 ? bz - g.R : 0;
+    if (p0 >= g.T0 + g.R) return -1;
     const int d0 = p0 < 0 ? -1 : (p0 >= g.T0 ? 1 : 0);
     const int d1 = p1 < 0 ? -1 : (p1 >= g.T1 ? 1 : 0);
     const int d2 = DIM == 3 ? (p2 < 0 ? -1 : (p2 >= g.T2 ? 1 : 0)) : 0;
@@ -87,51 +135,76 @@ __device__ __forceinline__ int64_t halo_row(const TileShape &g, const int32_t *t
     return (int64_t)nt * 64 + (p0 - d0 * g.T0) + g.T0 * ((p1 - d1 * g.T1) + g.T1 * (p2 - d2 * g.T2));
 }
 
-__device__ __forceinline__ void stage_tables(const StepArgs &a, const TileShape &g, double Q, float4 *sst, int *soff,
-                                             uint64_t *smask, int64_t mbase, int L4) {
-    for (int s = threadIdx.x; s < 128; s += blockDim.x) {
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        int o = 0;
-        if (s < a.n_stencil) {
-            v = make_float4((float)(a.stencil[4 * s] * Q), (float)(a.stencil[4 * s + 1] * Q),
-                            (float)(a.stencil[4 * s + 2] * Q), (float)a.stencil[4 * s + 3]);
-            const int *so = a.stencil_off + 3 * s;
-            o = so[0] + g.Bx * (so[1] + g.By * so[2]);
-        }
-        sst[s] = v;
-        soff[s] = o;
-    }
-    for (int k = threadIdx.x; k < L4; k += blockDim.x) smask[k] = a.mask[mbase + k];
-}
+// slots per thread staged at once: 1280 slots in 3D, 512 in 2D
+template <int DIM>
+struct StageCap {
+    static constexpr int value = DIM == 3 ? 5 : 2;
+};
 
 // ---------------------------------------------------------------------------
-// pass 1: breaking (with double recheck) and dilatation
+// pass 1: breaking (with double recheck), dilatation, deviatoric pair force
 // ---------------------------------------------------------------------------
+// The pair force of Eq. 2.2 is the sum of a dilatational part,
+// (K - G/3) x (q_i + q_j) M V_i V_j, which needs the dilatation of both ends
+// and is summed in pass 2, and a deviatoric part, G e (1/m_i + 1/m_j) M V_i V_j,
+// which needs only the extension and the bond status after this step's
+// breaking, and is summed here where e is at hand (fe32, without the V_i).
 template <int DIM, bool BREAK>
-__global__ __launch_bounds__(256) void k_tpass1_f32(StepArgs a, int cur) {
+__global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int cur,
+                                                                const KEnt *__restrict__ kt) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const TileShape g = tile_shape<DIM>(a);
+    constexpr int MS = StageCap<DIM>::value;
+    const Box g = make_box(a, DIM);
     const int64_t tile = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
-    int4 *halo = reinterpret_cast<int4 *>(smem);
-    float4 *sst = reinterpret_cast<float4 *>(halo + g.nslot);
-    int *soff = reinterpret_cast<int *>(sst + 128);
-    uint64_t *smask = reinterpret_cast<uint64_t *>(soff + 128);
-    float *red = reinterpret_cast<float *>(smask + L4);
+    int4 *halo = reinterpret_cast<int4 *>(smem);                 // shadow, V bits
+    float *hrv = reinterpret_cast<float *>(halo + g.nslot);      // G Q V_j / m_j
+    uint64_t *smask = reinterpret_cast<uint64_t *>(hrv + ((g.nslot + 1) & ~1));
+    float *red = reinterpret_cast<float *>(smask + 128);
+    int *stn = reinterpret_cast<int *>(red + 4 * PD_TILE_WAVES * 64);
     pd_ctl *ctl = a.ctl;
     const double Q = ctl->qs[cur];
     const int4 *__restrict__ sh = a.ush[cur];
+    const float2 *__restrict__ qr = a.qr32;
     const double4 *__restrict__ uv = a.uv[cur];
     const double4 *__restrict__ sten = reinterpret_cast<const double4 *>(a.stencil);
-    stage_tables(a, g, Q, sst, soff, smask, base >> 6, L4);
-    const int32_t *tn = a.tile_nbr + 27 * tile;
-    for (int s = tid; s < g.nslot; s += blockDim.x) {
-        const int64_t r = halo_row<DIM>(g, tn, s);
-        halo[s] = r >= 0 ? sh[r] : make_int4(0, 0, 0, 0);
-    }
+    uint64_t *mrow = a.mask + (base >> 6);
+    const int64_t row = tile * 64 + lane;
+    if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
+    const uint64_t mword = tid < L4 ? mrow[tid] : 0ull;
+    const pd_spec sp = a.spec[tile_specimen(a.aux[row])];
+    const float GQ = (float)(sp.G * Q);  // extension carried in units of Q
     __syncthreads();
+    bool sent = false;
+    {
+        int64_t rw[MS];
+        int4 v[MS];
+        float r[MS];
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            const int s = tid + i * PD_TILE_THREADS;
+            rw[i] = s < g.nslot ? halo_row<DIM>(g, stn, s) : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            v[i] = rw[i] >= 0 ? sh[rw[i]] : make_int4(0, 0, 0, 0);
+            r[i] = rw[i] >= 0 ? qr[rw[i]].y : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            const int s = tid + i * PD_TILE_THREADS;
+            if (s < g.nslot) {
+                halo[s] = v[i];
+                hrv[s] = GQ * r[i] * __int_as_float(v[i].w);
+                sent |= v[i].x == PD_SENTINEL_T;
+            }
+        }
+    }
+    if (tid < 128) smask[tid] = mword;
+    const bool anysent = __syncthreads_or(sent);
     if (BREAK && tile == 0 && tid == 0) {
         ctl->s1 = ctl->s2;
         ctl->qs[cur ^ 1] = shadow_scale_t(ctl->umax_bits[cur]);
@@ -139,83 +212,114 @@ __global__ __launch_bounds__(256) void k_tpass1_f32(StepArgs a, int cur) {
     }
     const int l0 = lane % g.T0, l1 = (lane / g.T0) % g.T1, l2 = lane / (g.T0 * g.T1);
     const int my = (l0 + g.R) + g.Bx * ((l1 + g.R) + g.By * (DIM == 3 ? l2 + g.R : 0));
-    const int64_t row = tile * 64 + lane;
     const int4 si = halo[my];
-    const uint32_t aux = a.aux[row];
-    const pd_spec sp = a.spec[aux >> 8];
+    const float ri = qr[row].y;
+    const float rpi = GQ * ri;
     const double s0 = sp.s0;
-    const float s0f = (float)s0 * (1.0f - 1e-6f);
-    const float Qf = (float)Q;
-    const float band0 = Qf * 1.7320509f;
-    const float band1 = Qf * 9.5367432e-7f;  // 2^-20
-    const int ns = a.n_stencil;
-    const int kper = (ns + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
-    const int k0 = wv * kper, k1 = min(ns, k0 + kper);
-    float acc = 0.0f;
+    // breaking threshold in units of Q, widened by the float rounding of the test
+    const float thrQ = (float)(s0 / Q) * (1.0f - 1e-6f);
+    const int G4 = L4 >> 2;
+    const int gper = (G4 + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
+    const int g0 = wv * gper, g1 = min(G4, g0 + gper);
+    float acc = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
     uint32_t nbroken = 0, nrecheck = 0, nfall = 0;
     double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
-    for (int k = k0; k < k1; k++) {
-        const uint64_t m64 = smask[k];
-        if (m64 == 0) continue;
-        const int4 sj = halo[my + soff[k]];
-        const float4 st = sst[k];
-        bool intact = (m64 >> lane) & 1ull;
-        bool broke = false;
-        float e;
-        if (__builtin_expect(si.x == PD_SENTINEL_T || sj.x == PD_SENTINEL_T, 0)) {
-            e = 0.0f;
-            const uint32_t w = a.words[pd_widx(base, k, lane)];
-            if ((w & 127u) != PD_PAD_ID) {
-                const double4 ui = uv[row], uj = uv[w >> 7];
-                const double4 sd = sten[k];
-                const double e64 = ext_canonical_t(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, uj.x - ui.x, uj.y - ui.y,
-                                                   DIM == 3 ? uj.z - ui.z : 0.0);
-                if (intact) nfall++;
-                if (BREAK && intact && e64 / sd.w >= s0) {
-                    intact = false;
-                    broke = true;
-                    const double xv = sd.w * uj.w;
-                    dd0 += xv * sd.x;
-                    dd1 += xv * sd.y;
-                    dd2 += xv * sd.z;
-                }
-                e = (float)e64;
+
+    // double decision for bond k of this row: breaks it (and takes it out of
+    // the row's intact x M V sum) when its stretch reaches s_c
+    auto recheck = [&](int k, bool &intact, bool &broke, double &e64) {
+        const uint32_t w = a.words[pd_widx(base, k, lane)];
+        const double4 ui = uv[row], uj = uv[w >> 7];
+        const double4 sd = sten[k];
+        e64 = ext_canonical_t(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, uj.x - ui.x, uj.y - ui.y,
+                              DIM == 3 ? uj.z - ui.z : 0.0);
+        if (BREAK && intact && e64 / sd.w >= s0) {
+            intact = false;
+            broke = true;
+            const double xv = sd.w * uj.w;
+            dd0 += xv * sd.x;
+            dd1 += xv * sd.y;
+            dd2 += xv * sd.z;
+        }
+    };
+
+    auto sweep = [&](auto chk) {
+        constexpr bool CHK = decltype(chk)::value;
+        KEnt en[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) en[c] = kt[4 * g0 + c];
+        for (int gg = g0; gg < g1; gg++) {
+            KEnt e[4];
+            int4 sj[4];
+            float rvj[4];
+            uint64_t mm[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                e[c] = en[c];
+                sj[c] = halo[my + e[c].soff];
+                rvj[c] = hrv[my + e[c].soff];
+                mm[c] = uni64_t(smask[4 * gg + c]);
             }
-        } else {
-            const float fdx = (float)(sj.x - si.x), fdy = (float)(sj.y - si.y);
-            const float fdz = DIM == 3 ? (float)(sj.z - si.z) : 0.0f;
-            e = st.x * fdx + st.y * fdy;
-            if (DIM == 3) e += st.z * fdz;
-            if (BREAK && intact) {
-                const float band = band0 + band1 * (fabsf(fdx) + fabsf(fdy) + fabsf(fdz));
-                if (e + band >= s0f * st.w) {
-                    const uint32_t w = a.words[pd_widx(base, k, lane)];
-                    const double4 ui = uv[row], uj = uv[w >> 7];
-                    const double4 sd = sten[k];
-                    const double e64 = ext_canonical_t(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, uj.x - ui.x,
-                                                       uj.y - ui.y, DIM == 3 ? uj.z - ui.z : 0.0);
-                    nrecheck++;
-                    if (e64 / sd.w >= s0) {
-                        intact = false;
-                        broke = true;
-                        const double xv = sd.w * uj.w;
-                        dd0 += xv * sd.x;
-                        dd1 += xv * sd.y;
-                        dd2 += xv * sd.z;
+            // next group's table rows (row index stays inside the 128-row table)
+            const int gn = min(gg + 1, 31);
+#pragma unroll
+            for (int c = 0; c < 4; c++) en[c] = kt[4 * gn + c];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int k = 4 * gg + c;
+                bool intact = lane_bit(mm[c]);
+                bool broke = false;
+                float ev;
+                if (CHK && (si.x == PD_SENTINEL_T || sj[c].x == PD_SENTINEL_T)) {
+                    ev = 0.0f;
+                    if (intact) {
+                        double e64;
+                        recheck(k, intact, broke, e64);
+                        nfall++;
+                        ev = (float)(e64 / Q);
+                    }
+                } else {
+                    const float fdx = (float)(sj[c].x - si.x), fdy = (float)(sj[c].y - si.y);
+                    const float fdz = DIM == 3 ? (float)(sj[c].z - si.z) : 0.0f;
+                    ev = e[c].m0 * fdx + e[c].m1 * fdy;
+                    if (DIM == 3) ev += e[c].m2 * fdz;
+                    if (BREAK) {
+                        // |ev - e64 / Q| <= sqrt(3) + 2^-20 sum |d|: recheck when
+                        // ev + that bound reaches the threshold
+                        const float lim = thrQ * e[c].x - 1.7320509f;
+                        const float sd = fabsf(fdx) + fabsf(fdy) + fabsf(fdz);
+                        if (intact && fmaf(9.5367432e-7f, sd, ev) >= lim) {
+                            double e64;
+                            recheck(k, intact, broke, e64);
+                            nrecheck++;
+                        }
                     }
                 }
+                if (BREAK) {
+                    const uint64_t bb = __ballot(broke);
+                    if (bb) {
+                        if (lane == 0) mrow[k] = mm[c] & ~bb;
+                        nbroken += __popcll(bb);
+                    }
+                }
+                const float Vj = __int_as_float(sj[c].w);
+                // dilatation: x V_j e;  deviatoric force: G e (1/m_i + 1/m_j) V_j
+                const float xv = e[c].x * Vj;
+                acc = fmaf(intact ? xv : 0.0f, ev, acc);
+                const float te = intact ? ev * fmaf(rpi, Vj, rvj[c]) : 0.0f;
+                fx = fmaf(te, e[c].m0, fx);
+                fy = fmaf(te, e[c].m1, fy);
+                if (DIM == 3) fz = fmaf(te, e[c].m2, fz);
             }
         }
-        if (BREAK) {
-            const uint64_t bb = __ballot(broke);
-            if (bb) {
-                if (lane == 0) a.mask[(base >> 6) + k] = m64 & ~bb;
-                nbroken += __popcll(bb);
-            }
-        }
-        if (intact) acc += st.w * __int_as_float(sj.w) * e;
-    }
-    red[wv * 64 + lane] = acc;
+    };
+    if (anysent) sweep(std::true_type{});
+    else sweep(std::false_type{});
+
+    red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = acc;
+    red[(1 * PD_TILE_WAVES + wv) * 64 + lane] = fx;
+    red[(2 * PD_TILE_WAVES + wv) * 64 + lane] = fy;
+    red[(3 * PD_TILE_WAVES + wv) * 64 + lane] = fz;
     if (BREAK) {
         if (dd0 != 0.0 || dd1 != 0.0 || dd2 != 0.0) {
             double *D = reinterpret_cast<double *>(a.dsum + row);
@@ -234,93 +338,103 @@ __global__ __launch_bounds__(256) void k_tpass1_f32(StepArgs a, int cur) {
     }
     __syncthreads();
     if (wv != 0) return;
-    float tot = red[lane];
-    for (int q = 1; q < PD_TILE_WAVES; q++) tot += red[q * 64 + lane];
-    const float2 qri = a.qr32[row];
-    const double acc64 = (double)tot;
-    a.qr32[row].x = (float)((double)sp.A * (double)qri.y * (double)qri.y * acc64);
-    if (a.theta_out) a.theta_out[row] = (double)sp.A * (double)qri.y * acc64;
+    float tot[4];
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        tot[v] = red[v * PD_TILE_WAVES * 64 + lane];
+        for (int q = 1; q < PD_TILE_WAVES; q++) tot[v] += red[(v * PD_TILE_WAVES + q) * 64 + lane];
+    }
+    // theta_i / m_i = A r_i^2 Q sum_j x V_j e'_j
+    const double accQ = (double)tot[0] * Q;
+    a.qr32[row].x = (float)((double)sp.A * (double)ri * (double)ri * accQ);
+    if (a.theta_out) a.theta_out[row] = (double)sp.A * (double)ri * accQ;
+    a.fe32[row] = make_float4(tot[1], tot[2], tot[3], 0.0f);
 }
 
 // ---------------------------------------------------------------------------
-// pass 2: pair force, explicit update, next shadow
+// pass 2: dilatational pair force, explicit update, next shadow
 // ---------------------------------------------------------------------------
 template <int DIM, bool UPDATE>
-__global__ __launch_bounds__(256) void k_tpass2_f32(StepArgs a, int cur) {
+__global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int cur,
+                                                                const KEnt *__restrict__ kt,
+                                                                const uint64_t *__restrict__ kmask) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const TileShape g = tile_shape<DIM>(a);
+    constexpr int MS = StageCap<DIM>::value;
+    const Box g = make_box(a, DIM);
     const int64_t tile = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
-    int4 *halo = reinterpret_cast<int4 *>(smem);
-    float2 *hqr = reinterpret_cast<float2 *>(halo + g.nslot);
-    float4 *sst = reinterpret_cast<float4 *>(hqr + ((g.nslot + 1) & ~1));
-    int *soff = reinterpret_cast<int *>(sst + 128);
-    uint64_t *smask = reinterpret_cast<uint64_t *>(soff + 128);
-    float *red = reinterpret_cast<float *>(smask + L4);
+    float2 *hq = reinterpret_cast<float2 *>(smem);  // ((K - G/3) theta_j/m_j, V_j)
+    uint64_t *smask = reinterpret_cast<uint64_t *>(hq + ((g.nslot + 1) & ~1));
+    float *red = reinterpret_cast<float *>(smask + 128);
+    int *stn = reinterpret_cast<int *>(red + 3 * PD_TILE_WAVES * 64);
     pd_ctl *ctl = a.ctl;
-    const double Q = ctl->qs[cur];
     const int4 *__restrict__ sh = a.ush[cur];
-    const double4 *__restrict__ uv = a.uv[cur];
     const float2 *__restrict__ qr = a.qr32;
-    const double4 *__restrict__ sten = reinterpret_cast<const double4 *>(a.stencil);
-    stage_tables(a, g, Q, sst, soff, smask, base >> 6, L4);
-    const int32_t *tn = a.tile_nbr + 27 * tile;
-    for (int s = tid; s < g.nslot; s += blockDim.x) {
-        const int64_t r = halo_row<DIM>(g, tn, s);
-        if (r >= 0) {
-            halo[s] = sh[r];
-            hqr[s] = qr[r];
-        } else {
-            halo[s] = make_int4(0, 0, 0, 0);
-            hqr[s] = make_float2(0.f, 0.f);
+    const int64_t row = tile * 64 + lane;
+    const uint32_t aux = a.aux[row];
+    if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
+    const uint64_t mword = tid < L4 ? kmask[(base >> 6) + tid] : 0ull;
+    const pd_spec sp = a.spec[tile_specimen(aux)];
+    const float kp = (float)sp.kp;
+    __syncthreads();
+    {
+        int64_t rw[MS];
+        float q[MS];
+        int vb[MS];
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            const int s = tid + i * PD_TILE_THREADS;
+            rw[i] = s < g.nslot ? halo_row<DIM>(g, stn, s) : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            q[i] = rw[i] >= 0 ? qr[rw[i]].x : 0.0f;
+            vb[i] = rw[i] >= 0 ? sh[rw[i]].w : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            const int s = tid + i * PD_TILE_THREADS;
+            if (s < g.nslot) hq[s] = make_float2(kp * q[i], __int_as_float(vb[i]));
         }
     }
+    if (tid < 128) smask[tid] = mword;
     __syncthreads();
     const int l0 = lane % g.T0, l1 = (lane / g.T0) % g.T1, l2 = lane / (g.T0 * g.T1);
     const int my = (l0 + g.R) + g.Bx * ((l1 + g.R) + g.By * (DIM == 3 ? l2 + g.R : 0));
-    const int64_t row = tile * 64 + lane;
-    const int4 si = halo[my];
-    const float2 qri = hqr[my];
-    const uint32_t aux = a.aux[row];
-    const pd_spec sp = a.spec[aux >> 8];
-    const float kp = (float)sp.kp, G = (float)sp.G;
-    const int ns = a.n_stencil;
-    const int kper = (ns + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
-    const int k0 = wv * kper, k1 = min(ns, k0 + kper);
+    const float qi = hq[my].x;
+    const int G4 = L4 >> 2;
+    const int gper = (G4 + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
+    const int g0 = wv * gper, g1 = min(G4, g0 + gper);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int k = k0; k < k1; k++) {
-        const uint64_t m64 = smask[k];
-        if (m64 == 0) continue;
-        const int slot = my + soff[k];
-        const int4 sj = halo[slot];
-        const float2 qrj = hqr[slot];
-        const float4 st = sst[k];
-        float e, Vj;
-        if (__builtin_expect(si.x == PD_SENTINEL_T || sj.x == PD_SENTINEL_T, 0)) {
-            e = 0.0f;
-            Vj = 0.0f;
-            const uint32_t w = a.words[pd_widx(base, k, lane)];
-            if ((w & 127u) != PD_PAD_ID) {
-                const double4 ui = uv[row], uj = uv[w >> 7];
-                const double4 sd = sten[k];
-                double e64 = sd.x * (uj.x - ui.x) + sd.y * (uj.y - ui.y);
-                if (DIM == 3) e64 += sd.z * (uj.z - ui.z);
-                e = (float)e64;
-                Vj = (float)uj.w;
+    {
+        KEnt en[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) en[c] = kt[4 * g0 + c];
+        for (int gg = g0; gg < g1; gg++) {
+            KEnt e[4];
+            float2 qj[4];
+            uint64_t mm[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                e[c] = en[c];
+                qj[c] = hq[my + e[c].soff];
+                mm[c] = uni64_t(smask[4 * gg + c]);
             }
-        } else {
-            e = st.x * (float)(sj.x - si.x) + st.y * (float)(sj.y - si.y);
-            if (DIM == 3) e += st.z * (float)(sj.z - si.z);
-            Vj = __int_as_float(sj.w);
-        }
-        // [(K - G/3) x (q_j - q_i) + G e (1/m_i + 1/m_j)] V_j, q = theta/m
-        const float t = (kp * st.w * (qrj.x - qri.x) + G * e * (qri.y + qrj.y)) * Vj;
-        if ((m64 >> lane) & 1ull) {
-            fx += t * st.x;
-            fy += t * st.y;
-            if (DIM == 3) fz += t * st.z;
+            const int gn = min(gg + 1, 31);
+#pragma unroll
+            for (int c = 0; c < 4; c++) en[c] = kt[4 * gn + c];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                // (K - G/3) (q_j - q_i) V_j, times x M from the table
+                float t = (qj[c].x - qi) * qj[c].y;
+                t = lane_bit(mm[c]) ? t : 0.0f;
+                fx = fmaf(t, __int_as_float(e[c].z0), fx);
+                fy = fmaf(t, __int_as_float(e[c].z1), fy);
+                if (DIM == 3) fz = fmaf(t, __int_as_float(e[c].z2), fz);
+            }
         }
     }
     red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = fx;
@@ -334,13 +448,15 @@ __global__ __launch_bounds__(256) void k_tpass2_f32(StepArgs a, int cur) {
         sy += red[(PD_TILE_WAVES + q) * 64 + lane];
         sz += red[(2 * PD_TILE_WAVES + q) * 64 + lane];
     }
-    const double4 ui = uv[row];
+    const double4 ui = a.uv[cur][row];
     const double4 D = a.dsum[row];
-    const double invQ = 1.0 / Q;
-    const double c2 = 2.0 * sp.kp * (double)qri.x;
-    double Fx = ((double)sx * invQ + c2 * D.x) * ui.w;
-    double Fy = ((double)sy * invQ + c2 * D.y) * ui.w;
-    double Fz = ((double)sz * invQ + c2 * D.z) * ui.w;
+    const float4 fe = a.fe32[row];
+    // dilatational sum in difference form plus its row constant 2 (K - G/3) q_i D_i,
+    // deviatoric sum from pass 1; all times V_i
+    const double c2 = 2.0 * (double)qi;
+    double Fx = ((double)sx + (double)fe.x + c2 * D.x) * ui.w;
+    double Fy = ((double)sy + (double)fe.y + c2 * D.y) * ui.w;
+    double Fz = ((double)sz + (double)fe.z + c2 * D.z) * ui.w;
     if (!UPDATE) {
         a.f_out[row] = make_double4(Fx, Fy, Fz, 0.0);
         return;
@@ -351,10 +467,10 @@ __global__ __launch_bounds__(256) void k_tpass2_f32(StepArgs a, int cur) {
     double r = 1.0;
     if (a.ramp_steps > 0) r = n >= a.ramp_steps ? 1.0 : (double)n / (double)a.ramp_steps;
     if (aux & 8u) {
-        const double4 fe = a.fext[row];
-        Fx += fe.x * r;
-        Fy += fe.y * r;
-        Fz += fe.z * r;
+        const double4 fx4 = a.fext[row];
+        Fx += fx4.x * r;
+        Fy += fx4.y * r;
+        Fz += fx4.z * r;
     }
     const double mass = sp.rho * ui.w;
     double4 v = a.vel[row];
@@ -376,7 +492,7 @@ __global__ __launch_bounds__(256) void k_tpass2_f32(StepArgs a, int cur) {
     s.x = quantise_t(u.x, invQn, bad);
     s.y = quantise_t(u.y, invQn, bad);
     s.z = quantise_t(u.z, invQn, bad);
-    s.w = si.w;
+    s.w = __float_as_int((float)ui.w);
     if (bad) s.x = PD_SENTINEL_T;
     a.ush[cur ^ 1][row] = s;
     float m = (float)fmax(fabs(u.x), fmax(fabs(u.y), fabs(u.z)));
@@ -391,49 +507,145 @@ __global__ __launch_bounds__(256) void k_tpass2_f32(StepArgs a, int cur) {
     if (__ballot(bad) && lane == 0) atomicOr(&ctl->flags, PD_CTL_FALLBACK);
 }
 
+// ---------------------------------------------------------------------------
+// D_i = sum over intact bonds of x M V_j (double precision), the row constant
+// of the difference form of the dilatation term
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(PD_TILE_THREADS) void k_tdsum(StepArgs a, int cur, const KEnt *__restrict__ kt,
+                                                           const double4 *__restrict__ sten) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int MS = StageCap<DIM>::value;
+    const Box g = make_box(a, DIM);
+    const int64_t tile = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t base = a.slice_ptr[tile];
+    const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
+    double *hv = reinterpret_cast<double *>(smem);
+    uint64_t *smask = reinterpret_cast<uint64_t *>(hv + g.nslot);
+    double *red = reinterpret_cast<double *>(smask + 128);
+    int *stn = reinterpret_cast<int *>(red + 3 * PD_TILE_WAVES * 64);
+    const double4 *__restrict__ uv = a.uv[cur];
+    if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
+    const uint64_t mword = tid < L4 ? a.mask[(base >> 6) + tid] : 0ull;
+    __syncthreads();
+    {
+        int64_t rw[MS];
+        double v[MS];
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            const int s = tid + i * PD_TILE_THREADS;
+            rw[i] = s < g.nslot ? halo_row<DIM>(g, stn, s) : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < MS; i++) v[i] = rw[i] >= 0 ? uv[rw[i]].w : 0.0;
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            const int s = tid + i * PD_TILE_THREADS;
+            if (s < g.nslot) hv[s] = v[i];
+        }
+    }
+    if (tid < 128) smask[tid] = mword;
+    __syncthreads();
+    const int l0 = lane % g.T0, l1 = (lane / g.T0) % g.T1, l2 = lane / (g.T0 * g.T1);
+    const int my = (l0 + g.R) + g.Bx * ((l1 + g.R) + g.By * (DIM == 3 ? l2 + g.R : 0));
+    const int G4 = L4 >> 2;
+    const int gper = (G4 + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
+    const int g0 = wv * gper, g1 = min(G4, g0 + gper);
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    const int ns = a.n_stencil;
+    for (int k = 4 * g0; k < 4 * g1; k++) {
+        const double Vj = hv[my + kt[k].soff];
+        const double4 sd = sten[min(k, ns - 1)];  // entries past n_stencil are padding (status bits 0)
+        const double xv = lane_bit(uni64_t(smask[k])) ? sd.w * Vj : 0.0;
+        d0 += xv * sd.x;
+        d1 += xv * sd.y;
+        if (DIM == 3) d2 += xv * sd.z;
+    }
+    red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = d0;
+    red[(1 * PD_TILE_WAVES + wv) * 64 + lane] = d1;
+    red[(2 * PD_TILE_WAVES + wv) * 64 + lane] = d2;
+    __syncthreads();
+    if (wv != 0) return;
+    double s0 = red[lane], s1 = red[PD_TILE_WAVES * 64 + lane], s2 = red[2 * PD_TILE_WAVES * 64 + lane];
+    for (int q = 1; q < PD_TILE_WAVES; q++) {
+        s0 += red[q * 64 + lane];
+        s1 += red[(PD_TILE_WAVES + q) * 64 + lane];
+        s2 += red[(2 * PD_TILE_WAVES + q) * 64 + lane];
+    }
+    a.dsum[tile * 64 + lane] = make_double4(s0, s1, s2, 0.0);
+}
+
+static size_t tdsum_lds(const StepArgs &a) {
+    int32_t B[3];
+    pd_tile_box(a.tile, a.reach, a.dim, B);
+    const size_t nslot = (size_t)B[0] * B[1] * B[2];
+    return nslot * sizeof(double) + 128 * sizeof(uint64_t) + 3 * PD_TILE_WAVES * 64 * sizeof(double) +
+           32 * sizeof(int);
+}
+
+hipError_t launch_tdsum(const StepArgs &a, int cur, hipStream_t s) {
+    const dim3 g((unsigned)a.n_slices), b(PD_TILE_THREADS);
+    const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
+    const double4 *sten = reinterpret_cast<const double4 *>(a.stencil);
+    if (a.dim == 3) hipLaunchKernelGGL((k_tdsum<3>), g, b, tdsum_lds(a), s, a, cur, kt, sten);
+    else hipLaunchKernelGGL((k_tdsum<2>), g, b, tdsum_lds(a), s, a, cur, kt, sten);
+    return hipGetLastError();
+}
+
 static size_t tiled_lds(const StepArgs &a, int pass) {
-    const int Bx = a.tile[0] + 2 * a.reach, By = a.tile[1] + 2 * a.reach;
-    const int Bz = a.dim == 3 ? a.tile[2] + 2 * a.reach : 1;
-    const size_t nslot = (size_t)Bx * By * Bz;
-    const size_t L4 = (size_t)((a.n_stencil + 3) / 4 * 4);
-    size_t b = nslot * sizeof(int4);
-    if (pass == 2) b += ((nslot + 1) & ~(size_t)1) * sizeof(float2);
-    b += 128 * sizeof(float4) + 128 * sizeof(int) + L4 * sizeof(uint64_t);
-    b += (pass == 2 ? 3 : 1) * PD_TILE_WAVES * 64 * sizeof(float);
-    return b;
+    int32_t B[3];
+    pd_tile_box(a.tile, a.reach, a.dim, B);
+    const size_t nslot = (size_t)B[0] * B[1] * B[2], nslot2 = (nslot + 1) & ~(size_t)1;
+    size_t b;
+    if (pass == 1)
+        b = nslot * sizeof(int4) + nslot2 * sizeof(float) + 4 * PD_TILE_WAVES * 64 * sizeof(float);
+    else
+        b = nslot2 * sizeof(float2) + 3 * PD_TILE_WAVES * 64 * sizeof(float);
+    return b + 128 * sizeof(uint64_t) + 32 * sizeof(int);
 }
 
 bool tiled_supported(const StepArgs &a) {
-    if (!a.tile_nbr || !a.stencil_off) return false;
+    if (!a.tile_nbr || !a.ktab) return false;
     if (a.tile[0] * a.tile[1] * a.tile[2] != 64) return false;
     if (a.reach < 1 || a.tile[0] < a.reach || a.tile[1] < a.reach) return false;
     if (a.dim == 3 && a.tile[2] < a.reach) return false;
     if (a.dim == 2 && a.tile[2] != 1) return false;
-    return tiled_lds(a, 2) <= 64 * 1024;
+    if (a.n_stencil > 124) return false;  // groups of four inside the 128-row table
+    int32_t B[3];
+    pd_tile_box(a.tile, a.reach, a.dim, B);
+    if (B[0] > 64 || B[1] > 64) return false;  // small_div range
+    const int cap = (a.dim == 3 ? StageCap<3>::value : StageCap<2>::value) * PD_TILE_THREADS;
+    if (B[0] * B[1] * B[2] > cap) return false;
+    return tiled_lds(a, 1) <= 64 * 1024 && tiled_lds(a, 2) <= 64 * 1024;
 }
 
 hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s) {
     const size_t lds = tiled_lds(a, 1);
-    const dim3 g((unsigned)a.n_slices), b(64 * PD_TILE_WAVES);
+    const dim3 g((unsigned)a.n_slices), b(PD_TILE_THREADS);
+    const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     if (a.dim == 3) {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true>), g, b, lds, s, a, cur);
-        else hipLaunchKernelGGL((k_tpass1_f32<3, false>), g, b, lds, s, a, cur);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true>), g, b, lds, s, a, cur, kt);
+        else hipLaunchKernelGGL((k_tpass1_f32<3, false>), g, b, lds, s, a, cur, kt);
     } else {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f32<2, true>), g, b, lds, s, a, cur);
-        else hipLaunchKernelGGL((k_tpass1_f32<2, false>), g, b, lds, s, a, cur);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f32<2, true>), g, b, lds, s, a, cur, kt);
+        else hipLaunchKernelGGL((k_tpass1_f32<2, false>), g, b, lds, s, a, cur, kt);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_tpass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s) {
     const size_t lds = tiled_lds(a, 2);
-    const dim3 g((unsigned)a.n_slices), b(64 * PD_TILE_WAVES);
+    const dim3 g((unsigned)a.n_slices), b(PD_TILE_THREADS);
+    const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
+    const uint64_t *km = a.mask;
     if (a.dim == 3) {
-        if (update) hipLaunchKernelGGL((k_tpass2_f32<3, true>), g, b, lds, s, a, cur);
-        else hipLaunchKernelGGL((k_tpass2_f32<3, false>), g, b, lds, s, a, cur);
+        if (update) hipLaunchKernelGGL((k_tpass2_f32<3, true>), g, b, lds, s, a, cur, kt, km);
+        else hipLaunchKernelGGL((k_tpass2_f32<3, false>), g, b, lds, s, a, cur, kt, km);
     } else {
-        if (update) hipLaunchKernelGGL((k_tpass2_f32<2, true>), g, b, lds, s, a, cur);
-        else hipLaunchKernelGGL((k_tpass2_f32<2, false>), g, b, lds, s, a, cur);
+        if (update) hipLaunchKernelGGL((k_tpass2_f32<2, true>), g, b, lds, s, a, cur, kt, km);
+        else hipLaunchKernelGGL((k_tpass2_f32<2, false>), g, b, lds, s, a, cur, kt, km);
     }
     return hipGetLastError();
 }

@@ -45,3 +45,14 @@ static_assert(sizeof(pd_ctl) <= PD_CTL_BYTES, "control block too large");
 PD_HD inline int64_t pd_widx(int64_t base, int64_t k, int lane) {
     return base + ((k >> 2) << 8) + ((int64_t)lane << 2) + (k & 3);
 }
+
+// LDS halo box of a 64-point tile T[0] x T[1] x T[2] with reach R: the tile
+// plus R lattice points on every side, x fastest.  In 3D with 4-wide tiles
+// the x pitch is padded up to 4 mod 8 so that the 16 lanes of a quarter wave
+// (4 x-positions, 4 y-positions) fall on distinct 16-byte LDS bank groups.
+PD_HD inline void pd_tile_box(const int32_t *T, int R, int dim, int32_t *B) {
+    B[0] = T[0] + 2 * R;
+    if (dim == 3 && T[0] == 4) B[0] += (12 - B[0] % 8) % 8;
+    B[1] = T[1] + 2 * R;
+    B[2] = dim == 3 ? T[2] + 2 * R : 1;
+}

@@ -106,10 +106,11 @@ class FamilyHost:
         self.lat4 = np.empty(s.n_pad * 4, np.int32)
         self.tile_org = np.empty(s.n_tiles * 4, np.int32)
         self.tile_nbr = np.empty(s.n_tiles * 27, np.int32)
+        self.ktab = np.empty(128 * 8, np.uint32)
         hb = A.pd_family_host(_np(self.perm), _np(self.row_of), _np(self.slice_ptr), _np(self.words),
                               _np(self.mask), _np(self.stencil), _np(self.stencil_off), _np(self.vol),
                               _np(self.inv_m), _np(self.spec), _np(self.lat4), _np(self.tile_org),
-                              _np(self.tile_nbr))
+                              _np(self.tile_nbr), _np(self.ktab))
         self._hb = hb
         A.check("pd_build_family", L.pd_build_family(C.byref(body), C.cast(carr, C.c_void_p), len(cuts),
                                                      C.byref(sizes), C.byref(hb)))
@@ -213,6 +214,8 @@ class Solver:
         self.stencil_off = t(self.fam.stencil_off)
         self.tile_nbr = t(self.fam.tile_nbr)
         P.stencil_off, P.tile_nbr = _tp(self.stencil_off), _tp(self.tile_nbr)
+        self.ktab = t(self.fam.ktab.view(np.int32))
+        P.ktab = _tp(self.ktab)
         for c in range(3):
             P.tile[c] = int(s.tile[c])
         P.reach = int(s.reach)
@@ -226,6 +229,7 @@ class Solver:
             if fp32_state else [None, None]
         self.qr32 = torch.zeros(self.n_pad * 2, dtype=torch.float32, device=d) if fp32_state else None
         self.dsum = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=d) if fp32_state else None
+        self.fe32 = torch.zeros(self.n_pad * 4, dtype=torch.float32, device=d) if fp32_state else None
         self.ctl = torch.zeros(A.PD_CTL_BYTES // 8, dtype=torch.int64, device=d)
         S = A.pd_state_dev()
         S.uv[0], S.uv[1] = self.uv[0].data_ptr(), self.uv[1].data_ptr()
@@ -234,6 +238,7 @@ class Solver:
             S.ush[0], S.ush[1] = self.ush[0].data_ptr(), self.ush[1].data_ptr()
             S.qr32 = _tp(self.qr32)
             S.dsum = _tp(self.dsum)
+            S.fe32 = _tp(self.fe32)
         S.ctl = _tp(self.ctl)
         S.cur = 0
         self.S = S
@@ -306,6 +311,37 @@ class Solver:
                                                        _tp(f), _tp(th)))
         torch.cuda.synchronize(self.dev)
         return self._to_caller(f), self._rows_to_caller(th)
+
+    def autotune(self, precision: str = "fp32", trial_steps: int = 20, cache: Optional[str] = None) -> dict:
+        """Pick the fastest kernel variant / block size (pd_autotune).  With a
+        cache path, results are stored in a JSON file keyed by
+        (gfx arch, dim, tile shape, stencil size, precision) and reused.
+        Tuning advances the state; the state is reset afterwards."""
+        import json
+        import os
+        s = self.fam.sizes
+        key = f"gfx950/d{int(s.dim)}/t{'x'.join(str(int(v)) for v in s.tile)}/s{int(s.n_stencil)}/{precision}"
+        data = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                data = json.load(f)
+            if key in data:
+                return data[key]
+        r = A.pd_tune_result()
+        prec = {"fp64": A.PD_FP64, "fp32": A.PD_FP32_RECHECK}[precision]
+        self.ctx.check("pd_autotune", A.load().pd_autotune(self.ctx.h, C.byref(self.P), C.byref(self.S), prec,
+                                                             int(trial_steps), C.byref(r)))
+        res = dict(kernel={0: "auto", 1: "gather", 2: "tiled"}[r.kernel], block=int(r.block),
+                   ms_per_step=r.ms_per_step,
+                   candidates=[dict(kernel=int(r.cand_kernel[i]), block=int(r.cand_block[i]),
+                                    ms=r.cand_ms[i]) for i in range(r.n_candidates)])
+        self.reset()
+        if cache:
+            data[key] = res
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(data, f, indent=1)
+        return res
 
     def tiled_supported(self) -> bool:
         """Whether the LDS-staged tile kernels apply (tile edges >= stencil reach)."""

@@ -157,3 +157,18 @@ def test_full_size_short_run(ctx, name, steps):
     o.run(steps, uo, vo)
     assert rel(u, uo) <= 1e-4
     assert np.array_equal(s.bond_status()[2], o.rho())
+
+
+def test_autotune_picks_a_measured_candidate(ctx, tmp_path):
+    w = W.impact3d(nx=36, ny=36, nz=9, dt=2.6e-7, steps=50)
+    s = solver(w, ctx)
+    cache = str(tmp_path / "tune.json")
+    r = s.autotune("fp32", trial_steps=5, cache=cache)
+    ms = [c["ms"] for c in r["candidates"]]
+    assert len(ms) == 4 and min(ms) == r["ms_per_step"]
+    assert r["kernel"] in ("tiled", "gather")
+    # cached result is reused and the state was reset
+    assert s.autotune("fp32", trial_steps=5, cache=cache) == r
+    assert s.step_count() == 0
+    r64 = s.autotune("fp64", trial_steps=5)
+    assert r64["block"] in (64, 128, 256)

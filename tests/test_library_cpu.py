@@ -86,12 +86,15 @@ def test_family_matches_reference(lib, case):
 
 def _halo_rows(f, tile):
     """Emulation of the LDS-staged kernels' halo gather: global row of every
-    slot of the (T0+2R)(T1+2R)(T2+2R) box around 'tile' (-1 = no tile)."""
+    slot of the (T0+2R)(T1+2R)(T2+2R) box around 'tile' (-1 = no tile).  In
+    3D with 4-wide tiles the x pitch is padded up to 4 mod 8."""
     s = f.sizes
     T0, T1, T2 = list(s.tile)
     R = int(s.reach)
     dim = int(s.dim)
     Bx, By = T0 + 2 * R, T1 + 2 * R
+    if dim == 3 and T0 == 4:
+        Bx += (12 - Bx % 8) % 8
     Bz = T2 + 2 * R if dim == 3 else 1
     tn = f.tile_nbr[27 * tile: 27 * tile + 27]
     out = np.full(Bx * By * Bz, -1, np.int64)
@@ -99,6 +102,8 @@ def _halo_rows(f, tile):
         bx, byz = slot % Bx, slot // Bx
         by, bz = byz % By, byz // By
         p = [bx - R, by - R, (bz - R) if dim == 3 else 0]
+        if p[0] >= T0 + R:
+            continue
         T = [T0, T1, T2]
         d = [(-1 if p[c] < 0 else (1 if p[c] >= T[c] else 0)) for c in range(3)]
         nt = tn[(d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1)]
@@ -126,6 +131,13 @@ def test_tile_halo_addressing_matches_bond_words(lib, case):
     for t in tiles:
         rows, (Bx, By, Bz) = _halo_rows(f, int(t))
         soff = off[:, 0] + Bx * (off[:, 1] + By * off[:, 2])
+        kt = f.ktab.view(np.int32).reshape(128, 8)
+        assert np.array_equal(kt[: len(soff), 4], soff)
+        assert not kt[len(soff):].any()
+        ktf = f.ktab.view(np.float32).reshape(128, 8)
+        sten = f.stencil.reshape(-1, 4)
+        assert np.array_equal(ktf[: len(soff), :4], sten.astype(np.float32))
+        assert np.array_equal(ktf[: len(soff), 5:], (sten[:, 3:4] * sten[:, :3]).astype(np.float32))
         base = f.slice_ptr[t]
         for lane in range(64):
             l0, l1, l2 = lane % T0, (lane // T0) % T1, lane // (T0 * T1)
