@@ -156,7 +156,8 @@ typedef struct pd_family_sizes {
     int32_t tile[3];    /* tile edge lengths in lattice units (product 64)         */
     int32_t words_per_row; /* bond words per row = n_stencil rounded up to 4      */
     int32_t reach;      /* largest |component| of a stencil offset                 */
-    int32_t pad1;
+    int32_t n_halo;     /* slots of a tile's LDS halo box (tile + reach on every
+                           side, x pitch padded; see pd_family_host.halo_map)      */
 } pd_family_sizes;
 
 /* Output arrays of pd_build_family, all [host], allocated by the caller
@@ -181,6 +182,10 @@ typedef struct pd_family_host {
                              0-3 M1, M2, M3, x as float, word 4 the int32 offset of
                              the entry's neighbour in the tile's LDS halo box, words
                              5-7 x M1, x M2, x M3 as float; all zero beyond n_stencil */
+    int16_t *halo_map;    /* [n_halo] for slot s of the LDS halo box (x fastest):
+                             64 * d + l, the point at local position l of the
+                             neighbour tile in direction d (tile_nbr index), or -1
+                             for x-pitch padding; the same for every tile          */
 } pd_family_host;
 
 /* Horizon search and bond-list construction (Sec. 2.1 family; Eqs. 1.2-1.5,
@@ -229,6 +234,7 @@ typedef struct pd_problem_dev {
     int32_t tile[3];            /* tile edge lengths (pd_family_sizes.tile)        */
     int32_t reach;              /* pd_family_sizes.reach                           */
     const uint32_t *ktab;       /* [device] 128*8 words, pd_family_host.ktab       */
+    const int16_t *halo_map;    /* [device] n_halo, pd_family_host.halo_map        */
 } pd_problem_dev;
 
 /* Device control block (step counter, diagnostics).  Size in bytes: */
@@ -245,6 +251,8 @@ typedef struct pd_state_dev {
     double *dsum;       /* n_pad*4 sum over intact bonds of x M V_j (FP32 path)      */
     float *fe32;        /* n_pad*4 deviatoric part of the pair force of the step,
                            carried from pass 1 to pass 2 (FP32 LDS-staged path)      */
+    double *fe64;       /* n_pad*4 the same for the FP64 LDS-staged path (NULL: the
+                           FP64 path uses the gather kernels)                        */
     void *ctl;          /* PD_CTL_BYTES control block                               */
     int32_t cur;        /* index of uv (and ush) holding the current state          */
     int32_t pad0;
@@ -280,8 +288,8 @@ pd_status pd_get_step(pd_ctx *ctx, const pd_state_dev *st, int64_t *step);
  * (n_pad, dilatation of Eq. 1.6); theta may be NULL.  precision selects
  * the double kernels or the single-precision force kernels of the
  * FP32_RECHECK path (which then also rebuild the shadow state st->ush,
- * st->qr32 and st->dsum from the double displacement).  Uses st->qr (or
- * st->qr32) as scratch. */
+ * st->qr32 and st->dsum from the double displacement).  Uses st->qr and
+ * st->fe64 (or st->qr32 and st->fe32) as scratch. */
 pd_status pd_force(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, int32_t precision,
                    double *f, double *theta);
 
@@ -297,10 +305,10 @@ typedef struct pd_step_opts {
     int32_t check_every; /* >0: check the non-finite flag every this many steps (sync) */
     int32_t profile;     /* 1: time every kernel with HIP events on the stream (eager
                             launches, one synchronisation per step); see pd_profile_read */
-    int32_t kernel;      /* FP32 matrix-free kernels: 0 = LDS-staged tile kernels when
-                            the family allows them (tile edges >= stencil reach), else
-                            gather kernels; 1 = gather kernels; 2 = tile kernels (error
-                            if not possible)                                           */
+    int32_t kernel;      /* matrix-free kernels: 0 = LDS-staged tile kernels when the
+                            family allows them (tile edges >= stencil reach; FP64 also
+                            needs st->fe64), else gather kernels; 1 = gather kernels;
+                            2 = tile kernels (error if not possible)                   */
     int32_t pad1;
 } pd_step_opts;
 
@@ -319,15 +327,15 @@ typedef struct pd_profile_stats {
 /* Read (and with reset != 0 clear) the context's accumulated timings. */
 pd_status pd_profile_read(pd_ctx *ctx, pd_profile_stats *out, int32_t reset);
 
-/* Launch-shape tuning of the matrix-free step.  Candidates: for
- * PD_FP32_RECHECK the LDS-staged tile kernels (when the family allows them)
- * and the gather kernels at 64, 128 and 256 threads per block; for PD_FP64
- * the gather kernels at the three block sizes.  Each candidate runs 2
- * untimed and 'trial_steps' timed steps (HIP events on the stream) on the
- * given state, which therefore advances by 3 + trial_steps per candidate
- * (reset it afterwards).  Results are bitwise independent of the block size
- * in FP64; the tile and gather kernels differ in the order of the float
- * sums.  out->kernel / out->block are the pd_step_opts values to use. */
+/* Launch-shape tuning of the matrix-free step.  Candidates: the LDS-staged
+ * tile kernels (when the family allows them) and the gather kernels at 64,
+ * 128 and 256 threads per block, in the given precision.  Each candidate
+ * runs 2 untimed and 'trial_steps' timed steps (HIP events on the stream)
+ * on the given state, which therefore advances by 2 + trial_steps per
+ * candidate (reset it afterwards).  The gather kernels give results
+ * independent of the block size; tile and gather kernels differ in the
+ * order of the force sums.  out->kernel / out->block are the pd_step_opts
+ * values to use. */
 typedef struct pd_tune_result {
     int32_t kernel;            /* best pd_step_opts.kernel                        */
     int32_t block;             /* best pd_step_opts.block                         */

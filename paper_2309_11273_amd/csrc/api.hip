@@ -84,11 +84,13 @@ pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
     a.qr32 = reinterpret_cast<float2 *>(st->qr32);
     a.dsum = reinterpret_cast<double4 *>(st->dsum);
     a.fe32 = reinterpret_cast<float4 *>(st->fe32);
+    a.fe64 = reinterpret_cast<double4 *>(st->fe64);
     a.stencil_off = p->stencil_off;
     a.tile_nbr = p->tile_nbr;
     for (int c = 0; c < 3; c++) a.tile[c] = p->tile[c];
     a.reach = p->reach;
     a.ktab = p->ktab;
+    a.halo_map = p->halo_map;
     return a;
 }
 
@@ -292,9 +294,12 @@ pd_status pd_force(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int32_t
     a.f_out = reinterpret_cast<double4 *>(f);
     a.theta_out = theta;
     if (precision == PD_FP64) {
-        HIP_TRY(c, pdk::launch_pass1_f64(a, st->cur, false, 256, c->stream));
+        const bool tiled = pdk::tiled64_supported(a);
+        if (tiled) HIP_TRY(c, pdk::launch_tpass1_f64(a, st->cur, false, c->stream));
+        else HIP_TRY(c, pdk::launch_pass1_f64(a, st->cur, false, 256, c->stream));
         a.theta_out = nullptr;
-        HIP_TRY(c, pdk::launch_pass2_f64(a, st->cur, false, 256, c->stream));
+        if (tiled) HIP_TRY(c, pdk::launch_tpass2_f64(a, st->cur, false, c->stream));
+        else HIP_TRY(c, pdk::launch_pass2_f64(a, st->cur, false, 256, c->stream));
     } else {
         const bool tiled = pdk::tiled_supported(a);
         HIP_TRY(c, pdk::launch_shadow_prep(a, st->cur, c->stream));
@@ -322,17 +327,16 @@ static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, in
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
         if ((e = pdk::launch_bsr_spmv(a, p, K, cur, true, s)) != hipSuccess) return e;
     } else {
-        // FP32: LDS-staged tile kernels unless the gather kernels are asked for
-        const bool tiled = o.precision == PD_FP32_RECHECK && o.kernel != 1 && pdk::tiled_supported(a);
-        if (o.precision == PD_FP64) e = pdk::launch_pass1_f64(a, cur, true, block, s);
-        else if (tiled) e = pdk::launch_tpass1_f32(a, cur, true, s);
-        else e = pdk::launch_pass1_f32(a, cur, true, block, s);
+        // LDS-staged tile kernels unless the gather kernels are asked for
+        const bool fp64 = o.precision == PD_FP64;
+        const bool tiled = o.kernel != 1 && (fp64 ? pdk::tiled64_supported(a) : pdk::tiled_supported(a));
+        if (fp64) e = tiled ? pdk::launch_tpass1_f64(a, cur, true, s) : pdk::launch_pass1_f64(a, cur, true, block, s);
+        else e = tiled ? pdk::launch_tpass1_f32(a, cur, true, s) : pdk::launch_pass1_f32(a, cur, true, block, s);
         if (e != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-        if (o.precision == PD_FP64) e = pdk::launch_pass2_f64(a, cur, true, block, s);
-        else if (tiled) e = pdk::launch_tpass2_f32(a, cur, true, s);
-        else e = pdk::launch_pass2_f32(a, cur, true, block, s);
+        if (fp64) e = tiled ? pdk::launch_tpass2_f64(a, cur, true, s) : pdk::launch_pass2_f64(a, cur, true, block, s);
+        else e = tiled ? pdk::launch_tpass2_f32(a, cur, true, s) : pdk::launch_pass2_f32(a, cur, true, block, s);
         if (e != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
@@ -353,10 +357,12 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
     if (o.graph_chunk < 0 || o.check_every < 0) return fail(c, PD_ERR_ARG, "negative option");
     if (o.profile != 0 && o.profile != 1) return fail(c, PD_ERR_ARG, "profile must be 0 or 1");
     if (o.kernel < 0 || o.kernel > 2) return fail(c, PD_ERR_ARG, "kernel must be 0, 1 or 2");
-    if (o.kernel == 2 && o.precision == PD_FP32_RECHECK && o.form == PD_MATRIX_FREE) {
+    if (o.kernel == 2 && o.form == PD_MATRIX_FREE) {
         pd_state_dev tmp = *st;
-        if (!pdk::tiled_supported(make_args(p, &tmp)))
-            return fail(c, PD_ERR_UNSUPPORTED, "tile kernels need tile edges >= the stencil reach");
+        const pdk::StepArgs ta = make_args(p, &tmp);
+        if (o.precision == PD_FP32_RECHECK ? !pdk::tiled_supported(ta) : !pdk::tiled64_supported(ta))
+            return fail(c, PD_ERR_UNSUPPORTED,
+                        "tile kernels need tile edges >= the stencil reach (and fe64 for FP64)");
     }
     if (o.profile && !c->ev[0]) {
         for (int k = 0; k < 4; k++) HIP_TRY(c, hipEventCreate(&c->ev[k]));
@@ -391,7 +397,9 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
                                        (uint64_t)(uintptr_t)st->vel, (uint64_t)o.precision,
                                        (uint64_t)o.block, (uint64_t)cur, (uint64_t)chunk,
                                        (uint64_t)p->ramp_steps, (uint64_t)(uintptr_t)p->fext,
-                                       (uint64_t)(uintptr_t)st->qr};
+                                       (uint64_t)(uintptr_t)st->qr, (uint64_t)o.kernel, (uint64_t)o.form,
+                                       (uint64_t)(uintptr_t)st->fe32, (uint64_t)(uintptr_t)st->fe64,
+                                       (uint64_t)(uintptr_t)K};
             for (uint64_t f : fields) key = mix(key, f);
             if (!c->gexec || c->gkey != key) {
                 if (c->gexec) {
@@ -520,13 +528,13 @@ pd_status pd_autotune(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int3
     int ck[8], cb[8];
     {
         pdk::StepArgs a = make_args(p, st);
-        if (precision == PD_FP32_RECHECK && pdk::tiled_supported(a)) {
+        if (precision == PD_FP32_RECHECK ? pdk::tiled_supported(a) : pdk::tiled64_supported(a)) {
             ck[nc] = 2;
             cb[nc++] = 0;
         }
     }
     for (int b : {64, 128, 256}) {
-        ck[nc] = precision == PD_FP32_RECHECK ? 1 : 0;
+        ck[nc] = 1;
         cb[nc++] = b;
     }
     hipEvent_t e0, e1;

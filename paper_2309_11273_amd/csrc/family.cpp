@@ -365,11 +365,15 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
     for (int c = 0; c < 3; c++) sizes->tile[c] = T[c];
     sizes->words_per_row = L4;
     sizes->reach = reach;
-    sizes->pad1 = 0;
+    {
+        int32_t B[3];
+        pd_tile_box(T, reach, dim, B);
+        sizes->n_halo = B[0] * B[1] * B[2];
+    }
     if (!out) return PD_OK;
     if (!out->perm || !out->row_of || !out->slice_ptr || !out->words || !out->mask || !out->stencil ||
         !out->stencil_off || !out->vol || !out->inv_m || !out->spec || !out->lat4 || !out->tile_org ||
-        !out->tile_nbr || !out->ktab)
+        !out->tile_nbr || !out->ktab || !out->halo_map)
         return PD_ERR_ARG;
 
     for (int64_t r = 0; r < n_pad; r++) out->perm[r] = (int32_t)node_of_row[r];
@@ -377,6 +381,21 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
     for (int64_t s = 0; s <= n_slices; s++) out->slice_ptr[s] = s * 64 * L4;
     int32_t box[3];
     pd_tile_box(T, reach, dim, box);
+    for (int32_t s = 0; s < box[0] * box[1] * box[2]; s++) {
+        const int32_t b[3] = {s % box[0], (s / box[0]) % box[1], s / (box[0] * box[1])};
+        int32_t p[3], d[3];
+        for (int c = 0; c < 3; c++) {
+            p[c] = (c < dim) ? b[c] - reach : 0;
+            d[c] = p[c] < 0 ? -1 : (p[c] >= T[c] ? 1 : 0);
+        }
+        if (p[0] >= T[0] + reach) {
+            out->halo_map[s] = -1;  // pitch padding
+            continue;
+        }
+        const int32_t dir = (d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1);
+        const int32_t loc = (p[0] - d[0] * T[0]) + T[0] * ((p[1] - d[1] * T[1]) + T[1] * (p[2] - d[2] * T[2]));
+        out->halo_map[s] = (int16_t)(64 * dir + loc);
+    }
     for (int q = 0; q < 8 * 128; q++) out->ktab[q] = 0u;
     auto fbits = [](double v) {
         const float f = (float)v;

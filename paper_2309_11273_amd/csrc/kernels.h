@@ -31,6 +31,7 @@ struct StepArgs {
     float2 *qr32;
     double4 *dsum;
     float4 *fe32;
+    double4 *fe64;
     // BSR path
     uint32_t *dirty;
     // tile description (LDS-staged kernels)
@@ -39,6 +40,7 @@ struct StepArgs {
     int32_t tile[3];
     int32_t reach;
     const uint32_t *ktab;
+    const int16_t *halo_map;
 };
 
 struct InitArgs {
@@ -79,6 +81,9 @@ bool tiled_supported(const StepArgs &a);
 hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s);
 hipError_t launch_tpass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s);
 hipError_t launch_tdsum(const StepArgs &a, int cur, hipStream_t s);
+bool tiled64_supported(const StepArgs &a);
+hipError_t launch_tpass1_f64(const StepArgs &a, int cur, bool brk, hipStream_t s);
+hipError_t launch_tpass2_f64(const StepArgs &a, int cur, bool update, hipStream_t s);
 hipError_t launch_state_init(const InitArgs &a, hipStream_t s);
 hipError_t launch_state_read(const int32_t *perm, int64_t n_pad, const double4 *uv, const double4 *vel,
                              double *u_out, double *v_out, hipStream_t s);

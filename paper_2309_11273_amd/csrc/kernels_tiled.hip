@@ -38,108 +38,18 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "tile_common.h"
 
 namespace pdk {
 
-#define PD_SENTINEL_T ((int)0x80000000)
-#define PD_TILE_WAVES 4
-#define PD_TILE_THREADS (64 * PD_TILE_WAVES)
-
-// one row of the per-entry table (pd_family_host.ktab)
-struct KEnt {
-    float m0, m1, m2, x;
-    int soff, z0, z1, z2;
-};
-static_assert(sizeof(KEnt) == 32, "ktab row is 8 words");
-
-__device__ __forceinline__ double ext_canonical_t(double m1, double m2, double m3, double e1, double e2,
-                                                  double e3) {
-#pragma clang fp contract(off)
-    double a = m1 * e1;
-    double b = m2 * e2;
-    double c = m3 * e3;
-    return (a + b) + c;
+// bytes of the first LDS region of pass 1: the staged box (shadow + G Q V / m
+// per slot), or the partial sums (4 floats and 3 doubles per thread) that
+// replace it after the sweep, whichever is larger
+__host__ __device__ inline int tile1_region0(int nslot) {
+    const int box = nslot * 16 + ((nslot + 1) & ~1) * 4;
+    const int sums = PD_TILE_WAVES * 64 * (4 * 4 + 3 * 8);
+    return box > sums ? box : sums;
 }
-
-__device__ __forceinline__ double shadow_scale_t(unsigned int mbits) {
-    const float m = __uint_as_float(mbits);
-    if (!(m > 0.0f) || !isfinite(m)) return ldexp(1.0, -100);
-    const int e = ilogb((double)m);
-    return ldexp(1.0, max(e - 27, -100));
-}
-
-__device__ __forceinline__ int quantise_t(double u, double invQ, bool &bad) {
-    const double t = u * invQ;
-    if (!(fabs(t) < 1073741824.0)) {
-        bad = true;
-        return 0;
-    }
-    return (int)rint(t);
-}
-
-__device__ __forceinline__ uint64_t uni64_t(uint64_t v) {
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// lane's bit of a wave-uniform 64-bit word, used as the condition mask as is
-__device__ __forceinline__ bool lane_bit(uint64_t uniform_word) {
-    return __builtin_amdgcn_inverse_ballot_w64(uniform_word);
-}
-
-// specimen of a tile: every row of a tile belongs to one specimen, padding
-// rows carry id 0
-__device__ __forceinline__ uint32_t tile_specimen(uint32_t aux) {
-    const uint64_t b = __ballot((aux >> 8) != 0u);
-    return b ? ((uint32_t)__builtin_amdgcn_readlane((int)aux, (int)__builtin_ctzll(b)) >> 8) : 0u;
-}
-
-struct Box {
-    int T0, T1, T2, R, Bx, By, nslot;
-    float iBx, iBy;
-};
-
-__device__ __forceinline__ Box make_box(const StepArgs &a, int dim) {
-    Box b;
-    int32_t B[3];
-    pd_tile_box(a.tile, a.reach, dim, B);
-    b.T0 = a.tile[0];
-    b.T1 = a.tile[1];
-    b.T2 = a.tile[2];
-    b.R = a.reach;
-    b.Bx = B[0];
-    b.By = B[1];
-    b.nslot = B[0] * B[1] * B[2];
-    b.iBx = 1.0f / (float)B[0];
-    b.iBy = 1.0f / (float)B[1];
-    return b;
-}
-
-// floor(s / d) for 0 <= s < 2^16, d <= 64: the float quotient of s + 1/2 is
-// at least 1/(2d) away from an integer and its rounding error is below 1e-4/d
-__device__ __forceinline__ int small_div(int s, float inv_d) { return (int)(((float)s + 0.5f) * inv_d); }
-
-// global row of halo slot s (-1: no tile there, or x-pitch padding)
-template <int DIM>
-__device__ __forceinline__ int64_t halo_row(const Box &g, const int *tn, int s) {
-    const int q = small_div(s, g.iBx), bx = s - q * g.Bx;
-    const int bz = DIM == 3 ? small_div(q, g.iBy) : 0, by = q - bz * g.By;
-    const int p0 = bx - g.R, p1 = by - g.R, p2 = DIM == 3 ? bz - g.R : 0;
-    if (p0 >= g.T0 + g.R) return -1;
-    const int d0 = p0 < 0 ? -1 : (p0 >= g.T0 ? 1 : 0);
-    const int d1 = p1 < 0 ? -1 : (p1 >= g.T1 ? 1 : 0);
-    const int d2 = DIM == 3 ? (p2 < 0 ? -1 : (p2 >= g.T2 ? 1 : 0)) : 0;
-    const int nt = tn[(d2 + 1) * 9 + (d1 + 1) * 3 + (d0 + 1)];
-    if (nt < 0) return -1;
-    return (int64_t)nt * 64 + (p0 - d0 * g.T0) + g.T0 * ((p1 - d1 * g.T1) + g.T1 * (p2 - d2 * g.T2));
-}
-
-// slots per thread staged at once: 1280 slots in 3D, 512 in 2D
-template <int DIM>
-struct StageCap {
-    static constexpr int value = DIM == 3 ? 5 : 2;
-};
 
 // ---------------------------------------------------------------------------
 // pass 1: breaking (with double recheck), dilatation, deviatoric pair force
@@ -155,16 +65,16 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MS = StageCap<DIM>::value;
     const Box g = make_box(a, DIM);
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
+    // region 0: the staged box, reused for the partial sums after the sweep
     int4 *halo = reinterpret_cast<int4 *>(smem);                 // shadow, V bits
     float *hrv = reinterpret_cast<float *>(halo + g.nslot);      // G Q V_j / m_j
-    uint64_t *smask = reinterpret_cast<uint64_t *>(hrv + ((g.nslot + 1) & ~1));
-    float *red = reinterpret_cast<float *>(smask + 128);
-    int *stn = reinterpret_cast<int *>(red + 4 * PD_TILE_WAVES * 64);
+    uint64_t *smask = reinterpret_cast<uint64_t *>(smem + tile1_region0(g.nslot));
+    int *stn = reinterpret_cast<int *>(smask + 128);
     pd_ctl *ctl = a.ctl;
     const double Q = ctl->qs[cur];
     const int4 *__restrict__ sh = a.ush[cur];
@@ -173,6 +83,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     const double4 *__restrict__ sten = reinterpret_cast<const double4 *>(a.stencil);
     uint64_t *mrow = a.mask + (base >> 6);
     const int64_t row = tile * 64 + lane;
+    int hmv[MS];
+#pragma unroll
+    for (int i = 0; i < MS; i++) {
+        const int s = tid + i * PD_TILE_THREADS;
+        hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
+    }
     if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
     const uint64_t mword = tid < L4 ? mrow[tid] : 0ull;
     const pd_spec sp = a.spec[tile_specimen(a.aux[row])];
@@ -185,8 +101,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         float r[MS];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            const int s = tid + i * PD_TILE_THREADS;
-            rw[i] = s < g.nslot ? halo_row<DIM>(g, stn, s) : -1;
+            rw[i] = halo_row_of(hmv[i], stn);
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
@@ -210,8 +125,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         ctl->qs[cur ^ 1] = shadow_scale_t(ctl->umax_bits[cur]);
         ctl->umax_bits[cur ^ 1] = 0u;
     }
-    const int l0 = lane % g.T0, l1 = (lane / g.T0) % g.T1, l2 = lane / (g.T0 * g.T1);
-    const int my = (l0 + g.R) + g.Bx * ((l1 + g.R) + g.By * (DIM == 3 ? l2 + g.R : 0));
+    const int my = own_slot<DIM>(g, lane);
     const int4 si = halo[my];
     const float ri = qr[row].y;
     const float rpi = GQ * ri;
@@ -225,24 +139,26 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     uint32_t nbroken = 0, nrecheck = 0, nfall = 0;
     double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
 
-    // double decision for bond k of this row: breaks it (and takes it out of
-    // the row's intact x M V sum) when its stretch reaches s_c
-    auto recheck = [&](int k, bool &intact, bool &broke, double &e64) {
+    // double extension of bond k of this row (canonical order, from the
+    // double state); a break takes the bond out of the row's D_i
+    auto decide = [&](int k, bool brk_ok, bool &broke) -> double {
         const uint32_t w = a.words[pd_widx(base, k, lane)];
         const double4 ui = uv[row], uj = uv[w >> 7];
         const double4 sd = sten[k];
-        e64 = ext_canonical_t(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, uj.x - ui.x, uj.y - ui.y,
-                              DIM == 3 ? uj.z - ui.z : 0.0);
-        if (BREAK && intact && e64 / sd.w >= s0) {
-            intact = false;
+        const double e64 = ext_canonical_t(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, uj.x - ui.x, uj.y - ui.y,
+                                           DIM == 3 ? uj.z - ui.z : 0.0);
+        if (BREAK && brk_ok && e64 / sd.w >= s0) {
             broke = true;
             const double xv = sd.w * uj.w;
             dd0 += xv * sd.x;
             dd1 += xv * sd.y;
             dd2 += xv * sd.z;
         }
+        return e64;
     };
 
+    // byte offsets of this row's own slot in the two staged arrays
+    const int o_halo = my * 16, o_rv = g.nslot * 16 + my * 4;
     auto sweep = [&](auto chk) {
         constexpr bool CHK = decltype(chk)::value;
         KEnt en[4];
@@ -256,8 +172,8 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 e[c] = en[c];
-                sj[c] = halo[my + e[c].soff];
-                rvj[c] = hrv[my + e[c].soff];
+                sj[c] = *reinterpret_cast<const int4 *>(smem + o_halo + 16 * e[c].soff);
+                rvj[c] = *reinterpret_cast<const float *>(smem + o_rv + 4 * e[c].soff);
                 mm[c] = uni64_t(smask[4 * gg + c]);
             }
             // next group's table rows (row index stays inside the 128-row table)
@@ -267,41 +183,47 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 const int k = 4 * gg + c;
-                bool intact = lane_bit(mm[c]);
-                bool broke = false;
-                float ev;
-                if (CHK && (si.x == PD_SENTINEL_T || sj[c].x == PD_SENTINEL_T)) {
-                    ev = 0.0f;
-                    if (intact) {
-                        double e64;
-                        recheck(k, intact, broke, e64);
-                        nfall++;
-                        ev = (float)(e64 / Q);
-                    }
-                } else {
-                    const float fdx = (float)(sj[c].x - si.x), fdy = (float)(sj[c].y - si.y);
-                    const float fdz = DIM == 3 ? (float)(sj[c].z - si.z) : 0.0f;
-                    ev = e[c].m0 * fdx + e[c].m1 * fdy;
-                    if (DIM == 3) ev += e[c].m2 * fdz;
-                    if (BREAK) {
-                        // |ev - e64 / Q| <= sqrt(3) + 2^-20 sum |d|: recheck when
-                        // ev + that bound reaches the threshold
-                        const float lim = thrQ * e[c].x - 1.7320509f;
-                        const float sd = fabsf(fdx) + fabsf(fdy) + fabsf(fdz);
-                        if (intact && fmaf(9.5367432e-7f, sd, ev) >= lim) {
-                            double e64;
-                            recheck(k, intact, broke, e64);
-                            nrecheck++;
+                uint64_t live = mm[c];
+                // (a sentinel makes these differences meaningless; such bonds are redone below)
+                const float fdx = idiff(sj[c].x, si.x), fdy = idiff(sj[c].y, si.y);
+                const float fdz = DIM == 3 ? idiff(sj[c].z, si.z) : 0.0f;
+                float ev = e[c].m0 * fdx + e[c].m1 * fdy;
+                if (DIM == 3) ev += e[c].m2 * fdz;
+                if (BREAK) {
+                    // |ev - e64 / Q| <= sqrt(3) + 2^-20 sum |d|: decide in double when
+                    // ev + that bound reaches the threshold
+                    const float lim = thrQ * e[c].x - 1.7320509f;
+                    const float sdd = fabsf(fdx) + fabsf(fdy) + fabsf(fdz);
+                    const bool need = lane_bit(live) && fmaf(9.5367432e-7f, sdd, ev) >= lim;
+                    const uint64_t needm = __ballot(need);
+                    if (needm) {
+                        nrecheck += __popcll(needm);
+                        bool broke = false;
+                        if (need) (void)decide(k, true, broke);
+                        const uint64_t bb = __ballot(broke);
+                        if (bb) {
+                            live &= ~bb;
+                            if (lane == 0) mrow[k] = live;
+                            nbroken += __popcll(bb);
                         }
                     }
                 }
-                if (BREAK) {
-                    const uint64_t bb = __ballot(broke);
-                    if (bb) {
-                        if (lane == 0) mrow[k] = mm[c] & ~bb;
-                        nbroken += __popcll(bb);
+                if (CHK) {
+                    // intact bonds next to a sentinel: extension (and decision) from the double state
+                    const uint64_t fbm = __ballot(si.x == PD_SENTINEL_T || sj[c].x == PD_SENTINEL_T) & live;
+                    if (fbm) {
+                        nfall += __popcll(fbm);
+                        bool broke = false;
+                        if (lane_bit(fbm)) ev = (float)(decide(k, true, broke) / Q);
+                        const uint64_t bb = BREAK ? __ballot(broke) : 0ull;
+                        if (bb) {
+                            live &= ~bb;
+                            if (lane == 0) mrow[k] = live;
+                            nbroken += __popcll(bb);
+                        }
                     }
                 }
+                const bool intact = lane_bit(live);
                 const float Vj = __int_as_float(sj[c].w);
                 // dilatation: x V_j e;  deviatoric force: G e (1/m_i + 1/m_j) V_j
                 const float xv = e[c].x * Vj;
@@ -316,25 +238,20 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     if (anysent) sweep(std::true_type{});
     else sweep(std::false_type{});
 
+    __syncthreads();  // every wave is done with the staged box
+    float *red = reinterpret_cast<float *>(smem);                                       // [4][waves][64]
+    double *redd = reinterpret_cast<double *>(smem + 4 * PD_TILE_WAVES * 64 * sizeof(float));  // [3][waves][64]
     red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = acc;
     red[(1 * PD_TILE_WAVES + wv) * 64 + lane] = fx;
     red[(2 * PD_TILE_WAVES + wv) * 64 + lane] = fy;
     red[(3 * PD_TILE_WAVES + wv) * 64 + lane] = fz;
     if (BREAK) {
-        if (dd0 != 0.0 || dd1 != 0.0 || dd2 != 0.0) {
-            double *D = reinterpret_cast<double *>(a.dsum + row);
-            atomicAdd(D, -dd0);
-            atomicAdd(D + 1, -dd1);
-            atomicAdd(D + 2, -dd2);
-        }
+        redd[(0 * PD_TILE_WAVES + wv) * 64 + lane] = dd0;
+        redd[(1 * PD_TILE_WAVES + wv) * 64 + lane] = dd1;
+        redd[(2 * PD_TILE_WAVES + wv) * 64 + lane] = dd2;
         if (lane == 0 && nbroken) atomicAdd(&ctl->broken, (unsigned long long)nbroken);
-        unsigned long long rc = nrecheck, fb = nfall;
-        for (int o = 32; o > 0; o >>= 1) {
-            rc += __shfl_xor(rc, o);
-            fb += __shfl_xor(fb, o);
-        }
-        if (lane == 0 && rc) atomicAdd(&ctl->rechecks, rc);
-        if (lane == 0 && fb) atomicAdd(&ctl->fallbacks, fb);
+        if (lane == 0 && nrecheck) atomicAdd(&ctl->rechecks, (unsigned long long)nrecheck);
+        if (lane == 0 && nfall) atomicAdd(&ctl->fallbacks, (unsigned long long)nfall);
     }
     __syncthreads();
     if (wv != 0) return;
@@ -343,6 +260,24 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     for (int v = 0; v < 4; v++) {
         tot[v] = red[v * PD_TILE_WAVES * 64 + lane];
         for (int q = 1; q < PD_TILE_WAVES; q++) tot[v] += red[(v * PD_TILE_WAVES + q) * 64 + lane];
+    }
+    if (BREAK) {
+        // bonds of this row broken in this step leave D_i, in wave order
+        double d[3];
+        bool any = false;
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            d[v] = 0.0;
+            for (int q = 0; q < PD_TILE_WAVES; q++) d[v] += redd[(v * PD_TILE_WAVES + q) * 64 + lane];
+            any |= d[v] != 0.0;
+        }
+        if (any) {
+            double4 D = a.dsum[row];
+            D.x -= d[0];
+            D.y -= d[1];
+            D.z -= d[2];
+            a.dsum[row] = D;
+        }
     }
     // theta_i / m_i = A r_i^2 Q sum_j x V_j e'_j
     const double accQ = (double)tot[0] * Q;
@@ -361,7 +296,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MS = StageCap<DIM>::value;
     const Box g = make_box(a, DIM);
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t base = a.slice_ptr[tile];
@@ -375,6 +310,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     const float2 *__restrict__ qr = a.qr32;
     const int64_t row = tile * 64 + lane;
     const uint32_t aux = a.aux[row];
+    int hmv[MS];
+#pragma unroll
+    for (int i = 0; i < MS; i++) {
+        const int s = tid + i * PD_TILE_THREADS;
+        hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
+    }
     if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
     const uint64_t mword = tid < L4 ? kmask[(base >> 6) + tid] : 0ull;
     const pd_spec sp = a.spec[tile_specimen(aux)];
@@ -386,8 +327,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         int vb[MS];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            const int s = tid + i * PD_TILE_THREADS;
-            rw[i] = s < g.nslot ? halo_row<DIM>(g, stn, s) : -1;
+            rw[i] = halo_row_of(hmv[i], stn);
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
@@ -402,9 +342,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     }
     if (tid < 128) smask[tid] = mword;
     __syncthreads();
-    const int l0 = lane % g.T0, l1 = (lane / g.T0) % g.T1, l2 = lane / (g.T0 * g.T1);
-    const int my = (l0 + g.R) + g.Bx * ((l1 + g.R) + g.By * (DIM == 3 ? l2 + g.R : 0));
+    const int my = own_slot<DIM>(g, lane);
     const float qi = hq[my].x;
+    const int o_q = my * 8;  // byte offset of this row's own slot
     const int G4 = L4 >> 2;
     const int gper = (G4 + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
     const int g0 = wv * gper, g1 = min(G4, g0 + gper);
@@ -420,7 +360,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 e[c] = en[c];
-                qj[c] = hq[my + e[c].soff];
+                qj[c] = *reinterpret_cast<const float2 *>(smem + o_q + 8 * e[c].soff);
                 mm[c] = uni64_t(smask[4 * gg + c]);
             }
             const int gn = min(gg + 1, 31);
@@ -517,7 +457,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tdsum(StepArgs a, int cur, 
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MS = StageCap<DIM>::value;
     const Box g = make_box(a, DIM);
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t base = a.slice_ptr[tile];
@@ -527,6 +467,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tdsum(StepArgs a, int cur, 
     double *red = reinterpret_cast<double *>(smask + 128);
     int *stn = reinterpret_cast<int *>(red + 3 * PD_TILE_WAVES * 64);
     const double4 *__restrict__ uv = a.uv[cur];
+    int hmv[MS];
+#pragma unroll
+    for (int i = 0; i < MS; i++) {
+        const int s = tid + i * PD_TILE_THREADS;
+        hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
+    }
     if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
     const uint64_t mword = tid < L4 ? a.mask[(base >> 6) + tid] : 0ull;
     __syncthreads();
@@ -535,8 +481,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tdsum(StepArgs a, int cur, 
         double v[MS];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            const int s = tid + i * PD_TILE_THREADS;
-            rw[i] = s < g.nslot ? halo_row<DIM>(g, stn, s) : -1;
+            rw[i] = halo_row_of(hmv[i], stn);
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) v[i] = rw[i] >= 0 ? uv[rw[i]].w : 0.0;
@@ -548,8 +493,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tdsum(StepArgs a, int cur, 
     }
     if (tid < 128) smask[tid] = mword;
     __syncthreads();
-    const int l0 = lane % g.T0, l1 = (lane / g.T0) % g.T1, l2 = lane / (g.T0 * g.T1);
-    const int my = (l0 + g.R) + g.Bx * ((l1 + g.R) + g.By * (DIM == 3 ? l2 + g.R : 0));
+    const int my = own_slot<DIM>(g, lane);
     const int G4 = L4 >> 2;
     const int gper = (G4 + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
     const int g0 = wv * gper, g1 = min(G4, g0 + gper);
@@ -600,14 +544,14 @@ static size_t tiled_lds(const StepArgs &a, int pass) {
     const size_t nslot = (size_t)B[0] * B[1] * B[2], nslot2 = (nslot + 1) & ~(size_t)1;
     size_t b;
     if (pass == 1)
-        b = nslot * sizeof(int4) + nslot2 * sizeof(float) + 4 * PD_TILE_WAVES * 64 * sizeof(float);
+        b = tile1_region0((int)nslot);
     else
         b = nslot2 * sizeof(float2) + 3 * PD_TILE_WAVES * 64 * sizeof(float);
     return b + 128 * sizeof(uint64_t) + 32 * sizeof(int);
 }
 
 bool tiled_supported(const StepArgs &a) {
-    if (!a.tile_nbr || !a.ktab) return false;
+    if (!a.tile_nbr || !a.ktab || !a.halo_map) return false;
     if (a.tile[0] * a.tile[1] * a.tile[2] != 64) return false;
     if (a.reach < 1 || a.tile[0] < a.reach || a.tile[1] < a.reach) return false;
     if (a.dim == 3 && a.tile[2] < a.reach) return false;
@@ -615,7 +559,6 @@ bool tiled_supported(const StepArgs &a) {
     if (a.n_stencil > 124) return false;  // groups of four inside the 128-row table
     int32_t B[3];
     pd_tile_box(a.tile, a.reach, a.dim, B);
-    if (B[0] > 64 || B[1] > 64) return false;  // small_div range
     const int cap = (a.dim == 3 ? StageCap<3>::value : StageCap<2>::value) * PD_TILE_THREADS;
     if (B[0] * B[1] * B[2] > cap) return false;
     return tiled_lds(a, 1) <= 64 * 1024 && tiled_lds(a, 2) <= 64 * 1024;

@@ -1,0 +1,117 @@
+// Device helpers shared by the LDS-staged ("tiled") kernels: the tile box
+// and halo addressing, the per-entry table row, wave-uniform bit tests.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace pdk {
+
+#define PD_SENTINEL_T ((int)0x80000000)
+#define PD_TILE_WAVES 4
+#define PD_TILE_THREADS (64 * PD_TILE_WAVES)
+
+// one row of the per-entry table (pd_family_host.ktab)
+struct KEnt {
+    float m0, m1, m2, x;
+    int soff, z0, z1, z2;
+};
+static_assert(sizeof(KEnt) == 32, "ktab row is 8 words");
+
+__device__ __forceinline__ double ext_canonical_t(double m1, double m2, double m3, double e1, double e2,
+                                                  double e3) {
+#pragma clang fp contract(off)
+    double a = m1 * e1;
+    double b = m2 * e2;
+    double c = m3 * e3;
+    return (a + b) + c;
+}
+
+__device__ __forceinline__ double shadow_scale_t(unsigned int mbits) {
+    const float m = __uint_as_float(mbits);
+    if (!(m > 0.0f) || !isfinite(m)) return ldexp(1.0, -100);
+    const int e = ilogb((double)m);
+    return ldexp(1.0, max(e - 27, -100));
+}
+
+__device__ __forceinline__ int quantise_t(double u, double invQ, bool &bad) {
+    const double t = u * invQ;
+    if (!(fabs(t) < 1073741824.0)) {
+        bad = true;
+        return 0;
+    }
+    return (int)rint(t);
+}
+
+__device__ __forceinline__ uint64_t uni64_t(uint64_t v) {
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// float of the 32-bit difference a - b (wrapping, never undefined)
+__device__ __forceinline__ float idiff(int a, int b) { return (float)(int)((uint32_t)a - (uint32_t)b); }
+
+// lane's bit of a wave-uniform 64-bit word, used as the condition mask as is
+__device__ __forceinline__ bool lane_bit(uint64_t uniform_word) {
+    return __builtin_amdgcn_inverse_ballot_w64(uniform_word);
+}
+
+// specimen of a tile: every row of a tile belongs to one specimen, padding
+// rows carry id 0
+__device__ __forceinline__ uint32_t tile_specimen(uint32_t aux) {
+    const uint64_t b = __ballot((aux >> 8) != 0u);
+    return b ? ((uint32_t)__builtin_amdgcn_readlane((int)aux, (int)__builtin_ctzll(b)) >> 8) : 0u;
+}
+
+struct Box {
+    int T0, T1, R, Bx, By, nslot;
+};
+
+__device__ __forceinline__ Box make_box(const StepArgs &a, int dim) {
+    Box b;
+    int32_t B[3];
+    pd_tile_box(a.tile, a.reach, dim, B);
+    b.T0 = a.tile[0];
+    b.T1 = a.tile[1];
+    b.R = a.reach;
+    b.Bx = B[0];
+    b.By = B[1];
+    b.nslot = B[0] * B[1] * B[2];
+    return b;
+}
+
+// LDS box slot of lane l of the tile (its own lattice point)
+template <int DIM>
+__device__ __forceinline__ int own_slot(const Box &g, int lane) {
+    const int l0 = lane % g.T0, l1 = (lane / g.T0) % g.T1, l2 = lane / (g.T0 * g.T1);
+    return (l0 + g.R) + g.Bx * ((l1 + g.R) + g.By * (DIM == 3 ? l2 + g.R : 0));
+}
+
+// global row of a halo slot from its halo_map entry and the tile's
+// neighbour table (-1: pitch padding or no tile in that direction)
+__device__ __forceinline__ int64_t halo_row_of(int m, const int *tn) {
+    if (m < 0) return -1;
+    const int nt = tn[m >> 6];
+    return nt < 0 ? -1 : (int64_t)nt * 64 + (m & 63);
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs of the chip, each with its
+// own L2.  Tile of workgroup b: every XCD gets a contiguous range of tiles,
+// so neighbouring tiles, whose halo boxes overlap, are staged through the
+// same L2.  A bijection of [0, n).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
+    const int64_t q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// slots per thread staged at once: 1280 slots in 3D, 512 in 2D
+template <int DIM>
+struct StageCap {
+    static constexpr int value = DIM == 3 ? 5 : 2;
+};
+
+}  // namespace pdk

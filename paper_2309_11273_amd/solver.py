@@ -107,10 +107,11 @@ class FamilyHost:
         self.tile_org = np.empty(s.n_tiles * 4, np.int32)
         self.tile_nbr = np.empty(s.n_tiles * 27, np.int32)
         self.ktab = np.empty(128 * 8, np.uint32)
+        self.halo_map = np.empty(max(1, s.n_halo), np.int16)
         hb = A.pd_family_host(_np(self.perm), _np(self.row_of), _np(self.slice_ptr), _np(self.words),
                               _np(self.mask), _np(self.stencil), _np(self.stencil_off), _np(self.vol),
                               _np(self.inv_m), _np(self.spec), _np(self.lat4), _np(self.tile_org),
-                              _np(self.tile_nbr), _np(self.ktab))
+                              _np(self.tile_nbr), _np(self.ktab), _np(self.halo_map))
         self._hb = hb
         A.check("pd_build_family", L.pd_build_family(C.byref(body), C.cast(carr, C.c_void_p), len(cuts),
                                                      C.byref(sizes), C.byref(hb)))
@@ -216,6 +217,8 @@ class Solver:
         P.stencil_off, P.tile_nbr = _tp(self.stencil_off), _tp(self.tile_nbr)
         self.ktab = t(self.fam.ktab.view(np.int32))
         P.ktab = _tp(self.ktab)
+        self.halo_map = t(self.fam.halo_map)
+        P.halo_map = _tp(self.halo_map)
         for c in range(3):
             P.tile[c] = int(s.tile[c])
         P.reach = int(s.reach)
@@ -230,10 +233,12 @@ class Solver:
         self.qr32 = torch.zeros(self.n_pad * 2, dtype=torch.float32, device=d) if fp32_state else None
         self.dsum = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=d) if fp32_state else None
         self.fe32 = torch.zeros(self.n_pad * 4, dtype=torch.float32, device=d) if fp32_state else None
+        self.fe64 = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=d)
         self.ctl = torch.zeros(A.PD_CTL_BYTES // 8, dtype=torch.int64, device=d)
         S = A.pd_state_dev()
         S.uv[0], S.uv[1] = self.uv[0].data_ptr(), self.uv[1].data_ptr()
         S.vel, S.qr, S.mask = _tp(self.vel), _tp(self.qr), _tp(self.mask)
+        S.fe64 = _tp(self.fe64)
         if fp32_state:
             S.ush[0], S.ush[1] = self.ush[0].data_ptr(), self.ush[1].data_ptr()
             S.qr32 = _tp(self.qr32)

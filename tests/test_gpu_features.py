@@ -171,4 +171,5 @@ def test_autotune_picks_a_measured_candidate(ctx, tmp_path):
     assert s.autotune("fp32", trial_steps=5, cache=cache) == r
     assert s.step_count() == 0
     r64 = s.autotune("fp64", trial_steps=5)
-    assert r64["block"] in (64, 128, 256)
+    assert len(r64["candidates"]) == 4 and min(c["ms"] for c in r64["candidates"]) == r64["ms_per_step"]
+    assert (r64["kernel"], r64["block"]) in [("tiled", 0), ("gather", 64), ("gather", 128), ("gather", 256)]

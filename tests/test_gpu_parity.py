@@ -85,16 +85,17 @@ def test_force_matches_reference(ctx, name):
     assert np.abs(th - tho).max() <= 1e-12 * np.abs(tho).max()
 
 
+@pytest.mark.parametrize("kernel", ["gather", "tiled"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("plane_strain", 100),
                                         ("impact", 200), ("cylinder", 200), ("batch", 200)])
-def test_fp64_trajectory(ctx, name, steps):
+def test_fp64_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
     o = Oracle(w)
     s = solver(w, ctx)
     uo, vo = o.initial_state()
     done = 0
     for target in (steps // 4, steps // 2, steps):
-        s.step(target - done, precision="fp64")
+        s.step(target - done, precision="fp64", kernel=kernel)
         o.run(target - done, uo, vo)
         done = target
         u, v = s.read()
@@ -152,15 +153,25 @@ def test_graph_replay_equals_eager(ctx):
 
 
 def test_deterministic_and_block_invariant(ctx):
+    """The gather kernels give the same bits at every block size; every
+    kernel gives the same bits on every run."""
     w = small_workloads()["impact"]
     outs = []
     for block in (64, 128, 256, 256):
         s = solver(w, ctx)
-        s.step(100, precision="fp64", block=block)
+        s.step(100, precision="fp64", block=block, kernel="gather")
         outs.append((s.read()[0], s.mask_host()))
     for u, m in outs[1:]:
         assert np.array_equal(u, outs[0][0])
         assert np.array_equal(m, outs[0][1])
+    for prec in ("fp64", "fp32"):
+        runs = []
+        for _ in range(2):
+            s = solver(w, ctx)
+            s.step(100, precision=prec, kernel="tiled")
+            runs.append((s.read()[0], s.mask_host()))
+        assert np.array_equal(runs[0][0], runs[1][0]), prec
+        assert np.array_equal(runs[0][1], runs[1][1]), prec
 
 
 def test_bsr_apply_matches_matrix_free(ctx):

@@ -131,6 +131,12 @@ def test_tile_halo_addressing_matches_bond_words(lib, case):
     for t in tiles:
         rows, (Bx, By, Bz) = _halo_rows(f, int(t))
         soff = off[:, 0] + Bx * (off[:, 1] + By * off[:, 2])
+        hm = f.halo_map.astype(np.int64)
+        tn = f.tile_nbr[27 * int(t): 27 * int(t) + 27]
+        assert len(hm) == Bx * By * Bz == int(s.n_halo)
+        nt = np.where(hm >= 0, tn[np.maximum(hm, 0) >> 6], -1)
+        rows_map = np.where((hm >= 0) & (nt >= 0), nt * 64 + (hm & 63), -1)
+        assert np.array_equal(rows_map, rows)
         kt = f.ktab.view(np.int32).reshape(128, 8)
         assert np.array_equal(kt[: len(soff), 4], soff)
         assert not kt[len(soff):].any()
@@ -317,3 +323,14 @@ def test_notches_have_no_ties(name):
         for k in range(1, 7):
             for q in range(0, k + 1):
                 assert abs(frac - q / k) > 1e-6
+
+
+def test_xcd_tile_order_is_a_bijection():
+    """The tile kernels hand workgroup b tile x*q + min(x, r) + b // 8 with
+    x = b % 8, n = 8q + r (every XCD a contiguous range); that must visit
+    every tile exactly once for any tile count."""
+    for n in list(range(1, 70)) + [15666, 95030, 7500]:
+        b = np.arange(n)
+        q, r, x = n // 8, n % 8, b % 8
+        t = x * q + np.minimum(x, r) + b // 8
+        assert np.array_equal(np.sort(t), b)
