@@ -20,7 +20,6 @@ usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# published MI355X vector peaks (TFLOP/s)
+VALU_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
 WORKLOADS = {
     # name: (generator kwargs, description)
@@ -54,25 +55,47 @@ def algorithmic_bytes(kernel: str, precision: str, nnz: int, n: int, n_loaded: i
     """Bytes one launch must move between HBM and the chip (each array read
     or written once; neighbour data is served by the caches or LDS).
 
-    Per directed bond: 4 B bond word + 1 bit of bond status (1/8 B); the
-    LDS-staged tile kernels read no bond word (the stencil position of a
-    bond gives its neighbour), only the status bit.
-    Per node (FP64 path):
-      pass 1: u,V 32 read; aux 4; (theta/m, 1/m) 16 read + 8 write
-      pass 2: u,V 32 read; (theta/m, 1/m) 16; aux 4; v 32 read + 32 write;
-              u,V 32 write
-    Per node (FP32 path):
-      pass 1: shadow 16; aux 4; (theta/m, 1/m) float 8 read + 4 write
-      pass 2: shadow 16; float (theta/m, 1/m) 8; aux 4; D 32; u,V 32 read;
-              v 32 + 32; u,V 32 write; next shadow 16 write
+    Per directed bond: 1 bit of bond status (1/8 B), plus the 4 B bond word
+    for the gather kernels; the LDS-staged tile kernels read no bond word
+    (the stencil position of a bond gives its neighbour).
+    Per node, gather kernels (pair force summed in pass 2):
+      FP64 pass 1: u,V 32; aux 4; (theta/m, 1/m) 16 read + 8 write
+      FP64 pass 2: u,V 32; (theta/m, 1/m) 16; aux 4; v 32 + 32; u,V 32 write
+      FP32 pass 1: shadow 16; aux 4; float (theta/m, 1/m) 8 + 4
+      FP32 pass 2: shadow 16; float (theta/m, 1/m) 8; aux 4; D 32; u,V 32;
+                   v 32 + 32; u,V 32 write; next shadow 16 write
+    Per node, tile kernels (deviatoric part of the pair force in pass 1):
+      FP64 pass 1: u,V 32; 1/m 8; aux 4; theta/m 8 write; force part 32 write
+      FP64 pass 2: theta/m 8; u,V 32; aux 4; force part 32; v 32 + 32;
+                   u,V 32 write
+      FP32 pass 1: shadow 16; 1/m 4; aux 4; theta/m 4 write; force part 16 write
+      FP32 pass 2: theta/m 4; V 4; aux 4; D 32; force part 16; u,V 32;
+                   v 32 + 32; u,V 32 write; next shadow 16 write
     Loaded nodes read their external force (32 B) in pass 2."""
     bond = nnz * (0.125 if tiled else 4.125)
-    if precision == "fp64":
-        node = {"pass1": 60, "pass2": 148}[kernel]
+    if tiled:
+        node = {("fp64", "pass1"): 84, ("fp64", "pass2"): 172,
+                ("fp32", "pass1"): 44, ("fp32", "pass2"): 204}[(precision, kernel)]
     else:
-        node = {"pass1": 32, "pass2": 204}[kernel]
+        node = {("fp64", "pass1"): 60, ("fp64", "pass2"): 148,
+                ("fp32", "pass1"): 32, ("fp32", "pass2"): 204}[(precision, kernel)]
     extra = 32 * n_loaded if kernel == "pass2" else 0
     return int(bond + node * n + extra)
+
+
+def algorithmic_flops(kernel: str, nnz: int, tiled: bool) -> int:
+    """Floating-point operations one launch must do, per directed bond (the
+    per-node update is negligible beside them):
+      extension M.(u_j - u_i): 3 sub + 3 mul + 2 add = 8; stretch test 1;
+      dilatation term x e V_j: 2 mul + 1 add = 3;
+      deviatoric force G e (1/m_i + 1/m_j) V_j M: 1 add + 2 mul + 3 mul + 3 add = 9;
+      dilatational force (K - G/3) x (q_i + q_j) V_j M: 1 add + 2 mul + 6 = 9.
+    Tile kernels: pass 1 = 8 + 1 + 3 + 9 = 21, pass 2 = 9.  Gather kernels:
+    pass 1 = 8 + 1 + 3 = 12; pass 2 recomputes the extension and sums the
+    whole bracket [(K - G/3) x (q_i + q_j) + G e (1/m_i + 1/m_j)] V_j M:
+    8 + 3 + 3 + 1 (sum) + 1 (V_j) + 6 (M, accumulate) = 22."""
+    per = {("pass1", True): 21, ("pass2", True): 9, ("pass1", False): 12, ("pass2", False): 22}[(kernel, tiled)]
+    return per * nnz
 
 
 def traffic_from_profiles(kernel_name: str, src_hash: str):
@@ -89,10 +112,32 @@ def traffic_from_profiles(kernel_name: str, src_hash: str):
     return e.get("bytes_per_launch")
 
 
-def kernel_source_hash(fname: str) -> str:
-    src = os.path.join(ROOT, "paper_2309_11273_amd", "csrc", fname)
-    with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
+    """Roofline of the dominant kernel: the ceiling that binds its algorithmic
+    work (bytes at the HBM peak vs flops at the vector peak of its precision),
+    the achieved fraction of it from the HIP-event duration, and the measured
+    HBM traffic per launch when profiles/traffic.json holds it for this
+    kernel source."""
+    tiled = args.kernel != "gather" and s.tiled_supported(args.precision)
+    kname = f"k_{'t' if tiled else ''}{dom}_{'f32' if args.precision == 'fp32' else 'f64'}"
+    ms_dom = ms1 if dom == "pass1" else ms2
+    sec = ms_dom * 1e-3
+    byt = algorithmic_bytes(dom, args.precision, nnz, n, n_loaded, tiled)
+    fl = algorithmic_flops(dom, nnz, tiled)
+    peak_fl = VALU_PEAK_TFLOPS[args.precision]
+    gbs, tfs = byt / sec / 1e9, fl / sec / 1e12
+    alu = fl / (peak_fl * 1e12) > byt / (HBM_PEAK_GBS * 1e9)
+    from paper_2309_11273_amd.profsum import kernel_source_hash
+    traffic = traffic_from_profiles(f"{kname}@{args.workload}", kernel_source_hash(kname))
+    return {"bound": "alu" if alu else "hbm",
+            "achieved": round(tfs if alu else gbs, 2), "peak": peak_fl if alu else HBM_PEAK_GBS,
+            "unit": "TFLOP/s" if alu else "GB/s",
+            "frac": round(tfs / peak_fl if alu else gbs / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "kernel": kname, "kernel_ms": round(ms_dom, 5),
+            "algorithmic_bytes": byt, "algorithmic_flops": fl,
+            "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "valu_tflops": round(tfs, 2), "valu_frac": round(tfs / peak_fl, 4),
+            "pass1_ms": round(ms1, 5), "pass2_ms": round(ms2, 5)}
 
 
 def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto"):
@@ -178,17 +223,8 @@ def main():
     ms1, ms2 = prof["ms_pass1"] / ps, prof["ms_pass2"] / ps
     dom = "pass2" if ms2 >= ms1 else "pass1"
     ms_dom = max(ms1, ms2)
-    tiled = args.precision == "fp32" and args.kernel != "gather" and s.tiled_supported()
-    alg = algorithmic_bytes(dom, args.precision, nnz, int(sz.n), n_loaded, tiled) if args.form == "mf" else None
-    kname = f"k_{'t' if tiled else ''}{dom}_{args.precision}"
-    if alg is not None:
-        achieved = alg / (ms_dom * 1e-3) / 1e9
-        src = "kernels_tiled.hip" if tiled else ("kernels_f32.hip" if args.precision == "fp32" else "kernels.hip")
-        traffic = traffic_from_profiles(f"{kname}_{args.workload}", kernel_source_hash(src))
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-                    "kernel_ms": round(ms_dom, 5), "algorithmic_bytes": alg,
-                    "pass1_ms": round(ms1, 5), "pass2_ms": round(ms2, 5)}
+    if args.form == "mf":
+        roofline = roofline_entry(s, args, dom, ms1, ms2, nnz, int(sz.n), n_loaded)
     else:
         roofline = None
 

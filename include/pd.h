@@ -278,6 +278,12 @@ pd_status pd_state_read(pd_ctx *ctx, const pd_problem_dev *prob, const int32_t *
 /* Read the step counter (synchronises the stream). */
 pd_status pd_get_step(pd_ctx *ctx, const pd_state_dev *st, int64_t *step);
 
+/* Whether pd_step / pd_force with opts.kernel = 0 run the LDS-staged tile
+ * kernels for this problem, state and precision (*yes = 1) or the gather
+ * kernels (*yes = 0).  Host only, no device work. */
+pd_status pd_tile_kernels_apply(const pd_problem_dev *prob, const pd_state_dev *st, int32_t precision,
+                                int32_t *yes);
+
 /* ------------------------------------------------------------------------ */
 /* the force operator                                                       */
 /* ------------------------------------------------------------------------ */

@@ -36,6 +36,22 @@
  *   - The extension is evaluated as (M1*eta1 + M2*eta2) + M3*eta3 with no
  *     fused multiply-add (the file is compiled with -ffp-contract=off).
  *
+ * Pins (the CPU test suite checks this file against facts that do not come
+ * from these formulas): the bond count the paper prints for a 10x10 grid and
+ * the 28 / 122 interior family sizes; rigid motion gives zero force; momentum
+ * balance; a uniform dilatation gives theta = A eps; the equibiaxial energy is
+ * the classical one; f = -grad E of the stored energy; the paper's matrix form
+ * equals the loop form; the stiffness is symmetric positive semi-definite with
+ * the rigid-motion null space; the beta constants by quadrature; the 3D
+ * critical stretch from the energy released across a crack; the two-node
+ * oscillator and the break step in closed form; the discrete energy invariant
+ * of the update; the cantilever's first bending frequency; notch cuts against
+ * sampled crossings of every bond segment.
+ * Parity unpinned: the 2D critical stretch (Eq. 1.28, taken as printed; the
+ * paper prints no value of it, and it is not what the 2D stored energy gives),
+ * and the crack paths of the fracture workloads (nothing outside this file
+ * predicts them).
+ *
  * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fno-fast-math -fopenmp
  */
 #include <math.h>

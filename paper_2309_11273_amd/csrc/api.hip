@@ -271,6 +271,15 @@ pd_status pd_state_read(pd_ctx *c, const pd_problem_dev *p, const int32_t *perm,
     return PD_OK;
 }
 
+pd_status pd_tile_kernels_apply(const pd_problem_dev *p, const pd_state_dev *st, int32_t precision, int32_t *yes) {
+    if (!p || !st || !yes) return PD_ERR_ARG;
+    if (precision != PD_FP64 && precision != PD_FP32_RECHECK) return PD_ERR_ARG;
+    pd_state_dev tmp = *st;
+    const pdk::StepArgs a = make_args(p, &tmp);
+    *yes = (precision == PD_FP64 ? pdk::tiled64_supported(a) : pdk::tiled_supported(a)) ? 1 : 0;
+    return PD_OK;
+}
+
 pd_status pd_get_step(pd_ctx *c, const pd_state_dev *st, int64_t *step) {
     if (!c || !st || !st->ctl || !step) return PD_ERR_ARG;
     HIP_TRY(c, hipSetDevice(c->device));

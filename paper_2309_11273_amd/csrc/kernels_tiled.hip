@@ -42,13 +42,29 @@
 
 namespace pdk {
 
-// bytes of the first LDS region of pass 1: the staged box (shadow + G Q V / m
-// per slot), or the partial sums (4 floats and 3 doubles per thread) that
-// replace it after the sweep, whichever is larger
-__host__ __device__ inline int tile1_region0(int nslot) {
-    const int box = nslot * 16 + ((nslot + 1) & ~1) * 4;
+// LDS of one tile in pass 1: the staged box (shadow + G Q V / m per slot) --
+// with TPW = 1 the partial sums (4 floats and 3 doubles per thread) reuse it
+// after the sweep, so it is at least that large -- then the tile's 128 status
+// words and its 27 neighbour tiles
+template <int TPW>
+__host__ __device__ inline int tile1_box_bytes(int nslot) {
+    const int box = (nslot * 16 + ((nslot + 1) & ~1) * 4 + 15) & ~15;
     const int sums = PD_TILE_WAVES * 64 * (4 * 4 + 3 * 8);
-    return box > sums ? box : sums;
+    return (TPW == 1 && sums > box) ? sums : box;
+}
+template <int TPW>
+__host__ __device__ inline int tile1_bytes(int nslot) {
+    return tile1_box_bytes<TPW>(nslot) + 128 * 8 + 32 * 4;
+}
+// pass 2: the staged box ((K - G/3) theta/m, V per slot), status words,
+// neighbour tiles, and with TPW = 1 the partial sums
+template <int TPW>
+__host__ __device__ inline int tile2_box_bytes(int nslot) {
+    return (((nslot + 1) & ~1) * 8 + 15) & ~15;
+}
+template <int TPW>
+__host__ __device__ inline int tile2_bytes(int nslot) {
+    return tile2_box_bytes<TPW>(nslot) + 128 * 8 + 32 * 4 + (TPW == 1 ? 3 * PD_TILE_WAVES * 64 * 4 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -59,21 +75,26 @@ __host__ __device__ inline int tile1_region0(int nslot) {
 // and is summed in pass 2, and a deviatoric part, G e (1/m_i + 1/m_j) M V_i V_j,
 // which needs only the extension and the bond status after this step's
 // breaking, and is summed here where e is at hand (fe32, without the V_i).
-template <int DIM, bool BREAK>
+template <int DIM, bool BREAK, int TPW>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int cur,
                                                                 const KEnt *__restrict__ kt) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int MS = StageCap<DIM>::value;
+    using GR = Grp<DIM, TPW>;
+    constexpr int MS = GR::MS;
     const Box g = make_box(a, DIM);
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int gt = TPW == 1 ? tid : lane;  // thread within its tile's group
+    const int sub = TPW == 1 ? 0 : wv;     // tile of the workgroup this wave serves
+    const int kq = TPW == 1 ? wv : 0;      // stencil part of this wave
+    bool valid;
+    const int64_t tile = group_tile<TPW>(a.n_slices, sub, valid);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
-    // region 0: the staged box, reused for the partial sums after the sweep
-    int4 *halo = reinterpret_cast<int4 *>(smem);                 // shadow, V bits
+    unsigned char *reg = smem + sub * tile1_bytes<TPW>(g.nslot);
+    int4 *halo = reinterpret_cast<int4 *>(reg);                  // shadow, V bits
     float *hrv = reinterpret_cast<float *>(halo + g.nslot);      // G Q V_j / m_j
-    uint64_t *smask = reinterpret_cast<uint64_t *>(smem + tile1_region0(g.nslot));
+    uint64_t *smask = reinterpret_cast<uint64_t *>(reg + tile1_box_bytes<TPW>(g.nslot));
     int *stn = reinterpret_cast<int *>(smask + 128);
     pd_ctl *ctl = a.ctl;
     const double Q = ctl->qs[cur];
@@ -86,11 +107,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     int hmv[MS];
 #pragma unroll
     for (int i = 0; i < MS; i++) {
-        const int s = tid + i * PD_TILE_THREADS;
+        const int s = gt + i * GR::NT;
         hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
     }
-    if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
-    const uint64_t mword = tid < L4 ? mrow[tid] : 0ull;
+    if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
+    const uint64_t mw0 = gt < L4 ? mrow[gt] : 0ull;
+    const uint64_t mw1 = (TPW != 1 && gt + 64 < L4) ? mrow[gt + 64] : 0ull;
     const pd_spec sp = a.spec[tile_specimen(a.aux[row])];
     const float GQ = (float)(sp.G * Q);  // extension carried in units of Q
     __syncthreads();
@@ -110,7 +132,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            const int s = tid + i * PD_TILE_THREADS;
+            const int s = gt + i * GR::NT;
             if (s < g.nslot) {
                 halo[s] = v[i];
                 hrv[s] = GQ * r[i] * __int_as_float(v[i].w);
@@ -118,9 +140,10 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
             }
         }
     }
-    if (tid < 128) smask[tid] = mword;
+    if (gt < 128) smask[gt] = mw0;
+    if (TPW != 1) smask[gt + 64] = mw1;
     const bool anysent = __syncthreads_or(sent);
-    if (BREAK && tile == 0 && tid == 0) {
+    if (BREAK && valid && tile == 0 && gt == 0) {
         ctl->s1 = ctl->s2;
         ctl->qs[cur ^ 1] = shadow_scale_t(ctl->umax_bits[cur]);
         ctl->umax_bits[cur ^ 1] = 0u;
@@ -133,8 +156,8 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     // breaking threshold in units of Q, widened by the float rounding of the test
     const float thrQ = (float)(s0 / Q) * (1.0f - 1e-6f);
     const int G4 = L4 >> 2;
-    const int gper = (G4 + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
-    const int g0 = wv * gper, g1 = min(G4, g0 + gper);
+    const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
+    const int g0 = kq * gper, g1 = min(G4, g0 + gper);
     float acc = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
     uint32_t nbroken = 0, nrecheck = 0, nfall = 0;
     double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
@@ -172,8 +195,8 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 e[c] = en[c];
-                sj[c] = *reinterpret_cast<const int4 *>(smem + o_halo + 16 * e[c].soff);
-                rvj[c] = *reinterpret_cast<const float *>(smem + o_rv + 4 * e[c].soff);
+                sj[c] = *reinterpret_cast<const int4 *>(reg + o_halo + 16 * e[c].soff);
+                rvj[c] = *reinterpret_cast<const float *>(reg + o_rv + 4 * e[c].soff);
                 mm[c] = uni64_t(smask[4 * gg + c]);
             }
             // next group's table rows (row index stays inside the 128-row table)
@@ -203,7 +226,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
                         const uint64_t bb = __ballot(broke);
                         if (bb) {
                             live &= ~bb;
-                            if (lane == 0) mrow[k] = live;
+                            if (lane == 0 && valid) mrow[k] = live;
                             nbroken += __popcll(bb);
                         }
                     }
@@ -218,7 +241,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
                         const uint64_t bb = BREAK ? __ballot(broke) : 0ull;
                         if (bb) {
                             live &= ~bb;
-                            if (lane == 0) mrow[k] = live;
+                            if (lane == 0 && valid) mrow[k] = live;
                             nbroken += __popcll(bb);
                         }
                     }
@@ -238,46 +261,46 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     if (anysent) sweep(std::true_type{});
     else sweep(std::false_type{});
 
-    __syncthreads();  // every wave is done with the staged box
-    float *red = reinterpret_cast<float *>(smem);                                       // [4][waves][64]
-    double *redd = reinterpret_cast<double *>(smem + 4 * PD_TILE_WAVES * 64 * sizeof(float));  // [3][waves][64]
-    red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = acc;
-    red[(1 * PD_TILE_WAVES + wv) * 64 + lane] = fx;
-    red[(2 * PD_TILE_WAVES + wv) * 64 + lane] = fy;
-    red[(3 * PD_TILE_WAVES + wv) * 64 + lane] = fz;
-    if (BREAK) {
-        redd[(0 * PD_TILE_WAVES + wv) * 64 + lane] = dd0;
-        redd[(1 * PD_TILE_WAVES + wv) * 64 + lane] = dd1;
-        redd[(2 * PD_TILE_WAVES + wv) * 64 + lane] = dd2;
+    if (BREAK && valid) {
         if (lane == 0 && nbroken) atomicAdd(&ctl->broken, (unsigned long long)nbroken);
         if (lane == 0 && nrecheck) atomicAdd(&ctl->rechecks, (unsigned long long)nrecheck);
         if (lane == 0 && nfall) atomicAdd(&ctl->fallbacks, (unsigned long long)nfall);
     }
-    __syncthreads();
-    if (wv != 0) return;
-    float tot[4];
+    float tot[4] = {acc, fx, fy, fz};
+    double d[3] = {dd0, dd1, dd2};
+    if constexpr (TPW == 1) {
+        __syncthreads();  // every wave is done with the staged box
+        float *red = reinterpret_cast<float *>(smem);                                              // [4][waves][64]
+        double *redd = reinterpret_cast<double *>(smem + 4 * PD_TILE_WAVES * 64 * sizeof(float));  // [3][waves][64]
 #pragma unroll
-    for (int v = 0; v < 4; v++) {
-        tot[v] = red[v * PD_TILE_WAVES * 64 + lane];
-        for (int q = 1; q < PD_TILE_WAVES; q++) tot[v] += red[(v * PD_TILE_WAVES + q) * 64 + lane];
+        for (int v = 0; v < 4; v++) red[(v * PD_TILE_WAVES + wv) * 64 + lane] = tot[v];
+        if (BREAK) {
+#pragma unroll
+            for (int v = 0; v < 3; v++) redd[(v * PD_TILE_WAVES + wv) * 64 + lane] = d[v];
+        }
+        __syncthreads();
+        if (wv != 0) return;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            tot[v] = red[v * PD_TILE_WAVES * 64 + lane];
+            for (int q = 1; q < PD_TILE_WAVES; q++) tot[v] += red[(v * PD_TILE_WAVES + q) * 64 + lane];
+        }
+        if (BREAK) {
+            // bonds of this row broken in this step leave D_i, in wave order
+#pragma unroll
+            for (int v = 0; v < 3; v++) {
+                d[v] = 0.0;
+                for (int q = 0; q < PD_TILE_WAVES; q++) d[v] += redd[(v * PD_TILE_WAVES + q) * 64 + lane];
+            }
+        }
     }
-    if (BREAK) {
-        // bonds of this row broken in this step leave D_i, in wave order
-        double d[3];
-        bool any = false;
-#pragma unroll
-        for (int v = 0; v < 3; v++) {
-            d[v] = 0.0;
-            for (int q = 0; q < PD_TILE_WAVES; q++) d[v] += redd[(v * PD_TILE_WAVES + q) * 64 + lane];
-            any |= d[v] != 0.0;
-        }
-        if (any) {
-            double4 D = a.dsum[row];
-            D.x -= d[0];
-            D.y -= d[1];
-            D.z -= d[2];
-            a.dsum[row] = D;
-        }
+    if (!valid) return;
+    if (BREAK && (d[0] != 0.0 || d[1] != 0.0 || d[2] != 0.0)) {
+        double4 D = a.dsum[row];
+        D.x -= d[0];
+        D.y -= d[1];
+        D.z -= d[2];
+        a.dsum[row] = D;
     }
     // theta_i / m_i = A r_i^2 Q sum_j x V_j e'_j
     const double accQ = (double)tot[0] * Q;
@@ -289,35 +312,43 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
 // ---------------------------------------------------------------------------
 // pass 2: dilatational pair force, explicit update, next shadow
 // ---------------------------------------------------------------------------
-template <int DIM, bool UPDATE>
+template <int DIM, bool UPDATE, int TPW>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int cur,
                                                                 const KEnt *__restrict__ kt,
                                                                 const uint64_t *__restrict__ kmask) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int MS = StageCap<DIM>::value;
+    using GR = Grp<DIM, TPW>;
+    constexpr int MS = GR::MS;
     const Box g = make_box(a, DIM);
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int gt = TPW == 1 ? tid : lane;
+    const int sub = TPW == 1 ? 0 : wv;
+    const int kq = TPW == 1 ? wv : 0;
+    bool valid;
+    const int64_t tile = group_tile<TPW>(a.n_slices, sub, valid);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
-    float2 *hq = reinterpret_cast<float2 *>(smem);  // ((K - G/3) theta_j/m_j, V_j)
-    uint64_t *smask = reinterpret_cast<uint64_t *>(hq + ((g.nslot + 1) & ~1));
-    float *red = reinterpret_cast<float *>(smask + 128);
-    int *stn = reinterpret_cast<int *>(red + 3 * PD_TILE_WAVES * 64);
+    unsigned char *reg = smem + sub * tile2_bytes<TPW>(g.nslot);
+    float2 *hq = reinterpret_cast<float2 *>(reg);  // ((K - G/3) theta_j/m_j, V_j)
+    uint64_t *smask = reinterpret_cast<uint64_t *>(reg + tile2_box_bytes<TPW>(g.nslot));
+    int *stn = reinterpret_cast<int *>(smask + 128);
+    float *red = reinterpret_cast<float *>(stn + 32);  // TPW = 1: [3][waves][64]
     pd_ctl *ctl = a.ctl;
     const int4 *__restrict__ sh = a.ush[cur];
     const float2 *__restrict__ qr = a.qr32;
     const int64_t row = tile * 64 + lane;
     const uint32_t aux = a.aux[row];
+    const uint64_t *__restrict__ mrow = kmask + (base >> 6);
     int hmv[MS];
 #pragma unroll
     for (int i = 0; i < MS; i++) {
-        const int s = tid + i * PD_TILE_THREADS;
+        const int s = gt + i * GR::NT;
         hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
     }
-    if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
-    const uint64_t mword = tid < L4 ? kmask[(base >> 6) + tid] : 0ull;
+    if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
+    const uint64_t mw0 = gt < L4 ? mrow[gt] : 0ull;
+    const uint64_t mw1 = (TPW != 1 && gt + 64 < L4) ? mrow[gt + 64] : 0ull;
     const pd_spec sp = a.spec[tile_specimen(aux)];
     const float kp = (float)sp.kp;
     __syncthreads();
@@ -336,18 +367,19 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            const int s = tid + i * PD_TILE_THREADS;
+            const int s = gt + i * GR::NT;
             if (s < g.nslot) hq[s] = make_float2(kp * q[i], __int_as_float(vb[i]));
         }
     }
-    if (tid < 128) smask[tid] = mword;
+    if (gt < 128) smask[gt] = mw0;
+    if (TPW != 1) smask[gt + 64] = mw1;
     __syncthreads();
     const int my = own_slot<DIM>(g, lane);
     const float qi = hq[my].x;
     const int o_q = my * 8;  // byte offset of this row's own slot
     const int G4 = L4 >> 2;
-    const int gper = (G4 + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
-    const int g0 = wv * gper, g1 = min(G4, g0 + gper);
+    const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
+    const int g0 = kq * gper, g1 = min(G4, g0 + gper);
     float fx = 0.f, fy = 0.f, fz = 0.f;
     {
         KEnt en[4];
@@ -360,7 +392,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 e[c] = en[c];
-                qj[c] = *reinterpret_cast<const float2 *>(smem + o_q + 8 * e[c].soff);
+                qj[c] = *reinterpret_cast<const float2 *>(reg + o_q + 8 * e[c].soff);
                 mm[c] = uni64_t(smask[4 * gg + c]);
             }
             const int gn = min(gg + 1, 31);
@@ -377,17 +409,23 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
             }
         }
     }
-    red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = fx;
-    red[(1 * PD_TILE_WAVES + wv) * 64 + lane] = fy;
-    red[(2 * PD_TILE_WAVES + wv) * 64 + lane] = fz;
-    __syncthreads();
-    if (wv != 0) return;
-    float sx = red[lane], sy = red[PD_TILE_WAVES * 64 + lane], sz = red[2 * PD_TILE_WAVES * 64 + lane];
-    for (int q = 1; q < PD_TILE_WAVES; q++) {
-        sx += red[q * 64 + lane];
-        sy += red[(PD_TILE_WAVES + q) * 64 + lane];
-        sz += red[(2 * PD_TILE_WAVES + q) * 64 + lane];
+    float sx = fx, sy = fy, sz = fz;
+    if constexpr (TPW == 1) {
+        red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = fx;
+        red[(1 * PD_TILE_WAVES + wv) * 64 + lane] = fy;
+        red[(2 * PD_TILE_WAVES + wv) * 64 + lane] = fz;
+        __syncthreads();
+        if (wv != 0) return;
+        sx = red[lane];
+        sy = red[PD_TILE_WAVES * 64 + lane];
+        sz = red[2 * PD_TILE_WAVES * 64 + lane];
+        for (int q = 1; q < PD_TILE_WAVES; q++) {
+            sx += red[q * 64 + lane];
+            sy += red[(PD_TILE_WAVES + q) * 64 + lane];
+            sz += red[(2 * PD_TILE_WAVES + q) * 64 + lane];
+        }
     }
+    if (!valid) return;
     const double4 ui = a.uv[cur][row];
     const double4 D = a.dsum[row];
     const float4 fe = a.fe32[row];
@@ -402,7 +440,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         return;
     }
     const int64_t n = ctl->s1;
-    if (tile == 0 && tid == 0) ctl->s2 = n + 1;
+    if (tile == 0 && gt == 0) ctl->s2 = n + 1;
     const double Qn = ctl->qs[cur ^ 1];
     double r = 1.0;
     if (a.ramp_steps > 0) r = n >= a.ramp_steps ? 1.0 : (double)n / (double)a.ramp_steps;
@@ -538,16 +576,16 @@ hipError_t launch_tdsum(const StepArgs &a, int cur, hipStream_t s) {
     return hipGetLastError();
 }
 
-static size_t tiled_lds(const StepArgs &a, int pass) {
+static int box_slots(const StepArgs &a) {
     int32_t B[3];
     pd_tile_box(a.tile, a.reach, a.dim, B);
-    const size_t nslot = (size_t)B[0] * B[1] * B[2], nslot2 = (nslot + 1) & ~(size_t)1;
-    size_t b;
-    if (pass == 1)
-        b = tile1_region0((int)nslot);
-    else
-        b = nslot2 * sizeof(float2) + 3 * PD_TILE_WAVES * 64 * sizeof(float);
-    return b + 128 * sizeof(uint64_t) + 32 * sizeof(int);
+    return B[0] * B[1] * B[2];
+}
+
+static size_t tiled_lds(const StepArgs &a, int pass, int tpw) {
+    const int ns = box_slots(a);
+    if (tpw == 1) return pass == 1 ? tile1_bytes<1>(ns) : tile2_bytes<1>(ns);
+    return (size_t)tpw * (pass == 1 ? tile1_bytes<4>(ns) : tile2_bytes<4>(ns));
 }
 
 bool tiled_supported(const StepArgs &a) {
@@ -557,38 +595,46 @@ bool tiled_supported(const StepArgs &a) {
     if (a.dim == 3 && a.tile[2] < a.reach) return false;
     if (a.dim == 2 && a.tile[2] != 1) return false;
     if (a.n_stencil > 124) return false;  // groups of four inside the 128-row table
-    int32_t B[3];
-    pd_tile_box(a.tile, a.reach, a.dim, B);
-    const int cap = (a.dim == 3 ? StageCap<3>::value : StageCap<2>::value) * PD_TILE_THREADS;
-    if (B[0] * B[1] * B[2] > cap) return false;
-    return tiled_lds(a, 1) <= 64 * 1024 && tiled_lds(a, 2) <= 64 * 1024;
+    const int ns = box_slots(a);
+    const int tpw = tiles_per_group(a.dim, ns);
+    const int cap = a.dim == 3 ? Grp<3, 1>::CAP : (tpw == 4 ? Grp<2, 4>::CAP : Grp<2, 1>::CAP);
+    if (ns > cap) return false;
+    return tiled_lds(a, 1, tpw) <= 64 * 1024 && tiled_lds(a, 2, tpw) <= 64 * 1024;
 }
 
 hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s) {
-    const size_t lds = tiled_lds(a, 1);
-    const dim3 g((unsigned)a.n_slices), b(PD_TILE_THREADS);
+    const int tpw = tiles_per_group(a.dim, box_slots(a));
+    const size_t lds = tiled_lds(a, 1, tpw);
+    const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     if (a.dim == 3) {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true>), g, b, lds, s, a, cur, kt);
-        else hipLaunchKernelGGL((k_tpass1_f32<3, false>), g, b, lds, s, a, cur, kt);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true, 1>), g, b, lds, s, a, cur, kt);
+        else hipLaunchKernelGGL((k_tpass1_f32<3, false, 1>), g, b, lds, s, a, cur, kt);
+    } else if (tpw == 4) {
+        if (brk) hipLaunchKernelGGL((k_tpass1_f32<2, true, 4>), g, b, lds, s, a, cur, kt);
+        else hipLaunchKernelGGL((k_tpass1_f32<2, false, 4>), g, b, lds, s, a, cur, kt);
     } else {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f32<2, true>), g, b, lds, s, a, cur, kt);
-        else hipLaunchKernelGGL((k_tpass1_f32<2, false>), g, b, lds, s, a, cur, kt);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f32<2, true, 1>), g, b, lds, s, a, cur, kt);
+        else hipLaunchKernelGGL((k_tpass1_f32<2, false, 1>), g, b, lds, s, a, cur, kt);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_tpass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s) {
-    const size_t lds = tiled_lds(a, 2);
-    const dim3 g((unsigned)a.n_slices), b(PD_TILE_THREADS);
+    const int tpw = tiles_per_group(a.dim, box_slots(a));
+    const size_t lds = tiled_lds(a, 2, tpw);
+    const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     const uint64_t *km = a.mask;
     if (a.dim == 3) {
-        if (update) hipLaunchKernelGGL((k_tpass2_f32<3, true>), g, b, lds, s, a, cur, kt, km);
-        else hipLaunchKernelGGL((k_tpass2_f32<3, false>), g, b, lds, s, a, cur, kt, km);
+        if (update) hipLaunchKernelGGL((k_tpass2_f32<3, true, 1>), g, b, lds, s, a, cur, kt, km);
+        else hipLaunchKernelGGL((k_tpass2_f32<3, false, 1>), g, b, lds, s, a, cur, kt, km);
+    } else if (tpw == 4) {
+        if (update) hipLaunchKernelGGL((k_tpass2_f32<2, true, 4>), g, b, lds, s, a, cur, kt, km);
+        else hipLaunchKernelGGL((k_tpass2_f32<2, false, 4>), g, b, lds, s, a, cur, kt, km);
     } else {
-        if (update) hipLaunchKernelGGL((k_tpass2_f32<2, true>), g, b, lds, s, a, cur, kt, km);
-        else hipLaunchKernelGGL((k_tpass2_f32<2, false>), g, b, lds, s, a, cur, kt, km);
+        if (update) hipLaunchKernelGGL((k_tpass2_f32<2, true, 1>), g, b, lds, s, a, cur, kt, km);
+        else hipLaunchKernelGGL((k_tpass2_f32<2, false, 1>), g, b, lds, s, a, cur, kt, km);
     }
     return hipGetLastError();
 }

@@ -26,11 +26,19 @@
 
 namespace pdk {
 
-// fixed array stride in the LDS box (doubles): room for every slot a
-// workgroup can stage
+// LDS of one tile: NA arrays of doubles at the fixed stride S (room for every
+// slot the tile's thread group can stage, a multiple of 64 elements), then the
+// tile's 128 status words and 27 neighbour tiles.  With TPW = 1 the partial
+// sums of the four waves reuse the arrays after the sweep.
+template <int DIM, int TPW, int NA>
+struct Lay64 {
+    static constexpr int S = Grp<DIM, TPW>::CAP;
+    static constexpr int BYTES = NA * S * 8 + 128 * 8 + 32 * 4;
+};
+// pass 1: G V/m, u_x, u_y, (u_z,) V;  pass 2: (K - G/3) theta/m, V
 template <int DIM>
-struct Stride64 {
-    static constexpr int value = StageCap<DIM>::value * PD_TILE_THREADS;
+struct NA1 {
+    static constexpr int value = DIM == 3 ? 5 : 4;
 };
 
 __device__ __forceinline__ double ext_canonical64(double m1, double m2, double m3, double e1, double e2,
@@ -45,21 +53,28 @@ __device__ __forceinline__ double ext_canonical64(double m1, double m2, double m
 // ---------------------------------------------------------------------------
 // pass 1: breaking, dilatation, deviatoric pair force
 // ---------------------------------------------------------------------------
-template <int DIM, bool BREAK>
+template <int DIM, bool BREAK, int TPW>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int cur, const KEnt *__restrict__ kt,
                                                                 const double4 *__restrict__ sten) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int MS = StageCap<DIM>::value;
-    constexpr int S = Stride64<DIM>::value;
+    using GR = Grp<DIM, TPW>;
+    constexpr int MS = GR::MS;
+    constexpr int NA = NA1<DIM>::value;
+    using LY = Lay64<DIM, TPW, NA>;
+    constexpr int S = LY::S;
+    constexpr int IV = NA - 1;  // index of the V array
     const Box g = make_box(a, DIM);
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int gt = TPW == 1 ? tid : lane;
+    const int sub = TPW == 1 ? 0 : wv;
+    const int kq = TPW == 1 ? wv : 0;
+    bool valid;
+    const int64_t tile = group_tile<TPW>(a.n_slices, sub, valid);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
-    // [0] G V_j / m_j, [1..3] u_j, [4] V_j; reused for the partial sums
-    double *hA = reinterpret_cast<double *>(smem);
-    uint64_t *smask = reinterpret_cast<uint64_t *>(hA + 5 * S);
+    double *hA = reinterpret_cast<double *>(smem + sub * LY::BYTES);
+    uint64_t *smask = reinterpret_cast<uint64_t *>(hA + NA * S);
     int *stn = reinterpret_cast<int *>(smask + 128);
     pd_ctl *ctl = a.ctl;
     const double4 *__restrict__ uv = a.uv[cur];
@@ -69,11 +84,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
     int hmv[MS];
 #pragma unroll
     for (int i = 0; i < MS; i++) {
-        const int s = tid + i * PD_TILE_THREADS;
+        const int s = gt + i * GR::NT;
         hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
     }
-    if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
-    const uint64_t mword = tid < L4 ? mrow[tid] : 0ull;
+    if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
+    const uint64_t mw0 = gt < L4 ? mrow[gt] : 0ull;
+    const uint64_t mw1 = (TPW != 1 && gt + 64 < L4) ? mrow[gt + 64] : 0ull;
     const pd_spec sp = a.spec[tile_specimen(a.aux[row])];
     const double G = sp.G;
     __syncthreads();
@@ -92,19 +108,20 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            const int s = tid + i * PD_TILE_THREADS;
+            const int s = gt + i * GR::NT;
             if (s < g.nslot) {
                 hA[s] = G * r[i] * u[i].w;
                 hA[S + s] = u[i].x;
                 hA[2 * S + s] = u[i].y;
                 if (DIM == 3) hA[3 * S + s] = u[i].z;
-                hA[4 * S + s] = u[i].w;
+                hA[IV * S + s] = u[i].w;
             }
         }
     }
-    if (tid < 128) smask[tid] = mword;
+    if (gt < 128) smask[gt] = mw0;
+    if (TPW != 1) smask[gt + 64] = mw1;
     __syncthreads();
-    if (BREAK && tile == 0 && tid == 0) ctl->s1 = ctl->s2;
+    if (BREAK && valid && tile == 0 && gt == 0) ctl->s1 = ctl->s2;
     const int my = own_slot<DIM>(g, lane);
     const double uix = hA[S + my], uiy = hA[2 * S + my], uiz = DIM == 3 ? hA[3 * S + my] : 0.0;
     const double ri = qr[row].y;
@@ -113,8 +130,8 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
     const double thr_scale = s0 * (1.0 - 1e-9);  // pre-filter, exact test below
     const int ns = a.n_stencil;
     const int G4 = L4 >> 2;
-    const int gper = (G4 + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
-    const int g0 = wv * gper, g1 = min(G4, g0 + gper);
+    const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
+    const int g0 = kq * gper, g1 = min(G4, g0 + gper);
     double acc = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     uint32_t nbroken = 0;
     for (int gg = g0; gg < g1; gg++) {
@@ -130,7 +147,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
             ux[c] = hA[S + slot];
             uy[c] = hA[2 * S + slot];
             uz[c] = DIM == 3 ? hA[3 * S + slot] : 0.0;
-            vj[c] = hA[4 * S + slot];
+            vj[c] = hA[IV * S + slot];
             mm[c] = uni64_t(smask[k]);
         }
 #pragma unroll
@@ -139,21 +156,20 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
             const double dx = ux[c] - uix, dy = uy[c] - uiy, dz = DIM == 3 ? uz[c] - uiz : 0.0;
             const double ev = DIM == 3 ? ext_canonical64(sd[c].x, sd[c].y, sd[c].z, dx, dy, dz)
                                        : ext_canonical64(sd[c].x, sd[c].y, 0.0, dx, dy, 0.0);
-            bool intact = lane_bit(mm[c]);
+            uint64_t live = mm[c];
             if (BREAK) {
-                bool broke = false;
-                if (intact && ev >= thr_scale * sd[c].w) {
-                    if (ev / sd[c].w >= s0) {
-                        intact = false;
-                        broke = true;
+                const bool need = lane_bit(live) && ev >= thr_scale * sd[c].w;
+                const uint64_t needm = __ballot(need);
+                if (needm) {
+                    const uint64_t bb = __ballot(need && ev / sd[c].w >= s0);
+                    if (bb) {
+                        live &= ~bb;
+                        if (lane == 0 && valid) mrow[k] = live;
+                        nbroken += __popcll(bb);
                     }
                 }
-                const uint64_t bb = __ballot(broke);
-                if (bb) {
-                    if (lane == 0) mrow[k] = mm[c] & ~bb;
-                    nbroken += __popcll(bb);
-                }
             }
+            const bool intact = lane_bit(live);
             // dilatation: x V_j e;  deviatoric force: G e (1/m_i + 1/m_j) V_j
             const double xv = sd[c].w * vj[c];
             acc = fma(intact ? xv : 0.0, ev, acc);
@@ -163,21 +179,22 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
             if (DIM == 3) fz = fma(te, sd[c].z, fz);
         }
     }
-    if (BREAK && lane == 0 && nbroken) atomicAdd(&ctl->broken, (unsigned long long)nbroken);
-    __syncthreads();  // every wave is done with the staged box: reuse it for the sums
-    double *red = hA;
-    red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = acc;
-    red[(1 * PD_TILE_WAVES + wv) * 64 + lane] = fx;
-    red[(2 * PD_TILE_WAVES + wv) * 64 + lane] = fy;
-    red[(3 * PD_TILE_WAVES + wv) * 64 + lane] = fz;
-    __syncthreads();
-    if (wv != 0) return;
-    double tot[4];
+    if (BREAK && valid && lane == 0 && nbroken) atomicAdd(&ctl->broken, (unsigned long long)nbroken);
+    double tot[4] = {acc, fx, fy, fz};
+    if constexpr (TPW == 1) {
+        __syncthreads();  // every wave is done with the staged box: reuse it for the sums
+        double *red = hA;
 #pragma unroll
-    for (int v = 0; v < 4; v++) {
-        tot[v] = red[v * PD_TILE_WAVES * 64 + lane];
-        for (int q = 1; q < PD_TILE_WAVES; q++) tot[v] += red[(v * PD_TILE_WAVES + q) * 64 + lane];
+        for (int v = 0; v < 4; v++) red[(v * PD_TILE_WAVES + wv) * 64 + lane] = tot[v];
+        __syncthreads();
+        if (wv != 0) return;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            tot[v] = red[v * PD_TILE_WAVES * 64 + lane];
+            for (int q = 1; q < PD_TILE_WAVES; q++) tot[v] += red[(v * PD_TILE_WAVES + q) * 64 + lane];
+        }
     }
+    if (!valid) return;
     // theta_i = A / m_i * acc; store theta_i / m_i
     a.qr[row].x = sp.A * ri * tot[0] * ri;
     if (a.theta_out) a.theta_out[row] = sp.A * ri * tot[0];
@@ -187,20 +204,26 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
 // ---------------------------------------------------------------------------
 // pass 2: dilatational pair force, explicit update
 // ---------------------------------------------------------------------------
-template <int DIM, bool UPDATE>
+template <int DIM, bool UPDATE, int TPW>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int cur, const KEnt *__restrict__ kt,
                                                                 const double4 *__restrict__ sten) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int MS = StageCap<DIM>::value;
-    constexpr int S = Stride64<DIM>::value;
+    using GR = Grp<DIM, TPW>;
+    constexpr int MS = GR::MS;
+    using LY = Lay64<DIM, TPW, 2>;
+    constexpr int S = LY::S;
     const Box g = make_box(a, DIM);
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int gt = TPW == 1 ? tid : lane;
+    const int sub = TPW == 1 ? 0 : wv;
+    const int kq = TPW == 1 ? wv : 0;
+    bool valid;
+    const int64_t tile = group_tile<TPW>(a.n_slices, sub, valid);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
     // [0] (K - G/3) theta_j / m_j, [1] V_j; reused for the partial sums
-    double *hB = reinterpret_cast<double *>(smem);
+    double *hB = reinterpret_cast<double *>(smem + sub * LY::BYTES);
     uint64_t *smask = reinterpret_cast<uint64_t *>(hB + 2 * S);
     int *stn = reinterpret_cast<int *>(smask + 128);
     pd_ctl *ctl = a.ctl;
@@ -208,14 +231,16 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
     const double2 *__restrict__ qr = a.qr;
     const int64_t row = tile * 64 + lane;
     const uint32_t aux = a.aux[row];
+    const uint64_t *mrow = a.mask + (base >> 6);
     int hmv[MS];
 #pragma unroll
     for (int i = 0; i < MS; i++) {
-        const int s = tid + i * PD_TILE_THREADS;
+        const int s = gt + i * GR::NT;
         hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
     }
-    if (tid < 27) stn[tid] = a.tile_nbr[27 * tile + tid];
-    const uint64_t mword = tid < L4 ? a.mask[(base >> 6) + tid] : 0ull;
+    if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
+    const uint64_t mw0 = gt < L4 ? mrow[gt] : 0ull;
+    const uint64_t mw1 = (TPW != 1 && gt + 64 < L4) ? mrow[gt + 64] : 0ull;
     const pd_spec sp = a.spec[tile_specimen(aux)];
     const double kp = sp.kp;
     __syncthreads();
@@ -233,21 +258,22 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            const int s = tid + i * PD_TILE_THREADS;
+            const int s = gt + i * GR::NT;
             if (s < g.nslot) {
                 hB[s] = kp * q[i];
                 hB[S + s] = v[i];
             }
         }
     }
-    if (tid < 128) smask[tid] = mword;
+    if (gt < 128) smask[gt] = mw0;
+    if (TPW != 1) smask[gt + 64] = mw1;
     __syncthreads();
     const int my = own_slot<DIM>(g, lane);
     const double qi = hB[my];
     const int ns = a.n_stencil;
     const int G4 = L4 >> 2;
-    const int gper = (G4 + PD_TILE_WAVES - 1) / PD_TILE_WAVES;
-    const int g0 = wv * gper, g1 = min(G4, g0 + gper);
+    const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
+    const int g0 = kq * gper, g1 = min(G4, g0 + gper);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int gg = g0; gg < g1; gg++) {
         double qj[4], vj[4];
@@ -272,19 +298,25 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
             if (DIM == 3) fz = fma(t, sd[c].z, fz);
         }
     }
-    __syncthreads();
-    double *red = hB;
-    red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = fx;
-    red[(1 * PD_TILE_WAVES + wv) * 64 + lane] = fy;
-    red[(2 * PD_TILE_WAVES + wv) * 64 + lane] = fz;
-    __syncthreads();
-    if (wv != 0) return;
-    double sx = red[lane], sy = red[PD_TILE_WAVES * 64 + lane], sz = red[2 * PD_TILE_WAVES * 64 + lane];
-    for (int q = 1; q < PD_TILE_WAVES; q++) {
-        sx += red[q * 64 + lane];
-        sy += red[(PD_TILE_WAVES + q) * 64 + lane];
-        sz += red[(2 * PD_TILE_WAVES + q) * 64 + lane];
+    double sx = fx, sy = fy, sz = fz;
+    if constexpr (TPW == 1) {
+        __syncthreads();
+        double *red = hB;
+        red[(0 * PD_TILE_WAVES + wv) * 64 + lane] = fx;
+        red[(1 * PD_TILE_WAVES + wv) * 64 + lane] = fy;
+        red[(2 * PD_TILE_WAVES + wv) * 64 + lane] = fz;
+        __syncthreads();
+        if (wv != 0) return;
+        sx = red[lane];
+        sy = red[PD_TILE_WAVES * 64 + lane];
+        sz = red[2 * PD_TILE_WAVES * 64 + lane];
+        for (int q = 1; q < PD_TILE_WAVES; q++) {
+            sx += red[q * 64 + lane];
+            sy += red[(PD_TILE_WAVES + q) * 64 + lane];
+            sz += red[(2 * PD_TILE_WAVES + q) * 64 + lane];
+        }
     }
+    if (!valid) return;
     const double4 ui = uv[row];
     const double4 fe = a.fe64[row];
     double Fx = (sx + fe.x) * ui.w;
@@ -295,7 +327,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
         return;
     }
     const int64_t n = ctl->s1;
-    if (tile == 0 && tid == 0) ctl->s2 = n + 1;
+    if (tile == 0 && gt == 0) ctl->s2 = n + 1;
     double r = 1.0;
     if (a.ramp_steps > 0) r = n >= a.ramp_steps ? 1.0 : (double)n / (double)a.ramp_steps;
     if (aux & 8u) {
@@ -322,44 +354,60 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
     if (__ballot(bad) && lane == 0) atomicOr(&ctl->flags, PD_CTL_NONFINITE);
 }
 
-static size_t tiled64_lds(int dim, int pass) {
-    const size_t S = dim == 3 ? Stride64<3>::value : Stride64<2>::value;
-    return (pass == 1 ? 5 : 2) * S * sizeof(double) + 128 * sizeof(uint64_t) + 32 * sizeof(int);
+static int box_slots64(const StepArgs &a) {
+    int32_t B[3];
+    pd_tile_box(a.tile, a.reach, a.dim, B);
+    return B[0] * B[1] * B[2];
+}
+
+static size_t tiled64_lds(int dim, int pass, int tpw) {
+    if (dim == 3) return pass == 1 ? Lay64<3, 1, 5>::BYTES : Lay64<3, 1, 2>::BYTES;
+    if (tpw == 4) return 4 * (size_t)(pass == 1 ? Lay64<2, 4, 4>::BYTES : Lay64<2, 4, 2>::BYTES);
+    return pass == 1 ? Lay64<2, 1, 4>::BYTES : Lay64<2, 1, 2>::BYTES;
 }
 
 bool tiled64_supported(const StepArgs &a) {
     if (!a.fe64 || !tiled_supported(a)) return false;
-    // the partial sums reuse the staged arrays
-    if (tiled64_lds(a.dim, 2) < 3 * PD_TILE_WAVES * 64 * sizeof(double) + 128 * sizeof(uint64_t)) return false;
-    return tiled64_lds(a.dim, 1) <= 64 * 1024;
+    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    // the partial sums of TPW = 1 reuse the staged arrays (2 of them in pass 2)
+    if (tpw == 1 && 2 * (a.dim == 3 ? Grp<3, 1>::CAP : Grp<2, 1>::CAP) < 3 * PD_TILE_WAVES * 64) return false;
+    return tiled64_lds(a.dim, 1, tpw) <= 64 * 1024 && tiled64_lds(a.dim, 2, tpw) <= 64 * 1024;
 }
 
 hipError_t launch_tpass1_f64(const StepArgs &a, int cur, bool brk, hipStream_t s) {
-    const size_t lds = tiled64_lds(a.dim, 1);
-    const dim3 g((unsigned)a.n_slices), b(PD_TILE_THREADS);
+    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    const size_t lds = tiled64_lds(a.dim, 1, tpw);
+    const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     const double4 *sten = reinterpret_cast<const double4 *>(a.stencil);
     if (a.dim == 3) {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f64<3, true>), g, b, lds, s, a, cur, kt, sten);
-        else hipLaunchKernelGGL((k_tpass1_f64<3, false>), g, b, lds, s, a, cur, kt, sten);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f64<3, true, 1>), g, b, lds, s, a, cur, kt, sten);
+        else hipLaunchKernelGGL((k_tpass1_f64<3, false, 1>), g, b, lds, s, a, cur, kt, sten);
+    } else if (tpw == 4) {
+        if (brk) hipLaunchKernelGGL((k_tpass1_f64<2, true, 4>), g, b, lds, s, a, cur, kt, sten);
+        else hipLaunchKernelGGL((k_tpass1_f64<2, false, 4>), g, b, lds, s, a, cur, kt, sten);
     } else {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f64<2, true>), g, b, lds, s, a, cur, kt, sten);
-        else hipLaunchKernelGGL((k_tpass1_f64<2, false>), g, b, lds, s, a, cur, kt, sten);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f64<2, true, 1>), g, b, lds, s, a, cur, kt, sten);
+        else hipLaunchKernelGGL((k_tpass1_f64<2, false, 1>), g, b, lds, s, a, cur, kt, sten);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_tpass2_f64(const StepArgs &a, int cur, bool update, hipStream_t s) {
-    const size_t lds = tiled64_lds(a.dim, 2);
-    const dim3 g((unsigned)a.n_slices), b(PD_TILE_THREADS);
+    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    const size_t lds = tiled64_lds(a.dim, 2, tpw);
+    const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     const double4 *sten = reinterpret_cast<const double4 *>(a.stencil);
     if (a.dim == 3) {
-        if (update) hipLaunchKernelGGL((k_tpass2_f64<3, true>), g, b, lds, s, a, cur, kt, sten);
-        else hipLaunchKernelGGL((k_tpass2_f64<3, false>), g, b, lds, s, a, cur, kt, sten);
+        if (update) hipLaunchKernelGGL((k_tpass2_f64<3, true, 1>), g, b, lds, s, a, cur, kt, sten);
+        else hipLaunchKernelGGL((k_tpass2_f64<3, false, 1>), g, b, lds, s, a, cur, kt, sten);
+    } else if (tpw == 4) {
+        if (update) hipLaunchKernelGGL((k_tpass2_f64<2, true, 4>), g, b, lds, s, a, cur, kt, sten);
+        else hipLaunchKernelGGL((k_tpass2_f64<2, false, 4>), g, b, lds, s, a, cur, kt, sten);
     } else {
-        if (update) hipLaunchKernelGGL((k_tpass2_f64<2, true>), g, b, lds, s, a, cur, kt, sten);
-        else hipLaunchKernelGGL((k_tpass2_f64<2, false>), g, b, lds, s, a, cur, kt, sten);
+        if (update) hipLaunchKernelGGL((k_tpass2_f64<2, true, 1>), g, b, lds, s, a, cur, kt, sten);
+        else hipLaunchKernelGGL((k_tpass2_f64<2, false, 1>), g, b, lds, s, a, cur, kt, sten);
     }
     return hipGetLastError();
 }

@@ -114,4 +114,33 @@ struct StageCap {
     static constexpr int value = DIM == 3 ? 5 : 2;
 };
 
+// How the four waves of a workgroup share the work: TPW tiles per workgroup.
+//   TPW = 1: the four waves split the stencil of one tile in quarters and add
+//            their partial sums in LDS (3D: a long stencil, a large halo box);
+//   TPW = 4: every wave takes a whole tile of its own (2D: a short stencil,
+//            whose quarters would leave each wave too little work per box).
+// SPLIT waves share a tile; NT threads stage its box, MS slots each, so a box
+// holds at most NT * MS slots (TPW = 4: 256).
+template <int DIM, int TPW>
+struct Grp {
+    static constexpr int SPLIT = PD_TILE_WAVES / TPW;
+    static constexpr int NT = 64 * SPLIT;
+    static constexpr int MS = TPW == 1 ? StageCap<DIM>::value : 4;
+    static constexpr int CAP = NT * MS;
+};
+
+// tile of this wave; waves of the last workgroup past the last tile (TPW > 1)
+// redo the last tile and must not write
+template <int TPW>
+__device__ __forceinline__ int64_t group_tile(int64_t n_tiles, int sub, bool &valid) {
+    const int64_t groups = (n_tiles + TPW - 1) / TPW;
+    const int64_t t = xcd_tile(blockIdx.x, groups) * TPW + sub;
+    valid = t < n_tiles;
+    return valid ? t : n_tiles - 1;
+}
+
+// workgroup tiling the launchers choose: whole tiles per wave in 2D when the
+// halo box fits the per-wave staging capacity
+inline int tiles_per_group(int dim, int nslot) { return (dim == 2 && nslot <= Grp<2, 4>::CAP) ? 4 : 1; }
+
 }  // namespace pdk

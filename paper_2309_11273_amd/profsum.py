@@ -1,0 +1,146 @@
+"""Summaries of rocprofv3 output for the committed profile records.
+
+  python -m paper_2309_11273_amd.profsum stats  CSV --command CMD
+      kernel-trace statistics (--kernel-trace --stats) as a markdown table
+  python -m paper_2309_11273_amd.profsum pmc    CSV [CSV ...] --command CMD [--command CMD ...]
+      per-kernel averages of the counters of --pmc runs as a markdown table
+  python -m paper_2309_11273_amd.profsum traffic --fetch CSV --write CSV --workload NAME
+                                                 --copy-bytes N --out JSON
+      HBM bytes per launch of every solver kernel from a FETCH_SIZE run and a
+      WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
+      reads for a plain read-and-write kernel of N bytes each way launched
+      in the same process; merged into the JSON file under
+      "<kernel>@<workload>" with the hash of the kernel's sources
+
+Nothing here touches the GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+# source files each solver kernel is compiled from
+KERNEL_SOURCES = {
+    "k_tpass1_f32": ["kernels_tiled.hip", "tile_common.h"], "k_tpass2_f32": ["kernels_tiled.hip", "tile_common.h"],
+    "k_tpass1_f64": ["kernels_tiled64.hip", "tile_common.h"], "k_tpass2_f64": ["kernels_tiled64.hip", "tile_common.h"],
+    "k_tdsum": ["kernels_tiled.hip", "tile_common.h"],
+    "k_pass1_f32": ["kernels_f32.hip"], "k_pass2_f32": ["kernels_f32.hip"],
+    "k_pass1_f64": ["kernels.hip"], "k_pass2_f64": ["kernels.hip"],
+}
+
+# the known-size reference kernel bench.py --copy-mb launches (torch.mul out=)
+COPY_KERNEL_MARK = "MulFunctor"
+
+
+def kernel_source_hash(kname: str) -> str:
+    """Hash of the sources a kernel is compiled from (and the shared header)."""
+    h = hashlib.sha256()
+    for fname in KERNEL_SOURCES[kname] + ["kernels.h"]:
+        with open(os.path.join(CSRC, fname), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(full: str) -> str:
+    """'void pdk::k_tpass1_f32<3, true>(...)' -> 'k_tpass1_f32<3, true>'."""
+    n = full.split("(")[0].replace("void ", "").strip()
+    return n.split("::")[-1] if n.startswith("pdk::") else n
+
+
+def base_name(full: str) -> str:
+    return short_name(full).split("<")[0]
+
+
+def stats_md(path: str, command: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = [f"Command: `{command}`", "",
+           "| kernel | calls | average (us) | min (us) | max (us) | total (ms) | % |",
+           "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def counter_means(paths):
+    """{kernel short name: {counter: mean value per dispatch}}."""
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for p in paths:
+        for r in csv.DictReader(open(p)):
+            acc[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+
+
+def pmc_md(paths, commands) -> str:
+    m = counter_means(paths)
+    counters = sorted({c for d in m.values() for c in d})
+    out = [f"Command: `{c}`" for c in commands] + ["", "Mean per dispatch.", "",
+                                                    "| kernel | " + " | ".join(counters) + " |",
+                                                    "|---|" + "---|" * len(counters)]
+    for k in sorted(m):
+        if not (k.startswith("k_") or COPY_KERNEL_MARK in k):
+            continue
+        name = "copy reference (torch.mul)" if COPY_KERNEL_MARK in k else f"`{k}`"
+        out.append(f"| {name} | " + " | ".join(f"{m[k].get(c, float('nan')):.0f}" for c in counters) + " |")
+    return "\n".join(out) + "\n"
+
+
+def traffic(fetch_csv: str, write_csv: str, copy_bytes: int, workload: str, out_json: str) -> dict:
+    fm, wm = counter_means([fetch_csv]), counter_means([write_csv])
+    ref = [k for k in fm if COPY_KERNEL_MARK in k]
+    if not ref:
+        raise SystemExit("no reference copy kernel in the FETCH_SIZE run")
+    kf = copy_bytes / (fm[ref[0]]["FETCH_SIZE"] * 1024.0)
+    kw = copy_bytes / (wm[ref[0]]["WRITE_SIZE"] * 1024.0)
+    db = json.load(open(out_json)) if os.path.exists(out_json) else {}
+    for k in fm:
+        b = base_name(k)
+        if b not in KERNEL_SOURCES or k not in wm:
+            continue
+        fetch = fm[k]["FETCH_SIZE"] * 1024.0 * kf
+        write = wm[k]["WRITE_SIZE"] * 1024.0 * kw
+        db[f"{b}@{workload}"] = {"bytes_per_launch": int(fetch + write), "fetch_bytes": int(fetch),
+                                 "write_bytes": int(write), "fetch_scale": round(kf, 4),
+                                 "write_scale": round(kw, 4), "source_sha": kernel_source_hash(b)}
+    with open(out_json, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return db
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="profsum")
+    sp = ap.add_subparsers(dest="cmd", required=True)
+    a = sp.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--command", required=True)
+    b = sp.add_parser("pmc")
+    b.add_argument("csv", nargs="+")
+    b.add_argument("--command", action="append", required=True)
+    c = sp.add_parser("traffic")
+    c.add_argument("--fetch", required=True)
+    c.add_argument("--write", required=True)
+    c.add_argument("--copy-bytes", type=int, required=True)
+    c.add_argument("--workload", required=True)
+    c.add_argument("--out", required=True)
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        sys.stdout.write(stats_md(args.csv, args.command))
+    elif args.cmd == "pmc":
+        sys.stdout.write(pmc_md(args.csv, args.command))
+    else:
+        json.dump(traffic(args.fetch, args.write, args.copy_bytes, args.workload, args.out), sys.stdout, indent=1)
+        sys.stdout.write("\n")
+
+
+if __name__ == "__main__":
+    main()

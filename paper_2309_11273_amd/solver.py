@@ -348,12 +348,13 @@ class Solver:
                 json.dump(data, f, indent=1)
         return res
 
-    def tiled_supported(self) -> bool:
-        """Whether the LDS-staged tile kernels apply (tile edges >= stencil reach)."""
-        s = self.fam.sizes
-        T = list(s.tile)
-        R = int(s.reach)
-        return T[0] * T[1] * T[2] == 64 and min(T[: int(s.dim)]) >= R and R >= 1
+    def tiled_supported(self, precision: str = "fp32") -> bool:
+        """Whether kernel='auto' runs the LDS-staged tile kernels (pd_tile_kernels_apply)."""
+        yes = C.c_int32(0)
+        self.ctx.check("pd_tile_kernels_apply", A.load().pd_tile_kernels_apply(
+            C.byref(self.P), C.byref(self.S), {"fp64": A.PD_FP64, "fp32": A.PD_FP32_RECHECK}[precision],
+            C.byref(yes)))
+        return bool(yes.value)
 
     def profile_read(self, reset: bool = True) -> dict:
         p = A.pd_profile_stats()

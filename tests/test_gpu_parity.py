@@ -36,8 +36,18 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def wide_plate():
+    """2D plate with a 5.015 dx horizon: its halo box (18 x 18 slots) is too
+    large for one wave per tile, so the 2D tile kernels split the stencil
+    over the four waves instead."""
+    w = W.plate2d(nx=48, ny=24, dt=1.2e-7, sigma=5e6, G0=None, notch_row=11, notch_tip=23.37, steps=200)
+    w.delta = 5.015 * w.dx
+    return w
+
+
 def small_workloads():
     return {
+        "plate_wide": wide_plate(),
         "cantilever": W.cantilever3d(),
         "plate_notched": W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37,
                                    steps=300),
@@ -49,7 +59,8 @@ def small_workloads():
     }
 
 
-@pytest.mark.parametrize("name", ["cantilever", "plate_notched", "plane_strain", "impact", "cylinder", "batch"])
+@pytest.mark.parametrize("name", ["cantilever", "plate_notched", "plane_strain", "impact", "cylinder", "batch",
+                                  "plate_wide"])
 def test_force_matches_reference(ctx, name):
     """One force evaluation (Eqs. 2.3, 2.2) for a random displacement and a
     random set of broken bonds."""
@@ -87,7 +98,8 @@ def test_force_matches_reference(ctx, name):
 
 @pytest.mark.parametrize("kernel", ["gather", "tiled"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("plane_strain", 100),
-                                        ("impact", 200), ("cylinder", 200), ("batch", 200)])
+                                        ("impact", 200), ("cylinder", 200), ("batch", 200),
+                                        ("plate_wide", 200)])
 def test_fp64_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
     o = Oracle(w)
@@ -125,7 +137,7 @@ def test_plate_full_size_fp64(ctx):
 
 @pytest.mark.parametrize("kernel", ["gather", "tiled"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("impact", 200),
-                                        ("cylinder", 200), ("batch", 200)])
+                                        ("cylinder", 200), ("batch", 200), ("plate_wide", 200)])
 def test_fp32_recheck_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
     o = Oracle(w)

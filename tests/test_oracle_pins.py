@@ -530,3 +530,81 @@ def test_stable_dt_table_matches_power_iteration():
     p = W.load_params()
     for key in ("cantilever3d", "plate2d"):
         assert key in p
+
+
+# ---------------------------------------------------------------------------
+# notch cuts -- initial bond status (reading R11): brute force by sampling
+# ---------------------------------------------------------------------------
+
+def _sampled_cuts(P, Q, cut, nsamp=256):
+    """For bonds P[b]-Q[b]: whether the segment crosses the notch patch,
+    found by sampling it densely -- a sign change of the side function
+    between neighbouring samples is a crossing, its point interpolated
+    between those two samples only, and it must lie in the patch.  Returns
+    (cut?, distance of the nearest crossing point from the patch edge, in
+    patch units for planar patches and in bond lengths for the helicoid)."""
+    t = np.linspace(0.0, 1.0, nsamp + 1)
+    t[1:-1] += 0.37 / nsamp  # interior samples off the rational fractions where lattice bonds cross
+    p = np.asarray(cut.p, float)
+    hit = np.zeros(len(P), bool)
+    margin = np.full(len(P), np.inf)
+    for lo in range(0, len(P), 4096):
+        Pc, Qc = P[lo:lo + 4096], Q[lo:lo + 4096]
+        X = Pc[:, None, :] + t[None, :, None] * (Qc - Pc)[:, None, :]
+        if cut.kind == "segment2d":
+            A, B = p[0:2], p[2:4]
+            g = (B[0] - A[0]) * (X[..., 1] - A[1]) - (B[1] - A[1]) * (X[..., 0] - A[0])
+        elif cut.kind == "rect3d":
+            c, a, b = p[0:3], p[3:6], p[6:9]
+            g = (X - c) @ np.cross(a, b)
+        else:
+            g = (X[..., 2] - p[0]) - p[1] * np.arctan2(X[..., 1], X[..., 0])
+        bb, kk = np.nonzero(g[:, :-1] * g[:, 1:] < 0)
+        for b_, k in zip(bb, kk):
+            w = g[b_, k] / (g[b_, k] - g[b_, k + 1])
+            Y = X[b_, k] + w * (X[b_, k + 1] - X[b_, k])
+            if cut.kind == "segment2d":
+                s_ = np.dot(Y[:2] - A, B - A) / np.dot(B - A, B - A)
+                inside, mg = 0 < s_ < 1, min(abs(s_), abs(1 - s_))
+            elif cut.kind == "rect3d":
+                (s_, u_), *_ = np.linalg.lstsq(np.stack([a, b], 1), Y - c, rcond=None)
+                inside, mg = (0 < s_ < 1 and 0 < u_ < 1), min(abs(s_), abs(1 - s_), abs(u_), abs(1 - u_))
+            else:
+                r, th = math.hypot(Y[0], Y[1]), math.atan2(Y[1], Y[0])
+                inside = p[2] < r < p[3] and p[4] < th < p[5]
+                mg = min(abs(r - p[2]), abs(r - p[3]), r * abs(th - p[4]), r * abs(th - p[5]))
+                mg /= np.linalg.norm(Qc[b_] - Pc[b_])
+            hit[lo + b_] |= inside
+            margin[lo + b_] = min(margin[lo + b_], mg)
+    return hit, margin
+
+
+@pytest.mark.parametrize("case", ["plate", "impact", "cylinder"])
+def test_notch_cuts_match_sampled_crossings(case):
+    """The bonds the oracle starts broken are exactly those whose segment
+    crosses a notch patch, found independently by sampling each segment.
+    Planar patches must agree bond for bond.  On the helicoid the oracle
+    places the crossing by linear interpolation of the level set between the
+    end points (the reading); that point lies on the bond, so the two may
+    differ only where the sampled crossing is within one bond length of the
+    patch edge, and only on a small fraction of the cut bonds."""
+    w = {"plate": lambda: W.plate2d(nx=48, ny=24, dt=1.347e-7, notch_row=11, notch_tip=23.37, steps=10),
+         "impact": lambda: W.impact3d(nx=40, ny=40, nz=6, dt=1e-7, steps=10),
+         "cylinder": lambda: W.cylinder3d(dx=2.5e-3, dt=2.4e-7, twist_rate=8.0, steps=10)}[case]()
+    o = Oracle(w)
+    bi, bj = o.bonds()
+    cut_o = o.rho() == 0
+    X = w.positions()
+    assert cut_o.sum() > 10
+    hit = np.zeros(o.nb, bool)
+    margin = np.full(o.nb, np.inf)
+    for c in w.cuts:
+        h, mg = _sampled_cuts(X[bi], X[bj], c)
+        hit |= h
+        margin = np.minimum(margin, mg)
+    mism = list(margin[hit != cut_o])
+    if case == "cylinder":
+        assert all(m < 1.0 for m in mism), mism[:10]
+        assert len(mism) <= 0.03 * cut_o.sum()
+    else:
+        assert not mism, mism[:10]
