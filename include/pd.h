@@ -178,10 +178,12 @@ typedef struct pd_family_host {
     int32_t *tile_org;    /* [n_tiles*4] lattice origin x,y,z of each tile, specimen */
     int32_t *tile_nbr;    /* [n_tiles*27] tile at offset (dx,dy,dz) in {-1,0,1}^3,
                              index (dz+1)*9 + (dy+1)*3 + (dx+1); -1 if absent        */
-    uint32_t *ktab;       /* [128*8] per-entry table of the LDS-staged kernels: words
-                             0-3 M1, M2, M3, x as float, word 4 the int32 offset of
-                             the entry's neighbour in the tile's LDS halo box, words
-                             5-7 x M1, x M2, x M3 as float; all zero beyond n_stencil */
+    uint32_t *ktab;       /* [128*12] per-entry tables of the LDS-staged kernels, zero
+                             beyond n_stencil.  Rows 0-127, 8 words each: M1, M2, M3,
+                             x as float, the int32 offset of the entry's neighbour in
+                             the tile's LDS halo box, 1/x as float, 0, 0.  Then rows
+                             of 4 words from word 1024: x M1, x M2, x M3 as float, the
+                             same int32 offset                                       */
     int16_t *halo_map;    /* [n_halo] for slot s of the LDS halo box (x fastest):
                              64 * d + l, the point at local position l of the
                              neighbour tile in direction d (tile_nbr index), or -1
@@ -233,7 +235,7 @@ typedef struct pd_problem_dev {
     const int32_t *tile_nbr;    /* [device] n_slices*27 neighbour tiles            */
     int32_t tile[3];            /* tile edge lengths (pd_family_sizes.tile)        */
     int32_t reach;              /* pd_family_sizes.reach                           */
-    const uint32_t *ktab;       /* [device] 128*8 words, pd_family_host.ktab       */
+    const uint32_t *ktab;       /* [device] 128*12 words, pd_family_host.ktab      */
     const int16_t *halo_map;    /* [device] n_halo, pd_family_host.halo_map        */
 } pd_problem_dev;
 

@@ -396,7 +396,7 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
         const int32_t loc = (p[0] - d[0] * T[0]) + T[0] * ((p[1] - d[1] * T[1]) + T[1] * (p[2] - d[2] * T[2]));
         out->halo_map[s] = (int16_t)(64 * dir + loc);
     }
-    for (int q = 0; q < 8 * 128; q++) out->ktab[q] = 0u;
+    for (int q = 0; q < 12 * 128; q++) out->ktab[q] = 0u;
     auto fbits = [](double v) {
         const float f = (float)v;
         uint32_t b;
@@ -413,7 +413,9 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
         out->ktab[8 * s + 3] = fbits(st[s].x);
         const int32_t so = st[s].off[0] + box[0] * (st[s].off[1] + box[1] * st[s].off[2]);
         out->ktab[8 * s + 4] = (uint32_t)so;
-        for (int c = 0; c < 3; c++) out->ktab[8 * s + 5 + c] = fbits(st[s].x * st[s].M[c]);
+        out->ktab[8 * s + 5] = fbits(1.0 / st[s].x);
+        for (int c = 0; c < 3; c++) out->ktab[1024 + 4 * s + c] = fbits(st[s].x * st[s].M[c]);
+        out->ktab[1024 + 4 * s + 3] = (uint32_t)so;
     }
     parallel_for(n_slices, [&](int64_t a, int64_t b) {
         for (int64_t sl = a; sl < b; sl++) {

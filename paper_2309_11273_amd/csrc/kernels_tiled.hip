@@ -155,6 +155,10 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     const double s0 = sp.s0;
     // breaking threshold in units of Q, widened by the float rounding of the test
     const float thrQ = (float)(s0 / Q) * (1.0f - 1e-6f);
+    // screen on e/x: the float extension is off by at most sqrt(3) + 2^-20 * 3 * 2^31
+    // (|shadow| < 2^30), so no bond with e/x below thr_lo can reach the threshold;
+    // entry 0 is the shortest bond of the stencil
+    const float thr_lo = thrQ * (1.0f - 9.5367432e-7f) - 6200.0f * kt[0].ix;
     const int G4 = L4 >> 2;
     const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
     const int g0 = kq * gper, g1 = min(G4, g0 + gper);
@@ -213,21 +217,24 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
                 float ev = e[c].m0 * fdx + e[c].m1 * fdy;
                 if (DIM == 3) ev += e[c].m2 * fdz;
                 if (BREAK) {
-                    // |ev - e64 / Q| <= sqrt(3) + 2^-20 sum |d|: decide in double when
-                    // ev + that bound reaches the threshold
-                    const float lim = thrQ * e[c].x - 1.7320509f;
-                    const float sdd = fabsf(fdx) + fabsf(fdy) + fabsf(fdz);
-                    const bool need = lane_bit(live) && fmaf(9.5367432e-7f, sdd, ev) >= lim;
-                    const uint64_t needm = __ballot(need);
-                    if (needm) {
-                        nrecheck += __popcll(needm);
-                        bool broke = false;
-                        if (need) (void)decide(k, true, broke);
-                        const uint64_t bb = __ballot(broke);
-                        if (bb) {
-                            live &= ~bb;
-                            if (lane == 0 && valid) mrow[k] = live;
-                            nbroken += __popcll(bb);
+                    const uint64_t maybe = __ballot(ev * e[c].ix >= thr_lo) & live;
+                    if (maybe) {
+                        // |ev - e64 / Q| <= sqrt(3) + 2^-20 sum |d|: decide in double when
+                        // ev + that bound reaches the threshold
+                        const float lim = thrQ * e[c].x - 1.7320509f;
+                        const float sdd = fabsf(fdx) + fabsf(fdy) + fabsf(fdz);
+                        const bool need = lane_bit(maybe) && fmaf(9.5367432e-7f, sdd, ev) >= lim;
+                        const uint64_t needm = __ballot(need);
+                        if (needm) {
+                            nrecheck += __popcll(needm);
+                            bool broke = false;
+                            if (need) (void)decide(k, true, broke);
+                            const uint64_t bb = __ballot(broke);
+                            if (bb) {
+                                live &= ~bb;
+                                if (lane == 0 && valid) mrow[k] = live;
+                                nbroken += __popcll(bb);
+                            }
                         }
                     }
                 }
@@ -246,12 +253,11 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
                         }
                     }
                 }
-                const bool intact = lane_bit(live);
+                const float evm = lane_bit(live) ? ev : 0.0f;  // broken bonds carry nothing
                 const float Vj = __int_as_float(sj[c].w);
                 // dilatation: x V_j e;  deviatoric force: G e (1/m_i + 1/m_j) V_j
-                const float xv = e[c].x * Vj;
-                acc = fmaf(intact ? xv : 0.0f, ev, acc);
-                const float te = intact ? ev * fmaf(rpi, Vj, rvj[c]) : 0.0f;
+                acc = fmaf(e[c].x * Vj, evm, acc);
+                const float te = evm * fmaf(rpi, Vj, rvj[c]);
                 fx = fmaf(te, e[c].m0, fx);
                 fy = fmaf(te, e[c].m1, fy);
                 if (DIM == 3) fz = fmaf(te, e[c].m2, fz);
@@ -314,7 +320,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
 // ---------------------------------------------------------------------------
 template <int DIM, bool UPDATE, int TPW>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int cur,
-                                                                const KEnt *__restrict__ kt,
+                                                                const KEnt2 *__restrict__ kt,
                                                                 const uint64_t *__restrict__ kmask) {
     extern __shared__ __align__(16) unsigned char smem[];
     using GR = Grp<DIM, TPW>;
@@ -382,11 +388,11 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     const int g0 = kq * gper, g1 = min(G4, g0 + gper);
     float fx = 0.f, fy = 0.f, fz = 0.f;
     {
-        KEnt en[4];
+        KEnt2 en[4];
 #pragma unroll
         for (int c = 0; c < 4; c++) en[c] = kt[4 * g0 + c];
         for (int gg = g0; gg < g1; gg++) {
-            KEnt e[4];
+            KEnt2 e[4];
             float2 qj[4];
             uint64_t mm[4];
 #pragma unroll
@@ -403,9 +409,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
                 // (K - G/3) (q_j - q_i) V_j, times x M from the table
                 float t = (qj[c].x - qi) * qj[c].y;
                 t = lane_bit(mm[c]) ? t : 0.0f;
-                fx = fmaf(t, __int_as_float(e[c].z0), fx);
-                fy = fmaf(t, __int_as_float(e[c].z1), fy);
-                if (DIM == 3) fz = fmaf(t, __int_as_float(e[c].z2), fz);
+                fx = fmaf(t, e[c].xm0, fx);
+                fy = fmaf(t, e[c].xm1, fy);
+                if (DIM == 3) fz = fmaf(t, e[c].xm2, fz);
             }
         }
     }
@@ -624,7 +630,7 @@ hipError_t launch_tpass2_f32(const StepArgs &a, int cur, bool update, hipStream_
     const int tpw = tiles_per_group(a.dim, box_slots(a));
     const size_t lds = tiled_lds(a, 2, tpw);
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
-    const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
+    const KEnt2 *kt = reinterpret_cast<const KEnt2 *>(a.ktab + 1024);
     const uint64_t *km = a.mask;
     if (a.dim == 3) {
         if (update) hipLaunchKernelGGL((k_tpass2_f32<3, true, 1>), g, b, lds, s, a, cur, kt, km);

@@ -17,9 +17,17 @@ namespace pdk {
 // one row of the per-entry table (pd_family_host.ktab)
 struct KEnt {
     float m0, m1, m2, x;
-    int soff, z0, z1, z2;
+    int soff;
+    float ix;  // 1 / x
+    int z0, z1;
 };
 static_assert(sizeof(KEnt) == 32, "ktab row is 8 words");
+// one row of the second table (from word 1024): x M and the LDS offset
+struct KEnt2 {
+    float xm0, xm1, xm2;
+    int soff;
+};
+static_assert(sizeof(KEnt2) == 16, "second ktab row is 4 words");
 
 __device__ __forceinline__ double ext_canonical_t(double m1, double m2, double m3, double e1, double e2,
                                                   double e3) {

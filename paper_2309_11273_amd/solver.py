@@ -106,7 +106,7 @@ class FamilyHost:
         self.lat4 = np.empty(s.n_pad * 4, np.int32)
         self.tile_org = np.empty(s.n_tiles * 4, np.int32)
         self.tile_nbr = np.empty(s.n_tiles * 27, np.int32)
-        self.ktab = np.empty(128 * 8, np.uint32)
+        self.ktab = np.empty(128 * 12, np.uint32)
         self.halo_map = np.empty(max(1, s.n_halo), np.int16)
         hb = A.pd_family_host(_np(self.perm), _np(self.row_of), _np(self.slice_ptr), _np(self.words),
                               _np(self.mask), _np(self.stencil), _np(self.stencil_off), _np(self.vol),

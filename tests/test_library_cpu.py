@@ -137,13 +137,17 @@ def test_tile_halo_addressing_matches_bond_words(lib, case):
         nt = np.where(hm >= 0, tn[np.maximum(hm, 0) >> 6], -1)
         rows_map = np.where((hm >= 0) & (nt >= 0), nt * 64 + (hm & 63), -1)
         assert np.array_equal(rows_map, rows)
-        kt = f.ktab.view(np.int32).reshape(128, 8)
-        assert np.array_equal(kt[: len(soff), 4], soff)
-        assert not kt[len(soff):].any()
-        ktf = f.ktab.view(np.float32).reshape(128, 8)
+        ns_ = len(soff)
+        kt1 = f.ktab[:1024].view(np.int32).reshape(128, 8)
+        kt2 = f.ktab[1024:].view(np.int32).reshape(128, 4)
+        assert np.array_equal(kt1[:ns_, 4], soff) and np.array_equal(kt2[:ns_, 3], soff)
+        assert not kt1[ns_:].any() and not kt2[ns_:].any() and not kt1[:, 6:].any()
+        kf1 = f.ktab[:1024].view(np.float32).reshape(128, 8)
+        kf2 = f.ktab[1024:].view(np.float32).reshape(128, 4)
         sten = f.stencil.reshape(-1, 4)
-        assert np.array_equal(ktf[: len(soff), :4], sten.astype(np.float32))
-        assert np.array_equal(ktf[: len(soff), 5:], (sten[:, 3:4] * sten[:, :3]).astype(np.float32))
+        assert np.array_equal(kf1[:ns_, :4], sten.astype(np.float32))
+        assert np.array_equal(kf1[:ns_, 5], (1.0 / sten[:, 3]).astype(np.float32))
+        assert np.array_equal(kf2[:ns_, :3], (sten[:, 3:4] * sten[:, :3]).astype(np.float32))
         base = f.slice_ptr[t]
         for lane in range(64):
             l0, l1, l2 = lane % T0, (lane // T0) % T1, lane // (T0 * T1)
