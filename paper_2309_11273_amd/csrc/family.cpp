@@ -366,9 +366,9 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
     sizes->words_per_row = L4;
     sizes->reach = reach;
     {
-        int32_t B[3];
+        int32_t B[4];
         pd_tile_box(T, reach, dim, B);
-        sizes->n_halo = B[0] * B[1] * B[2];
+        sizes->n_halo = B[3] * B[2];
     }
     if (!out) return PD_OK;
     if (!out->perm || !out->row_of || !out->slice_ptr || !out->words || !out->mask || !out->stencil ||
@@ -379,16 +379,16 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
     for (int64_t r = 0; r < n_pad; r++) out->perm[r] = (int32_t)node_of_row[r];
     for (int64_t p = 0; p < n; p++) out->row_of[p] = row_of[p];
     for (int64_t s = 0; s <= n_slices; s++) out->slice_ptr[s] = s * 64 * L4;
-    int32_t box[3];
+    int32_t box[4];
     pd_tile_box(T, reach, dim, box);
-    for (int32_t s = 0; s < box[0] * box[1] * box[2]; s++) {
-        const int32_t b[3] = {s % box[0], (s / box[0]) % box[1], s / (box[0] * box[1])};
+    for (int32_t s = 0; s < box[3] * box[2]; s++) {
+        const int32_t b[3] = {(s % box[3]) % box[0], (s % box[3]) / box[0], s / box[3]};
         int32_t p[3], d[3];
         for (int c = 0; c < 3; c++) {
             p[c] = (c < dim) ? b[c] - reach : 0;
             d[c] = p[c] < 0 ? -1 : (p[c] >= T[c] ? 1 : 0);
         }
-        if (p[0] >= T[0] + reach) {
+        if (p[0] >= T[0] + reach || p[1] >= T[1] + reach) {
             out->halo_map[s] = -1;  // pitch padding
             continue;
         }
@@ -411,7 +411,7 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
         }
         out->stencil[4 * s + 3] = st[s].x;
         out->ktab[8 * s + 3] = fbits(st[s].x);
-        const int32_t so = st[s].off[0] + box[0] * (st[s].off[1] + box[1] * st[s].off[2]);
+        const int32_t so = st[s].off[0] + box[0] * st[s].off[1] + box[3] * st[s].off[2];
         out->ktab[8 * s + 4] = (uint32_t)so;
         out->ktab[8 * s + 5] = fbits(1.0 / st[s].x);
         for (int c = 0; c < 3; c++) out->ktab[1024 + 4 * s + c] = fbits(st[s].x * st[s].M[c]);

@@ -154,7 +154,8 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     const float rpi = GQ * ri;
     const double s0 = sp.s0;
     // breaking threshold in units of Q, widened by the float rounding of the test
-    const float thrQ = (float)(s0 / Q) * (1.0f - 1e-6f);
+    const double invQ = inv_pow2(Q);
+    const float thrQ = (float)(s0 * invQ) * (1.0f - 1e-6f);
     // screen on e/x: the float extension is off by at most sqrt(3) + 2^-20 * 3 * 2^31
     // (|shadow| < 2^30), so no bond with e/x below thr_lo can reach the threshold;
     // entry 0 is the shortest bond of the stencil
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
                     if (fbm) {
                         nfall += __popcll(fbm);
                         bool broke = false;
-                        if (lane_bit(fbm)) ev = (float)(decide(k, true, broke) / Q);
+                        if (lane_bit(fbm)) ev = (float)(decide(k, true, broke) * invQ);
                         const uint64_t bb = BREAK ? __ballot(broke) : 0ull;
                         if (bb) {
                             live &= ~bb;
@@ -470,7 +471,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     u.z = u.z + sp.dt * v.z;
     a.uv[cur ^ 1][row] = u;
     a.vel[row] = v;
-    const double invQn = 1.0 / Qn;
+    const double invQn = inv_pow2(Qn);
     bool bad = false;
     int4 s;
     s.x = quantise_t(u.x, invQn, bad);
@@ -566,9 +567,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tdsum(StepArgs a, int cur, 
 }
 
 static size_t tdsum_lds(const StepArgs &a) {
-    int32_t B[3];
+    int32_t B[4];
     pd_tile_box(a.tile, a.reach, a.dim, B);
-    const size_t nslot = (size_t)B[0] * B[1] * B[2];
+    const size_t nslot = (size_t)B[3] * B[2];
     return nslot * sizeof(double) + 128 * sizeof(uint64_t) + 3 * PD_TILE_WAVES * 64 * sizeof(double) +
            32 * sizeof(int);
 }
@@ -583,9 +584,9 @@ hipError_t launch_tdsum(const StepArgs &a, int cur, hipStream_t s) {
 }
 
 static int box_slots(const StepArgs &a) {
-    int32_t B[3];
+    int32_t B[4];
     pd_tile_box(a.tile, a.reach, a.dim, B);
-    return B[0] * B[1] * B[2];
+    return B[3] * B[2];
 }
 
 static size_t tiled_lds(const StepArgs &a, int pass, int tpw) {
@@ -597,6 +598,8 @@ static size_t tiled_lds(const StepArgs &a, int pass, int tpw) {
 bool tiled_supported(const StepArgs &a) {
     if (!a.tile_nbr || !a.ktab || !a.halo_map) return false;
     if (a.tile[0] * a.tile[1] * a.tile[2] != 64) return false;
+    for (int c = 0; c < 3; c++)
+        if (a.tile[c] < 1 || (a.tile[c] & (a.tile[c] - 1))) return false;  // powers of two
     if (a.reach < 1 || a.tile[0] < a.reach || a.tile[1] < a.reach) return false;
     if (a.dim == 3 && a.tile[2] < a.reach) return false;
     if (a.dim == 2 && a.tile[2] != 1) return false;

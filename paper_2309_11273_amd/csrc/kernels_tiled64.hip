@@ -355,9 +355,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
 }
 
 static int box_slots64(const StepArgs &a) {
-    int32_t B[3];
+    int32_t B[4];
     pd_tile_box(a.tile, a.reach, a.dim, B);
-    return B[0] * B[1] * B[2];
+    return B[3] * B[2];
 }
 
 static size_t tiled64_lds(int dim, int pass, int tpw) {

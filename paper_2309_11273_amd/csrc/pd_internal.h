@@ -47,12 +47,17 @@ PD_HD inline int64_t pd_widx(int64_t base, int64_t k, int lane) {
 }
 
 // LDS halo box of a 64-point tile T[0] x T[1] x T[2] with reach R: the tile
-// plus R lattice points on every side, x fastest.  In 3D with 4-wide tiles
-// the x pitch is padded up to 4 mod 8 so that the 16 lanes of a quarter wave
-// (4 x-positions, 4 y-positions) fall on distinct 16-byte LDS bank groups.
+// plus R lattice points on every side; slot of box point (x, y, z) is
+// x + B[0] y + B[3] z, and the box has B[3] * B[2] slots.  B[1] and B[2] are
+// the y and z extents.  In 3D with 4x4x4 tiles the x pitch B[0] is padded up
+// to 4 mod 8, which spreads each quarter-wave's 16-byte reads over the LDS
+// banks.  (Padding the z pitch as well, up to 16 mod 32, removes the
+// remaining bank conflicts of the wave-wide reads, but the larger box costs
+// more in staging and occupancy than the conflicts do: measured slower.)
 PD_HD inline void pd_tile_box(const int32_t *T, int R, int dim, int32_t *B) {
     B[0] = T[0] + 2 * R;
     if (dim == 3 && T[0] == 4) B[0] += (12 - B[0] % 8) % 8;
     B[1] = T[1] + 2 * R;
     B[2] = dim == 3 ? T[2] + 2 * R : 1;
+    B[3] = B[0] * B[1];
 }

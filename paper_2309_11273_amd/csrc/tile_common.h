@@ -76,28 +76,33 @@ __device__ __forceinline__ uint32_t tile_specimen(uint32_t aux) {
 }
 
 struct Box {
-    int T0, T1, R, Bx, By, nslot;
+    int T0, T1, R, Bx, Pz, nslot;
 };
 
 __device__ __forceinline__ Box make_box(const StepArgs &a, int dim) {
     Box b;
-    int32_t B[3];
+    int32_t B[4];
     pd_tile_box(a.tile, a.reach, dim, B);
     b.T0 = a.tile[0];
     b.T1 = a.tile[1];
     b.R = a.reach;
     b.Bx = B[0];
-    b.By = B[1];
-    b.nslot = B[0] * B[1] * B[2];
+    b.Pz = B[3];
+    b.nslot = B[3] * B[2];
     return b;
 }
 
-// LDS box slot of lane l of the tile (its own lattice point)
+// LDS box slot of lane l of the tile (its own lattice point); tile edges
+// are powers of two
 template <int DIM>
 __device__ __forceinline__ int own_slot(const Box &g, int lane) {
-    const int l0 = lane % g.T0, l1 = (lane / g.T0) % g.T1, l2 = lane / (g.T0 * g.T1);
-    return (l0 + g.R) + g.Bx * ((l1 + g.R) + g.By * (DIM == 3 ? l2 + g.R : 0));
+    const int s0 = __builtin_ctz((unsigned)g.T0), s1 = __builtin_ctz((unsigned)g.T1);
+    const int l0 = lane & (g.T0 - 1), l1 = (lane >> s0) & (g.T1 - 1), l2 = lane >> (s0 + s1);
+    return (l0 + g.R) + g.Bx * (l1 + g.R) + g.Pz * (DIM == 3 ? l2 + g.R : 0);
 }
+
+// 1 / q for a power of two q (exact, no division)
+__device__ __forceinline__ double inv_pow2(double q) { return ldexp(1.0, -ilogb(q)); }
 
 // global row of a halo slot from its halo_map entry and the tile's
 // neighbour table (-1: pitch padding or no tile in that direction)

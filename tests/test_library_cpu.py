@@ -95,14 +95,14 @@ def _halo_rows(f, tile):
     Bx, By = T0 + 2 * R, T1 + 2 * R
     if dim == 3 and T0 == 4:
         Bx += (12 - Bx % 8) % 8
+    Pz = Bx * By
     Bz = T2 + 2 * R if dim == 3 else 1
     tn = f.tile_nbr[27 * tile: 27 * tile + 27]
-    out = np.full(Bx * By * Bz, -1, np.int64)
-    for slot in range(Bx * By * Bz):
-        bx, byz = slot % Bx, slot // Bx
-        by, bz = byz % By, byz // By
+    out = np.full(Pz * Bz, -1, np.int64)
+    for slot in range(Pz * Bz):
+        bx, by, bz = (slot % Pz) % Bx, (slot % Pz) // Bx, slot // Pz
         p = [bx - R, by - R, (bz - R) if dim == 3 else 0]
-        if p[0] >= T0 + R:
+        if p[0] >= T0 + R or p[1] >= T1 + R:
             continue
         T = [T0, T1, T2]
         d = [(-1 if p[c] < 0 else (1 if p[c] >= T[c] else 0)) for c in range(3)]
@@ -110,7 +110,7 @@ def _halo_rows(f, tile):
         if nt >= 0:
             loc = [p[c] - d[c] * T[c] for c in range(3)]
             out[slot] = nt * 64 + loc[0] + T0 * (loc[1] + T1 * loc[2])
-    return out, (Bx, By, Bz)
+    return out, (Bx, Pz, Bz)
 
 
 @pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate"])
@@ -129,11 +129,11 @@ def test_tile_halo_addressing_matches_bond_words(lib, case):
     rng = np.random.default_rng(0)
     tiles = rng.choice(int(s.n_tiles), size=min(40, int(s.n_tiles)), replace=False)
     for t in tiles:
-        rows, (Bx, By, Bz) = _halo_rows(f, int(t))
-        soff = off[:, 0] + Bx * (off[:, 1] + By * off[:, 2])
+        rows, (Bx, Pz, Bz) = _halo_rows(f, int(t))
+        soff = off[:, 0] + Bx * off[:, 1] + Pz * off[:, 2]
         hm = f.halo_map.astype(np.int64)
         tn = f.tile_nbr[27 * int(t): 27 * int(t) + 27]
-        assert len(hm) == Bx * By * Bz == int(s.n_halo)
+        assert len(hm) == Pz * Bz == int(s.n_halo)
         nt = np.where(hm >= 0, tn[np.maximum(hm, 0) >> 6], -1)
         rows_map = np.where((hm >= 0) & (nt >= 0), nt * 64 + (hm & 63), -1)
         assert np.array_equal(rows_map, rows)
@@ -151,12 +151,12 @@ def test_tile_halo_addressing_matches_bond_words(lib, case):
         base = f.slice_ptr[t]
         for lane in range(64):
             l0, l1, l2 = lane % T0, (lane // T0) % T1, lane // (T0 * T1)
-            my = (l0 + R) + Bx * ((l1 + R) + By * ((l2 + R) if s.dim == 3 else 0))
+            my = (l0 + R) + Bx * (l1 + R) + Pz * ((l2 + R) if s.dim == 3 else 0)
             assert rows[my] == t * 64 + lane
             for k in range(int(s.n_stencil)):
                 wd = f.words[base + (k // 4) * 256 + lane * 4 + (k % 4)]
                 slot = my + soff[k]
-                assert 0 <= slot < Bx * By * Bz
+                assert 0 <= slot < Pz * Bz
                 if (wd & 127) != 127:
                     assert (wd & 127) == k
                     assert rows[slot] == (wd >> 7)
@@ -338,3 +338,4 @@ def test_xcd_tile_order_is_a_bijection():
         q, r, x = n // 8, n % 8, b % 8
         t = x * q + np.minimum(x, r) + b // 8
         assert np.array_equal(np.sort(t), b)
+
