@@ -158,6 +158,8 @@ typedef struct pd_family_sizes {
     int32_t reach;      /* largest |component| of a stencil offset                 */
     int32_t n_halo;     /* slots of a tile's LDS halo box (tile + reach on every
                            side, x pitch padded; see pd_family_host.halo_map)      */
+    int32_t n_box;      /* points of that box without padding (tile + reach on
+                           every side); see pd_family_host.halo_pos                */
 } pd_family_sizes;
 
 /* Output arrays of pd_build_family, all [host], allocated by the caller
@@ -178,16 +180,24 @@ typedef struct pd_family_host {
     int32_t *tile_org;    /* [n_tiles*4] lattice origin x,y,z of each tile, specimen */
     int32_t *tile_nbr;    /* [n_tiles*27] tile at offset (dx,dy,dz) in {-1,0,1}^3,
                              index (dz+1)*9 + (dy+1)*3 + (dx+1); -1 if absent        */
-    uint32_t *ktab;       /* [128*12] per-entry tables of the LDS-staged kernels, zero
+    uint32_t *ktab;       /* [128*20] per-entry tables of the LDS-staged kernels, zero
                              beyond n_stencil.  Rows 0-127, 8 words each: M1, M2, M3,
                              x as float, the int32 offset of the entry's neighbour in
                              the tile's LDS halo box, 1/x as float, 0, 0.  Then rows
                              of 4 words from word 1024: x M1, x M2, x M3 as float, the
-                             same int32 offset                                       */
+                             same int32 offset.  Then rows of 8 words from word 1536:
+                             M1/x, M2/x, x^2, x M1, x M2 as float, the int32 offset
+                             of the neighbour in the single-precision box (the
+                             pitches of halo_pos), M3/x, x M3 as float               */
     int16_t *halo_map;    /* [n_halo] for slot s of the LDS halo box (x fastest):
                              64 * d + l, the point at local position l of the
                              neighbour tile in direction d (tile_nbr index), or -1
                              for x-pitch padding; the same for every tile          */
+    int32_t *halo_pos;    /* [n_box] for point b of the unpadded box (x fastest):
+                             (slot << 11) | (64 * d + l), d and l as in halo_map and
+                             slot the point's place in the single-precision pass-1
+                             box, whose x and y pitches are padded so that the 64
+                             lanes of a tile read 64 distinct LDS banks            */
 } pd_family_host;
 
 /* Horizon search and bond-list construction (Sec. 2.1 family; Eqs. 1.2-1.5,
@@ -235,8 +245,9 @@ typedef struct pd_problem_dev {
     const int32_t *tile_nbr;    /* [device] n_slices*27 neighbour tiles            */
     int32_t tile[3];            /* tile edge lengths (pd_family_sizes.tile)        */
     int32_t reach;              /* pd_family_sizes.reach                           */
-    const uint32_t *ktab;       /* [device] 128*12 words, pd_family_host.ktab      */
+    const uint32_t *ktab;       /* [device] 128*20 words, pd_family_host.ktab      */
     const int16_t *halo_map;    /* [device] n_halo, pd_family_host.halo_map        */
+    const int32_t *halo_pos;    /* [device] n_box, pd_family_host.halo_pos         */
 } pd_problem_dev;
 
 /* Device control block (step counter, diagnostics).  Size in bytes: */

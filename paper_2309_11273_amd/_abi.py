@@ -33,13 +33,13 @@ class pd_family_sizes(C.Structure):
     _fields_ = [("n", i64), ("n_pad", i64), ("n_slices", i64), ("n_words", i64), ("n_mask", i64),
                 ("nnz", i64), ("n_bonds", i64), ("n_cut", i64), ("n_stencil", i32), ("max_row", i32),
                 ("dim", i32), ("n_specimens", i32), ("n_tiles", i64), ("tile", i32 * 3),
-                ("words_per_row", i32), ("reach", i32), ("n_halo", i32)]
+                ("words_per_row", i32), ("reach", i32), ("n_halo", i32), ("n_box", i32)]
 
 
 class pd_family_host(C.Structure):
     _fields_ = [("perm", P), ("row_of", P), ("slice_ptr", P), ("words", P), ("mask", P), ("stencil", P),
                 ("stencil_off", P), ("vol", P), ("inv_m", P), ("spec", P), ("lat4", P), ("tile_org", P),
-                ("tile_nbr", P), ("ktab", P), ("halo_map", P)]
+                ("tile_nbr", P), ("ktab", P), ("halo_map", P), ("halo_pos", P)]
 
 
 class pd_spec(C.Structure):
@@ -52,7 +52,7 @@ class pd_problem_dev(C.Structure):
                 ("n_specimens", i32), ("pad0", i32), ("slice_ptr", P), ("words", P), ("stencil", P),
                 ("vol", P), ("inv_m", P), ("lat4", P), ("spec", P), ("aux", P), ("fext", P),
                 ("ramp_steps", i64), ("stencil_off", P), ("tile_nbr", P), ("tile", i32 * 3), ("reach", i32),
-                ("ktab", P), ("halo_map", P)]
+                ("ktab", P), ("halo_map", P), ("halo_pos", P)]
 
 
 class pd_state_dev(C.Structure):

@@ -369,11 +369,12 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
         int32_t B[4];
         pd_tile_box(T, reach, dim, B);
         sizes->n_halo = B[3] * B[2];
+        sizes->n_box = pd_box_points(T, reach, dim);
     }
     if (!out) return PD_OK;
     if (!out->perm || !out->row_of || !out->slice_ptr || !out->words || !out->mask || !out->stencil ||
         !out->stencil_off || !out->vol || !out->inv_m || !out->spec || !out->lat4 || !out->tile_org ||
-        !out->tile_nbr || !out->ktab || !out->halo_map)
+        !out->tile_nbr || !out->ktab || !out->halo_map || !out->halo_pos)
         return PD_ERR_ARG;
 
     for (int64_t r = 0; r < n_pad; r++) out->perm[r] = (int32_t)node_of_row[r];
@@ -396,7 +397,24 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
         const int32_t loc = (p[0] - d[0] * T[0]) + T[0] * ((p[1] - d[1] * T[1]) + T[1] * (p[2] - d[2] * T[2]));
         out->halo_map[s] = (int16_t)(64 * dir + loc);
     }
-    for (int q = 0; q < 12 * 128; q++) out->ktab[q] = 0u;
+    // the unpadded box point by point, with its slot in the pass-1 box
+    int32_t box1[4];
+    pd_tile_box1(T, reach, dim, box1);
+    {
+        const int32_t e0 = T[0] + 2 * reach, e1 = T[1] + 2 * reach;
+        const int32_t nb = pd_box_points(T, reach, dim);
+        for (int32_t b = 0; b < nb; b++) {
+            const int32_t bx = b % e0, by = (b / e0) % e1, bz = b / (e0 * e1);
+            const int32_t p[3] = {bx - reach, by - reach, dim == 3 ? bz - reach : 0};
+            int32_t d[3];
+            for (int c = 0; c < 3; c++) d[c] = p[c] < 0 ? -1 : (p[c] >= T[c] ? 1 : 0);
+            const int32_t dir = (d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1);
+            const int32_t loc = (p[0] - d[0] * T[0]) + T[0] * ((p[1] - d[1] * T[1]) + T[1] * (p[2] - d[2] * T[2]));
+            const int32_t slot = bx + box1[0] * by + box1[3] * bz;
+            out->halo_pos[b] = (slot << 11) | (64 * dir + loc);
+        }
+    }
+    for (int q = 0; q < 20 * 128; q++) out->ktab[q] = 0u;
     auto fbits = [](double v) {
         const float f = (float)v;
         uint32_t b;
@@ -416,6 +434,15 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
         out->ktab[8 * s + 5] = fbits(1.0 / st[s].x);
         for (int c = 0; c < 3; c++) out->ktab[1024 + 4 * s + c] = fbits(st[s].x * st[s].M[c]);
         out->ktab[1024 + 4 * s + 3] = (uint32_t)so;
+        uint32_t *k1 = out->ktab + 1536 + 8 * s;
+        k1[0] = fbits(st[s].M[0] / st[s].x);
+        k1[1] = fbits(st[s].M[1] / st[s].x);
+        k1[2] = fbits(st[s].x * st[s].x);
+        k1[3] = fbits(st[s].x * st[s].M[0]);
+        k1[4] = fbits(st[s].x * st[s].M[1]);
+        k1[5] = (uint32_t)(st[s].off[0] + box1[0] * st[s].off[1] + box1[3] * st[s].off[2]);
+        k1[6] = fbits(st[s].M[2] / st[s].x);
+        k1[7] = fbits(st[s].x * st[s].M[2]);
     }
     parallel_for(n_slices, [&](int64_t a, int64_t b) {
         for (int64_t sl = a; sl < b; sl++) {

@@ -41,6 +41,7 @@ struct StepArgs {
     int32_t reach;
     const uint32_t *ktab;
     const int16_t *halo_map;
+    const int32_t *halo_pos;
 };
 
 struct InitArgs {

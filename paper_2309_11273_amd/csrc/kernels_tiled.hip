@@ -5,33 +5,42 @@
 // stencil offset component R); tile t owns rows 64t .. 64t+63 and lane l of
 // the tile sits on local lattice position (l % T0, (l / T0) % T1,
 // l / (T0 T1)).  Bond k of every row is stencil entry k.  A workgroup of
-// four waves takes one tile:
+// four waves takes one tile (in 2D with short stencils, four tiles, one per
+// wave):
 //   1. stages what the pass needs of the tile plus an R-wide halo -- a box
-//      gathered from the tile and its 3^dim neighbour tiles -- into LDS
-//      (pass 1: the fixed-point displacement shadow, V and G Q V / m; pass 2:
-//      (K - G/3) theta/m and V), all of a thread's slot loads issued before
-//      any is consumed, together with the tile's bond-status words;
+//      gathered from the tile and its 3^dim neighbour tiles, point by point
+//      from the halo_pos table -- into LDS as separate float arrays at a
+//      fixed stride (pass 1: the fixed-point displacement shadow relative to
+//      a reference point of the tile, V and G Q r V; pass 2: (K - G/3) theta/m
+//      and V), all of a thread's loads issued before any is consumed.  The
+//      box pitches are padded so that the 64 lanes of a tile, each reading
+//      the element at the same offset from its own point, hit 64 distinct
+//      LDS banks;
 //   2. every wave sweeps a quarter of the stencil for all 64 rows, four
-//      entries at a time: the neighbour of row l through entry k is LDS slot
-//      slot(l) + soff[k], soff[k] the same for every lane, and the float bond
-//      geometry, soff and status word of entry k are wave-uniform (scalar)
-//      values, the status word used directly as the lane mask;
+//      entries at a time: the neighbour of row l through entry k is point
+//      slot(l) + soff[k], soff[k] the same for every lane, so one address
+//      per bond serves all arrays (their distance is a multiple of 256
+//      bytes: one ds_read2st64 per pair).  The entry's table row and bond-
+//      status word are wave-uniform scalar loads, the status word used
+//      directly as the lane mask; the status words of the next group are
+//      requested once the current group's LDS data are in registers;
 //   3. the four partial sums of each row are added in wave order and wave 0
-//      writes the row's result (and, in pass 2, the explicit update).
+//      writes the row's result (and, in pass 2, the explicit update, whose
+//      inputs it requests before the staging).
 //
 // The arithmetic follows the gather kernels of kernels_f32.hip (same
-// fixed-point shadow and error band, same double recheck of near-threshold
-// bonds, same difference form of the dilatation term) with the shadow scale
-// Q factored out of the per-bond work: the float extension is carried in
-// units of Q, e' = M . (s_j - s_i), and Q enters once per row (the breaking
-// threshold becomes s_c x / Q, the deviatoric modulus G Q), and with the
-// pair force split between the passes: pass 1, which has the extension,
-// sums the deviatoric part; pass 2 only the dilatational part.  Rows next
-// to a shadow sentinel (a displacement too large for the fixed-point range)
-// take the double gather path bond by bond; the per-bond test is compiled
-// only into the sweep used when the tile's halo holds a sentinel.  Every row
-// of a tile belongs to one specimen, so the material constants are
-// wave-uniform and folded into the staged values.
+// fixed-point shadow, same double recheck of near-threshold bonds, same
+// difference form of the dilatation term) with the shadow scale Q factored
+// out of the per-bond work: the bond strain is carried in units of Q,
+// e' = (M / x) . (a_j - a_i) with a the staged shadow, and Q enters once per
+// row (the breaking threshold becomes s_c / Q, the deviatoric modulus G Q),
+// and with the pair force split between the passes: pass 1, which has the
+// strain, sums the deviatoric part; pass 2 only the dilatational part.  Rows
+// next to a shadow sentinel (a displacement too large for the fixed-point
+// range) take the double gather path bond by bond; the per-bond test is
+// compiled only into the sweep used when the tile's halo holds a sentinel.
+// Every row of a tile belongs to one specimen, so the material constants
+// are wave-uniform and folded into the staged values.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -42,30 +51,72 @@
 
 namespace pdk {
 
-// LDS of one tile in pass 1: the staged box (shadow + G Q V / m per slot) --
-// with TPW = 1 the partial sums (4 floats and 3 doubles per thread) reuse it
-// after the sweep, so it is at least that large -- then the tile's 128 status
-// words and its 27 neighbour tiles
-template <int TPW>
-__host__ __device__ inline int tile1_box_bytes(int nslot) {
-    const int box = (nslot * 16 + ((nslot + 1) & ~1) * 4 + 15) & ~15;
-    const int sums = PD_TILE_WAVES * 64 * (4 * 4 + 3 * 8);
-    return (TPW == 1 && sums > box) ? sums : box;
-}
-template <int TPW>
-__host__ __device__ inline int tile1_bytes(int nslot) {
-    return tile1_box_bytes<TPW>(nslot) + 128 * 8 + 32 * 4;
-}
-// pass 2: the staged box ((K - G/3) theta/m, V per slot), status words,
-// neighbour tiles, and with TPW = 1 the partial sums
-template <int TPW>
-__host__ __device__ inline int tile2_box_bytes(int nslot) {
-    return (((nslot + 1) & ~1) * 8 + 15) & ~15;
-}
-template <int TPW>
-__host__ __device__ inline int tile2_bytes(int nslot) {
-    return tile2_box_bytes<TPW>(nslot) + 128 * 8 + 32 * 4 + (TPW == 1 ? 3 * PD_TILE_WAVES * 64 * 4 : 0);
-}
+// LDS of one tile in pass 1: the staged box (per point: the shadow
+// components relative to the tile's reference point, V, and G Q r V with
+// r = 1/m) at the fixed stride S (pd_box1_stride); with TPW = 1 the partial
+// sums (4 floats and 3 doubles per thread) reuse it after the sweep; then the
+// 27 neighbour tiles.  3D: five float arrays, read per point with two
+// ds_read2st64 and one ds_read (array distances are multiples of 256 bytes);
+// 2D: two float2 arrays, (x, y) and (V, G Q r V), read with two 8-byte reads
+// from one address, which keeps the box of a one-wave tile small.
+template <int DIM, int TPW>
+struct Lay1 {
+    static constexpr int S = DIM == 3 ? 1472 : (TPW == 4 ? 336 : 1024);
+    // box points staged per thread: 3D boxes of up to 1024 points (R <= 3),
+    // 2D up to 256 per wave (TPW = 4) or 512 per workgroup
+    static constexpr int MP = DIM == 3 ? 4 : (TPW == 4 ? 4 : 2);
+    static constexpr int BOX = DIM == 3 ? 5 * S * 4 : 2 * S * 8;
+    static constexpr int SUMS = TPW == 1 ? PD_TILE_WAVES * 64 * (4 * 4 + 3 * 8) : 0;
+    static constexpr int AREA = BOX > SUMS ? BOX : SUMS;
+    static constexpr int BYTES = AREA + 32 * 4;
+    static_assert(DIM == 2 || (S % 64 == 0 && 4 * S * 4 / 256 <= 255), "array offsets fit the st64 encoding");
+};
+
+// access to the staged pass-1 box of Lay1
+template <int DIM, int S>
+struct View1 {
+    float *b;
+    __device__ __forceinline__ void put(int slot, float x, float y, float z, float V, float h) const {
+        if constexpr (DIM == 3) {
+            b[slot] = x;
+            b[S + slot] = y;
+            b[2 * S + slot] = z;
+            b[3 * S + slot] = V;
+            b[4 * S + slot] = h;
+        } else {
+            float2 *q = reinterpret_cast<float2 *>(b);
+            q[slot] = make_float2(x, y);
+            q[S + slot] = make_float2(V, h);
+        }
+    }
+    __device__ __forceinline__ void pos(int slot, float &x, float &y, float &z) const {
+        if constexpr (DIM == 3) {
+            x = b[slot];
+            y = b[S + slot];
+            z = b[2 * S + slot];
+        } else {
+            const float2 t = reinterpret_cast<const float2 *>(b)[slot];
+            x = t.x;
+            y = t.y;
+            z = 0.0f;
+        }
+    }
+    __device__ __forceinline__ void get(int slot, float &x, float &y, float &z, float &V, float &h) const {
+        if constexpr (DIM == 3) {
+            pos(slot, x, y, z);
+            V = b[3 * S + slot];
+            h = b[4 * S + slot];
+        } else {
+            const float2 *q = reinterpret_cast<const float2 *>(b);
+            const float2 t = q[slot], u = q[S + slot];
+            x = t.x;
+            y = t.y;
+            z = 0.0f;
+            V = u.x;
+            h = u.y;
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // pass 1: breaking (with double recheck), dilatation, deviatoric pair force
@@ -75,13 +126,34 @@ __host__ __device__ inline int tile2_bytes(int nslot) {
 // and is summed in pass 2, and a deviatoric part, G e (1/m_i + 1/m_j) M V_i V_j,
 // which needs only the extension and the bond status after this step's
 // breaking, and is summed here where e is at hand (fe32, without the V_i).
+//
+// Per bond the kernel forms e' = (M / x) . (a_j - a_i), the bond strain e / x
+// in units of the shadow scale Q, from the staged floats a = fl(s - s_ref)
+// (s the fixed-point shadow, s_ref the tile's reference point; s - s_ref is
+// an exact integer, rounded only if its magnitude exceeds 2^24).  With
+// u = 2^-24: each staged component is off by at most u |a| if |a| >= 2^24 and
+// not at all below; the difference a_j - a_i of two such integers is exact
+// when it is below 2^24 and off by at most u |a_j - a_i| above; the
+// three-term product with the rounded table entries M/x and the later
+// product with x add at most 6 u sum_c |a_jc - a_ic|.  With the shadow's own
+// rounding (half a unit per component of each end, at most sqrt(3) after the
+// product with the unit vector M), in units of Q:
+//     |e' x - e / Q| <= sqrt(3) + 2^-21 D + 2^-24 A,
+// D = sum_c |a_jc - a_ic|, A = the sum of the |a| at least 2^24 of both ends.
+// The screen passes every bond with e' >= thr_lo, thr_lo = s_c / Q minus
+// (sqrt(3) + 2^-21 * 3 * 2^31 + 2^-24 * 6 * 2^31) / x_min (|s| < 2^30: every
+// |a| and |a_j - a_i| is below 2^31), so no bond that can reach the critical
+// stretch escapes it; a screened bond whose e' x + 2^-20 D + 2^-23 A reaches
+// s_c x / Q - sqrt(3) is decided from the double state.
 template <int DIM, bool BREAK, int TPW>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int cur,
-                                                                const KEnt *__restrict__ kt) {
+                                                                const KEnt *__restrict__ kt,
+                                                                const KEnt1 *__restrict__ kn) {
     extern __shared__ __align__(16) unsigned char smem[];
     using GR = Grp<DIM, TPW>;
-    constexpr int MS = GR::MS;
-    const Box g = make_box(a, DIM);
+    using LY = Lay1<DIM, TPW>;
+    constexpr int S = LY::S;
+    constexpr int MS = LY::MP;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int gt = TPW == 1 ? tid : lane;  // thread within its tile's group
@@ -91,11 +163,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     const int64_t tile = group_tile<TPW>(a.n_slices, sub, valid);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
-    unsigned char *reg = smem + sub * tile1_bytes<TPW>(g.nslot);
-    int4 *halo = reinterpret_cast<int4 *>(reg);                  // shadow, V bits
-    float *hrv = reinterpret_cast<float *>(halo + g.nslot);      // G Q V_j / m_j
-    uint64_t *smask = reinterpret_cast<uint64_t *>(reg + tile1_box_bytes<TPW>(g.nslot));
-    int *stn = reinterpret_cast<int *>(smask + 128);
+    unsigned char *reg = smem + sub * LY::BYTES;
+    const View1<DIM, S> box{reinterpret_cast<float *>(reg)};
+    int *stn = reinterpret_cast<int *>(reg + LY::AREA);
+    int32_t B1[4];
+    pd_tile_box1(a.tile, a.reach, DIM, B1);
+    const int npts = pd_box_points(a.tile, a.reach, DIM);
     pd_ctl *ctl = a.ctl;
     const double Q = ctl->qs[cur];
     const int4 *__restrict__ sh = a.ush[cur];
@@ -103,166 +176,223 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     const double4 *__restrict__ uv = a.uv[cur];
     const double4 *__restrict__ sten = reinterpret_cast<const double4 *>(a.stencil);
     uint64_t *mrow = a.mask + (base >> 6);
+    // the tile's status words through the scalar cache: a wave reads each of
+    // its words once, before it rewrites that word, and no other wave reads it
+    const cu64_t *mks = (const cu64_t *)mrow;
     const int64_t row = tile * 64 + lane;
-    int hmv[MS];
+    // box points of this thread; threads past the last point redo it (the
+    // same value into the same slot)
+    int hp[MS];
 #pragma unroll
-    for (int i = 0; i < MS; i++) {
-        const int s = gt + i * GR::NT;
-        hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
-    }
+    for (int i = 0; i < MS; i++) hp[i] = a.halo_pos[min(gt + i * GR::NT, npts - 1)];
     if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
-    const uint64_t mw0 = gt < L4 ? mrow[gt] : 0ull;
-    const uint64_t mw1 = (TPW != 1 && gt + 64 < L4) ? mrow[gt + 64] : 0ull;
+    const int G4 = L4 >> 2;
+    const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
+    const int g0 = kq * gper, g1 = min(G4, g0 + gper);
+    // this wave's first status words, requested before the staging
+    uint64_t mw[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) mw[c] = g0 < g1 ? mks[4 * g0 + c] : 0ull;
     const pd_spec sp = a.spec[tile_specimen(a.aux[row])];
     const float GQ = (float)(sp.G * Q);  // extension carried in units of Q
+    // reference point: the shadow of the tile's centre lattice point, or of
+    // its first node if the centre is padding (V = 0); zero if a sentinel
+    const int4 own = sh[row];
+    const uint64_t nodes = __ballot(own.w != 0);
+    const int lc = (a.tile[0] >> 1) + a.tile[0] * ((a.tile[1] >> 1) + a.tile[1] * (a.tile[2] >> 1));
+    const int lr = ((nodes >> lc) & 1ull) || !nodes ? lc : (int)__builtin_ctzll(nodes);
+    const int r0 = __builtin_amdgcn_readlane(own.x, lr);
+    const bool rsent = r0 == PD_SENTINEL_T;
+    const int rx = rsent ? 0 : r0;
+    const int ry = rsent ? 0 : __builtin_amdgcn_readlane(own.y, lr);
+    const int rz = rsent ? 0 : __builtin_amdgcn_readlane(own.z, lr);
     __syncthreads();
     bool sent = false;
     {
-        int64_t rw[MS];
+        uint32_t rw[MS];
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            const int h = hp[i] & 2047;
+            const int nt = stn[h >> 6];
+            // no tile in that direction: any row of this tile (finite values on a
+            // point no intact bond reaches)
+            rw[i] = (uint32_t)(nt < 0 ? (int)tile : nt) * 64u + (uint32_t)(h & 63);
+        }
         int4 v[MS];
         float r[MS];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            rw[i] = halo_row_of(hmv[i], stn);
+            v[i] = sh[rw[i]];
+            r[i] = qr[rw[i]].y;
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            v[i] = rw[i] >= 0 ? sh[rw[i]] : make_int4(0, 0, 0, 0);
-            r[i] = rw[i] >= 0 ? qr[rw[i]].y : 0.0f;
-        }
-#pragma unroll
-        for (int i = 0; i < MS; i++) {
-            const int s = gt + i * GR::NT;
-            if (s < g.nslot) {
-                halo[s] = v[i];
-                hrv[s] = GQ * r[i] * __int_as_float(v[i].w);
-                sent |= v[i].x == PD_SENTINEL_T;
-            }
+            const bool st = v[i].x == PD_SENTINEL_T;
+            sent |= st;
+            const float Vv = __int_as_float(v[i].w);
+            box.put(hp[i] >> 11, st ? __builtin_inff() : idiff(v[i].x, rx), idiff(v[i].y, ry),
+                    DIM == 3 ? idiff(v[i].z, rz) : 0.0f, Vv, GQ * r[i] * Vv);
         }
     }
-    if (gt < 128) smask[gt] = mw0;
-    if (TPW != 1) smask[gt + 64] = mw1;
     const bool anysent = __syncthreads_or(sent);
     if (BREAK && valid && tile == 0 && gt == 0) {
         ctl->s1 = ctl->s2;
         ctl->qs[cur ^ 1] = shadow_scale_t(ctl->umax_bits[cur]);
         ctl->umax_bits[cur ^ 1] = 0u;
     }
-    const int my = own_slot<DIM>(g, lane);
-    const int4 si = halo[my];
+    const int my = own_slot1<DIM>(a.tile, a.reach, B1, lane);
+    float aix, aiy, aiz;
+    box.pos(my, aix, aiy, aiz);
+    const float big_i = big_abs(aix) + big_abs(aiy) + big_abs(aiz);
     const float ri = qr[row].y;
     const float rpi = GQ * ri;
     const double s0 = sp.s0;
     // breaking threshold in units of Q, widened by the float rounding of the test
     const double invQ = inv_pow2(Q);
     const float thrQ = (float)(s0 * invQ) * (1.0f - 1e-6f);
-    // screen on e/x: the float extension is off by at most sqrt(3) + 2^-20 * 3 * 2^31
-    // (|shadow| < 2^30), so no bond with e/x below thr_lo can reach the threshold;
-    // entry 0 is the shortest bond of the stencil
+    // screen on e': below thr_lo no bond can reach the threshold (entry 0 is
+    // the shortest bond of the stencil; 6200 > sqrt(3) + 3072 + 768)
     const float thr_lo = thrQ * (1.0f - 9.5367432e-7f) - 6200.0f * kt[0].ix;
-    const int G4 = L4 >> 2;
-    const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
-    const int g0 = kq * gper, g1 = min(G4, g0 + gper);
     float acc = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
     uint32_t nbroken = 0, nrecheck = 0, nfall = 0;
     double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
 
-    // double extension of bond k of this row (canonical order, from the
-    // double state); a break takes the bond out of the row's D_i
-    auto decide = [&](int k, bool brk_ok, bool &broke) -> double {
+    // double bond strain e / x of bond k of this row (canonical order, from
+    // the double state); a break takes the bond out of the row's D_i
+    auto decide = [&](int k, bool &broke) -> double {
         const uint32_t w = a.words[pd_widx(base, k, lane)];
         const double4 ui = uv[row], uj = uv[w >> 7];
         const double4 sd = sten[k];
         const double e64 = ext_canonical_t(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, uj.x - ui.x, uj.y - ui.y,
                                            DIM == 3 ? uj.z - ui.z : 0.0);
-        if (BREAK && brk_ok && e64 / sd.w >= s0) {
+        const double st = e64 / sd.w;
+        if (BREAK && st >= s0) {
             broke = true;
             const double xv = sd.w * uj.w;
             dd0 += xv * sd.x;
             dd1 += xv * sd.y;
             dd2 += xv * sd.z;
         }
-        return e64;
+        return st;
     };
 
-    // byte offsets of this row's own slot in the two staged arrays
-    const int o_halo = my * 16, o_rv = g.nslot * 16 + my * 4;
-    auto sweep = [&](auto chk) {
+    // one group of four stencil entries with its status words mm; requests
+    // the status words of group gn into mn
+    auto group = [&](auto chk, int gg, const uint64_t(&mm)[4], uint64_t(&mn)[4], int gn) {
         constexpr bool CHK = decltype(chk)::value;
-        KEnt en[4];
-#pragma unroll
-        for (int c = 0; c < 4; c++) en[c] = kt[4 * g0 + c];
-        for (int gg = g0; gg < g1; gg++) {
-            KEnt e[4];
-            int4 sj[4];
-            float rvj[4];
-            uint64_t mm[4];
+        {
+            KEnt1 e[4];
+            float ajx[4], ajy[4], ajz[4], vj[4], hj[4], evs[4];
 #pragma unroll
             for (int c = 0; c < 4; c++) {
-                e[c] = en[c];
-                sj[c] = *reinterpret_cast<const int4 *>(reg + o_halo + 16 * e[c].soff);
-                rvj[c] = *reinterpret_cast<const float *>(reg + o_rv + 4 * e[c].soff);
-                mm[c] = uni64_t(smask[4 * gg + c]);
+                e[c] = kn[4 * gg + c];  // a 4 KiB table: scalar-cache hits
+                box.get(my + e[c].soff, ajx[c], ajy[c], ajz[c], vj[c], hj[c]);
             }
-            // next group's table rows (row index stays inside the 128-row table)
-            const int gn = min(gg + 1, 31);
-#pragma unroll
-            for (int c = 0; c < 4; c++) en[c] = kt[4 * gn + c];
 #pragma unroll
             for (int c = 0; c < 4; c++) {
-                const int k = 4 * gg + c;
-                uint64_t live = mm[c];
-                // (a sentinel makes these differences meaningless; such bonds are redone below)
-                const float fdx = idiff(sj[c].x, si.x), fdy = idiff(sj[c].y, si.y);
-                const float fdz = DIM == 3 ? idiff(sj[c].z, si.z) : 0.0f;
-                float ev = e[c].m0 * fdx + e[c].m1 * fdy;
-                if (DIM == 3) ev += e[c].m2 * fdz;
-                if (BREAK) {
-                    const uint64_t maybe = __ballot(ev * e[c].ix >= thr_lo) & live;
-                    if (maybe) {
-                        // |ev - e64 / Q| <= sqrt(3) + 2^-20 sum |d|: decide in double when
-                        // ev + that bound reaches the threshold
-                        const float lim = thrQ * e[c].x - 1.7320509f;
-                        const float sdd = fabsf(fdx) + fabsf(fdy) + fabsf(fdz);
-                        const bool need = lane_bit(maybe) && fmaf(9.5367432e-7f, sdd, ev) >= lim;
+                const float fdx = ajx[c] - aix, fdy = ajy[c] - aiy;
+                const float fdz = DIM == 3 ? ajz[c] - aiz : 0.0f;
+                float ev = e[c].mx0 * fdx + e[c].mx1 * fdy;  // e / (x Q)
+                if (DIM == 3) ev += e[c].mx2 * fdz;
+                evs[c] = ev;
+            }
+            // the next group's status words (inside this wave's range), requested
+            // only once this group's LDS reads have been consumed: scalar and
+            // LDS reads share one completion counter, so a scalar read in
+            // flight would hold up the wait for the LDS data (the empty asm
+            // pins the strains and the staged values here and keeps the
+            // scalar reads after them)
+            asm volatile("" : "+v"(evs[0]), "+v"(evs[1]), "+v"(evs[2]), "+v"(evs[3]), "+v"(vj[0]), "+v"(vj[1]),
+                         "+v"(vj[2]), "+v"(vj[3]), "+v"(hj[0]), "+v"(hj[1]), "+v"(hj[2]), "+v"(hj[3])::"memory");
+#pragma unroll
+            for (int c = 0; c < 4; c++) mn[c] = mks[4 * gn + c];
+            uint64_t live[4], fbm[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                live[c] = mm[c];
+                fbm[c] = 0ull;
+            }
+            if (CHK) {
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    // intact bonds next to a sentinel: strain (and decision) from the
+                    // double state, taken out of the screen below
+                    int so = e[c].soff;
+                    asm volatile("" : "+s"(so));
+                    float bx, by, bz;
+                    box.pos(my + so, bx, by, bz);
+                    fbm[c] = __ballot(__builtin_isinf(aix) || __builtin_isinf(bx)) & live[c];
+                    if (fbm[c]) {
+                        nfall += __popcll(fbm[c]);
+                        bool broke = false;
+                        if (lane_bit(fbm[c])) evs[c] = (float)(decide(4 * gg + c, broke) * invQ);
+                        const uint64_t bb = BREAK ? __ballot(broke) : 0ull;
+                        if (bb) {
+                            live[c] &= ~bb;
+                            if (lane == 0 && valid) mrow[4 * gg + c] = live[c];
+                            nbroken += __popcll(bb);
+                        }
+                    }
+                }
+            }
+            if (BREAK) {
+                // the screen of the four entries, one branch for the group
+                uint64_t maybe[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) maybe[c] = __ballot(evs[c] >= thr_lo) & live[c] & ~fbm[c];
+                if (maybe[0] | maybe[1] | maybe[2] | maybe[3]) {
+#pragma unroll
+                    for (int c = 0; c < 4; c++) {
+                        if (!maybe[c]) continue;
+                        const int k = 4 * gg + c;
+                        // the neighbour's staged values read again (through an
+                        // opaque offset: not kept in registers for this rare test)
+                        int so = e[c].soff;
+                        asm volatile("" : "+s"(so));
+                        float bx, by, bz;
+                        box.pos(my + so, bx, by, bz);
+                        const float xk = kt[k].x;
+                        const float sd = fabsf(bx - aix) + fabsf(by - aiy) + (DIM == 3 ? fabsf(bz - aiz) : 0.0f);
+                        const float sa = big_abs(bx) + big_abs(by) + (DIM == 3 ? big_abs(bz) : 0.0f) + big_i;
+                        const float lim = thrQ * xk - 1.7320509f;
+                        const bool need = lane_bit(maybe[c]) &&
+                                          fmaf(1.1920929e-7f, sa, fmaf(9.5367432e-7f, sd, evs[c] * xk)) >= lim;
                         const uint64_t needm = __ballot(need);
                         if (needm) {
                             nrecheck += __popcll(needm);
                             bool broke = false;
-                            if (need) (void)decide(k, true, broke);
+                            if (need) (void)decide(k, broke);
                             const uint64_t bb = __ballot(broke);
                             if (bb) {
-                                live &= ~bb;
-                                if (lane == 0 && valid) mrow[k] = live;
+                                live[c] &= ~bb;
+                                if (lane == 0 && valid) mrow[k] = live[c];
                                 nbroken += __popcll(bb);
                             }
                         }
                     }
                 }
-                if (CHK) {
-                    // intact bonds next to a sentinel: extension (and decision) from the double state
-                    const uint64_t fbm = __ballot(si.x == PD_SENTINEL_T || sj[c].x == PD_SENTINEL_T) & live;
-                    if (fbm) {
-                        nfall += __popcll(fbm);
-                        bool broke = false;
-                        if (lane_bit(fbm)) ev = (float)(decide(k, true, broke) * invQ);
-                        const uint64_t bb = BREAK ? __ballot(broke) : 0ull;
-                        if (bb) {
-                            live &= ~bb;
-                            if (lane == 0 && valid) mrow[k] = live;
-                            nbroken += __popcll(bb);
-                        }
-                    }
-                }
-                const float evm = lane_bit(live) ? ev : 0.0f;  // broken bonds carry nothing
-                const float Vj = __int_as_float(sj[c].w);
-                // dilatation: x V_j e;  deviatoric force: G e (1/m_i + 1/m_j) V_j
-                acc = fmaf(e[c].x * Vj, evm, acc);
-                const float te = evm * fmaf(rpi, Vj, rvj[c]);
-                fx = fmaf(te, e[c].m0, fx);
-                fy = fmaf(te, e[c].m1, fy);
-                if (DIM == 3) fz = fmaf(te, e[c].m2, fz);
             }
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const float evm = lane_bit(live[c]) ? evs[c] : 0.0f;  // broken bonds carry nothing
+                // dilatation: x V_j e = x^2 V_j e';  deviatoric force: G e (1/m_i + 1/m_j) V_j M
+                acc = fmaf(e[c].x2 * vj[c], evm, acc);
+                const float te = evm * fmaf(rpi, vj[c], hj[c]);
+                fx = fmaf(te, e[c].xm0, fx);
+                fy = fmaf(te, e[c].xm1, fy);
+                if (DIM == 3) fz = fmaf(te, e[c].xm2, fz);
+            }
+        }
+    };
+    // groups in pairs with two sets of status words, so that the words in
+    // flight are never copied (a copy would wait for them)
+    auto sweep = [&](auto chk) {
+        uint64_t ma[4], mb[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) ma[c] = mw[c];
+        for (int gg = g0; gg < g1; gg += 2) {
+            group(chk, gg, ma, mb, min(gg + 1, g1 - 1));
+            if (gg + 1 < g1) group(chk, gg + 1, mb, ma, min(gg + 2, g1 - 1));
         }
     };
     if (anysent) sweep(std::true_type{});
@@ -309,7 +439,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         D.z -= d[2];
         a.dsum[row] = D;
     }
-    // theta_i / m_i = A r_i^2 Q sum_j x V_j e'_j
+    // theta_i / m_i = A r_i^2 sum_j x V_j e_j, the sum carried in units of Q
     const double accQ = (double)tot[0] * Q;
     a.qr32[row].x = (float)((double)sp.A * (double)ri * (double)ri * accQ);
     if (a.theta_out) a.theta_out[row] = (double)sp.A * (double)ri * accQ;
@@ -319,14 +449,26 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
 // ---------------------------------------------------------------------------
 // pass 2: dilatational pair force, explicit update, next shadow
 // ---------------------------------------------------------------------------
+// LDS of one tile in pass 2: (K - G/3) theta/m and V per point in the
+// layout of pass 1's box (3D: two float arrays, read with one
+// ds_read2st64; 2D: one float2 array), with TPW = 1 the partial sums (3
+// floats per thread), then the 27 neighbour tiles.
+template <int DIM, int TPW>
+struct Lay2 {
+    static constexpr int S = Lay1<DIM, TPW>::S;
+    static constexpr int BOX = 2 * S * 4;
+    static constexpr int SUMS = TPW == 1 ? 3 * PD_TILE_WAVES * 64 * 4 : 0;
+    static constexpr int BYTES = BOX + SUMS + 32 * 4;
+};
+
 template <int DIM, bool UPDATE, int TPW>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int cur,
-                                                                const KEnt2 *__restrict__ kt,
-                                                                const uint64_t *__restrict__ kmask) {
+                                                                const KEnt1 *__restrict__ kn) {
     extern __shared__ __align__(16) unsigned char smem[];
     using GR = Grp<DIM, TPW>;
-    constexpr int MS = GR::MS;
-    const Box g = make_box(a, DIM);
+    using LY = Lay2<DIM, TPW>;
+    constexpr int S = LY::S;
+    constexpr int MS = Lay1<DIM, TPW>::MP;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int gt = TPW == 1 ? tid : lane;
@@ -336,84 +478,113 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     const int64_t tile = group_tile<TPW>(a.n_slices, sub, valid);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
-    unsigned char *reg = smem + sub * tile2_bytes<TPW>(g.nslot);
-    float2 *hq = reinterpret_cast<float2 *>(reg);  // ((K - G/3) theta_j/m_j, V_j)
-    uint64_t *smask = reinterpret_cast<uint64_t *>(reg + tile2_box_bytes<TPW>(g.nslot));
-    int *stn = reinterpret_cast<int *>(smask + 128);
-    float *red = reinterpret_cast<float *>(stn + 32);  // TPW = 1: [3][waves][64]
+    unsigned char *reg = smem + sub * LY::BYTES;
+    float *hb = reinterpret_cast<float *>(reg);  // [2][S]: (K - G/3) theta_j/m_j, V_j
+    float *red = reinterpret_cast<float *>(reg + LY::BOX);  // TPW = 1: [3][waves][64]
+    int *stn = reinterpret_cast<int *>(reg + LY::BOX + LY::SUMS);
+    int32_t B1[4];
+    pd_tile_box1(a.tile, a.reach, DIM, B1);
+    const int npts = pd_box_points(a.tile, a.reach, DIM);
     pd_ctl *ctl = a.ctl;
     const int4 *__restrict__ sh = a.ush[cur];
     const float2 *__restrict__ qr = a.qr32;
     const int64_t row = tile * 64 + lane;
-    const uint32_t aux = a.aux[row];
-    const uint64_t *__restrict__ mrow = kmask + (base >> 6);
-    int hmv[MS];
+    const cu64_t *mks = (const cu64_t *)(a.mask + (base >> 6));
+    int hp[MS];
 #pragma unroll
-    for (int i = 0; i < MS; i++) {
-        const int s = gt + i * GR::NT;
-        hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
-    }
+    for (int i = 0; i < MS; i++) hp[i] = a.halo_pos[min(gt + i * GR::NT, npts - 1)];
     if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
-    const uint64_t mw0 = gt < L4 ? mrow[gt] : 0ull;
-    const uint64_t mw1 = (TPW != 1 && gt + 64 < L4) ? mrow[gt + 64] : 0ull;
+    const int G4 = L4 >> 2;
+    const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
+    const int g0 = kq * gper, g1 = min(G4, g0 + gper);
+    uint64_t mw[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) mw[c] = g0 < g1 ? mks[4 * g0 + c] : 0ull;
+    const uint32_t aux = a.aux[row];
     const pd_spec sp = a.spec[tile_specimen(aux)];
     const float kp = (float)sp.kp;
+    // the row's own data for the update, requested now by the wave that
+    // finishes the rows, so that it arrives during the staging and the sweep
+    double4 ui = make_double4(0.0, 0.0, 0.0, 0.0), D = ui, v = ui;
+    float4 fe = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (kq == 0 && valid) {
+        ui = a.uv[cur][row];
+        D = a.dsum[row];
+        fe = a.fe32[row];
+        if (UPDATE) v = a.vel[row];
+    }
     __syncthreads();
     {
-        int64_t rw[MS];
+        uint32_t rw[MS];
+#pragma unroll
+        for (int i = 0; i < MS; i++) {
+            const int h = hp[i] & 2047;
+            const int nt = stn[h >> 6];
+            rw[i] = (uint32_t)(nt < 0 ? (int)tile : nt) * 64u + (uint32_t)(h & 63);
+        }
         float q[MS];
         int vb[MS];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            rw[i] = halo_row_of(hmv[i], stn);
+            q[i] = qr[rw[i]].x;
+            vb[i] = sh[rw[i]].w;
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            q[i] = rw[i] >= 0 ? qr[rw[i]].x : 0.0f;
-            vb[i] = rw[i] >= 0 ? sh[rw[i]].w : 0;
-        }
-#pragma unroll
-        for (int i = 0; i < MS; i++) {
-            const int s = gt + i * GR::NT;
-            if (s < g.nslot) hq[s] = make_float2(kp * q[i], __int_as_float(vb[i]));
+            const int slot = hp[i] >> 11;
+            if constexpr (DIM == 3) {
+                hb[slot] = kp * q[i];
+                hb[S + slot] = __int_as_float(vb[i]);
+            } else {
+                reinterpret_cast<float2 *>(hb)[slot] = make_float2(kp * q[i], __int_as_float(vb[i]));
+            }
         }
     }
-    if (gt < 128) smask[gt] = mw0;
-    if (TPW != 1) smask[gt + 64] = mw1;
     __syncthreads();
-    const int my = own_slot<DIM>(g, lane);
-    const float qi = hq[my].x;
-    const int o_q = my * 8;  // byte offset of this row's own slot
-    const int G4 = L4 >> 2;
-    const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
-    const int g0 = kq * gper, g1 = min(G4, g0 + gper);
+    const int my = own_slot1<DIM>(a.tile, a.reach, B1, lane);
+    const float qi = DIM == 3 ? hb[my] : reinterpret_cast<const float2 *>(hb)[my].x;
     float fx = 0.f, fy = 0.f, fz = 0.f;
     {
-        KEnt2 en[4];
-#pragma unroll
-        for (int c = 0; c < 4; c++) en[c] = kt[4 * g0 + c];
-        for (int gg = g0; gg < g1; gg++) {
-            KEnt2 e[4];
-            float2 qj[4];
-            uint64_t mm[4];
+        auto group = [&](int gg, const uint64_t(&mm)[4], uint64_t(&mn)[4], int gn) {
+            float xm0[4], xm1[4], xm2[4], qj[4], vj[4];
 #pragma unroll
             for (int c = 0; c < 4; c++) {
-                e[c] = en[c];
-                qj[c] = *reinterpret_cast<const float2 *>(reg + o_q + 8 * e[c].soff);
-                mm[c] = uni64_t(smask[4 * gg + c]);
+                const KEnt1 &e = kn[4 * gg + c];  // a 4 KiB table: scalar-cache hits
+                xm0[c] = e.xm0;
+                xm1[c] = e.xm1;
+                xm2[c] = e.xm2;
+                if constexpr (DIM == 3) {
+                    qj[c] = hb[my + e.soff];
+                    vj[c] = hb[S + my + e.soff];
+                } else {
+                    const float2 t = reinterpret_cast<const float2 *>(hb)[my + e.soff];
+                    qj[c] = t.x;
+                    vj[c] = t.y;
+                }
             }
-            const int gn = min(gg + 1, 31);
+            // next group's status words once this group's LDS reads are consumed
+            // (scalar and LDS reads share one completion counter)
+            asm volatile("" : "+v"(qj[0]), "+v"(qj[1]), "+v"(qj[2]), "+v"(qj[3]), "+v"(vj[0]), "+v"(vj[1]),
+                         "+v"(vj[2]), "+v"(vj[3])::"memory");
 #pragma unroll
-            for (int c = 0; c < 4; c++) en[c] = kt[4 * gn + c];
+            for (int c = 0; c < 4; c++) mn[c] = mks[4 * gn + c];
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 // (K - G/3) (q_j - q_i) V_j, times x M from the table
-                float t = (qj[c].x - qi) * qj[c].y;
+                float t = (qj[c] - qi) * vj[c];
                 t = lane_bit(mm[c]) ? t : 0.0f;
-                fx = fmaf(t, e[c].xm0, fx);
-                fy = fmaf(t, e[c].xm1, fy);
-                if (DIM == 3) fz = fmaf(t, e[c].xm2, fz);
+                fx = fmaf(t, xm0[c], fx);
+                fy = fmaf(t, xm1[c], fy);
+                if (DIM == 3) fz = fmaf(t, xm2[c], fz);
             }
+        };
+        // groups in pairs with two sets of status words (no copy of words in flight)
+        uint64_t ma[4], mb[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) ma[c] = mw[c];
+        for (int gg = g0; gg < g1; gg += 2) {
+            group(gg, ma, mb, min(gg + 1, g1 - 1));
+            if (gg + 1 < g1) group(gg + 1, mb, ma, min(gg + 2, g1 - 1));
         }
     }
     float sx = fx, sy = fy, sz = fz;
@@ -433,9 +604,6 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         }
     }
     if (!valid) return;
-    const double4 ui = a.uv[cur][row];
-    const double4 D = a.dsum[row];
-    const float4 fe = a.fe32[row];
     // dilatational sum in difference form plus its row constant 2 (K - G/3) q_i D_i,
     // deviatoric sum from pass 1; all times V_i
     const double c2 = 2.0 * (double)qi;
@@ -458,7 +626,6 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         Fz += fx4.z * r;
     }
     const double mass = sp.rho * ui.w;
-    double4 v = a.vel[row];
     const double ax = (aux & 1u) ? 0.0 : Fx / mass;
     const double ay = (aux & 2u) ? 0.0 : Fy / mass;
     const double az = (aux & 4u) ? 0.0 : Fz / mass;
@@ -589,14 +756,18 @@ static int box_slots(const StepArgs &a) {
     return B[3] * B[2];
 }
 
+static int box_points(const StepArgs &a) { return pd_box_points(a.tile, a.reach, a.dim); }
+
+static_assert(Lay1<3, 1>::S == 1472 && Lay1<2, 4>::S == 336 && Lay1<2, 1>::S == 1024,
+              "pass-1 array strides follow pd_box1_stride");
+
 static size_t tiled_lds(const StepArgs &a, int pass, int tpw) {
-    const int ns = box_slots(a);
-    if (tpw == 1) return pass == 1 ? tile1_bytes<1>(ns) : tile2_bytes<1>(ns);
-    return (size_t)tpw * (pass == 1 ? tile1_bytes<4>(ns) : tile2_bytes<4>(ns));
+    if (pass == 1) return a.dim == 3 ? Lay1<3, 1>::BYTES : (tpw == 4 ? 4 * Lay1<2, 4>::BYTES : Lay1<2, 1>::BYTES);
+    return a.dim == 3 ? Lay2<3, 1>::BYTES : (tpw == 4 ? 4 * Lay2<2, 4>::BYTES : Lay2<2, 1>::BYTES);
 }
 
 bool tiled_supported(const StepArgs &a) {
-    if (!a.tile_nbr || !a.ktab || !a.halo_map) return false;
+    if (!a.tile_nbr || !a.ktab || !a.halo_map || !a.halo_pos) return false;
     if (a.tile[0] * a.tile[1] * a.tile[2] != 64) return false;
     for (int c = 0; c < 3; c++)
         if (a.tile[c] < 1 || (a.tile[c] & (a.tile[c] - 1))) return false;  // powers of two
@@ -604,46 +775,52 @@ bool tiled_supported(const StepArgs &a) {
     if (a.dim == 3 && a.tile[2] < a.reach) return false;
     if (a.dim == 2 && a.tile[2] != 1) return false;
     if (a.n_stencil > 124) return false;  // groups of four inside the 128-row table
-    const int ns = box_slots(a);
-    const int tpw = tiles_per_group(a.dim, ns);
+    const int ns = box_slots(a), np = box_points(a);
+    const int tpw = tiles_per_group(a.dim, np);
     const int cap = a.dim == 3 ? Grp<3, 1>::CAP : (tpw == 4 ? Grp<2, 4>::CAP : Grp<2, 1>::CAP);
-    if (ns > cap) return false;
+    if (ns > cap || np > cap) return false;
+    int32_t B1[4];
+    pd_tile_box1(a.tile, a.reach, a.dim, B1);
+    if (B1[3] * B1[2] > pd_box1_stride(a.dim, np)) return false;
+    const int cap1 = a.dim == 3 ? 256 * Lay1<3, 1>::MP : (tpw == 4 ? 64 * Lay1<2, 4>::MP : 256 * Lay1<2, 1>::MP);
+    if (np > cap1) return false;
+    if (a.n_pad >= (int64_t(1) << 31)) return false;  // 32-bit row numbers in the staging
     return tiled_lds(a, 1, tpw) <= 64 * 1024 && tiled_lds(a, 2, tpw) <= 64 * 1024;
 }
 
 hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s) {
-    const int tpw = tiles_per_group(a.dim, box_slots(a));
+    const int tpw = tiles_per_group(a.dim, box_points(a));
     const size_t lds = tiled_lds(a, 1, tpw);
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
+    const KEnt1 *kn = reinterpret_cast<const KEnt1 *>(a.ktab + 1536);
     if (a.dim == 3) {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true, 1>), g, b, lds, s, a, cur, kt);
-        else hipLaunchKernelGGL((k_tpass1_f32<3, false, 1>), g, b, lds, s, a, cur, kt);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true, 1>), g, b, lds, s, a, cur, kt, kn);
+        else hipLaunchKernelGGL((k_tpass1_f32<3, false, 1>), g, b, lds, s, a, cur, kt, kn);
     } else if (tpw == 4) {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f32<2, true, 4>), g, b, lds, s, a, cur, kt);
-        else hipLaunchKernelGGL((k_tpass1_f32<2, false, 4>), g, b, lds, s, a, cur, kt);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f32<2, true, 4>), g, b, lds, s, a, cur, kt, kn);
+        else hipLaunchKernelGGL((k_tpass1_f32<2, false, 4>), g, b, lds, s, a, cur, kt, kn);
     } else {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f32<2, true, 1>), g, b, lds, s, a, cur, kt);
-        else hipLaunchKernelGGL((k_tpass1_f32<2, false, 1>), g, b, lds, s, a, cur, kt);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f32<2, true, 1>), g, b, lds, s, a, cur, kt, kn);
+        else hipLaunchKernelGGL((k_tpass1_f32<2, false, 1>), g, b, lds, s, a, cur, kt, kn);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_tpass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s) {
-    const int tpw = tiles_per_group(a.dim, box_slots(a));
+    const int tpw = tiles_per_group(a.dim, box_points(a));
     const size_t lds = tiled_lds(a, 2, tpw);
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
-    const KEnt2 *kt = reinterpret_cast<const KEnt2 *>(a.ktab + 1024);
-    const uint64_t *km = a.mask;
+    const KEnt1 *kn = reinterpret_cast<const KEnt1 *>(a.ktab + 1536);
     if (a.dim == 3) {
-        if (update) hipLaunchKernelGGL((k_tpass2_f32<3, true, 1>), g, b, lds, s, a, cur, kt, km);
-        else hipLaunchKernelGGL((k_tpass2_f32<3, false, 1>), g, b, lds, s, a, cur, kt, km);
+        if (update) hipLaunchKernelGGL((k_tpass2_f32<3, true, 1>), g, b, lds, s, a, cur, kn);
+        else hipLaunchKernelGGL((k_tpass2_f32<3, false, 1>), g, b, lds, s, a, cur, kn);
     } else if (tpw == 4) {
-        if (update) hipLaunchKernelGGL((k_tpass2_f32<2, true, 4>), g, b, lds, s, a, cur, kt, km);
-        else hipLaunchKernelGGL((k_tpass2_f32<2, false, 4>), g, b, lds, s, a, cur, kt, km);
+        if (update) hipLaunchKernelGGL((k_tpass2_f32<2, true, 4>), g, b, lds, s, a, cur, kn);
+        else hipLaunchKernelGGL((k_tpass2_f32<2, false, 4>), g, b, lds, s, a, cur, kn);
     } else {
-        if (update) hipLaunchKernelGGL((k_tpass2_f32<2, true, 1>), g, b, lds, s, a, cur, kt, km);
-        else hipLaunchKernelGGL((k_tpass2_f32<2, false, 1>), g, b, lds, s, a, cur, kt, km);
+        if (update) hipLaunchKernelGGL((k_tpass2_f32<2, true, 1>), g, b, lds, s, a, cur, kn);
+        else hipLaunchKernelGGL((k_tpass2_f32<2, false, 1>), g, b, lds, s, a, cur, kn);
     }
     return hipGetLastError();
 }

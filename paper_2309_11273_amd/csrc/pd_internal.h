@@ -61,3 +61,40 @@ PD_HD inline void pd_tile_box(const int32_t *T, int R, int dim, int32_t *B) {
     B[2] = dim == 3 ? T[2] + 2 * R : 1;
     B[3] = B[0] * B[1];
 }
+
+// Points of the halo box itself (tile + R on every side, no padding).
+PD_HD inline int pd_box_points(const int32_t *T, int R, int dim) {
+    return (T[0] + 2 * R) * (T[1] + 2 * R) * (dim == 3 ? T[2] + 2 * R : 1);
+}
+
+// Fixed array stride (points) of the box the single-precision kernels
+// stage as separate arrays: 3D (a multiple of 64, for the st64 reads); 2D
+// boxes of at most 256 points (one wave per tile) or more (four waves per
+// tile).
+PD_HD inline int pd_box1_stride(int dim, int npoints) { return dim == 3 ? 1472 : (npoints <= 256 ? 336 : 1024); }
+
+// Pitches of that box, laid out like pd_tile_box (B[0] x pitch, B[1] y
+// pitch, B[2] z extent, B[3] = B[0] B[1] z pitch) but padded so that the 64
+// lanes of a tile, reading one 4-byte element each at the same offset from
+// their own points, hit 64 distinct LDS banks: x + B[0] y + B[3] z must be
+// distinct mod 64 over the tile's positions, which pitches 12 and 144 give a
+// 4x4x4 tile and an x pitch that is an odd multiple of 8 gives an 8x8 tile.
+// Boxes the padding would push past the stride stay unpadded.
+PD_HD inline void pd_tile_box1(const int32_t *T, int R, int dim, int32_t *B) {
+    const int e0 = T[0] + 2 * R, e1 = T[1] + 2 * R, e2 = dim == 3 ? T[2] + 2 * R : 1;
+    int p0 = e0, p1 = e1;
+    if (dim == 3 && T[0] == 4 && T[1] == 4 && e0 <= 12) {
+        p0 = 12;
+        p1 = 12;
+    } else if (dim == 2 && T[0] == 8 && e0 <= 24) {
+        p0 = 24;
+    }
+    if (p0 * p1 * e2 > pd_box1_stride(dim, e0 * e1 * e2)) {
+        p0 = e0;
+        p1 = e1;
+    }
+    B[0] = p0;
+    B[1] = p1;
+    B[2] = e2;
+    B[3] = p0 * p1;
+}

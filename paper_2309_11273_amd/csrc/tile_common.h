@@ -28,6 +28,18 @@ struct KEnt2 {
     int soff;
 };
 static_assert(sizeof(KEnt2) == 16, "second ktab row is 4 words");
+// one row of the third table (from word 1536), used by the single-precision
+// kernels: M / x, x^2, x M and the neighbour's offset in their box; the
+// third components last, so that a 2D row's used words are contiguous
+struct KEnt1 {
+    float mx0, mx1, x2, xm0, xm1;
+    int soff;
+    float mx2, xm2;
+};
+static_assert(sizeof(KEnt1) == 32, "third ktab row is 8 words");
+
+// 64-bit words read through the scalar data cache (wave-uniform addresses)
+typedef __attribute__((address_space(4))) const uint64_t cu64_t;
 
 __device__ __forceinline__ double ext_canonical_t(double m1, double m2, double m3, double e1, double e2,
                                                   double e3) {
@@ -62,6 +74,12 @@ __device__ __forceinline__ uint64_t uni64_t(uint64_t v) {
 
 // float of the 32-bit difference a - b (wrapping, never undefined)
 __device__ __forceinline__ float idiff(int a, int b) { return (float)(int)((uint32_t)a - (uint32_t)b); }
+
+// |v| if |v| >= 2^24 (a float that may hold a rounded integer), else 0
+__device__ __forceinline__ float big_abs(float v) {
+    const float m = fabsf(v);
+    return m >= 16777216.0f ? m : 0.0f;
+}
 
 // lane's bit of a wave-uniform 64-bit word, used as the condition mask as is
 __device__ __forceinline__ bool lane_bit(uint64_t uniform_word) {
@@ -99,6 +117,15 @@ __device__ __forceinline__ int own_slot(const Box &g, int lane) {
     const int s0 = __builtin_ctz((unsigned)g.T0), s1 = __builtin_ctz((unsigned)g.T1);
     const int l0 = lane & (g.T0 - 1), l1 = (lane >> s0) & (g.T1 - 1), l2 = lane >> (s0 + s1);
     return (l0 + g.R) + g.Bx * (l1 + g.R) + g.Pz * (DIM == 3 ? l2 + g.R : 0);
+}
+
+// slot of lane l's own point in the single-precision pass-1 box (pitches B
+// from pd_tile_box1)
+template <int DIM>
+__device__ __forceinline__ int own_slot1(const int32_t *T, int R, const int32_t *B, int lane) {
+    const int s0 = __builtin_ctz((unsigned)T[0]), s1 = __builtin_ctz((unsigned)T[1]);
+    const int l0 = lane & (T[0] - 1), l1 = (lane >> s0) & (T[1] - 1), l2 = lane >> (s0 + s1);
+    return (l0 + R) + B[0] * (l1 + R) + B[3] * (DIM == 3 ? l2 + R : 0);
 }
 
 // 1 / q for a power of two q (exact, no division)
@@ -153,7 +180,7 @@ __device__ __forceinline__ int64_t group_tile(int64_t n_tiles, int sub, bool &va
 }
 
 // workgroup tiling the launchers choose: whole tiles per wave in 2D when the
-// halo box fits the per-wave staging capacity
-inline int tiles_per_group(int dim, int nslot) { return (dim == 2 && nslot <= Grp<2, 4>::CAP) ? 4 : 1; }
+// halo box (npoints points, unpadded) fits the per-wave staging capacity
+inline int tiles_per_group(int dim, int npoints) { return (dim == 2 && npoints <= Grp<2, 4>::CAP) ? 4 : 1; }
 
 }  // namespace pdk

@@ -106,12 +106,14 @@ class FamilyHost:
         self.lat4 = np.empty(s.n_pad * 4, np.int32)
         self.tile_org = np.empty(s.n_tiles * 4, np.int32)
         self.tile_nbr = np.empty(s.n_tiles * 27, np.int32)
-        self.ktab = np.empty(128 * 12, np.uint32)
+        self.ktab = np.empty(128 * 20, np.uint32)
         self.halo_map = np.empty(max(1, s.n_halo), np.int16)
+        self.halo_pos = np.empty(max(1, s.n_box), np.int32)
         hb = A.pd_family_host(_np(self.perm), _np(self.row_of), _np(self.slice_ptr), _np(self.words),
                               _np(self.mask), _np(self.stencil), _np(self.stencil_off), _np(self.vol),
                               _np(self.inv_m), _np(self.spec), _np(self.lat4), _np(self.tile_org),
-                              _np(self.tile_nbr), _np(self.ktab), _np(self.halo_map))
+                              _np(self.tile_nbr), _np(self.ktab), _np(self.halo_map),
+                              _np(self.halo_pos))
         self._hb = hb
         A.check("pd_build_family", L.pd_build_family(C.byref(body), C.cast(carr, C.c_void_p), len(cuts),
                                                      C.byref(sizes), C.byref(hb)))
@@ -219,6 +221,8 @@ class Solver:
         P.ktab = _tp(self.ktab)
         self.halo_map = t(self.fam.halo_map)
         P.halo_map = _tp(self.halo_map)
+        self.halo_pos = t(self.fam.halo_pos)
+        P.halo_pos = _tp(self.halo_pos)
         for c in range(3):
             P.tile[c] = int(s.tile[c])
         P.reach = int(s.reach)

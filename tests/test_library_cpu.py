@@ -139,11 +139,11 @@ def test_tile_halo_addressing_matches_bond_words(lib, case):
         assert np.array_equal(rows_map, rows)
         ns_ = len(soff)
         kt1 = f.ktab[:1024].view(np.int32).reshape(128, 8)
-        kt2 = f.ktab[1024:].view(np.int32).reshape(128, 4)
+        kt2 = f.ktab[1024:1536].view(np.int32).reshape(128, 4)
         assert np.array_equal(kt1[:ns_, 4], soff) and np.array_equal(kt2[:ns_, 3], soff)
         assert not kt1[ns_:].any() and not kt2[ns_:].any() and not kt1[:, 6:].any()
         kf1 = f.ktab[:1024].view(np.float32).reshape(128, 8)
-        kf2 = f.ktab[1024:].view(np.float32).reshape(128, 4)
+        kf2 = f.ktab[1024:1536].view(np.float32).reshape(128, 4)
         sten = f.stencil.reshape(-1, 4)
         assert np.array_equal(kf1[:ns_, :4], sten.astype(np.float32))
         assert np.array_equal(kf1[:ns_, 5], (1.0 / sten[:, 3]).astype(np.float32))
@@ -162,6 +162,81 @@ def test_tile_halo_addressing_matches_bond_words(lib, case):
                     assert rows[slot] == (wd >> 7)
             for k in range(int(s.n_stencil), L4):
                 assert (f.words[base + (k // 4) * 256 + lane * 4 + (k % 4)] & 127) == 127
+
+
+def _box1_pitches(T, R, dim):
+    """Pitches of the single-precision pass-1 box: 64 distinct LDS banks
+    (mod 64) over a tile's lanes when padded, unpadded if the padded box
+    exceeds the kernel's array stride."""
+    e0, e1, e2 = T[0] + 2 * R, T[1] + 2 * R, (T[2] + 2 * R) if dim == 3 else 1
+    p0, p1 = e0, e1
+    if dim == 3 and T[0] == 4 and T[1] == 4 and e0 <= 12:
+        p0 = p1 = 12
+    elif dim == 2 and T[0] == 8 and e0 <= 24:
+        p0 = 24
+    stride = 1472 if dim == 3 else (336 if e0 * e1 * e2 <= 256 else 1024)
+    if p0 * p1 * e2 > stride:
+        p0, p1 = e0, e1
+    return p0, p1, e2
+
+
+@pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate"])
+def test_pass1_box_addressing_matches_bond_words(lib, case):
+    """The single-precision pass 1 stages the unpadded box point by point
+    (halo_pos) into a padded box and finds neighbour k of lane l at
+    slot(l) + soff1[k] (third table); that slot must receive exactly the row
+    the bond word names.  Its third-table entries are M/x, x^2 and x M."""
+    w = CASES[case]()
+    f = _family(w)
+    s = f.sizes
+    T = list(s.tile)
+    R, dim = int(s.reach), int(s.dim)
+    p0, p1, e2 = _box1_pitches(T, R, dim)
+    e0, e1 = T[0] + 2 * R, T[1] + 2 * R
+    assert int(s.n_box) == e0 * e1 * e2
+    if dim == 3 and T[:2] == [4, 4] and e0 <= 12:
+        # the lanes of a tile hit 64 distinct banks (4-byte elements)
+        lanes = [(l % 4) + p0 * ((l // 4) % 4) + p0 * p1 * (l // 16) for l in range(64)]
+        assert len({v % 64 for v in lanes}) == 64
+    if dim == 2 and T[:2] == [8, 8] and p0 == 24:
+        # 8-byte elements: each half-wave's 32 lanes hit 32 distinct bank pairs
+        lanes = [(l % 8) + p0 * (l // 8) for l in range(64)]
+        for h in (lanes[:32], lanes[32:]):
+            assert len({v % 32 for v in h}) == 32
+    hp = f.halo_pos[: int(s.n_box)].astype(np.int64)
+    off = f.stencil_off.reshape(-1, 3)
+    ns_ = int(s.n_stencil)
+    kt = f.ktab[1536:].view(np.int32).reshape(128, 8)
+    kf = f.ktab[1536:].view(np.float32).reshape(128, 8)
+    soff1 = off[:, 0] + p0 * off[:, 1] + p0 * p1 * off[:, 2]
+    assert np.array_equal(kt[:ns_, 5], soff1) and not kt[ns_:].any()
+    sten = f.stencil.reshape(-1, 4)
+    mx = (sten[:, :3] / sten[:, 3:4]).astype(np.float32)
+    xm = (sten[:, 3:4] * sten[:, :3]).astype(np.float32)
+    assert np.array_equal(kf[:ns_, [0, 1, 6]], mx)
+    assert np.array_equal(kf[:ns_, 2], (sten[:, 3] * sten[:, 3]).astype(np.float32))
+    assert np.array_equal(kf[:ns_, [3, 4, 7]], xm)
+    # every box point lands on a distinct slot of the padded box
+    slots = hp >> 11
+    assert len(np.unique(slots)) == len(slots) and slots.max() < p0 * p1 * e2
+    rng = np.random.default_rng(1)
+    tiles = rng.choice(int(s.n_tiles), size=min(40, int(s.n_tiles)), replace=False)
+    for t in tiles:
+        tn = f.tile_nbr[27 * int(t): 27 * int(t) + 27]
+        rows = np.full(p0 * p1 * e2, -1, np.int64)
+        nt = tn[(hp & 2047) >> 6]
+        rows[slots] = np.where(nt >= 0, nt * 64 + (hp & 63), -1)
+        base = f.slice_ptr[t]
+        for lane in range(64):
+            l0, l1, l2 = lane % T[0], (lane // T[0]) % T[1], lane // (T[0] * T[1])
+            my = (l0 + R) + p0 * (l1 + R) + p0 * p1 * ((l2 + R) if dim == 3 else 0)
+            assert rows[my] == t * 64 + lane
+            for k in range(ns_):
+                wd = f.words[base + (k // 4) * 256 + lane * 4 + (k % 4)]
+                slot = my + soff1[k]
+                assert 0 <= slot < p0 * p1 * e2
+                if (wd & 127) != 127:
+                    assert rows[slot] == (wd >> 7)
 
 
 def test_internal_order_is_tile_major(lib):
