@@ -266,6 +266,9 @@ typedef struct pd_state_dev {
                            carried from pass 1 to pass 2 (FP32 LDS-staged path)      */
     double *fe64;       /* n_pad*4 the same for the FP64 LDS-staged path (NULL: the
                            FP64 path uses the gather kernels)                        */
+    float *qv32;        /* n_pad*2 (theta/m, V) of the step in FP32, written by the
+                           FP32 LDS-staged pass 1 for its pass 2 (NULL: the FP32
+                           path uses the gather kernels)                             */
     void *ctl;          /* PD_CTL_BYTES control block                               */
     int32_t cur;        /* index of uv (and ush) holding the current state          */
     int32_t pad0;

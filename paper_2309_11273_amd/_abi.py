@@ -57,7 +57,7 @@ class pd_problem_dev(C.Structure):
 
 class pd_state_dev(C.Structure):
     _fields_ = [("uv", P * 2), ("vel", P), ("qr", P), ("mask", P), ("ush", P * 2), ("qr32", P),
-                ("dsum", P), ("fe32", P), ("fe64", P), ("ctl", P), ("cur", i32), ("pad0", i32)]
+                ("dsum", P), ("fe32", P), ("fe64", P), ("qv32", P), ("ctl", P), ("cur", i32), ("pad0", i32)]
 
 
 class pd_step_opts(C.Structure):

@@ -85,6 +85,7 @@ pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
     a.dsum = reinterpret_cast<double4 *>(st->dsum);
     a.fe32 = reinterpret_cast<float4 *>(st->fe32);
     a.fe64 = reinterpret_cast<double4 *>(st->fe64);
+    a.qv32 = reinterpret_cast<float2 *>(st->qv32);
     a.stencil_off = p->stencil_off;
     a.tile_nbr = p->tile_nbr;
     for (int c = 0; c < 3; c++) a.tile[c] = p->tile[c];
@@ -372,7 +373,7 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
         const pdk::StepArgs ta = make_args(p, &tmp);
         if (o.precision == PD_FP32_RECHECK ? !pdk::tiled_supported(ta) : !pdk::tiled64_supported(ta))
             return fail(c, PD_ERR_UNSUPPORTED,
-                        "tile kernels need tile edges >= the stencil reach (and fe64 for FP64)");
+                        "tile kernels need tile edges >= the stencil reach (and qv32 for FP32, fe64 for FP64)");
     }
     if (o.profile && !c->ev[0]) {
         for (int k = 0; k < 4; k++) HIP_TRY(c, hipEventCreate(&c->ev[k]));
@@ -409,6 +410,7 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
                                        (uint64_t)p->ramp_steps, (uint64_t)(uintptr_t)p->fext,
                                        (uint64_t)(uintptr_t)st->qr, (uint64_t)o.kernel, (uint64_t)o.form,
                                        (uint64_t)(uintptr_t)st->fe32, (uint64_t)(uintptr_t)st->fe64,
+                                       (uint64_t)(uintptr_t)st->qv32,
                                        (uint64_t)(uintptr_t)K};
             for (uint64_t f : fields) key = mix(key, f);
             if (!c->gexec || c->gkey != key) {

@@ -32,6 +32,7 @@ struct StepArgs {
     double4 *dsum;
     float4 *fe32;
     double4 *fe64;
+    float2 *qv32;
     // BSR path
     uint32_t *dirty;
     // tile description (LDS-staged kernels)

@@ -439,9 +439,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         D.z -= d[2];
         a.dsum[row] = D;
     }
-    // theta_i / m_i = A r_i^2 sum_j x V_j e_j, the sum carried in units of Q
+    // theta_i / m_i = A r_i^2 sum_j x V_j e_j, the sum carried in units of Q;
+    // pass 2 stages it with V_i
     const double accQ = (double)tot[0] * Q;
-    a.qr32[row].x = (float)((double)sp.A * (double)ri * (double)ri * accQ);
+    const float qi = (float)((double)sp.A * (double)ri * (double)ri * accQ);
+    a.qr32[row].x = qi;
+    a.qv32[row] = make_float2(qi, __int_as_float(own.w));
     if (a.theta_out) a.theta_out[row] = (double)sp.A * (double)ri * accQ;
     a.fe32[row] = make_float4(tot[1], tot[2], tot[3], 0.0f);
 }
@@ -486,8 +489,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     pd_tile_box1(a.tile, a.reach, DIM, B1);
     const int npts = pd_box_points(a.tile, a.reach, DIM);
     pd_ctl *ctl = a.ctl;
-    const int4 *__restrict__ sh = a.ush[cur];
-    const float2 *__restrict__ qr = a.qr32;
+    const float2 *__restrict__ qvs = a.qv32;
     const int64_t row = tile * 64 + lane;
     const cu64_t *mks = (const cu64_t *)(a.mask + (base >> 6));
     int hp[MS];
@@ -522,21 +524,17 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
             const int nt = stn[h >> 6];
             rw[i] = (uint32_t)(nt < 0 ? (int)tile : nt) * 64u + (uint32_t)(h & 63);
         }
-        float q[MS];
-        int vb[MS];
+        float2 qv[MS];  // (theta/m, V) of the point, one 8-byte record
 #pragma unroll
-        for (int i = 0; i < MS; i++) {
-            q[i] = qr[rw[i]].x;
-            vb[i] = sh[rw[i]].w;
-        }
+        for (int i = 0; i < MS; i++) qv[i] = qvs[rw[i]];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             const int slot = hp[i] >> 11;
             if constexpr (DIM == 3) {
-                hb[slot] = kp * q[i];
-                hb[S + slot] = __int_as_float(vb[i]);
+                hb[slot] = kp * qv[i].x;
+                hb[S + slot] = qv[i].y;
             } else {
-                reinterpret_cast<float2 *>(hb)[slot] = make_float2(kp * q[i], __int_as_float(vb[i]));
+                reinterpret_cast<float2 *>(hb)[slot] = make_float2(kp * qv[i].x, qv[i].y);
             }
         }
     }
@@ -767,7 +765,7 @@ static size_t tiled_lds(const StepArgs &a, int pass, int tpw) {
 }
 
 bool tiled_supported(const StepArgs &a) {
-    if (!a.tile_nbr || !a.ktab || !a.halo_map || !a.halo_pos) return false;
+    if (!a.tile_nbr || !a.ktab || !a.halo_map || !a.halo_pos || !a.qv32) return false;
     if (a.tile[0] * a.tile[1] * a.tile[2] != 64) return false;
     for (int c = 0; c < 3; c++)
         if (a.tile[c] < 1 || (a.tile[c] & (a.tile[c] - 1))) return false;  // powers of two

@@ -237,6 +237,7 @@ class Solver:
         self.qr32 = torch.zeros(self.n_pad * 2, dtype=torch.float32, device=d) if fp32_state else None
         self.dsum = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=d) if fp32_state else None
         self.fe32 = torch.zeros(self.n_pad * 4, dtype=torch.float32, device=d) if fp32_state else None
+        self.qv32 = torch.zeros(self.n_pad * 2, dtype=torch.float32, device=d) if fp32_state else None
         self.fe64 = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=d)
         self.ctl = torch.zeros(A.PD_CTL_BYTES // 8, dtype=torch.int64, device=d)
         S = A.pd_state_dev()
@@ -248,6 +249,7 @@ class Solver:
             S.qr32 = _tp(self.qr32)
             S.dsum = _tp(self.dsum)
             S.fe32 = _tp(self.fe32)
+            S.qv32 = _tp(self.qv32)
         S.ctl = _tp(self.ctl)
         S.cur = 0
         self.S = S
