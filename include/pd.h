@@ -158,8 +158,9 @@ typedef struct pd_family_sizes {
     int32_t reach;      /* largest |component| of a stencil offset                 */
     int32_t n_halo;     /* slots of a tile's LDS halo box (tile + reach on every
                            side, x pitch padded; see pd_family_host.halo_map)      */
-    int32_t n_box;      /* points of that box without padding (tile + reach on
-                           every side); see pd_family_host.halo_pos                */
+    int32_t n_box;      /* points of that box (tile + reach on every side) that
+                           some stencil entry of some tile point reaches; see
+                           pd_family_host.halo_pos                                 */
 } pd_family_sizes;
 
 /* Output arrays of pd_build_family, all [host], allocated by the caller
@@ -193,8 +194,10 @@ typedef struct pd_family_host {
                              64 * d + l, the point at local position l of the
                              neighbour tile in direction d (tile_nbr index), or -1
                              for x-pitch padding; the same for every tile          */
-    int32_t *halo_pos;    /* [n_box] for point b of the unpadded box (x fastest):
-                             (slot << 11) | (64 * d + l), d and l as in halo_map and
+    int32_t *halo_pos;    /* [n_box] for each point of the unpadded box that a
+                             stencil entry of a tile point reaches, in box order
+                             (x fastest): (slot << 11) | (64 * d + l), d and l as
+                             in halo_map and
                              slot the point's place in the single-precision pass-1
                              box, whose x and y pitches are padded so that the 64
                              lanes of a tile read 64 distinct LDS banks            */
@@ -248,6 +251,8 @@ typedef struct pd_problem_dev {
     const uint32_t *ktab;       /* [device] 128*20 words, pd_family_host.ktab      */
     const int16_t *halo_map;    /* [device] n_halo, pd_family_host.halo_map        */
     const int32_t *halo_pos;    /* [device] n_box, pd_family_host.halo_pos         */
+    int32_t n_pos;              /* pd_family_sizes.n_box                           */
+    int32_t pad1;
 } pd_problem_dev;
 
 /* Device control block (step counter, diagnostics).  Size in bytes: */

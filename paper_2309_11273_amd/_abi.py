@@ -52,7 +52,7 @@ class pd_problem_dev(C.Structure):
                 ("n_specimens", i32), ("pad0", i32), ("slice_ptr", P), ("words", P), ("stencil", P),
                 ("vol", P), ("inv_m", P), ("lat4", P), ("spec", P), ("aux", P), ("fext", P),
                 ("ramp_steps", i64), ("stencil_off", P), ("tile_nbr", P), ("tile", i32 * 3), ("reach", i32),
-                ("ktab", P), ("halo_map", P), ("halo_pos", P)]
+                ("ktab", P), ("halo_map", P), ("halo_pos", P), ("n_pos", i32), ("pad1", i32)]
 
 
 class pd_state_dev(C.Structure):

@@ -93,6 +93,7 @@ pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
     a.ktab = p->ktab;
     a.halo_map = p->halo_map;
     a.halo_pos = p->halo_pos;
+    a.n_pos = p->n_pos;
     return a;
 }
 

@@ -369,7 +369,25 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
         int32_t B[4];
         pd_tile_box(T, reach, dim, B);
         sizes->n_halo = B[3] * B[2];
-        sizes->n_box = pd_box_points(T, reach, dim);
+    }
+    // points of the box that some stencil entry of some tile point reaches (the
+    // corners of the box beyond the horizon are never read)
+    std::vector<uint8_t> reached(pd_box_points(T, reach, dim), 0);
+    {
+        const int32_t e0 = T[0] + 2 * reach, e1 = T[1] + 2 * reach;
+        for (int s = 0; s < ns; s++)
+            for (int32_t l = 0; l < T[0] * T[1] * T[2]; l++) {
+                const int32_t q[3] = {l % T[0] + st[s].off[0] + reach, (l / T[0]) % T[1] + st[s].off[1] + reach,
+                                      dim == 3 ? l / (T[0] * T[1]) + st[s].off[2] + reach : 0};
+                reached[q[0] + e0 * (q[1] + e1 * q[2])] = 1;
+            }
+        for (int32_t l = 0; l < T[0] * T[1] * T[2]; l++) {  // the tile's own points
+            const int32_t q[3] = {l % T[0] + reach, (l / T[0]) % T[1] + reach, dim == 3 ? l / (T[0] * T[1]) + reach : 0};
+            reached[q[0] + e0 * (q[1] + e1 * q[2])] = 1;
+        }
+        int32_t nr = 0;
+        for (uint8_t r : reached) nr += r;
+        sizes->n_box = nr;
     }
     if (!out) return PD_OK;
     if (!out->perm || !out->row_of || !out->slice_ptr || !out->words || !out->mask || !out->stencil ||
@@ -403,7 +421,9 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
     {
         const int32_t e0 = T[0] + 2 * reach, e1 = T[1] + 2 * reach;
         const int32_t nb = pd_box_points(T, reach, dim);
+        int32_t np = 0;
         for (int32_t b = 0; b < nb; b++) {
+            if (!reached[b]) continue;
             const int32_t bx = b % e0, by = (b / e0) % e1, bz = b / (e0 * e1);
             const int32_t p[3] = {bx - reach, by - reach, dim == 3 ? bz - reach : 0};
             int32_t d[3];
@@ -411,7 +431,7 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
             const int32_t dir = (d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1);
             const int32_t loc = (p[0] - d[0] * T[0]) + T[0] * ((p[1] - d[1] * T[1]) + T[1] * (p[2] - d[2] * T[2]));
             const int32_t slot = bx + box1[0] * by + box1[3] * bz;
-            out->halo_pos[b] = (slot << 11) | (64 * dir + loc);
+            out->halo_pos[np++] = (slot << 11) | (64 * dir + loc);
         }
     }
     for (int q = 0; q < 20 * 128; q++) out->ktab[q] = 0u;

@@ -43,6 +43,7 @@ struct StepArgs {
     const uint32_t *ktab;
     const int16_t *halo_map;
     const int32_t *halo_pos;
+    int32_t n_pos;
 };
 
 struct InitArgs {

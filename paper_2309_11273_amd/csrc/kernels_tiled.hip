@@ -168,7 +168,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     int *stn = reinterpret_cast<int *>(reg + LY::AREA);
     int32_t B1[4];
     pd_tile_box1(a.tile, a.reach, DIM, B1);
-    const int npts = pd_box_points(a.tile, a.reach, DIM);
+    const int npts = a.n_pos;  // box points the stencil reaches
     pd_ctl *ctl = a.ctl;
     const double Q = ctl->qs[cur];
     const int4 *__restrict__ sh = a.ush[cur];
@@ -182,9 +182,14 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     const int64_t row = tile * 64 + lane;
     // box points of this thread; threads past the last point redo it (the
     // same value into the same slot)
+    // (act[i]: some thread of this wave has a point in round i)
     int hp[MS];
+    bool act[MS];
 #pragma unroll
-    for (int i = 0; i < MS; i++) hp[i] = a.halo_pos[min(gt + i * GR::NT, npts - 1)];
+    for (int i = 0; i < MS; i++) {
+        act[i] = (gt & ~63) + i * GR::NT < npts;
+        hp[i] = act[i] ? a.halo_pos[min(gt + i * GR::NT, npts - 1)] : 0;
+    }
     if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
     const int G4 = L4 >> 2;
     const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             const int h = hp[i] & 2047;
-            const int nt = stn[h >> 6];
+            const int nt = act[i] ? stn[h >> 6] : 0;
             // no tile in that direction: any row of this tile (finite values on a
             // point no intact bond reaches)
             rw[i] = (uint32_t)(nt < 0 ? (int)tile : nt) * 64u + (uint32_t)(h & 63);
@@ -222,11 +227,13 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         float r[MS];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
+            if (!act[i]) continue;
             v[i] = sh[rw[i]];
             r[i] = qr[rw[i]].y;
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
+            if (!act[i]) continue;
             const bool st = v[i].x == PD_SENTINEL_T;
             sent |= st;
             const float Vv = __int_as_float(v[i].w);
@@ -487,14 +494,19 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     int *stn = reinterpret_cast<int *>(reg + LY::BOX + LY::SUMS);
     int32_t B1[4];
     pd_tile_box1(a.tile, a.reach, DIM, B1);
-    const int npts = pd_box_points(a.tile, a.reach, DIM);
+    const int npts = a.n_pos;  // box points the stencil reaches
     pd_ctl *ctl = a.ctl;
     const float2 *__restrict__ qvs = a.qv32;
     const int64_t row = tile * 64 + lane;
     const cu64_t *mks = (const cu64_t *)(a.mask + (base >> 6));
+    // (act[i]: some thread of this wave has a point in round i)
     int hp[MS];
+    bool act[MS];
 #pragma unroll
-    for (int i = 0; i < MS; i++) hp[i] = a.halo_pos[min(gt + i * GR::NT, npts - 1)];
+    for (int i = 0; i < MS; i++) {
+        act[i] = (gt & ~63) + i * GR::NT < npts;
+        hp[i] = act[i] ? a.halo_pos[min(gt + i * GR::NT, npts - 1)] : 0;
+    }
     if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
     const int G4 = L4 >> 2;
     const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
@@ -521,14 +533,16 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             const int h = hp[i] & 2047;
-            const int nt = stn[h >> 6];
+            const int nt = act[i] ? stn[h >> 6] : 0;
             rw[i] = (uint32_t)(nt < 0 ? (int)tile : nt) * 64u + (uint32_t)(h & 63);
         }
         float2 qv[MS];  // (theta/m, V) of the point, one 8-byte record
 #pragma unroll
-        for (int i = 0; i < MS; i++) qv[i] = qvs[rw[i]];
+        for (int i = 0; i < MS; i++)
+            if (act[i]) qv[i] = qvs[rw[i]];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
+            if (!act[i]) continue;
             const int slot = hp[i] >> 11;
             if constexpr (DIM == 3) {
                 hb[slot] = kp * qv[i].x;
@@ -773,13 +787,14 @@ bool tiled_supported(const StepArgs &a) {
     if (a.dim == 3 && a.tile[2] < a.reach) return false;
     if (a.dim == 2 && a.tile[2] != 1) return false;
     if (a.n_stencil > 124) return false;  // groups of four inside the 128-row table
-    const int ns = box_slots(a), np = box_points(a);
-    const int tpw = tiles_per_group(a.dim, np);
+    const int ns = box_slots(a), np = a.n_pos;
+    if (np < 1 || np > box_points(a)) return false;
+    const int tpw = tiles_per_group(a.dim, box_points(a));
     const int cap = a.dim == 3 ? Grp<3, 1>::CAP : (tpw == 4 ? Grp<2, 4>::CAP : Grp<2, 1>::CAP);
     if (ns > cap || np > cap) return false;
     int32_t B1[4];
     pd_tile_box1(a.tile, a.reach, a.dim, B1);
-    if (B1[3] * B1[2] > pd_box1_stride(a.dim, np)) return false;
+    if (B1[3] * B1[2] > pd_box1_stride(a.dim, box_points(a))) return false;
     const int cap1 = a.dim == 3 ? 256 * Lay1<3, 1>::MP : (tpw == 4 ? 64 * Lay1<2, 4>::MP : 256 * Lay1<2, 1>::MP);
     if (np > cap1) return false;
     if (a.n_pad >= (int64_t(1) << 31)) return false;  // 32-bit row numbers in the staging

@@ -223,6 +223,7 @@ class Solver:
         P.halo_map = _tp(self.halo_map)
         self.halo_pos = t(self.fam.halo_pos)
         P.halo_pos = _tp(self.halo_pos)
+        P.n_pos = int(s.n_box)
         for c in range(3):
             P.tile[c] = int(s.tile[c])
         P.reach = int(s.reach)

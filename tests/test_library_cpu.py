@@ -193,7 +193,15 @@ def test_pass1_box_addressing_matches_bond_words(lib, case):
     R, dim = int(s.reach), int(s.dim)
     p0, p1, e2 = _box1_pitches(T, R, dim)
     e0, e1 = T[0] + 2 * R, T[1] + 2 * R
-    assert int(s.n_box) == e0 * e1 * e2
+    # the staged points: exactly the box points a stencil entry of a tile point reaches
+    off3 = f.stencil_off.reshape(-1, 3)
+    reached = set()
+    for l in range(64):
+        lp = (l % T[0], (l // T[0]) % T[1], l // (T[0] * T[1]) if dim == 3 else 0)
+        reached.add((lp[0] + R, lp[1] + R, lp[2] + (R if dim == 3 else 0)))
+        for o in off3:
+            reached.add((lp[0] + o[0] + R, lp[1] + o[1] + R, lp[2] + (o[2] + R if dim == 3 else 0)))
+    assert int(s.n_box) == len(reached) <= e0 * e1 * e2
     if dim == 3 and T[:2] == [4, 4] and e0 <= 12:
         # the lanes of a tile hit 64 distinct banks (4-byte elements)
         lanes = [(l % 4) + p0 * ((l // 4) % 4) + p0 * p1 * (l // 16) for l in range(64)]
