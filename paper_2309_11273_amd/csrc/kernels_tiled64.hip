@@ -367,7 +367,18 @@ static size_t tiled64_lds(int dim, int pass, int tpw) {
 }
 
 bool tiled64_supported(const StepArgs &a) {
-    if (!a.fe64 || !tiled_supported(a)) return false;
+    if (!a.fe64 || !a.tile_nbr || !a.ktab || !a.halo_map) return false;
+    if (a.tile[0] * a.tile[1] * a.tile[2] != 64) return false;
+    for (int c = 0; c < 3; c++)
+        if (a.tile[c] < 1 || (a.tile[c] & (a.tile[c] - 1))) return false;  // powers of two
+    if (a.reach < 1 || a.tile[0] < a.reach || a.tile[1] < a.reach) return false;
+    if (a.dim == 3 && a.tile[2] < a.reach) return false;
+    if (a.dim == 2 && a.tile[2] != 1) return false;
+    if (a.n_stencil > 124) return false;  // groups of four inside the 128-row table
+    if (a.n_pad >= (int64_t(1) << 31)) return false;
+    const int cap = a.dim == 3 ? Grp<3, 1>::CAP
+                               : (tiles_per_group(a.dim, box_slots64(a)) == 4 ? Grp<2, 4>::CAP : Grp<2, 1>::CAP);
+    if (box_slots64(a) > cap) return false;
     const int tpw = tiles_per_group(a.dim, box_slots64(a));
     // the partial sums of TPW = 1 reuse the staged arrays (2 of them in pass 2)
     if (tpw == 1 && 2 * (a.dim == 3 ? Grp<3, 1>::CAP : Grp<2, 1>::CAP) < 3 * PD_TILE_WAVES * 64) return false;

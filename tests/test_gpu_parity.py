@@ -45,8 +45,17 @@ def wide_plate():
     return w
 
 
+def short_horizon_plate():
+    """3D plate with a 2.015 dx horizon (stencil reach 2): a smaller halo box
+    with the same padded pitches and fewer reached points."""
+    w = W.impact3d(nx=36, ny=36, nz=9, dt=1.6e-7, steps=200)
+    w.delta = 2.015 * w.dx
+    return w
+
+
 def small_workloads():
     return {
+        "impact_r2": short_horizon_plate(),
         "plate_wide": wide_plate(),
         "cantilever": W.cantilever3d(),
         "plate_notched": W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37,
@@ -59,7 +68,8 @@ def small_workloads():
     }
 
 
-@pytest.mark.parametrize("name", ["cantilever", "plate_notched", "plane_strain", "impact", "cylinder", "batch",
+@pytest.mark.parametrize("name", ["cantilever", "plate_notched", "plane_strain", "impact", "impact_r2", "cylinder",
+                                  "batch",
                                   "plate_wide"])
 def test_force_matches_reference(ctx, name):
     """One force evaluation (Eqs. 2.3, 2.2) for a random displacement and a
@@ -98,7 +108,7 @@ def test_force_matches_reference(ctx, name):
 
 @pytest.mark.parametrize("kernel", ["gather", "tiled"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("plane_strain", 100),
-                                        ("impact", 200), ("cylinder", 200), ("batch", 200),
+                                        ("impact", 200), ("impact_r2", 200), ("cylinder", 200), ("batch", 200),
                                         ("plate_wide", 200)])
 def test_fp64_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
@@ -137,7 +147,7 @@ def test_plate_full_size_fp64(ctx):
 
 @pytest.mark.parametrize("kernel", ["gather", "tiled"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("impact", 200),
-                                        ("cylinder", 200), ("batch", 200), ("plate_wide", 200)])
+                                        ("impact_r2", 200), ("cylinder", 200), ("batch", 200), ("plate_wide", 200)])
 def test_fp32_recheck_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
     o = Oracle(w)

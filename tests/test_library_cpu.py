@@ -247,6 +247,32 @@ def test_pass1_box_addressing_matches_bond_words(lib, case):
                     assert rows[slot] == (wd >> 7)
 
 
+@pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate"])
+def test_halo_pos_agrees_with_halo_map(lib, case):
+    """halo_pos and halo_map describe the same box points: the slot of the
+    halo box (pitches of halo_map) that a halo_pos entry's direction and
+    local position give is the one halo_map maps back to them."""
+    w = CASES[case]()
+    f = _family(w)
+    s = f.sizes
+    T = list(s.tile)
+    R, dim = int(s.reach), int(s.dim)
+    Bx = T[0] + 2 * R
+    if dim == 3 and T[0] == 4:
+        Bx += (12 - Bx % 8) % 8
+    Pz = Bx * (T[1] + 2 * R)
+    hm = f.halo_map.astype(np.int64)
+    s0, s1 = T[0].bit_length() - 1, T[1].bit_length() - 1
+    for h in f.halo_pos[: int(s.n_box)].astype(np.int64):
+        d, l = (h & 2047) >> 6, h & 63
+        dx, dy, dz = d % 3 - 1, (d // 3) % 3 - 1, d // 9 - 1
+        bx = T[0] * dx + (l & (T[0] - 1)) + R
+        by = T[1] * dy + ((l >> s0) & (T[1] - 1)) + R
+        bz = T[2] * dz + (l >> (s0 + s1)) + R if dim == 3 else 0
+        slot = bx + Bx * by + Pz * bz
+        assert 0 <= slot < len(hm) and hm[slot] == (h & 2047)
+
+
 def test_internal_order_is_tile_major(lib):
     w = W.impact3d(nx=16, ny=16, nz=8, dt=1e-7)
     f = _family(w)
