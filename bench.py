@@ -68,14 +68,15 @@ def algorithmic_bytes(kernel: str, precision: str, nnz: int, n: int, n_loaded: i
       FP64 pass 1: u,V 32; 1/m 8; aux 4; theta/m 8 write; force part 32 write
       FP64 pass 2: theta/m 8; u,V 32; aux 4; force part 32; v 32 + 32;
                    u,V 32 write
-      FP32 pass 1: shadow 16; 1/m 4; aux 4; theta/m 4 write; force part 16 write
-      FP32 pass 2: theta/m 4; V 4; aux 4; D 32; force part 16; u,V 32;
+      FP32 pass 1: shadow 16; 1/m 4; aux 4; theta/m 4 write; (theta/m, V) 8
+                   write; force part 16 write
+      FP32 pass 2: (theta/m, V) 8; aux 4; D 32; force part 16; u,V 32;
                    v 32 + 32; u,V 32 write; next shadow 16 write
     Loaded nodes read their external force (32 B) in pass 2."""
     bond = nnz * (0.125 if tiled else 4.125)
     if tiled:
         node = {("fp64", "pass1"): 84, ("fp64", "pass2"): 172,
-                ("fp32", "pass1"): 44, ("fp32", "pass2"): 204}[(precision, kernel)]
+                ("fp32", "pass1"): 52, ("fp32", "pass2"): 204}[(precision, kernel)]
     else:
         node = {("fp64", "pass1"): 60, ("fp64", "pass2"): 148,
                 ("fp32", "pass1"): 32, ("fp32", "pass2"): 204}[(precision, kernel)]
