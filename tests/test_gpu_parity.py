@@ -56,6 +56,8 @@ def short_horizon_plate():
 def small_workloads():
     return {
         "impact_r2": short_horizon_plate(),
+        # a 64 x 20 plate gets 16 x 4 tiles (unpadded pitches in the tile kernels)
+        "plate_16x4": W.plate2d(nx=64, ny=20, dt=1.347e-7, sigma=2e6, notch_row=9, notch_tip=31.37, steps=200),
         "plate_wide": wide_plate(),
         "cantilever": W.cantilever3d(),
         "plate_notched": W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37,
@@ -69,8 +71,7 @@ def small_workloads():
 
 
 @pytest.mark.parametrize("name", ["cantilever", "plate_notched", "plane_strain", "impact", "impact_r2", "cylinder",
-                                  "batch",
-                                  "plate_wide"])
+                                  "batch", "plate_wide", "plate_16x4"])
 def test_force_matches_reference(ctx, name):
     """One force evaluation (Eqs. 2.3, 2.2) for a random displacement and a
     random set of broken bonds."""
@@ -109,7 +110,7 @@ def test_force_matches_reference(ctx, name):
 @pytest.mark.parametrize("kernel", ["gather", "tiled"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("plane_strain", 100),
                                         ("impact", 200), ("impact_r2", 200), ("cylinder", 200), ("batch", 200),
-                                        ("plate_wide", 200)])
+                                        ("plate_wide", 200), ("plate_16x4", 200)])
 def test_fp64_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
     o = Oracle(w)
@@ -147,7 +148,8 @@ def test_plate_full_size_fp64(ctx):
 
 @pytest.mark.parametrize("kernel", ["gather", "tiled"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("impact", 200),
-                                        ("impact_r2", 200), ("cylinder", 200), ("batch", 200), ("plate_wide", 200)])
+                                        ("impact_r2", 200), ("cylinder", 200), ("batch", 200), ("plate_wide", 200),
+                                        ("plate_16x4", 200)])
 def test_fp32_recheck_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
     o = Oracle(w)

@@ -50,6 +50,7 @@ CASES = {
     "batch3": lambda: W.batch2d(n_plates=3, dt=np.ones(3)),
     "plane_strain": lambda: W.plate2d(nx=30, ny=20, dt=1e-7, mode="plane_strain", notch_row=9,
                                       notch_tip=14.37),
+    "plate_16x4": lambda: W.plate2d(nx=64, ny=20, dt=1e-7, notch_row=9, notch_tip=31.37),
 }
 
 
@@ -113,7 +114,7 @@ def _halo_rows(f, tile):
     return out, (Bx, Pz, Bz)
 
 
-@pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate"])
+@pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate", "plate_16x4"])
 def test_tile_halo_addressing_matches_bond_words(lib, case):
     """The tile kernels find neighbour k of lane l at halo slot
     slot(l) + soff[k]; that slot must hold exactly the row the bond word
@@ -180,7 +181,7 @@ def _box1_pitches(T, R, dim):
     return p0, p1, e2
 
 
-@pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate"])
+@pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate", "plate_16x4"])
 def test_pass1_box_addressing_matches_bond_words(lib, case):
     """The single-precision pass 1 stages the unpadded box point by point
     (halo_pos) into a padded box and finds neighbour k of lane l at
@@ -247,7 +248,7 @@ def test_pass1_box_addressing_matches_bond_words(lib, case):
                     assert rows[slot] == (wd >> 7)
 
 
-@pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate"])
+@pytest.mark.parametrize("case", ["cantilever", "cylinder_small", "batch3", "plate", "plate_16x4"])
 def test_halo_pos_agrees_with_halo_map(lib, case):
     """halo_pos and halo_map describe the same box points: the slot of the
     halo box (pitches of halo_map) that a halo_pos entry's direction and
