@@ -141,6 +141,45 @@ def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
             "pass1_ms": round(ms1, 5), "pass2_ms": round(ms2, 5)}
 
 
+def fac_bytes(kernel: str, dim: int, nnz: int, nb: int, n: int, n_loaded: int) -> int:
+    """Algorithmic bytes of one launch of a factored-scheme kernel: every
+    stored value and column index of the operator it applies read once
+    (double values, int32 columns), the vectors it multiplies read once, its
+    result written once.
+
+      k_fac_extension  E = C_e U: per bond 2 dim values, 2 columns, x_b,
+                       the owner position, 1 status bit, E_b written;
+                       U (32 B per node) read
+      k_fac_dilatation Theta = C_theta E: per directed bond 1 value, 1 column;
+                       E read; Theta written
+      k_fac_force      F = K_theta Theta + K_e E and the update: per directed
+                       bond 2 dim values, 2 columns; K_theta diagonal (8 dim
+                       per node), Theta and E read; per node u, v, aux
+                       (68 B) read, u and v (64 B) written; F_ext rows
+    """
+    if kernel == "k_fac_extension":
+        return nb * (16 * dim + 8 + 8 + 4 + 8) + nnz // 8 + 32 * n
+    if kernel == "k_fac_dilatation":
+        return nnz * 12 + 8 * nb + 8 * n
+    return nnz * (16 * dim + 8) + n * (8 * dim + 8 + 68 + 64) + 8 * nb + 32 * n_loaded
+
+
+def fac_roofline(ms, dim, nnz, nb, n, n_loaded, workload):
+    """Roofline of the factored scheme's dominant kernel (HBM-bound: about
+    two flops per 12 bytes of value and column)."""
+    kname = max(ms, key=ms.get)
+    byt = fac_bytes(kname, dim, nnz, nb, n, n_loaded)
+    gbs = byt / (ms[kname] * 1e-3) / 1e9
+    from paper_2309_11273_amd.profsum import kernel_source_hash
+    traffic = traffic_from_profiles(f"{kname}@{workload}", kernel_source_hash(kname))
+    return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+            "kernel_ms": round(ms[kname], 5), "algorithmic_bytes": byt,
+            "kernels_ms": {k: round(v, 5) for k, v in ms.items()},
+            "kernels_gbs": {k: round(fac_bytes(k, dim, nnz, nb, n, n_loaded) / (v * 1e-3) / 1e9, 1)
+                            for k, v in ms.items()}}
+
+
 def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto"):
     import torch
     s.step(warmup, precision=precision, form=form, graph_chunk=chunk, report=False, kernel=kernel)
@@ -176,7 +215,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="cylinder3d", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--form", default="mf", choices=["mf", "bsr"])
+    ap.add_argument("--form", default="mf", choices=["mf", "bsr", "fac"],
+                    help="mf: matrix-free tile kernels; bsr: block-sparse K; fac: the paper's four "
+                         "factored matrices (double values, so --precision fp64)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tiled"])
     ap.add_argument("--graph-chunk", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=20)
@@ -210,6 +251,10 @@ def main():
     if args.form == "bsr":
         s.build_K(fp32=(args.precision == "fp32"))
         s.assemble_K()
+    if args.form == "fac":
+        args.precision = "fp64"
+        s.build_factored()
+        s.assemble_factored()
 
     el = time_gpu(s, args.steps, args.warmup, args.precision, args.form, args.graph_chunk, args.kernel)
     ms_per_step = 1e3 * el / args.steps
@@ -226,6 +271,11 @@ def main():
     ms_dom = max(ms1, ms2)
     if args.form == "mf":
         roofline = roofline_entry(s, args, dom, ms1, ms2, nnz, int(sz.n), n_loaded)
+    elif args.form == "fac":
+        # pass 1: E product + breaking; extra: K_theta re-assembly check + Theta
+        # product; pass 2: F product + update
+        ms_fac = {"k_fac_extension": ms1, "k_fac_dilatation": prof["ms_extra"] / ps, "k_fac_force": ms2}
+        roofline = fac_roofline(ms_fac, int(sz.dim), nnz, int(s.F.nb), int(sz.n), n_loaded, args.workload)
     else:
         roofline = None
 
@@ -244,7 +294,8 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "nodes": int(sz.n), "unique_bonds": n_bonds, "directed_bonds": nnz,
-                   "form": "matrix-free" if args.form == "mf" else "block-sparse K",
+                   "form": {"mf": "matrix-free", "bsr": "block-sparse K",
+                            "fac": "factored matrices C_e, C_theta, K_theta, K_e"}[args.form],
                    "state_dtype": "f64", "graph_chunk": args.graph_chunk, "setup_s": round(setup_s, 2),
                    "broken_bonds_after_run": int(st["broken_total"]) // 2,
                    "fp64_rechecks": int(st["rechecks"])},

@@ -8,9 +8,11 @@
  * state-based peridynamic models in MATLAB": per step, bond stretch and the
  * critical-stretch breaking rule (Eqs. 1.17, 1.30), the nodal dilatation
  * (Eqs. 1.6, 2.3), the pair forces (Eq. 2.2) and the explicit update
- * (Eqs. 2.11, 2.12).  The internal force is available in two forms: a
- * matrix-free two-pass kernel over a bond list, and the block-sparse global
- * stiffness matrix of Eq. 2.14 applied to the displacement.
+ * (Eqs. 2.11, 2.12).  The internal force is available in three forms: a
+ * matrix-free two-pass kernel over a bond list, the block-sparse global
+ * stiffness matrix of Eq. 2.14 applied to the displacement, and the
+ * paper's factored matrix scheme (four stored sparse operators C_e,
+ * C_theta, K_theta, K_e of Eqs. 2.4-2.10 applied in turn).
  *
  * Conventions
  *  - Every function returns a pd_status; PD_OK = 0, errors are negative.
@@ -51,7 +53,7 @@ typedef enum {
 
 typedef enum { PD_3D = 0, PD_PLANE_STRESS = 1, PD_PLANE_STRAIN = 2 } pd_mode;
 typedef enum { PD_FP64 = 0, PD_FP32_RECHECK = 1 } pd_precision;
-typedef enum { PD_MATRIX_FREE = 0, PD_BSR = 1 } pd_form;
+typedef enum { PD_MATRIX_FREE = 0, PD_BSR = 1, PD_FACTORED = 2 } pd_form;
 
 /* Largest supported sizes. */
 #define PD_MAX_NODES (1LL << 25)  /* node index is stored in 25 bits            */
@@ -401,7 +403,8 @@ typedef struct pd_step_report {
  * 'rep' (may be NULL) is filled after synchronising the stream; with
  * rep == NULL and check_every == 0 the call is fully asynchronous.
  * Errors: PD_ERR_ARG, PD_ERR_UNSUPPORTED (PD_BSR without K, unknown
- * option), PD_ERR_UNSTABLE (non-finite state seen at a check), PD_ERR_HIP. */
+ * option, PD_FACTORED: use pd_fac_step), PD_ERR_UNSTABLE (non-finite state
+ * seen at a check), PD_ERR_HIP. */
 struct pd_bsr_dev;
 pd_status pd_step(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, int64_t nsteps,
                   const pd_step_opts *opts, struct pd_bsr_dev *K, pd_step_report *rep);
@@ -450,6 +453,89 @@ pd_status pd_assemble_K(pd_ctx *ctx, const pd_problem_dev *prob, const uint64_t 
 /* f = Kt u for the current displacement of st (internal order, n_pad*4). */
 pd_status pd_bsr_apply(pd_ctx *ctx, const pd_problem_dev *prob, const pd_bsr_dev *K,
                        const pd_state_dev *st, double *f);
+
+/* ------------------------------------------------------------------------ */
+/* factored matrix scheme (Eqs. 2.4-2.10; solver loop of Appendix B)        */
+/* ------------------------------------------------------------------------ */
+
+/* The four global operators of the matrix-based scheme, stored as sparse
+ * matrices and applied in the paper's order every step:
+ *   E     = C_e U              (N_b x dim N; Eqs. 2.4, 2.7)
+ *   Theta = C_theta E          (N x N_b;     Eqs. 2.6, 2.10)
+ *   F     = K_theta Theta + K_e E  (dim N x N and dim N x N_b; Eqs. 2.5, 2.8, 2.9)
+ * Bonds are numbered 0..N_b-1 in the order of their owning directed entry
+ * (the entry whose stencil id k is below that of its reverse) in the bond
+ * word layout of the family.  Layouts (internal row order):
+ *   C_e      row b: blocks at columns i = bond_ij[2b], j = bond_ij[2b+1]
+ *            (owner row i), values ce[c*nb + b] for c < dim (block i, = -M)
+ *            and ce[(dim+c)*nb + b] (block j, = +M), M the unit vector i->j.
+ *   C_theta, K_e  share one pattern: row i holds one entry per directed bond
+ *            position p of row i (the family's bond words, padding positions
+ *            included with value 0); its column is the bond id bid[p];
+ *            values cth[p] and ke[c*n_words + p].
+ *   K_theta  diagonal block kth_diag[4 i + c] plus one off-diagonal entry per
+ *            directed position p of row i with column words[p] >> 7 (the
+ *            neighbour row) and values kth[c*n_words + p].
+ * Breaking (Eq. 1.30) clears the bond status bits and zeroes E_b; C_theta
+ * and K_e then need no change, while the rows of K_theta of both ends of a
+ * newly broken bond are re-assembled in the same step. */
+typedef struct pd_fac_sizes {
+    int64_t nb;              /* unique bonds N_b                                     */
+    int64_t n_words;         /* directed positions (pd_family_sizes.n_words)          */
+} pd_fac_sizes;
+
+/* Bond numbering and index arrays (host, two-phase like pd_build_family:
+ * with bond_ij == NULL only *out is set).  bond_ij [2 nb]: owner row and
+ * neighbour row of each bond; bond_pos [2 nb]: word position of the owner
+ * entry and of its reverse entry; bid [n_words]: bond id of every position
+ * (0 at padding positions).  Errors: PD_ERR_ARG (NULL arrays, a family whose
+ * bond words are not symmetric), PD_ERR_SIZE (n_words >= 2^31). */
+pd_status pd_fac_pattern(const pd_family_sizes *sizes, const pd_family_host *fam, pd_fac_sizes *out,
+                         int32_t *bond_ij, int32_t *bond_pos, int32_t *bid);
+
+typedef struct pd_fac_dev {
+    int64_t nb;              /* unique bonds, from pd_fac_pattern                     */
+    int64_t n_words;         /* directed positions, from pd_fac_pattern               */
+    int32_t dim;             /* 2 or 3                                                 */
+    int32_t assembled;       /* set by pd_fac_assemble                                 */
+    const int32_t *bond_ij;  /* [device] 2 nb   (pattern)                              */
+    const int32_t *bond_pos; /* [device] 2 nb   (pattern)                              */
+    const int32_t *bid;      /* [device] n_words (pattern)                             */
+    double *ce;              /* [device] 2 dim nb   C_e values                         */
+    double *xi;              /* [device] nb         bond lengths |xi| (Eq. 1.5)         */
+    double *cth;             /* [device] n_words    C_theta values                     */
+    double *ke;              /* [device] dim n_words K_e values                        */
+    double *kth;             /* [device] dim n_words K_theta off-diagonal values        */
+    double *kth_diag;        /* [device] 4 n_pad    K_theta diagonal blocks             */
+    double *E;               /* [device] max(1, nb) extension vector E                  */
+    double *theta;           /* [device] n_pad      dilatation vector Theta             */
+    uint32_t *dirty;         /* [device] n_pad flags of K_theta rows to re-assemble,
+                                zero-initialised by the caller                         */
+} pd_fac_dev;
+
+/* Assemble the values of the four operators (w = 1) for the bond status
+ * 'mask' (K_theta carries the status; C_e, C_theta and K_e do not, since a
+ * broken bond's E_b is zero).  Device-side, asynchronous; needs prob->aux
+ * (pd_state_init).  Errors: PD_ERR_ARG (NULL arrays, dim mismatch),
+ * PD_ERR_SIZE (nb or n_words inconsistent with the problem). */
+pd_status pd_fac_assemble(pd_ctx *ctx, const pd_problem_dev *prob, const uint64_t *mask, pd_fac_dev *F);
+
+/* One evaluation of the factored products for the current displacement of
+ * st and its bond status (no breaking, no update): E, Theta into F->E and
+ * F->theta, and f = K_theta Theta + K_e E into f [device] (n_pad*4,
+ * f_x f_y f_z 0, internal order).  Errors as pd_fac_assemble, plus
+ * PD_ERR_STATE if F is not assembled. */
+pd_status pd_fac_apply(pd_ctx *ctx, const pd_problem_dev *prob, pd_fac_dev *F, const pd_state_dev *st,
+                       double *f);
+
+/* pd_step with the factored form: per step E = C_e U with the breaking
+ * test on E / |xi| (Eq. 1.30; newly broken bonds get E_b = 0 and their
+ * K_theta rows re-assembled), Theta = C_theta E, F = K_theta Theta + K_e E,
+ * then the update of pd_step.  opts->form must be PD_FACTORED and
+ * opts->precision PD_FP64 (the values are stored in double); the other
+ * options, the report and the errors are those of pd_step. */
+pd_status pd_fac_step(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, int64_t nsteps,
+                      const pd_step_opts *opts, pd_fac_dev *F, pd_step_report *rep);
 
 /* ------------------------------------------------------------------------ */
 /* outputs                                                                  */

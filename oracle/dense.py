@@ -110,3 +110,54 @@ def free_dofs(w):
             if not (int(w.bc[p]) >> c) & 1:
                 idx.append(3 * p + c)
     return np.array(idx, dtype=np.int64)
+
+
+def factored_run(w, nsteps, u, v, s0, dt, rho_bond=None, step0=0, rebuild_ktheta=True):
+    """The paper's matrix-based solver loop (Appendix B) on the four global
+    matrices, advancing (u, v) in place (n x 3 arrays) by nsteps steps.
+
+    Reading of the failure block, which the listing elides: every intact
+    bond whose stretch E_b / x_b (Eq. 1.17, E from C_e U) reaches s0 breaks
+    for good (Eq. 1.30) before the dilatation of the same step; a broken
+    bond's E_b is zeroed, which removes it from C_theta E and K_e E, and
+    K_theta, which does not act through E, is rebuilt for the new bond
+    status.  rebuild_ktheta=False keeps K_theta of the initial status (the
+    reading in which breaking only masks E; the tests use it to show that it
+    is not the loop form).  Returns the bond status (order of
+    bonds_bruteforce)."""
+    import scipy.sparse as sparse
+
+    intact = matrices(w)
+    x = intact["x"]
+    nb = len(x)
+    rho = np.ones(nb) if rho_bond is None else np.asarray(rho_bond, dtype=np.float64).copy()
+    CE = sparse.csr_matrix(intact["CE"])
+    CTH = sparse.csr_matrix(intact["CTH"])
+    KE = sparse.csr_matrix(intact["KE"])
+    KTH = sparse.csr_matrix(matrices(w, rho_bond=rho)["KTH"])
+    M = mass_vector(w)
+    fixed = np.zeros(3 * w.n, dtype=bool)
+    for p in range(w.n):
+        for c in range(3):
+            fixed[3 * p + c] = bool((int(w.bc[p]) >> c) & 1)
+    fext = np.asarray(w.fext, dtype=np.float64).reshape(-1)
+    s0b = np.array([s0[w.specimen[i]] for i in intact["bi"]])
+    U = u.reshape(-1)
+    VEL = v.reshape(-1)
+    for it in range(nsteps):
+        n = step0 + it
+        r = 1.0 if w.ramp_steps <= 0 else min(1.0, n / w.ramp_steps)
+        E = CE @ U
+        newly = (rho == 1) & (E / x >= s0b)
+        if newly.any():
+            rho[newly] = 0
+            if rebuild_ktheta:
+                KTH = sparse.csr_matrix(matrices(w, rho_bond=rho)["KTH"])
+        E = E * rho
+        Theta = CTH @ E
+        PDF = KTH @ Theta + KE @ E
+        ACC = (PDF + fext * r) / M
+        ACC[fixed] = 0.0
+        VEL += dt * ACC
+        U += dt * VEL
+    return rho.astype(np.uint8)

@@ -16,7 +16,7 @@ STATUS = {0: "PD_OK", -1: "PD_ERR_ARG", -2: "PD_ERR_SIZE", -3: "PD_ERR_HIP", -4:
           -5: "PD_ERR_UNSUPPORTED", -6: "PD_ERR_STATE"}
 PD_3D, PD_PLANE_STRESS, PD_PLANE_STRAIN = 0, 1, 2
 PD_FP64, PD_FP32_RECHECK = 0, 1
-PD_MATRIX_FREE, PD_BSR = 0, 1
+PD_MATRIX_FREE, PD_BSR, PD_FACTORED = 0, 1, 2
 PD_CTL_BYTES = 256
 
 
@@ -89,6 +89,16 @@ class pd_bsr_dev(C.Structure):
                 ("pad0", i32)]
 
 
+class pd_fac_sizes(C.Structure):
+    _fields_ = [("nb", i64), ("n_words", i64)]
+
+
+class pd_fac_dev(C.Structure):
+    _fields_ = [("nb", i64), ("n_words", i64), ("dim", i32), ("assembled", i32),
+                ("bond_ij", P), ("bond_pos", P), ("bid", P), ("ce", P), ("xi", P), ("cth", P),
+                ("ke", P), ("kth", P), ("kth_diag", P), ("E", P), ("theta", P), ("dirty", P)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "pd_version": (C.c_char_p, []),
@@ -115,6 +125,12 @@ SIGNATURES = {
     "pd_assemble_K": (i32, [P, C.POINTER(pd_problem_dev), P, C.POINTER(pd_bsr_dev)]),
     "pd_bsr_apply": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_bsr_dev),
                            C.POINTER(pd_state_dev), P]),
+    "pd_fac_pattern": (i32, [C.POINTER(pd_family_sizes), C.POINTER(pd_family_host),
+                             C.POINTER(pd_fac_sizes), P, P, P]),
+    "pd_fac_assemble": (i32, [P, C.POINTER(pd_problem_dev), P, C.POINTER(pd_fac_dev)]),
+    "pd_fac_apply": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_fac_dev), C.POINTER(pd_state_dev), P]),
+    "pd_fac_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i64,
+                          C.POINTER(pd_step_opts), C.POINTER(pd_fac_dev), C.POINTER(pd_step_report)]),
     "pd_damage": (i32, [P, C.POINTER(pd_problem_dev), P, P]),
     "pd_energy": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), P,
                         C.POINTER(dbl), C.POINTER(dbl)]),

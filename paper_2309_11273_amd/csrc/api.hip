@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 
+#include "factored.h"
 #include "kernels.h"
 #include "pd.h"
 #include "pd_internal.h"
@@ -325,14 +326,23 @@ pd_status pd_force(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int32_t
 }
 
 static pd_status check_bsr(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *K);
+static pd_status check_fac(pd_ctx *c, const pd_problem_dev *p, const pd_fac_dev *F);
 
 // one explicit step on 'stream' starting from displacement buffer 'cur'
 static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, int cur, hipStream_t s,
-                               const pd_problem_dev *p, const pd_bsr_dev *K, hipEvent_t *ev = nullptr) {
+                               const pd_problem_dev *p, const pd_bsr_dev *K, const pd_fac_dev *F,
+                               hipEvent_t *ev = nullptr) {
     hipError_t e;
     const int block = o.block > 0 ? o.block : 256;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    if (o.form == PD_BSR) {
+    if (o.form == PD_FACTORED) {
+        if ((e = pdk::launch_fac_extension(a, p, F, cur, true, s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+        if ((e = pdk::launch_fac_kth_dirty(a, p, F, cur, s)) != hipSuccess) return e;
+        if ((e = pdk::launch_fac_dilatation(a, p, F, s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+        if ((e = pdk::launch_fac_force(a, p, F, cur, true, s)) != hipSuccess) return e;
+    } else if (o.form == PD_BSR) {
         if ((e = pdk::launch_break_mark(a, p, K, cur, s)) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
         if ((e = pdk::launch_bsr_prep_assemble(a, p, K, false, cur, s)) != hipSuccess) return e;
@@ -355,15 +365,18 @@ static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, in
     return hipSuccess;
 }
 
-pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps, const pd_step_opts *opts,
-                  pd_bsr_dev *K, pd_step_report *rep) {
+static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps,
+                           const pd_step_opts *opts, pd_bsr_dev *K, pd_fac_dev *F, pd_step_report *rep) {
     if (!c) return PD_ERR_ARG;
     pd_status s = check_problem(c, p);
     if (s != PD_OK) return s;
     pd_step_opts o{};
     if (opts) o = *opts;
     if (o.precision != PD_FP64 && o.precision != PD_FP32_RECHECK) return fail(c, PD_ERR_ARG, "unknown precision");
-    if (o.form != PD_MATRIX_FREE && o.form != PD_BSR) return fail(c, PD_ERR_ARG, "unknown form");
+    if (o.form != PD_MATRIX_FREE && o.form != PD_BSR && o.form != PD_FACTORED)
+        return fail(c, PD_ERR_ARG, "unknown form");
+    if ((o.form == PD_FACTORED) != (F != nullptr))
+        return fail(c, PD_ERR_UNSUPPORTED, "the factored form runs through pd_fac_step (and only it)");
     if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
         return fail(c, PD_ERR_ARG, "block must be 0, 64, 128 or 256");
     if (o.graph_chunk < 0 || o.check_every < 0) return fail(c, PD_ERR_ARG, "negative option");
@@ -389,6 +402,12 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
             return fail(c, PD_ERR_UNSUPPORTED, "BSR precision must match the K value type");
         if (!K->dirty || !K->bc || !p->lat4) return fail(c, PD_ERR_ARG, "BSR needs dirty, bc and lat4");
     }
+    if (o.form == PD_FACTORED) {
+        if ((s = check_fac(c, p, F)) != PD_OK) return s;
+        if (!F->assembled) return fail(c, PD_ERR_STATE, "the factored operators are not assembled");
+        if (o.precision != PD_FP64)
+            return fail(c, PD_ERR_UNSUPPORTED, "the factored form stores double values (precision PD_FP64)");
+    }
     HIP_TRY(c, hipSetDevice(c->device));
     pdk::StepArgs a = make_args(p, st);
     int cur = st->cur;
@@ -412,7 +431,7 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
                                        (uint64_t)(uintptr_t)st->qr, (uint64_t)o.kernel, (uint64_t)o.form,
                                        (uint64_t)(uintptr_t)st->fe32, (uint64_t)(uintptr_t)st->fe64,
                                        (uint64_t)(uintptr_t)st->qv32,
-                                       (uint64_t)(uintptr_t)K};
+                                       (uint64_t)(uintptr_t)K, (uint64_t)(uintptr_t)F};
             for (uint64_t f : fields) key = mix(key, f);
             if (!c->gexec || c->gkey != key) {
                 if (c->gexec) {
@@ -423,7 +442,7 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
                 HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
                 hipError_t ce = hipSuccess;
                 for (int64_t i = 0; i < chunk && ce == hipSuccess; i++)
-                    ce = enqueue_step(a, o, (cur + (int)i) & 1, c->cap_stream, p, K);
+                    ce = enqueue_step(a, o, (cur + (int)i) & 1, c->cap_stream, p, K, F);
                 hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
                 if (ce != hipSuccess) return fail(c, PD_ERR_HIP, "capture launch: %s", hipGetErrorString(ce));
                 if (ee != hipSuccess) return fail(c, PD_ERR_HIP, "end capture: %s", hipGetErrorString(ee));
@@ -440,7 +459,7 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
             }
         }
         for (int64_t i = 0; i < todo; i++) {
-            hipError_t e = enqueue_step(a, o, cur, c->stream, p, K, o.profile ? c->ev : nullptr);
+            hipError_t e = enqueue_step(a, o, cur, c->stream, p, K, F, o.profile ? c->ev : nullptr);
             if (e != hipSuccess) return fail(c, PD_ERR_HIP, "step launch: %s", hipGetErrorString(e));
             if (o.profile) {
                 float t1 = 0, t2 = 0, t3 = 0;
@@ -480,6 +499,72 @@ pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t 
         rep->umax = (double)um;
         if (rep->nonfinite) return fail(c, PD_ERR_UNSTABLE, "non-finite displacement");
     }
+    return PD_OK;
+}
+
+pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps, const pd_step_opts *opts,
+                  pd_bsr_dev *K, pd_step_report *rep) {
+    return step_impl(c, p, st, nsteps, opts, K, nullptr, rep);
+}
+
+pd_status pd_fac_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps,
+                      const pd_step_opts *opts, pd_fac_dev *F, pd_step_report *rep) {
+    if (!c) return PD_ERR_ARG;
+    if (!F) return fail(c, PD_ERR_ARG, "F is NULL");
+    if (opts && opts->form != PD_FACTORED) return fail(c, PD_ERR_ARG, "pd_fac_step needs opts->form = PD_FACTORED");
+    pd_step_opts o{};
+    if (opts) o = *opts;
+    o.form = PD_FACTORED;
+    return step_impl(c, p, st, nsteps, &o, nullptr, F, rep);
+}
+
+static pd_status check_fac(pd_ctx *c, const pd_problem_dev *p, const pd_fac_dev *F) {
+    if (!F) return fail(c, PD_ERR_ARG, "F is NULL");
+    if (!F->bond_ij || !F->bond_pos || !F->bid || !F->ce || !F->xi || !F->cth || !F->ke || !F->kth ||
+        !F->kth_diag || !F->E || !F->theta || !F->dirty)
+        return fail(c, PD_ERR_ARG, "F has a NULL array");
+    if (F->dim != p->dim) return fail(c, PD_ERR_ARG, "F dim differs from the problem");
+    if (F->nb < 0 || F->n_words <= 0 || F->n_words >= ((int64_t)1 << 31) || p->n_slices <= 0 ||
+        F->n_words % (256 * p->n_slices) != 0 || 2 * F->nb > F->n_words)
+        return fail(c, PD_ERR_SIZE, "F sizes do not fit the problem (nb %lld, n_words %lld)", (long long)F->nb,
+                    (long long)F->n_words);
+    const void *al[] = {F->ce, F->cth, F->ke, F->kth, F->kth_diag, F->bid, F->bond_ij, F->bond_pos};
+    for (const void *q : al)
+        if (reinterpret_cast<uintptr_t>(q) % 32 != 0) return fail(c, PD_ERR_ARG, "F arrays must be 32-byte aligned");
+    if (!p->vol || !p->inv_m) return fail(c, PD_ERR_ARG, "problem vol/inv_m is NULL");
+    return PD_OK;
+}
+
+pd_status pd_fac_assemble(pd_ctx *c, const pd_problem_dev *p, const uint64_t *mask, pd_fac_dev *F) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_fac(c, p, F)) != PD_OK) return s;
+    if (!mask || !p->aux) return fail(c, PD_ERR_ARG, "NULL mask or aux (call pd_state_init first)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pd_state_dev tmp{};
+    tmp.mask = const_cast<uint64_t *>(mask);
+    pdk::StepArgs a = make_args(p, &tmp);
+    HIP_TRY(c, pdk::launch_fac_assemble(a, p, F, c->stream));
+    F->assembled = 1;
+    return PD_OK;
+}
+
+pd_status pd_fac_apply(pd_ctx *c, const pd_problem_dev *p, pd_fac_dev *F, const pd_state_dev *st, double *f) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_fac(c, p, F)) != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!F->assembled) return fail(c, PD_ERR_STATE, "the factored operators are not assembled");
+    if (!f) return fail(c, PD_ERR_ARG, "f is NULL");
+    if (!p->aux) return fail(c, PD_ERR_ARG, "aux is NULL (call pd_state_init first)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pdk::StepArgs a = make_args(p, st);
+    a.f_out = reinterpret_cast<double4 *>(f);
+    HIP_TRY(c, pdk::launch_fac_extension(a, p, F, st->cur, false, c->stream));
+    HIP_TRY(c, pdk::launch_fac_dilatation(a, p, F, c->stream));
+    HIP_TRY(c, pdk::launch_fac_force(a, p, F, st->cur, false, c->stream));
     return PD_OK;
 }
 

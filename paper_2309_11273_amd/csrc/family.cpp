@@ -9,6 +9,7 @@
 // a small set of lattice offsets: the geometry is stored once per offset
 // (the "stencil") and each bond stores the neighbour row and the offset id.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -573,6 +574,75 @@ extern "C" pd_status pd_bsr_pattern(const pd_family_sizes *sz, const pd_family_h
     parallel_for(n_pad, [&](int64_t a, int64_t b) {
         for (int64_t r = a; r < b; r++)
             std::memcpy(col + row_ptr[r], rows[r].data(), sizeof(int32_t) * rows[r].size());
+    });
+    return PD_OK;
+}
+
+// Bond numbering of the factored scheme.  Bond k of a row is stencil entry
+// k, so the reverse of entry k of row i is entry rev[k] of row j; the entry
+// with the smaller stencil id owns the bond.  Owners are numbered in word
+// order, slice by slice, so that consecutive bonds sit on consecutive lanes.
+extern "C" pd_status pd_fac_pattern(const pd_family_sizes *sz, const pd_family_host *fam, pd_fac_sizes *out,
+                                    int32_t *bond_ij, int32_t *bond_pos, int32_t *bid) {
+    if (!sz || !fam || !out || !fam->slice_ptr || !fam->words || !fam->stencil_off) return PD_ERR_ARG;
+    if (sz->n_words >= ((int64_t)1 << 31)) return PD_ERR_SIZE;
+    const int ns = sz->n_stencil;
+    const int64_t n_slices = sz->n_slices;
+    std::vector<int32_t> rev((size_t)ns, -1);
+    for (int a = 0; a < ns; a++)
+        for (int b = 0; b < ns; b++) {
+            const int32_t *oa = fam->stencil_off + 3 * a, *ob = fam->stencil_off + 3 * b;
+            if (oa[0] == -ob[0] && oa[1] == -ob[1] && oa[2] == -ob[2]) rev[a] = b;
+        }
+    for (int a = 0; a < ns; a++)
+        if (rev[a] < 0 || rev[a] == a) return PD_ERR_ARG;
+    auto owner = [&](uint32_t w) { return (w & 127u) != 127u && (int)(w & 127u) < rev[w & 127u]; };
+    std::vector<int64_t> first((size_t)n_slices + 1, 0);
+    parallel_for(n_slices, [&](int64_t a, int64_t b) {
+        for (int64_t sl = a; sl < b; sl++) {
+            int64_t c = 0;
+            for (int64_t p = fam->slice_ptr[sl]; p < fam->slice_ptr[sl + 1]; p++) c += owner(fam->words[p]);
+            first[sl + 1] = c;
+        }
+    });
+    for (int64_t sl = 0; sl < n_slices; sl++) first[sl + 1] += first[sl];
+    out->nb = first[n_slices];
+    out->n_words = sz->n_words;
+    if (!bond_ij) return PD_OK;
+    if (!bond_pos || !bid) return PD_ERR_ARG;
+    auto pos_of = [&](int64_t row, int k) { return pd_widx(fam->slice_ptr[row / 64], k, (int)(row % 64)); };
+    std::atomic<bool> asym{false};
+    parallel_for(n_slices, [&](int64_t a, int64_t b) {
+        for (int64_t sl = a; sl < b; sl++) {
+            int64_t nb = first[sl];
+            const int64_t base = fam->slice_ptr[sl];
+            for (int64_t p = base; p < fam->slice_ptr[sl + 1]; p++) {
+                const uint32_t w = fam->words[p];
+                if (!owner(w)) continue;
+                const int64_t q = p - base;
+                const int64_t row = 64 * sl + ((q & 255) >> 2);
+                const int64_t j = w >> 7;
+                const int64_t pr = pos_of(j, rev[w & 127u]);
+                if (fam->words[pr] != (((uint32_t)row << 7) | (uint32_t)rev[w & 127u])) asym = true;
+                bond_ij[2 * nb] = (int32_t)row;
+                bond_ij[2 * nb + 1] = (int32_t)j;
+                bond_pos[2 * nb] = (int32_t)p;
+                bond_pos[2 * nb + 1] = (int32_t)pr;
+                bid[p] = (int32_t)nb;
+                nb++;
+            }
+        }
+    });
+    if (asym) return PD_ERR_ARG;
+    parallel_for(n_slices, [&](int64_t a, int64_t b) {
+        for (int64_t sl = a; sl < b; sl++) {
+            const int64_t base = fam->slice_ptr[sl];
+            for (int64_t p = base; p < fam->slice_ptr[sl + 1]; p++) {
+                const uint32_t w = fam->words[p];
+                if ((w & 127u) == 127u) bid[p] = 0;
+                else if (!owner(w)) bid[p] = bid[pos_of(w >> 7, rev[w & 127u])];
+            }
+        }
     });
     return PD_OK;
 }

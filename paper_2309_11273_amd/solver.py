@@ -255,6 +255,7 @@ class Solver:
         S.cur = 0
         self.S = S
         self.K = None
+        self.F = None
         self.reset(u0=u0)
 
     # ---- state -----------------------------------------------------------
@@ -277,6 +278,8 @@ class Solver:
             _tp(self.spec_rows), _tp(self.aux), _tp(self.fext), C.byref(self.S), int(start_step)))
         if self.K is not None:
             self.K.assembled = 0
+        if self.F is not None:
+            self.F.assembled = 0
 
     def read(self):
         d = self.dev
@@ -373,14 +376,20 @@ class Solver:
              kernel: str = "auto"):
         o = A.pd_step_opts()
         o.precision = {"fp64": A.PD_FP64, "fp32": A.PD_FP32_RECHECK}[precision]
-        o.form = {"mf": A.PD_MATRIX_FREE, "bsr": A.PD_BSR}[form]
+        o.form = {"mf": A.PD_MATRIX_FREE, "bsr": A.PD_BSR, "fac": A.PD_FACTORED}[form]
         o.graph_chunk, o.block, o.check_every = int(graph_chunk), int(block), int(check_every)
         o.profile = 1 if profile else 0
         o.kernel = {"auto": 0, "gather": 1, "tiled": 2}[kernel]
         rep = A.pd_step_report()
-        Kp = C.byref(self.K) if self.K is not None else None
-        self.ctx.check("pd_step", A.load().pd_step(self.ctx.h, C.byref(self.P), C.byref(self.S), int(nsteps),
-                                                     C.byref(o), Kp, C.byref(rep) if report else None))
+        if form == "fac":
+            Fp = C.byref(self.F) if self.F is not None else None
+            self.ctx.check("pd_fac_step", A.load().pd_fac_step(self.ctx.h, C.byref(self.P), C.byref(self.S),
+                                                               int(nsteps), C.byref(o), Fp,
+                                                               C.byref(rep) if report else None))
+        else:
+            Kp = C.byref(self.K) if self.K is not None else None
+            self.ctx.check("pd_step", A.load().pd_step(self.ctx.h, C.byref(self.P), C.byref(self.S), int(nsteps),
+                                                         C.byref(o), Kp, C.byref(rep) if report else None))
         if not report:
             return None
         return dict(step=rep.step, broken_total=rep.broken_total, rechecks=rep.rechecks,
@@ -444,3 +453,61 @@ class Solver:
                                                                C.byref(self.S), _tp(f)))
         torch.cuda.synchronize(self.dev)
         return self._to_caller(f)
+
+    # ---- factored matrix scheme ------------------------------------------
+    def build_factored(self):
+        """Bond numbering and index arrays (pd_fac_pattern), device buffers of
+        the four operators; call assemble_factored() afterwards."""
+        L = A.load()
+        fs = A.pd_fac_sizes()
+        A.check("pd_fac_pattern", L.pd_fac_pattern(C.byref(self.fam.sizes), C.byref(self.fam._hb), C.byref(fs),
+                                                     None, None, None))
+        nb, nw = int(fs.nb), int(fs.n_words)
+        bond_ij = np.empty(2 * max(1, nb), np.int32)
+        bond_pos = np.empty(2 * max(1, nb), np.int32)
+        bid = np.empty(nw, np.int32)
+        A.check("pd_fac_pattern", L.pd_fac_pattern(C.byref(self.fam.sizes), C.byref(self.fam._hb), C.byref(fs),
+                                                     _np(bond_ij), _np(bond_pos), _np(bid)))
+        d, dim = self.dev, int(self.fam.sizes.dim)
+        f64 = dict(dtype=torch.float64, device=d)
+        self.F_bond_ij = torch.from_numpy(bond_ij).to(d)
+        self.F_bond_pos = torch.from_numpy(bond_pos).to(d)
+        self.F_bid = torch.from_numpy(bid).to(d)
+        self.F_ce = torch.zeros(2 * dim * max(1, nb), **f64)
+        self.F_xi = torch.zeros(max(1, nb), **f64)
+        self.F_cth = torch.zeros(nw, **f64)
+        self.F_ke = torch.zeros(dim * nw, **f64)
+        self.F_kth = torch.zeros(dim * nw, **f64)
+        self.F_kdiag = torch.zeros(4 * self.n_pad, **f64)
+        self.F_E = torch.zeros(max(1, nb), **f64)
+        self.F_theta = torch.zeros(self.n_pad, **f64)
+        self.F_dirty = torch.zeros(self.n_pad, dtype=torch.int32, device=d)
+        F = A.pd_fac_dev()
+        F.nb, F.n_words, F.dim = nb, nw, dim
+        F.bond_ij, F.bond_pos, F.bid = _tp(self.F_bond_ij), _tp(self.F_bond_pos), _tp(self.F_bid)
+        F.ce, F.xi, F.cth, F.ke = _tp(self.F_ce), _tp(self.F_xi), _tp(self.F_cth), _tp(self.F_ke)
+        F.kth, F.kth_diag = _tp(self.F_kth), _tp(self.F_kdiag)
+        F.E, F.theta, F.dirty = _tp(self.F_E), _tp(self.F_theta), _tp(self.F_dirty)
+        self.F = F
+        self.F_sizes = fs
+        return fs
+
+    def assemble_factored(self):
+        self.ctx.check("pd_fac_assemble", A.load().pd_fac_assemble(self.ctx.h, C.byref(self.P), _tp(self.mask),
+                                                                     C.byref(self.F)))
+
+    def fac_apply(self):
+        """(f, theta, E) of the factored products for the current state: f and
+        theta in caller order, E per bond in the library's bond numbering."""
+        f = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=self.dev)
+        self.ctx.check("pd_fac_apply", A.load().pd_fac_apply(self.ctx.h, C.byref(self.P), C.byref(self.F),
+                                                               C.byref(self.S), _tp(f)))
+        torch.cuda.synchronize(self.dev)
+        nb = int(self.F.nb)
+        return self._to_caller(f), self._rows_to_caller(self.F_theta), self.F_E[:nb].cpu().numpy()
+
+    def fac_bonds(self):
+        """Caller node pair (i, j) of every bond in the library's numbering."""
+        nb = int(self.F.nb)
+        ij = self.F_bond_ij[:2 * nb].cpu().numpy().reshape(nb, 2)
+        return self.fam.perm[ij[:, 0]], self.fam.perm[ij[:, 1]]

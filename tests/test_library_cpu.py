@@ -332,6 +332,68 @@ def test_bsr_pattern_is_two_hop_closure(lib):
         assert total == bs.nnzb
 
 
+def _fac_pattern(lib, f):
+    from paper_2309_11273_amd import _abi as A
+    fs = A.pd_fac_sizes()
+    A.check("pd_fac_pattern", lib.pd_fac_pattern(C.byref(f.sizes), C.byref(f._hb), C.byref(fs), None, None, None))
+    nb = int(fs.nb)
+    ij = np.empty(2 * max(1, nb), np.int32)
+    pos = np.empty(2 * max(1, nb), np.int32)
+    bid = np.full(int(fs.n_words), -7, np.int32)
+    v = lambda a: a.ctypes.data_as(C.c_void_p)
+    A.check("pd_fac_pattern", lib.pd_fac_pattern(C.byref(f.sizes), C.byref(f._hb), C.byref(fs), v(ij), v(pos),
+                                                 v(bid)))
+    return fs, ij[:2 * nb].reshape(nb, 2), pos[:2 * nb].reshape(nb, 2), bid
+
+
+@pytest.mark.parametrize("case", ["cantilever", "plate", "batch3", "plate_16x4", "cylinder_small"])
+def test_factored_bond_numbering(lib, case):
+    """Columns of C_e (bond end rows), the owner / reverse word positions and
+    the bond id of every directed position (the column of C_theta and K_e)
+    describe exactly the reference's unique bonds, each once."""
+    w = CASES[case]()
+    f = _family(w)
+    o = Oracle(w)
+    fs, ij, pos, bid = _fac_pattern(lib, f)
+    nb = int(fs.nb)
+    assert nb == o.nb == int(f.sizes.n_bonds)
+    assert int(fs.n_words) == int(f.sizes.n_words)
+    # the unordered caller pairs are the reference's bonds
+    ci, cj = f.perm[ij[:, 0]], f.perm[ij[:, 1]]
+    assert (ci >= 0).all() and (cj >= 0).all()
+    lo, hi = np.minimum(ci, cj).astype(np.int64), np.maximum(ci, cj).astype(np.int64)
+    obi, obj = o.bonds()
+    np.testing.assert_array_equal(np.sort(lo * w.n + hi), obi.astype(np.int64) * w.n + obj)
+    # owner and reverse positions hold the two directed words of the bond
+    words = f.words
+    assert (np.diff(pos[:, 0]) > 0).all()  # numbered in word order
+    wo, wr = words[pos[:, 0]], words[pos[:, 1]]
+    np.testing.assert_array_equal(wo >> 7, ij[:, 1].astype(np.uint32))
+    np.testing.assert_array_equal(wr >> 7, ij[:, 0].astype(np.uint32))
+    off = f.stencil_off.reshape(-1, 3)
+    np.testing.assert_array_equal(off[wo & 127], -off[wr & 127])
+    assert ((wo & 127) < (wr & 127)).all()
+    # the row of a position follows the interleaved layout
+    rows, ks, _, _, _ = f.bond_table()
+    slice_of = rows // 64
+    widx = f.slice_ptr[slice_of] + (ks // 4) * 256 + (rows % 64) * 4 + ks % 4
+    row_at = np.full(f.sizes.n_words, -1, np.int64)
+    row_at[widx] = rows
+    np.testing.assert_array_equal(row_at[pos[:, 0]], ij[:, 0])
+    np.testing.assert_array_equal(row_at[pos[:, 1]], ij[:, 1])
+    # every directed position names its bond; padding positions name bond 0
+    b = bid[widx]
+    assert (b >= 0).all() and (b < nb).all()
+    j_at = (words[widx] >> 7).astype(np.int64)
+    ok = ((ij[b, 0] == rows) & (ij[b, 1] == j_at)) | ((ij[b, 1] == rows) & (ij[b, 0] == j_at))
+    assert ok.all()
+    pad = np.ones(f.sizes.n_words, bool)
+    pad[widx] = False
+    assert (bid[pad] == 0).all()
+    # each bond is named by exactly two positions
+    np.testing.assert_array_equal(np.bincount(b, minlength=nb), np.full(nb, 2))
+
+
 def test_argument_errors(lib):
     from paper_2309_11273_amd import _abi as A
     s0 = C.c_double()

@@ -288,6 +288,28 @@ def test_matrix_form_equals_loop_form(case):
     np.testing.assert_allclose(A * 0 + theta_mat, th, rtol=0, atol=1e-13 * np.abs(th).max())
 
 
+def test_factored_solver_loop_equals_loop_form_with_breaking():
+    """The matrix-based solver loop (E = C_e U, Theta = C_theta E,
+    F = K_theta Theta + K_e E, then the update) on a notched plate that
+    breaks several hundred bonds follows the loop form's trajectory and
+    breaks the same bonds, when a broken bond's E_b is zeroed and K_theta is
+    rebuilt.  Zeroing E_b alone leaves the bond's dilatation force in
+    K_theta Theta and gives another trajectory."""
+    w = W.plate2d(nx=20, ny=12, dt=1.347e-7, sigma=12e6, notch_row=5, notch_tip=9.37, steps=300)
+    o = Oracle(w)
+    u, v = o.initial_state()
+    u1, v1 = u.copy(), v.copy()
+    u2, v2 = u.copy(), v.copy()
+    rho0 = o.rho()
+    rho1 = dense.factored_run(w, 300, u1, v1, o.s0, float(o.dt[0]), rho_bond=rho0)
+    rho2 = dense.factored_run(w, 300, u2, v2, o.s0, float(o.dt[0]), rho_bond=rho0, rebuild_ktheta=False)
+    o.run(300, u, v)
+    assert int(rho0.sum() - o.rho().sum()) > 300
+    np.testing.assert_array_equal(rho1, o.rho())
+    assert np.linalg.norm(u1 - u) <= 1e-12 * np.linalg.norm(u)
+    assert np.linalg.norm(u2 - u) > 1e-4 * np.linalg.norm(u)
+
+
 @pytest.mark.parametrize("shape,mode,nullity", [((5, 4, 3), "3d", 6), ((7, 6), "plane_stress", 3)])
 def test_stiffness_symmetric_psd_with_rigid_null_space(shape, mode, nullity):
     """-(K^v + K^d) is symmetric positive semi-definite; for a free body its
