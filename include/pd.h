@@ -487,7 +487,8 @@ typedef struct pd_fac_sizes {
 /* Bond numbering and index arrays (host, two-phase like pd_build_family:
  * with bond_ij == NULL only *out is set).  bond_ij [2 nb]: owner row and
  * neighbour row of each bond; bond_pos [2 nb]: word position of the owner
- * entry and of its reverse entry; bid [n_words]: bond id of every position
+ * entry of bond b at b, of its reverse entry at nb + b (the step reads the
+ * first half only); bid [n_words]: bond id of every position
  * (0 at padding positions).  Errors: PD_ERR_ARG (NULL arrays, a family whose
  * bond words are not symmetric), PD_ERR_SIZE (n_words >= 2^31). */
 pd_status pd_fac_pattern(const pd_family_sizes *sizes, const pd_family_host *fam, pd_fac_sizes *out,

@@ -15,6 +15,11 @@
 // Every directed entry i -> j of row i therefore carries the row-i values
 // with M = M_ij, which is how the row kernels below assemble them.
 //
+// The dilatation product maps workgroups to slices so that each XCD works
+// through a contiguous range of tiles: its own L2 then serves the E gathers
+// of neighbouring rows (measured faster; the other products stream their
+// operator and are not helped by it).
+//
 // Layout for the GPU: the bond words of the family already place the
 // directed entries of 64 rows (one tile) in a slice, interleaved in groups of
 // four per lane.  C_theta, K_e and K_theta use those positions as their
@@ -32,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include "factored.h"
+#include "tile_common.h"
 
 namespace pdk {
 
@@ -88,7 +94,7 @@ template <int DIM>
 __global__ __launch_bounds__(256) void k_fac_bonds(StepArgs a, FacArgs f) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= f.nb) return;
-    const uint32_t t = a.words[f.bond_pos[2 * b]] & 127u;
+    const uint32_t t = a.words[f.bond_pos[b]] & 127u;
     const double *st = a.stencil + 4 * t;
     for (int c = 0; c < DIM; c++) {
         f.ce[c * f.nb + b] = -st[c];
@@ -158,7 +164,7 @@ __global__ __launch_bounds__(256) void k_fac_extension(StepArgs a, FacArgs f, in
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= f.nb) return;
     const int2 ij = reinterpret_cast<const int2 *>(f.bond_ij)[b];
-    const int2 pp = reinterpret_cast<const int2 *>(f.bond_pos)[b];
+    const int32_t pown = f.bond_pos[b];
     const double4 *__restrict__ uv = a.uv[cur];
     const double4 ui = uv[ij.x], uj = uv[ij.y];
     const double *ce = f.ce + b;
@@ -169,14 +175,14 @@ __global__ __launch_bounds__(256) void k_fac_extension(StepArgs a, FacArgs f, in
     e += ce[DIM * nb] * uj.x;
     e += ce[(DIM + 1) * nb] * uj.y;
     if (DIM == 3) e += ce[(DIM + 2) * nb] * uj.z;
-    const int64_t wi = status_word(a, ij.x, pp.x);
+    const int64_t wi = status_word(a, ij.x, pown);
     bool intact = (a.mask[wi] >> (ij.x & 63)) & 1ull;
     if (BREAK && intact) {
         const pd_spec sp = a.spec[a.aux[ij.x] >> 8];
         if (e / f.xi[b] >= sp.s0) {
             intact = false;
             atomicAnd(reinterpret_cast<unsigned long long *>(a.mask + wi), ~(1ull << (ij.x & 63)));
-            const int64_t wj = status_word(a, ij.y, pp.y);
+            const int64_t wj = status_word(a, ij.y, f.bond_pos[nb + b]);
             atomicAnd(reinterpret_cast<unsigned long long *>(a.mask + wj), ~(1ull << (ij.y & 63)));
             f.dirty[ij.x] = 1u;
             f.dirty[ij.y] = 1u;
@@ -187,17 +193,19 @@ __global__ __launch_bounds__(256) void k_fac_extension(StepArgs a, FacArgs f, in
     f.E[b] = intact ? e : 0.0;
 }
 
-// Theta = C_theta E, one lane per row
+// Theta = C_theta E.  One workgroup of four waves per slice: wave q takes
+// the groups q, q + 4, ... of all 64 rows (lane = row), and the partial sums
+// are added in wave order through LDS.
 __global__ __launch_bounds__(256) void k_fac_dilatation(StepArgs a, FacArgs f) {
-    const int lane = threadIdx.x & 63;
-    const int64_t slice = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (slice >= a.n_slices) return;
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t slice = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t row = slice * 64 + lane;
     const int64_t base = a.slice_ptr[slice];
     const int64_t G = (a.slice_ptr[slice + 1] - base) >> 8;
     const double *__restrict__ E = f.E;
     double th = 0.0;
-    for (int64_t g = 0; g < G; g++) {
+    for (int64_t g = q; g < G; g += 4) {
         const int64_t p0 = base + (g << 8) + 4 * lane;
         const int4 b4 = *reinterpret_cast<const int4 *>(f.bid + p0);
         const double2 c01 = *reinterpret_cast<const double2 *>(f.cth + p0);
@@ -207,26 +215,30 @@ __global__ __launch_bounds__(256) void k_fac_dilatation(StepArgs a, FacArgs f) {
         th += c23.x * E[b4.z];
         th += c23.y * E[b4.w];
     }
+    part[q][lane] = th;
+    __syncthreads();
+    if (q != 0) return;
+    th = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
     f.theta[row] = th;
     if (a.theta_out) a.theta_out[row] = th;
 }
 
-// F = K_theta Theta + K_e E, one lane per row; UPDATE: the explicit update
-// (Eqs. 2.11, 2.12) instead of writing F.
+// F = K_theta Theta + K_e E, one workgroup of four waves per slice as in the
+// dilatation product; UPDATE: wave 0 applies the explicit update (Eqs. 2.11,
+// 2.12) instead of writing F.
 template <int DIM, bool UPDATE>
 __global__ __launch_bounds__(256) void k_fac_force(StepArgs a, FacArgs f, int cur) {
-    const int lane = threadIdx.x & 63;
-    const int64_t slice = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (slice >= a.n_slices) return;
+    __shared__ double part[4][2 * DIM][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t slice = blockIdx.x;
     const int64_t row = slice * 64 + lane;
     const int64_t base = a.slice_ptr[slice];
     const int64_t G = (a.slice_ptr[slice + 1] - base) >> 8;
     const double *__restrict__ E = f.E;
     const double *__restrict__ th = f.theta;
-    const double thi = th[row];
-    double fk[3], fe[3] = {0.0, 0.0, 0.0};
-    for (int c = 0; c < 3; c++) fk[c] = f.kdiag[4 * row + c] * thi;
-    for (int64_t g = 0; g < G; g++) {
+    double fk[DIM], fe[DIM];
+    for (int c = 0; c < DIM; c++) fk[c] = fe[c] = 0.0;
+    for (int64_t g = q; g < G; g += 4) {
         const int64_t p0 = base + (g << 8) + 4 * lane;
         const uint4 w4 = *reinterpret_cast<const uint4 *>(a.words + p0);
         const int4 b4 = *reinterpret_cast<const int4 *>(f.bid + p0);
@@ -247,7 +259,22 @@ __global__ __launch_bounds__(256) void k_fac_force(StepArgs a, FacArgs f, int cu
             fe[c] += e23.y * e[3];
         }
     }
-    const double fx = fk[0] + fe[0], fy = fk[1] + fe[1], fz = DIM == 3 ? fk[2] + fe[2] : 0.0;
+    for (int c = 0; c < DIM; c++) {
+        part[q][c][lane] = fk[c];
+        part[q][DIM + c][lane] = fe[c];
+    }
+    __syncthreads();
+    if (q != 0) return;
+    const double thi = th[row];
+    double fv[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < DIM; c++) {
+        const double sk = f.kdiag[4 * row + c] * thi +
+                          (((part[0][c][lane] + part[1][c][lane]) + part[2][c][lane]) + part[3][c][lane]);
+        const double se = ((part[0][DIM + c][lane] + part[1][DIM + c][lane]) + part[2][DIM + c][lane]) +
+                          part[3][DIM + c][lane];
+        fv[c] = sk + se;
+    }
+    const double fx = fv[0], fy = fv[1], fz = fv[2];
     if (!UPDATE) {
         a.f_out[row] = make_double4(fx, fy, fz, 0.0);
         return;
@@ -320,15 +347,14 @@ hipError_t launch_fac_kth_dirty(const StepArgs &a, const pd_problem_dev *p, cons
 
 hipError_t launch_fac_dilatation(const StepArgs &a, const pd_problem_dev *p, const pd_fac_dev *F, hipStream_t s) {
     const FacArgs f = fac_args(p, F);
-    const dim3 g((unsigned)((a.n_slices + 3) / 4));
-    hipLaunchKernelGGL(k_fac_dilatation, g, dim3(256), 0, s, a, f);
+    hipLaunchKernelGGL(k_fac_dilatation, dim3((unsigned)a.n_slices), dim3(256), 0, s, a, f);
     return hipGetLastError();
 }
 
 hipError_t launch_fac_force(const StepArgs &a, const pd_problem_dev *p, const pd_fac_dev *F, int cur, bool update,
                             hipStream_t s) {
     const FacArgs f = fac_args(p, F);
-    const dim3 g((unsigned)((a.n_slices + 3) / 4));
+    const dim3 g((unsigned)a.n_slices);
 #define PD_FRC(D, U) hipLaunchKernelGGL((k_fac_force<D, U>), g, dim3(256), 0, s, a, f, cur)
     if (a.dim == 3) { if (update) PD_FRC(3, true); else PD_FRC(3, false); }
     else { if (update) PD_FRC(2, true); else PD_FRC(2, false); }

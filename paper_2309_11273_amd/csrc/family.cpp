@@ -626,8 +626,8 @@ extern "C" pd_status pd_fac_pattern(const pd_family_sizes *sz, const pd_family_h
                 if (fam->words[pr] != (((uint32_t)row << 7) | (uint32_t)rev[w & 127u])) asym = true;
                 bond_ij[2 * nb] = (int32_t)row;
                 bond_ij[2 * nb + 1] = (int32_t)j;
-                bond_pos[2 * nb] = (int32_t)p;
-                bond_pos[2 * nb + 1] = (int32_t)pr;
+                bond_pos[nb] = (int32_t)p;
+                bond_pos[out->nb + nb] = (int32_t)pr;
                 bid[p] = (int32_t)nb;
                 nb++;
             }

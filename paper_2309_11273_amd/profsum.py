@@ -34,8 +34,10 @@ KERNEL_SOURCES = {
     "k_tdsum": ["kernels_tiled.hip", "tile_common.h"],
     "k_pass1_f32": ["kernels_f32.hip"], "k_pass2_f32": ["kernels_f32.hip"],
     "k_pass1_f64": ["kernels.hip"], "k_pass2_f64": ["kernels.hip"],
-    "k_fac_extension": ["factored.hip", "factored.h"], "k_fac_dilatation": ["factored.hip", "factored.h"],
-    "k_fac_force": ["factored.hip", "factored.h"], "k_fac_rows": ["factored.hip", "factored.h"],
+    "k_fac_extension": ["factored.hip", "factored.h", "tile_common.h"],
+    "k_fac_dilatation": ["factored.hip", "factored.h", "tile_common.h"],
+    "k_fac_force": ["factored.hip", "factored.h", "tile_common.h"],
+    "k_fac_rows": ["factored.hip", "factored.h", "tile_common.h"],
 }
 
 # the known-size reference kernel bench.py --copy-mb launches (torch.mul out=)

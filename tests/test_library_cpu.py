@@ -343,7 +343,7 @@ def _fac_pattern(lib, f):
     v = lambda a: a.ctypes.data_as(C.c_void_p)
     A.check("pd_fac_pattern", lib.pd_fac_pattern(C.byref(f.sizes), C.byref(f._hb), C.byref(fs), v(ij), v(pos),
                                                  v(bid)))
-    return fs, ij[:2 * nb].reshape(nb, 2), pos[:2 * nb].reshape(nb, 2), bid
+    return fs, ij[:2 * nb].reshape(nb, 2), pos[:2 * nb].reshape(2, nb).T, bid
 
 
 @pytest.mark.parametrize("case", ["cantilever", "plate", "batch3", "plate_16x4", "cylinder_small"])
