@@ -190,6 +190,16 @@ def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto"):
     return time.perf_counter() - t0
 
 
+def time_adr(s, steps, warmup, chunk, kernel="auto"):
+    import torch
+    s.adr_step(warmup, graph_chunk=chunk, report=False, kernel=kernel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.adr_step(steps, graph_chunk=chunk, report=False, kernel=kernel)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(w, budget_s: float):
     from oracle import Oracle
     from oracle.oracle import num_threads
@@ -219,6 +229,9 @@ def main():
                     help="mf: matrix-free tile kernels; bsr: block-sparse K; fac: the paper's four "
                          "factored matrices (double values, so --precision fp64)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tiled"])
+    ap.add_argument("--adr", action="store_true",
+                    help="time iterations of the adaptive dynamic relaxation (FP64 matrix-free force, "
+                         "fictitious time step 1) instead of explicit steps")
     ap.add_argument("--graph-chunk", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -242,6 +255,13 @@ def main():
     from paper_2309_11273_amd.solver import Solver
 
     w, desc = make_workload(args.workload)
+    if args.adr:
+        # quasi-static loading: each relaxation iteration (fictitious time
+        # step 1) moves the prescribed components by what one explicit step
+        # of the dynamic run moves them
+        dts = np.asarray(w.dt, dtype=np.float64).reshape(-1)
+        w.v0 = w.v0 * dts[np.asarray(w.specimen)][:, None] if dts.size > 1 else w.v0 * float(dts[0])
+        desc += "; prescribed displacement increment per iteration = one explicit step's"
     t_setup = time.perf_counter()
     s = Solver(w, device=0)
     setup_s = time.perf_counter() - t_setup
@@ -255,15 +275,26 @@ def main():
         args.precision = "fp64"
         s.build_factored()
         s.assemble_factored()
+    if args.adr:
+        if args.form != "mf":
+            sys.exit("bench.py: --adr runs with the matrix-free force (--form mf)")
+        args.precision = "fp64"
+        s.adr_setup(1.0)
 
-    el = time_gpu(s, args.steps, args.warmup, args.precision, args.form, args.graph_chunk, args.kernel)
+    if args.adr:
+        el = time_adr(s, args.steps, args.warmup, args.graph_chunk, args.kernel)
+    else:
+        el = time_gpu(s, args.steps, args.warmup, args.precision, args.form, args.graph_chunk, args.kernel)
     ms_per_step = 1e3 * el / args.steps
     value = n_bonds * args.steps / el
 
     # kernel durations with HIP events on the launch stream
     s.profile_read(reset=True)
-    s.step(args.profile_steps, precision=args.precision, form=args.form, profile=True, report=False,
-           kernel=args.kernel)
+    if args.adr:
+        s.adr_step(args.profile_steps, profile=True, report=False, kernel=args.kernel)
+    else:
+        s.step(args.profile_steps, precision=args.precision, form=args.form, profile=True, report=False,
+               kernel=args.kernel)
     prof = s.profile_read(reset=True)
     ps = max(1, prof["steps"])
     ms1, ms2 = prof["ms_pass1"] / ps, prof["ms_pass2"] / ps
@@ -271,6 +302,9 @@ def main():
     ms_dom = max(ms1, ms2)
     if args.form == "mf":
         roofline = roofline_entry(s, args, dom, ms1, ms2, nnz, int(sz.n), n_loaded)
+        if args.adr:
+            # pass 2 runs without its update here; the relaxation's own kernels
+            roofline["relaxation_kernels_ms"] = round(prof["ms_extra"] / ps, 5)
     elif args.form == "fac":
         # pass 1: E product + breaking; extra: K_theta re-assembly check + Theta
         # product; pass 2: F product + update
@@ -279,7 +313,9 @@ def main():
     else:
         roofline = None
 
-    st = s.step(0, precision=args.precision, form=args.form)
+    st = s.adr_step(0) if args.adr else s.step(0, precision=args.precision, form=args.form)
+    if args.adr:
+        st["rechecks"] = 0
     out = {
         "metric": "bond-updates/s per explicit step",
         "value": value,
@@ -295,7 +331,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "nodes": int(sz.n), "unique_bonds": n_bonds, "directed_bonds": nnz,
                    "form": {"mf": "matrix-free", "bsr": "block-sparse K",
-                            "fac": "factored matrices C_e, C_theta, K_theta, K_e"}[args.form],
+                            "fac": "factored matrices C_e, C_theta, K_theta, K_e"}[args.form]
+                           + (", adaptive dynamic relaxation iterations" if args.adr else ""),
                    "state_dtype": "f64", "graph_chunk": args.graph_chunk, "setup_s": round(setup_s, 2),
                    "broken_bonds_after_run": int(st["broken_total"]) // 2,
                    "fp64_rechecks": int(st["rechecks"])},
@@ -323,7 +360,7 @@ def main():
         out["copy_reference_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
         torch.cuda.empty_cache()
-    if not args.no_cpu:
+    if not args.no_cpu and not args.adr:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

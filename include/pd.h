@@ -539,6 +539,54 @@ pd_status pd_fac_step(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st,
                       const pd_step_opts *opts, pd_fac_dev *F, pd_step_report *rep);
 
 /* ------------------------------------------------------------------------ */
+/* adaptive dynamic relaxation (quasi-static loading, Sec. 4 Example 4)      */
+/* ------------------------------------------------------------------------ */
+
+/* The paper solves its quasi-static example by adaptive dynamic relaxation;
+ * the method (Kilic and Madenci's, cited there) is restated here.  Per
+ * iteration n, with fictitious time step dt and fictitious density lambda
+ * (one value per displacement component):
+ *   F^n = f(u^n) + F_ext r(n)   (breaking first, as in pd_step; FP64 force)
+ *   k_r = -(F_r^n - F_r^(n-1)) / (lambda_r dt v_r)     (free r with v_r != 0)
+ *   c   = 2 sqrt(sum u_r k_r u_r / sum u_r^2) if that is positive, else 0
+ *   v   = ((2 - c dt) v + 2 dt F^n / lambda) / (2 + c dt)
+ *         (first iteration after pd_adr_density: v = dt F^n / (2 lambda))
+ *   u  += dt v
+ * over the free components (sums included); prescribed components keep v
+ * and advance u by dt v, as in pd_step. */
+typedef struct pd_adr_dev {
+    double dt;          /* fictitious time step > 0                                    */
+    double *lambda;     /* [device] n_pad*4 fictitious density (pd_adr_density)          */
+    double *f_prev;     /* [device] n_pad*4 F of the previous iteration                  */
+    double *f_int;      /* [device] n_pad*4 scratch: internal force of the iteration      */
+    double *partial;    /* [device] 4 ceil(n_pad/256) per-workgroup sums                 */
+    double *stats;      /* [device] 8: of the last iteration c, sum u k u, sum u^2,
+                           sum F^2 over free components; [4] 1 if it was the first;
+                           [5] iterations since pd_adr_density                           */
+} pd_adr_dev;
+
+/* Fictitious density for the bond status 'mask': lambda_(i,a) = dt^2/4
+ * times an upper bound of the row sum of |K| (K = -df/du of Eq. 2.2), the
+ * condition under which the relaxation is stable:
+ *   2 sum_j c_ij |M_a| |M|_1 + |B_(i,a)| Gam_i + sum_j |b_ij| |M_a| Gam_j
+ * with c_ij = G V_i V_j (1/m_i + 1/m_j), b_ij = (K - G/3) x V_i V_j,
+ * B_i = sum_j b_ij M_ij, Gam_l = 2 sum_k A x V_k / m_l^2 |M_lk|_1 (intact
+ * bonds, w = 1); components with a zero bound get 1.  Also restarts the
+ * relaxation (stats and f_prev cleared).  Device-side, asynchronous.
+ * Errors: PD_ERR_ARG (NULL arrays, dt <= 0). */
+pd_status pd_adr_density(pd_ctx *ctx, const pd_problem_dev *prob, const uint64_t *mask, pd_adr_dev *R);
+
+/* nsteps relaxation iterations on st (u = st->uv[st->cur], v = st->vel).
+ * opts: precision PD_FP64 and form PD_MATRIX_FREE (the force kernels of
+ * pd_force); graph_chunk, block, kernel, check_every and the report as in
+ * pd_step.  The step counter advances once per iteration (it drives the
+ * load ramp r(n)).  With profile = 1, pass1 times the breaking and
+ * dilatation kernel, pass2 the force kernel and extra the relaxation's own
+ * kernels.  Errors: as pd_step, PD_ERR_UNSUPPORTED for other options. */
+pd_status pd_adr_step(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, int64_t nsteps,
+                      const pd_step_opts *opts, pd_adr_dev *R, pd_step_report *rep);
+
+/* ------------------------------------------------------------------------ */
 /* outputs                                                                  */
 /* ------------------------------------------------------------------------ */
 

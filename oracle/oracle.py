@@ -70,6 +70,10 @@ def lib():
         L.orc_run.argtypes = [P, i64, P, P, P, P, i64, P]
         L.orc_lambda_max.restype = dbl
         L.orc_lambda_max.argtypes = [P, P, i32, C.c_uint64]
+        L.orc_adr_density.restype = None
+        L.orc_adr_density.argtypes = [P, dbl, P]
+        L.orc_adr_run.restype = i32
+        L.orc_adr_run.argtypes = [P, i64, P, P, P, P, P, P, P, i64, dbl, P]
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.argtypes = [i32]
         _lib = L
@@ -222,6 +226,25 @@ class Oracle:
         lib().orc_run(self.h, int(nsteps), _p(u), _p(v), _p(self._bc), _p(self._fext),
                       int(self.w.ramp_steps), _p(f) if f is not None else None)
         return f
+
+    def adr_density(self, dt: float = 1.0) -> np.ndarray:
+        """Fictitious density of the relaxation (n x 3) for the current bond
+        status."""
+        lam = np.empty((self.n, 3))
+        lib().orc_adr_density(self.h, float(dt), _p(lam))
+        return lam
+
+    def adr_start(self, dt: float = 1.0):
+        """Relaxation state: (u, v, fprev, iteration counter, lambda)."""
+        u, v = self.initial_state()
+        return dict(u=u, v=v, fprev=np.zeros((self.n, 3)), it=np.zeros(1, np.int64), lam=self.adr_density(dt),
+                    dt=float(dt), stats=np.zeros(4))
+
+    def adr_run(self, nsteps: int, st: dict):
+        """Advance a relaxation state in place by nsteps iterations."""
+        lib().orc_adr_run(self.h, int(nsteps), _p(st["u"]), _p(st["v"]), _p(st["fprev"]), _p(st["it"]),
+                          _p(st["lam"]), _p(self._bc), _p(self._fext), int(self.w.ramp_steps), st["dt"],
+                          _p(st["stats"]))
 
     def lambda_max(self, iters: int = 500, seed: int = 0) -> float:
         return float(lib().orc_lambda_max(self.h, _p(self._bc), int(iters), C.c_uint64(seed)))

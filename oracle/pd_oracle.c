@@ -20,6 +20,9 @@
  *                                  + G e (1/m_i + 1/m_j)] w M_ij V_i V_j     (Eq. 2.2)
  *   update          v += dt a, u += dt v, a = (f + F_ext)/(rho V)   (Eqs. 2.11, 2.12)
  *   damage          phi_i = 1 - sum rho w V_j / sum w V_j           (Eq. 1.31)
+ *   quasi-static    adaptive dynamic relaxation (the solver of Sec. 4
+ *                   Example 4; its formulas are Kilic and Madenci's, cited
+ *                   there, restated below with a Gershgorin density)
  *   constants       A (Eq. 1.8), K (Eq. 1.15), G (Eq. 1.16)
  *   critical stretch s_c (Eqs. 1.26-1.29)
  *
@@ -604,6 +607,127 @@ int orc_run(orc_model *o, int64_t nsteps, double *u, double *v, const uint8_t *b
         o->step = step + 1;
     }
     if (f_out) memcpy(f_out, f, sizeof(double) * 3 * n);
+    free(f);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* adaptive dynamic relaxation (quasi-static loading, Sec. 4 Example 4)      */
+/* ------------------------------------------------------------------------ */
+
+/* Fictitious density of the relaxation, one value per component.  The
+ * relaxation is stable when lambda_ii >= dt^2/4 sum_j |K_ij| (the Gershgorin
+ * condition of Kilic and Madenci's method), K = -df/du.  Writing the force
+ * of Eq. 2.2 as
+ *   f_i = sum_j c_ij M (M . (u_j - u_i)) + sum_j b_ij M (g_i + g_j),
+ *   g_l = theta_l / m_l = sum_k gamma_lk M_lk . (u_k - u_l)        (Eq. 2.3)
+ * with c_ij = G V_i V_j (1/m_i + 1/m_j), b_ij = (K - G/3) x V_i V_j and
+ * gamma_lk = A x V_k / m_l^2 (w = 1, intact bonds), the triangle inequality
+ * bounds the row sums of |K| term by term:
+ *   lambda_(i,a) = dt^2/4 [ 2 sum_j c_ij |M_a| |M|_1 + |B_(i,a)| Gam_i
+ *                           + sum_j |b_ij| |M_a| Gam_j ]
+ * (K - G/3 is negative for small Poisson ratios),
+ *   B_i = sum_j b_ij M_ij,  Gam_l = 2 sum_k gamma_lk |M_lk|_1.
+ * A component whose bound is zero gets lambda = 1.  lam: n*3. */
+void orc_adr_density(const orc_model *o, double dt, double *lam) {
+    int64_t n = o->n;
+    double *B = (double *)calloc(3 * n, sizeof(double));
+    double *Gam = (double *)calloc(n, sizeof(double));
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        const orc_spec *sp = &o->spec[o->sp[i]];
+        for (int64_t k = o->aptr[i]; k < o->aptr[i + 1]; k++) {
+            int64_t b = o->abond[k];
+            if (!o->rho[b]) continue;
+            int64_t j = (o->bi[b] == i) ? o->bj[b] : o->bi[b];
+            double sgn = (o->bi[b] == i) ? 1.0 : -1.0;
+            const double *M = o->M + 3 * b;
+            double x = o->xl[b];
+            double bij = (sp->K - sp->G / 3.0) * x * o->V[i] * o->V[j];
+            double gam = sp->A * x * o->V[j] / (o->m[i] * o->m[i]);
+            double m1 = fabs(M[0]) + fabs(M[1]) + fabs(M[2]);
+            for (int c = 0; c < 3; c++) B[3 * i + c] += bij * sgn * M[c];
+            Gam[i] += 2.0 * gam * m1;
+        }
+    }
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        const orc_spec *sp = &o->spec[o->sp[i]];
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t k = o->aptr[i]; k < o->aptr[i + 1]; k++) {
+            int64_t b = o->abond[k];
+            if (!o->rho[b]) continue;
+            int64_t j = (o->bi[b] == i) ? o->bj[b] : o->bi[b];
+            const double *M = o->M + 3 * b;
+            double x = o->xl[b];
+            double cij = sp->G * o->V[i] * o->V[j] * (1.0 / o->m[i] + 1.0 / o->m[j]);
+            double bij = (sp->K - sp->G / 3.0) * x * o->V[i] * o->V[j];
+            double m1 = fabs(M[0]) + fabs(M[1]) + fabs(M[2]);
+            for (int c = 0; c < 3; c++) acc[c] += 2.0 * cij * fabs(M[c]) * m1 + fabs(bij) * fabs(M[c]) * Gam[j];
+        }
+        for (int c = 0; c < 3; c++) {
+            double l = 0.25 * dt * dt * (acc[c] + fabs(B[3 * i + c]) * Gam[i]);
+            lam[3 * i + c] = l > 0.0 ? l : 1.0;
+        }
+    }
+    free(B);
+    free(Gam);
+}
+
+/* Adaptive dynamic relaxation (Kilic and Madenci's form of the method of
+ * Underwood), nsteps iterations of fictitious time step dt from (u, v):
+ *   F^n = f(u^n) + F_ext r(n)        (breaking first, as in orc_run)
+ *   first iteration (*iter == 0):  v = dt F^n / (2 lambda)
+ *   later:  k_r = -(F_r^n - F_r^(n-1)) / (lambda_r dt v_r)   (v_r != 0)
+ *           c = 2 sqrt(sum u_r k_r u_r / sum u_r^2) when positive, else 0
+ *           v = ((2 - c dt) v + 2 dt F^n / lambda) / (2 + c dt)
+ *   u += dt v
+ * over the free components r; prescribed components keep v and advance u by
+ * dt v (as in orc_run).  fprev (n*3) carries F^(n-1) between calls, *iter
+ * the number of iterations done.  stats (4): c, sum u k u, sum u^2 and
+ * sum F^2 over the free components, of the last iteration. */
+int orc_adr_run(orc_model *o, int64_t nsteps, double *u, double *v, double *fprev, int64_t *iter,
+                const double *lam, const uint8_t *bc, const double *fext, int64_t ramp_steps, double dt,
+                double *stats) {
+    int64_t n = o->n;
+    double *f = (double *)malloc(sizeof(double) * 3 * n);
+    for (int64_t it = 0; it < nsteps; it++) {
+        int64_t step = o->step;
+        double r = 1.0;
+        if (ramp_steps > 0) r = step >= ramp_steps ? 1.0 : (double)step / (double)ramp_steps;
+        break_bonds(o, u, step);
+        dilatation_and_force(o, f);
+        int first = (*iter == 0);
+        double num = 0.0, den = 0.0, res = 0.0;
+        #pragma omp parallel for schedule(static) reduction(+ : num, den, res)
+        for (int64_t q = 0; q < 3 * n; q++) {
+            f[q] += fext[q] * r;
+            if (bc[q / 3] & (1u << (q % 3))) continue;
+            res += f[q] * f[q];
+            if (!first && v[q] != 0.0) {
+                double k = -(f[q] / lam[q] - fprev[q] / lam[q]) / (dt * v[q]);
+                num += u[q] * k * u[q];
+            }
+            den += u[q] * u[q];
+        }
+        double c = 0.0;
+        if (!first && den > 0.0 && num > 0.0) c = 2.0 * sqrt(num / den);
+        #pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < 3 * n; q++) {
+            if (!(bc[q / 3] & (1u << (q % 3)))) {
+                if (first) v[q] = dt * f[q] / (2.0 * lam[q]);
+                else v[q] = ((2.0 - c * dt) * v[q] + 2.0 * dt * f[q] / lam[q]) / (2.0 + c * dt);
+            }
+            u[q] = u[q] + dt * v[q];
+            fprev[q] = f[q];
+        }
+        stats[0] = c;
+        stats[1] = num;
+        stats[2] = den;
+        stats[3] = res;
+        *iter += 1;
+        o->step = step + 1;
+    }
     free(f);
     return 0;
 }

@@ -99,6 +99,10 @@ class pd_fac_dev(C.Structure):
                 ("ke", P), ("kth", P), ("kth_diag", P), ("E", P), ("theta", P), ("dirty", P)]
 
 
+class pd_adr_dev(C.Structure):
+    _fields_ = [("dt", dbl), ("lambda_", P), ("f_prev", P), ("f_int", P), ("partial", P), ("stats", P)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "pd_version": (C.c_char_p, []),
@@ -131,6 +135,9 @@ SIGNATURES = {
     "pd_fac_apply": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_fac_dev), C.POINTER(pd_state_dev), P]),
     "pd_fac_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i64,
                           C.POINTER(pd_step_opts), C.POINTER(pd_fac_dev), C.POINTER(pd_step_report)]),
+    "pd_adr_density": (i32, [P, C.POINTER(pd_problem_dev), P, C.POINTER(pd_adr_dev)]),
+    "pd_adr_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i64,
+                          C.POINTER(pd_step_opts), C.POINTER(pd_adr_dev), C.POINTER(pd_step_report)]),
     "pd_damage": (i32, [P, C.POINTER(pd_problem_dev), P, P]),
     "pd_energy": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), P,
                         C.POINTER(dbl), C.POINTER(dbl)]),

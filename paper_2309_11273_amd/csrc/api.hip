@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 
+#include "adr.h"
 #include "factored.h"
 #include "kernels.h"
 #include "pd.h"
@@ -331,11 +332,23 @@ static pd_status check_fac(pd_ctx *c, const pd_problem_dev *p, const pd_fac_dev 
 // one explicit step on 'stream' starting from displacement buffer 'cur'
 static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, int cur, hipStream_t s,
                                const pd_problem_dev *p, const pd_bsr_dev *K, const pd_fac_dev *F,
-                               hipEvent_t *ev = nullptr) {
+                               const pd_adr_dev *R, hipEvent_t *ev = nullptr) {
     hipError_t e;
     const int block = o.block > 0 ? o.block : 256;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    if (o.form == PD_FACTORED) {
+    if (R) {
+        // relaxation: FP64 force without its update, then the relaxation kernels
+        pdk::StepArgs af = a;
+        af.f_out = reinterpret_cast<double4 *>(R->f_int);
+        const bool tiled = o.kernel != 1 && pdk::tiled64_supported(af);
+        e = tiled ? pdk::launch_tpass1_f64(af, cur, true, s) : pdk::launch_pass1_f64(af, cur, true, block, s);
+        if (e != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+        e = tiled ? pdk::launch_tpass2_f64(af, cur, false, s) : pdk::launch_pass2_f64(af, cur, false, block, s);
+        if (e != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+        if ((e = pdk::launch_adr_iteration(a, p, R, cur, s)) != hipSuccess) return e;
+    } else if (o.form == PD_FACTORED) {
         if ((e = pdk::launch_fac_extension(a, p, F, cur, true, s)) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
         if ((e = pdk::launch_fac_kth_dirty(a, p, F, cur, s)) != hipSuccess) return e;
@@ -366,7 +379,8 @@ static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, in
 }
 
 static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps,
-                           const pd_step_opts *opts, pd_bsr_dev *K, pd_fac_dev *F, pd_step_report *rep) {
+                           const pd_step_opts *opts, pd_bsr_dev *K, pd_fac_dev *F, pd_adr_dev *R,
+                           pd_step_report *rep) {
     if (!c) return PD_ERR_ARG;
     pd_status s = check_problem(c, p);
     if (s != PD_OK) return s;
@@ -402,6 +416,13 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
             return fail(c, PD_ERR_UNSUPPORTED, "BSR precision must match the K value type");
         if (!K->dirty || !K->bc || !p->lat4) return fail(c, PD_ERR_ARG, "BSR needs dirty, bc and lat4");
     }
+    if (R) {
+        if (o.form != PD_MATRIX_FREE || o.precision != PD_FP64)
+            return fail(c, PD_ERR_UNSUPPORTED, "the relaxation uses the FP64 matrix-free force (PD_FP64, PD_MATRIX_FREE)");
+        if (!R->lambda || !R->f_prev || !R->f_int || !R->partial || !R->stats)
+            return fail(c, PD_ERR_ARG, "R has a NULL array");
+        if (!(R->dt > 0.0)) return fail(c, PD_ERR_ARG, "relaxation dt must be > 0");
+    }
     if (o.form == PD_FACTORED) {
         if ((s = check_fac(c, p, F)) != PD_OK) return s;
         if (!F->assembled) return fail(c, PD_ERR_STATE, "the factored operators are not assembled");
@@ -431,8 +452,17 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
                                        (uint64_t)(uintptr_t)st->qr, (uint64_t)o.kernel, (uint64_t)o.form,
                                        (uint64_t)(uintptr_t)st->fe32, (uint64_t)(uintptr_t)st->fe64,
                                        (uint64_t)(uintptr_t)st->qv32,
-                                       (uint64_t)(uintptr_t)K, (uint64_t)(uintptr_t)F};
+                                       (uint64_t)(uintptr_t)K, (uint64_t)(uintptr_t)F,
+                                       (uint64_t)(uintptr_t)R};
             for (uint64_t f : fields) key = mix(key, f);
+            if (R) {
+                uint64_t dtb;
+                std::memcpy(&dtb, &R->dt, 8);
+                const uint64_t rf[] = {dtb, (uint64_t)(uintptr_t)R->lambda, (uint64_t)(uintptr_t)R->f_prev,
+                                       (uint64_t)(uintptr_t)R->f_int, (uint64_t)(uintptr_t)R->partial,
+                                       (uint64_t)(uintptr_t)R->stats};
+                for (uint64_t f : rf) key = mix(key, f);
+            }
             if (!c->gexec || c->gkey != key) {
                 if (c->gexec) {
                     (void)hipGraphExecDestroy(c->gexec);
@@ -442,7 +472,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
                 HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
                 hipError_t ce = hipSuccess;
                 for (int64_t i = 0; i < chunk && ce == hipSuccess; i++)
-                    ce = enqueue_step(a, o, (cur + (int)i) & 1, c->cap_stream, p, K, F);
+                    ce = enqueue_step(a, o, (cur + (int)i) & 1, c->cap_stream, p, K, F, R);
                 hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
                 if (ce != hipSuccess) return fail(c, PD_ERR_HIP, "capture launch: %s", hipGetErrorString(ce));
                 if (ee != hipSuccess) return fail(c, PD_ERR_HIP, "end capture: %s", hipGetErrorString(ee));
@@ -459,7 +489,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
             }
         }
         for (int64_t i = 0; i < todo; i++) {
-            hipError_t e = enqueue_step(a, o, cur, c->stream, p, K, F, o.profile ? c->ev : nullptr);
+            hipError_t e = enqueue_step(a, o, cur, c->stream, p, K, F, R, o.profile ? c->ev : nullptr);
             if (e != hipSuccess) return fail(c, PD_ERR_HIP, "step launch: %s", hipGetErrorString(e));
             if (o.profile) {
                 float t1 = 0, t2 = 0, t3 = 0;
@@ -469,8 +499,9 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
                 HIP_TRY(c, hipEventElapsedTime(&t3, c->ev[2], c->ev[3]));
                 c->prof.steps++;
                 c->prof.ms_pass1 += t1;
-                c->prof.ms_extra += t2;
-                c->prof.ms_pass2 += t3;
+                // the relaxation records pass 2 before its own kernels
+                c->prof.ms_extra += R ? t3 : t2;
+                c->prof.ms_pass2 += R ? t2 : t3;
             }
             cur ^= 1;
             done++;
@@ -504,7 +535,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
 
 pd_status pd_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps, const pd_step_opts *opts,
                   pd_bsr_dev *K, pd_step_report *rep) {
-    return step_impl(c, p, st, nsteps, opts, K, nullptr, rep);
+    return step_impl(c, p, st, nsteps, opts, K, nullptr, nullptr, rep);
 }
 
 pd_status pd_fac_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps,
@@ -515,7 +546,30 @@ pd_status pd_fac_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int6
     pd_step_opts o{};
     if (opts) o = *opts;
     o.form = PD_FACTORED;
-    return step_impl(c, p, st, nsteps, &o, nullptr, F, rep);
+    return step_impl(c, p, st, nsteps, &o, nullptr, F, nullptr, rep);
+}
+
+pd_status pd_adr_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps,
+                      const pd_step_opts *opts, pd_adr_dev *R, pd_step_report *rep) {
+    if (!c) return PD_ERR_ARG;
+    if (!R) return fail(c, PD_ERR_ARG, "R is NULL");
+    return step_impl(c, p, st, nsteps, opts, nullptr, nullptr, R, rep);
+}
+
+pd_status pd_adr_density(pd_ctx *c, const pd_problem_dev *p, const uint64_t *mask, pd_adr_dev *R) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if (!R || !R->lambda || !R->f_prev || !R->f_int || !R->partial || !R->stats)
+        return fail(c, PD_ERR_ARG, "R or one of its arrays is NULL");
+    if (!(R->dt > 0.0)) return fail(c, PD_ERR_ARG, "relaxation dt must be > 0");
+    if (!mask || !p->aux || !p->vol || !p->inv_m) return fail(c, PD_ERR_ARG, "NULL mask, aux, vol or inv_m");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pd_state_dev tmp{};
+    tmp.mask = const_cast<uint64_t *>(mask);
+    pdk::StepArgs a = make_args(p, &tmp);
+    HIP_TRY(c, pdk::launch_adr_density(a, p, R, c->stream));
+    return PD_OK;
 }
 
 static pd_status check_fac(pd_ctx *c, const pd_problem_dev *p, const pd_fac_dev *F) {

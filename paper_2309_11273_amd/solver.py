@@ -511,3 +511,47 @@ class Solver:
         nb = int(self.F.nb)
         ij = self.F_bond_ij[:2 * nb].cpu().numpy().reshape(nb, 2)
         return self.fam.perm[ij[:, 0]], self.fam.perm[ij[:, 1]]
+
+    # ---- adaptive dynamic relaxation -------------------------------------
+    def adr_setup(self, dt: float = 1.0):
+        """Buffers of the relaxation and its fictitious density for the
+        current bond status (pd_adr_density); the next adr_step starts the
+        relaxation.  The state (u, v) is whatever reset() left."""
+        d, n4 = self.dev, self.n_pad * 4
+        f64 = dict(dtype=torch.float64, device=d)
+        self.R_lambda = torch.zeros(n4, **f64)
+        self.R_fprev = torch.zeros(n4, **f64)
+        self.R_fint = torch.zeros(n4, **f64)
+        self.R_partial = torch.zeros(4 * ((self.n_pad + 255) // 256), **f64)
+        self.R_stats = torch.zeros(8, **f64)
+        R = A.pd_adr_dev()
+        R.dt = float(dt)
+        R.lambda_, R.f_prev, R.f_int = _tp(self.R_lambda), _tp(self.R_fprev), _tp(self.R_fint)
+        R.partial, R.stats = _tp(self.R_partial), _tp(self.R_stats)
+        self.R = R
+        self.ctx.check("pd_adr_density", A.load().pd_adr_density(self.ctx.h, C.byref(self.P), _tp(self.mask),
+                                                                   C.byref(self.R)))
+
+    def adr_step(self, nsteps: int, graph_chunk: int = 0, kernel: str = "auto", report: bool = True,
+                 profile: bool = False, check_every: int = 0):
+        o = A.pd_step_opts()
+        o.precision, o.form = A.PD_FP64, A.PD_MATRIX_FREE
+        o.graph_chunk, o.check_every = int(graph_chunk), int(check_every)
+        o.profile = 1 if profile else 0
+        o.kernel = {"auto": 0, "gather": 1, "tiled": 2}[kernel]
+        rep = A.pd_step_report()
+        self.ctx.check("pd_adr_step", A.load().pd_adr_step(self.ctx.h, C.byref(self.P), C.byref(self.S),
+                                                             int(nsteps), C.byref(o), C.byref(self.R),
+                                                             C.byref(rep) if report else None))
+        if not report:
+            return None
+        return dict(step=rep.step, broken_total=rep.broken_total, nonfinite=rep.nonfinite)
+
+    def adr_stats(self) -> dict:
+        torch.cuda.synchronize(self.dev)
+        s = self.R_stats.cpu().numpy()
+        return dict(c=s[0], ukU=s[1], uu=s[2], res2=s[3], first=s[4], iterations=int(s[5]))
+
+    def adr_lambda(self) -> np.ndarray:
+        torch.cuda.synchronize(self.dev)
+        return self._to_caller(self.R_lambda)

@@ -310,6 +310,94 @@ def test_factored_solver_loop_equals_loop_form_with_breaking():
     assert np.linalg.norm(u2 - u) > 1e-4 * np.linalg.norm(u)
 
 
+# ---------------------------------------------------------------------------
+# adaptive dynamic relaxation (the quasi-static solver of Example 4)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["cantilever", "plate_notched"])
+def test_adr_density_bounds_the_stiffness_rows(case):
+    """lambda_r >= dt^2/4 sum_c |K_rc| for every component (the stability
+    condition of the relaxation), K = -dF/du from the paper's matrix form,
+    also after bonds break; and the largest eigenvalue of lambda^-1 K stays
+    below 4 / dt^2."""
+    import scipy.linalg as sl
+    if case == "cantilever":
+        w = W.cantilever3d()
+    else:
+        w = W.plate2d(nx=14, ny=10, dt=1e-8, notch_row=4, notch_tip=6.37)
+    o = Oracle(w)
+    rho = o.rho()
+    rho[np.random.default_rng(5).random(o.nb) < 0.2] = 0
+    o.set_rho(rho)
+    dt = 0.7
+    lam = o.adr_density(dt).reshape(-1)
+    L, _ = dense.internal_force_operator(w, rho_bond=rho)
+    K = -L
+    rows = 0.25 * dt * dt * np.abs(K).sum(1)
+    assert np.all(lam >= rows * (1 - 1e-12))
+    keep = rows > 0
+    S = K[np.ix_(keep, keep)] / np.sqrt(np.outer(lam[keep], lam[keep]))
+    assert sl.eigvalsh(S)[-1] * dt * dt < 4.0
+
+
+def test_adr_converges_to_the_static_solution_with_critical_damping():
+    """The relaxation of the cantilever under its tip load reaches the direct
+    solution of K u = F_ext on the free components, and its adaptive damping
+    approaches 2 sqrt(omega_min^2), omega_min^2 the smallest eigenvalue of
+    lambda^-1 K (critical damping of the slowest mode; the median over 500
+    iterations, since the estimate of a single iteration is noisy)."""
+    import scipy.linalg as sl
+    w = W.cantilever3d()
+    o = Oracle(w)
+    st = o.adr_start()
+    L, _ = dense.internal_force_operator(w)
+    K = -L
+    free = dense.free_dofs(w)
+    F = np.asarray(w.fext).reshape(-1)
+    u_static = np.zeros(3 * w.n)
+    u_static[free] = np.linalg.solve(K[np.ix_(free, free)], F[free])
+    o.adr_run(1000, st)
+    cs = []
+    for _ in range(500):
+        o.adr_run(1, st)
+        if st["stats"][0] > 0:
+            cs.append(st["stats"][0])
+    lam = st["lam"].reshape(-1)[free]
+    wmin2 = sl.eigvalsh(K[np.ix_(free, free)] / np.sqrt(np.outer(lam, lam)))[0]
+    assert len(cs) > 250
+    assert np.median(cs) == pytest.approx(2.0 * np.sqrt(wmin2), rel=2e-2)
+    o.adr_run(1500, st)
+    u = st["u"].reshape(-1)
+    assert np.linalg.norm(u - u_static) <= 1e-12 * np.linalg.norm(u_static)
+
+
+def test_adr_iterates_depend_on_summation_order():
+    """The relaxation's iterates are not a well-conditioned function of the
+    data: run with one thread and with seven (only the order of the damping
+    sums changes), the reference agrees with itself to round-off for twenty
+    iterations and then drifts by orders of magnitude.  This is why the GPU
+    parity tests compare early iterates and relaxed states only."""
+    from oracle.oracle import num_threads, set_num_threads
+    w = W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=1e6, notch_row=11, notch_tip=23.37, steps=200)
+    saved = num_threads()
+    runs = {}
+    try:
+        for nt in (1, 7):
+            set_num_threads(nt)
+            o = Oracle(w)
+            st = o.adr_start()
+            o.adr_run(20, st)
+            u20 = st["u"].copy()
+            o.adr_run(130, st)
+            runs[nt] = (u20, st["u"].copy())
+    finally:
+        set_num_threads(saved)
+    d20 = np.linalg.norm(runs[1][0] - runs[7][0]) / np.linalg.norm(runs[1][0])
+    d150 = np.linalg.norm(runs[1][1] - runs[7][1]) / np.linalg.norm(runs[1][1])
+    assert d20 <= 1e-13
+    assert d150 >= 1e3 * max(d20, 1e-16)
+
+
 @pytest.mark.parametrize("shape,mode,nullity", [((5, 4, 3), "3d", 6), ((7, 6), "plane_stress", 3)])
 def test_stiffness_symmetric_psd_with_rigid_null_space(shape, mode, nullity):
     """-(K^v + K^d) is symmetric positive semi-definite; for a free body its
