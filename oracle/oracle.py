@@ -70,6 +70,8 @@ def lib():
         L.orc_run.argtypes = [P, i64, P, P, P, P, i64, P]
         L.orc_lambda_max.restype = dbl
         L.orc_lambda_max.argtypes = [P, P, i32, C.c_uint64]
+        L.orc_set_finite.restype = None
+        L.orc_set_finite.argtypes = [P, i32]
         L.orc_adr_density.restype = None
         L.orc_adr_density.argtypes = [P, dbl, P]
         L.orc_adr_run.restype = i32
@@ -226,6 +228,11 @@ class Oracle:
         lib().orc_run(self.h, int(nsteps), _p(u), _p(v), _p(self._bc), _p(self._fext),
                       int(self.w.ramp_steps), _p(f) if f is not None else None)
         return f
+
+    def set_finite(self, finite: bool):
+        """Select the finite extension and deformed force direction (Eqs.
+        1.10, 1.13) instead of the linearized ones (Eqs. 2.4, 2.7)."""
+        lib().orc_set_finite(self.h, 1 if finite else 0)
 
     def adr_density(self, dt: float = 1.0) -> np.ndarray:
         """Fictitious density of the relaxation (n x 3) for the current bond

@@ -14,6 +14,8 @@
  *   bond geometry   xi = x_j - x_i, x = |xi|, M = xi / x            (Eqs. 1.2-1.5, 1.13 linearized)
  *   weighted volume m_i = sum_j w x^2 V_j, w = 1                    (Eq. 1.9, Sec. 2.3 w=1)
  *   extension       e_ij = M_ij . (u_j - u_i)                       (Eqs. 2.4, 2.7)
+ *                   or, for the finite model, e = |x M + u_j - u_i| - x with
+ *                   force direction (x M + u_j - u_i)/|...|          (Eqs. 1.10, 1.13)
  *   stretch         s = e / x ; bond status rho = 1 iff s < s_c     (Eqs. 1.17, 1.30)
  *   dilatation      theta_i = (A/m_i) sum_j rho w x e V_j           (Eqs. 1.6, 2.3)
  *   pair force      f_i = sum_j rho [(K-G/3) x (theta_i/m_i + theta_j/m_j)
@@ -90,6 +92,8 @@ typedef struct {
     uint8_t *rho;       /* nb bond status (Eq. 1.30) */
     int32_t *brk;       /* nb step at which the bond broke (-1 intact, -2 cut) */
     double *e;          /* nb scratch: extension */
+    int finite;         /* 0: linearized extension (Eqs. 2.4, 2.7); 1: finite (Eqs. 1.10, 1.13) */
+    double *My;         /* nb*3 scratch: deformed direction Y/|Y| (finite model) */
     /* node -> incident bonds, sorted by the other node */
     int64_t *aptr;
     int64_t *abond;
@@ -247,6 +251,7 @@ orc_model *orc_create(int64_t n, int dim, const int32_t *lat, double dx, const d
     o->rho = (uint8_t *)malloc(nb + 1);
     o->brk = (int32_t *)malloc(sizeof(int32_t) * (nb + 1));
     o->e = (double *)calloc(nb + 1, sizeof(double));
+    o->My = (double *)calloc(3 * (nb + 1), sizeof(double));
     #pragma omp parallel for schedule(static)
     for (int64_t b = 0; b < nb; b++) {
         int64_t i = pairs[b].i, j = pairs[b].j;
@@ -295,7 +300,7 @@ orc_model *orc_create(int64_t n, int dim, const int32_t *lat, double dx, const d
 void orc_free(orc_model *o) {
     if (!o) return;
     free(o->X); free(o->lat); free(o->V); free(o->sp);
-    free(o->bi); free(o->bj); free(o->xl); free(o->M); free(o->rho); free(o->brk); free(o->e);
+    free(o->bi); free(o->bj); free(o->xl); free(o->M); free(o->rho); free(o->brk); free(o->e); free(o->My);
     free(o->aptr); free(o->abond); free(o->m); free(o->theta);
     free(o);
 }
@@ -462,15 +467,28 @@ int64_t orc_apply_cuts(orc_model *o, const double *cuts, int ncut) {
 /* force evaluation                                                         */
 /* ------------------------------------------------------------------------ */
 
-/* Extension of bond b (Eqs. 2.4, 2.7): e = M . (u_j - u_i). */
-static double extension(const orc_model *o, int64_t b, const double *u) {
+/* Extension of bond b.  Linearized (Eqs. 2.4, 2.7): e = M . (u_j - u_i).
+ * Finite (Eqs. 1.10, 1.13): Y = x M + (u_j - u_i), e = |Y| - x, and the
+ * force direction becomes Y / |Y| (stored in My); |Y|^2 is summed as
+ * (Y1^2 + Y2^2) + Y3^2. */
+static double extension(orc_model *o, int64_t b, const double *u) {
     const double *M = o->M + 3 * b;
     int64_t i = o->bi[b], j = o->bj[b];
     double eta0 = u[3 * j] - u[3 * i];
     double eta1 = u[3 * j + 1] - u[3 * i + 1];
     double eta2 = u[3 * j + 2] - u[3 * i + 2];
-    return (M[0] * eta0 + M[1] * eta1) + M[2] * eta2;
+    if (!o->finite) return (M[0] * eta0 + M[1] * eta1) + M[2] * eta2;
+    double x = o->xl[b];
+    double Y0 = x * M[0] + eta0, Y1 = x * M[1] + eta1, Y2 = x * M[2] + eta2;
+    double y = sqrt((Y0 * Y0 + Y1 * Y1) + Y2 * Y2);
+    double *my = o->My + 3 * b;
+    my[0] = Y0 / y;
+    my[1] = Y1 / y;
+    my[2] = Y2 / y;
+    return y - x;
 }
+
+void orc_set_finite(orc_model *o, int finite) { o->finite = finite ? 1 : 0; }
 
 /* Breaking check (Eqs. 1.17, 1.30) at step 'step'. */
 static void break_bonds(orc_model *o, const double *u, int64_t step) {
@@ -529,7 +547,8 @@ static void dilatation_and_force(orc_model *o, double *f) {
             double t = ((sp->K - sp->G / 3.0) * th_t * x + sp->G * e_t) * o->V[i] * o->V[j];
             /* M<xi_ij> points from i to j */
             double sgn = i_is_first ? 1.0 : -1.0;
-            for (int c = 0; c < 3; c++) fi[c] += t * sgn * o->M[3 * b + c];
+            const double *Md = o->finite ? o->My : o->M;
+            for (int c = 0; c < 3; c++) fi[c] += t * sgn * Md[3 * b + c];
         }
         for (int c = 0; c < 3; c++) f[3 * i + c] = fi[c];
     }

@@ -311,6 +311,83 @@ def test_factored_solver_loop_equals_loop_form_with_breaking():
 
 
 # ---------------------------------------------------------------------------
+# finite extension and deformed direction (Eqs. 1.10, 1.13)
+# ---------------------------------------------------------------------------
+
+def _rotation(axis, ang):
+    a = np.asarray(axis, float)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + np.sin(ang) * K + (1 - np.cos(ang)) * K @ K
+
+
+@pytest.mark.parametrize("shape,mode,axis", [((8, 5, 4), "3d", (1, 2, 3)), ((12, 9), "plane_stress", (0, 0, 1))])
+def test_finite_model_is_objective(shape, mode, axis):
+    """A rigid rotation by 60 degrees plus a translation leaves every bond
+    length unchanged: the finite model gives theta = 0 and f = 0 to
+    round-off, where the linearized model gives a force hundreds of times
+    that of a 1e-3 stretch.  Under a uniform stretch both models agree."""
+    w = small_box(shape, mode=mode)
+    o = Oracle(w)
+    X = w.positions()
+    c = np.array([0.3, -0.2, 0.1 if w.dim == 3 else 0.0])
+    u = X @ (_rotation(axis, np.pi / 3) - np.eye(3)).T + c
+    f_stretch = o.force(1e-3 * X)[0]
+    scale = np.abs(f_stretch).max()
+    f_lin, _ = o.force(u)
+    o.set_finite(True)
+    f, th = o.force(u)
+    assert np.abs(f).max() <= 1e-10 * scale
+    assert np.abs(th).max() <= 1e-12
+    assert np.abs(f_lin).max() >= 1e2 * scale
+    assert np.abs(o.force(1e-3 * X)[0] - f_stretch).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("shape,mode,axis", [((6, 4, 4), "3d", (1, 2, 3)), ((9, 8), "plane_stress", (0, 0, 1))])
+def test_finite_force_is_gradient_of_energy(shape, mode, axis):
+    """With e = |Y| - x the stored energy of Eq. 1.20 has gradient -f with
+    the force along Y/|Y|: central differences along a random direction at
+    a 20 degree rotation plus 1 % strain noise converge to -f.d as h^2."""
+    w = small_box(shape, mode=mode, nu=0.21)
+    o = Oracle(w)
+    o.set_finite(True)
+    rho = o.rho()
+    rng = np.random.default_rng(13)
+    rho[rng.random(o.nb) < 0.15] = 0
+    o.set_rho(rho)
+    X = w.positions()
+    u = X @ (_rotation(axis, 0.35) - np.eye(3)).T + rng.standard_normal((w.n, 3)) * 1e-2 * w.dx
+    d = rng.standard_normal((w.n, 3)) * 1e-2 * w.dx
+    if w.dim == 2:
+        u[:, 2] = 0
+        d[:, 2] = 0
+    f, _ = o.force(u)
+    errs = []
+    for h in (1e-3, 1e-4):
+        dE = (o.strain_energy(u + h * d) - o.strain_energy(u - h * d)) / (2 * h)
+        errs.append(abs(dE / -(f * d).sum() - 1))
+    assert errs[1] <= 1e-8
+    assert errs[1] <= 0.2 * errs[0]
+
+
+def test_finite_model_reduces_to_linearized():
+    """For displacements eps u the two models differ by O(eps) relative."""
+    w = small_box((8, 5, 4))
+    o = Oracle(w)
+    ub = np.random.default_rng(2).standard_normal((w.n, 3)) * w.dx
+    diffs = []
+    for eps in (1e-4, 1e-5, 1e-6):
+        o.set_finite(True)
+        ff = o.force(eps * ub)[0]
+        o.set_finite(False)
+        fl = o.force(eps * ub)[0]
+        diffs.append(np.abs(ff - fl).max() / np.abs(fl).max())
+    assert diffs[2] <= 1e-5
+    assert diffs[0] / diffs[1] == pytest.approx(10.0, rel=0.05)
+    assert diffs[1] / diffs[2] == pytest.approx(10.0, rel=0.05)
+
+
+# ---------------------------------------------------------------------------
 # adaptive dynamic relaxation (the quasi-static solver of Example 4)
 # ---------------------------------------------------------------------------
 
