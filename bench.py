@@ -121,10 +121,17 @@ def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
     kernel source."""
     tiled = args.kernel != "gather" and s.tiled_supported(args.precision)
     kname = f"k_{'t' if tiled else ''}{dom}_{'f32' if args.precision == 'fp32' else 'f64'}"
+    if args.extension == "finite":
+        kname = f"k_fin_{dom}"
     ms_dom = ms1 if dom == "pass1" else ms2
     sec = ms_dom * 1e-3
     byt = algorithmic_bytes(dom, args.precision, nnz, n, n_loaded, tiled)
     fl = algorithmic_flops(dom, nnz, tiled)
+    if args.extension == "finite":
+        # per directed bond: deformed bond 6, |Y| 5 + sqrt, e 1, stretch 1,
+        # dilatation 3 (pass 1: 20 with eta 3); pass 2 adds Y/|Y| 3 and the
+        # bracket and accumulation 13 (31)
+        fl = (20 if dom == "pass1" else 31) * nnz
     peak_fl = VALU_PEAK_TFLOPS[args.precision]
     gbs, tfs = byt / sec / 1e9, fl / sec / 1e12
     alu = fl / (peak_fl * 1e12) > byt / (HBM_PEAK_GBS * 1e9)
@@ -180,22 +187,24 @@ def fac_roofline(ms, dim, nnz, nb, n, n_loaded, workload):
                             for k, v in ms.items()}}
 
 
-def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto"):
+def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto", extension="linear"):
     import torch
-    s.step(warmup, precision=precision, form=form, graph_chunk=chunk, report=False, kernel=kernel)
+    s.step(warmup, precision=precision, form=form, graph_chunk=chunk, report=False, kernel=kernel,
+           extension=extension)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.step(steps, precision=precision, form=form, graph_chunk=chunk, report=False, kernel=kernel)
+    s.step(steps, precision=precision, form=form, graph_chunk=chunk, report=False, kernel=kernel,
+           extension=extension)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 
 
-def time_adr(s, steps, warmup, chunk, kernel="auto"):
+def time_adr(s, steps, warmup, chunk, kernel="auto", extension="linear"):
     import torch
-    s.adr_step(warmup, graph_chunk=chunk, report=False, kernel=kernel)
+    s.adr_step(warmup, graph_chunk=chunk, report=False, kernel=kernel, extension=extension)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.adr_step(steps, graph_chunk=chunk, report=False, kernel=kernel)
+    s.adr_step(steps, graph_chunk=chunk, report=False, kernel=kernel, extension=extension)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 
@@ -229,6 +238,9 @@ def main():
                     help="mf: matrix-free tile kernels; bsr: block-sparse K; fac: the paper's four "
                          "factored matrices (double values, so --precision fp64)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tiled"])
+    ap.add_argument("--extension", default="linear", choices=["linear", "finite"],
+                    help="finite: e = |x M + u_j - u_i| - x with the force along the deformed bond "
+                         "(FP64 gather kernels)")
     ap.add_argument("--adr", action="store_true",
                     help="time iterations of the adaptive dynamic relaxation (FP64 matrix-free force, "
                          "fictitious time step 1) instead of explicit steps")
@@ -275,6 +287,10 @@ def main():
         args.precision = "fp64"
         s.build_factored()
         s.assemble_factored()
+    if args.extension == "finite":
+        if args.form != "mf":
+            sys.exit("bench.py: --extension finite runs with the matrix-free force (--form mf)")
+        args.precision, args.kernel = "fp64", "gather"
     if args.adr:
         if args.form != "mf":
             sys.exit("bench.py: --adr runs with the matrix-free force (--form mf)")
@@ -282,19 +298,20 @@ def main():
         s.adr_setup(1.0)
 
     if args.adr:
-        el = time_adr(s, args.steps, args.warmup, args.graph_chunk, args.kernel)
+        el = time_adr(s, args.steps, args.warmup, args.graph_chunk, args.kernel, args.extension)
     else:
-        el = time_gpu(s, args.steps, args.warmup, args.precision, args.form, args.graph_chunk, args.kernel)
+        el = time_gpu(s, args.steps, args.warmup, args.precision, args.form, args.graph_chunk, args.kernel,
+                      args.extension)
     ms_per_step = 1e3 * el / args.steps
     value = n_bonds * args.steps / el
 
     # kernel durations with HIP events on the launch stream
     s.profile_read(reset=True)
     if args.adr:
-        s.adr_step(args.profile_steps, profile=True, report=False, kernel=args.kernel)
+        s.adr_step(args.profile_steps, profile=True, report=False, kernel=args.kernel, extension=args.extension)
     else:
         s.step(args.profile_steps, precision=args.precision, form=args.form, profile=True, report=False,
-               kernel=args.kernel)
+               kernel=args.kernel, extension=args.extension)
     prof = s.profile_read(reset=True)
     ps = max(1, prof["steps"])
     ms1, ms2 = prof["ms_pass1"] / ps, prof["ms_pass2"] / ps
@@ -332,6 +349,7 @@ def main():
         "config": {"workload": desc, "nodes": int(sz.n), "unique_bonds": n_bonds, "directed_bonds": nnz,
                    "form": {"mf": "matrix-free", "bsr": "block-sparse K",
                             "fac": "factored matrices C_e, C_theta, K_theta, K_e"}[args.form]
+                           + (", finite extension (Eqs. 1.10, 1.13)" if args.extension == "finite" else "")
                            + (", adaptive dynamic relaxation iterations" if args.adr else ""),
                    "state_dtype": "f64", "graph_chunk": args.graph_chunk, "setup_s": round(setup_s, 2),
                    "broken_bonds_after_run": int(st["broken_total"]) // 2,

@@ -322,6 +322,12 @@ pd_status pd_tile_kernels_apply(const pd_problem_dev *prob, const pd_state_dev *
 pd_status pd_force(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, int32_t precision,
                    double *f, double *theta);
 
+/* The same force with the finite extension and the deformed direction of
+ * Eqs. 1.10, 1.13 (e = |Y| - x, Y = x M + u_j - u_i, pair force of Eq. 2.2
+ * along Y/|Y|), in double precision with the gather kernels.  Uses st->qr
+ * as scratch.  Errors as pd_force. */
+pd_status pd_force_finite(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, double *f, double *theta);
+
 /* ------------------------------------------------------------------------ */
 /* explicit stepping                                                        */
 /* ------------------------------------------------------------------------ */
@@ -338,7 +344,10 @@ typedef struct pd_step_opts {
                             family allows them (tile edges >= stencil reach; FP64 also
                             needs st->fe64), else gather kernels; 1 = gather kernels;
                             2 = tile kernels (error if not possible)                   */
-    int32_t pad1;
+    int32_t extension;   /* 0: linearized e = M.(u_j - u_i) along M (Eqs. 2.4, 2.7);
+                            1: finite e = |x M + u_j - u_i| - x with the pair force
+                            along the deformed bond (Eqs. 1.10, 1.13): PD_FP64,
+                            PD_MATRIX_FREE, gather kernels                           */
 } pd_step_opts;
 
 /* Kernel timings gathered by pd_step with opts->profile = 1 (milliseconds,

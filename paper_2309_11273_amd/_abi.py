@@ -62,7 +62,7 @@ class pd_state_dev(C.Structure):
 
 class pd_step_opts(C.Structure):
     _fields_ = [("precision", i32), ("form", i32), ("graph_chunk", i32), ("block", i32),
-                ("check_every", i32), ("profile", i32), ("kernel", i32), ("pad1", i32)]
+                ("check_every", i32), ("profile", i32), ("kernel", i32), ("extension", i32)]
 
 
 class pd_profile_stats(C.Structure):
@@ -135,6 +135,7 @@ SIGNATURES = {
     "pd_fac_apply": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_fac_dev), C.POINTER(pd_state_dev), P]),
     "pd_fac_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i64,
                           C.POINTER(pd_step_opts), C.POINTER(pd_fac_dev), C.POINTER(pd_step_report)]),
+    "pd_force_finite": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), P, P]),
     "pd_adr_density": (i32, [P, C.POINTER(pd_problem_dev), P, C.POINTER(pd_adr_dev)]),
     "pd_adr_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i64,
                           C.POINTER(pd_step_opts), C.POINTER(pd_adr_dev), C.POINTER(pd_step_report)]),

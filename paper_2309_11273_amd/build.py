@@ -19,7 +19,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpd.so")
 
 HIP_SOURCES = ["api.hip", "kernels.hip", "kernels_f32.hip", "kernels_tiled.hip", "kernels_tiled64.hip", "bsr.hip",
-               "factored.hip", "adr.hip"]
+               "factored.hip", "adr.hip", "finite.hip"]
 CXX_SOURCES = ["family.cpp"]
 
 ARCH = "gfx950"

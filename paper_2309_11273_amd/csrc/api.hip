@@ -11,6 +11,7 @@
 
 #include "adr.h"
 #include "factored.h"
+#include "finite.h"
 #include "kernels.h"
 #include "pd.h"
 #include "pd_internal.h"
@@ -340,11 +341,13 @@ static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, in
         // relaxation: FP64 force without its update, then the relaxation kernels
         pdk::StepArgs af = a;
         af.f_out = reinterpret_cast<double4 *>(R->f_int);
-        const bool tiled = o.kernel != 1 && pdk::tiled64_supported(af);
-        e = tiled ? pdk::launch_tpass1_f64(af, cur, true, s) : pdk::launch_pass1_f64(af, cur, true, block, s);
+        const bool tiled = o.kernel != 1 && o.extension == 0 && pdk::tiled64_supported(af);
+        if (o.extension) e = pdk::launch_fin_pass1(af, cur, true, block, s);
+        else e = tiled ? pdk::launch_tpass1_f64(af, cur, true, s) : pdk::launch_pass1_f64(af, cur, true, block, s);
         if (e != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-        e = tiled ? pdk::launch_tpass2_f64(af, cur, false, s) : pdk::launch_pass2_f64(af, cur, false, block, s);
+        if (o.extension) e = pdk::launch_fin_pass2(af, cur, false, block, s);
+        else e = tiled ? pdk::launch_tpass2_f64(af, cur, false, s) : pdk::launch_pass2_f64(af, cur, false, block, s);
         if (e != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
         if ((e = pdk::launch_adr_iteration(a, p, R, cur, s)) != hipSuccess) return e;
@@ -361,6 +364,11 @@ static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, in
         if ((e = pdk::launch_bsr_prep_assemble(a, p, K, false, cur, s)) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
         if ((e = pdk::launch_bsr_spmv(a, p, K, cur, true, s)) != hipSuccess) return e;
+    } else if (o.extension) {
+        if ((e = pdk::launch_fin_pass1(a, cur, true, block, s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+        if ((e = pdk::launch_fin_pass2(a, cur, true, block, s)) != hipSuccess) return e;
     } else {
         // LDS-staged tile kernels unless the gather kernels are asked for
         const bool fp64 = o.precision == PD_FP64;
@@ -396,6 +404,9 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
     if (o.graph_chunk < 0 || o.check_every < 0) return fail(c, PD_ERR_ARG, "negative option");
     if (o.profile != 0 && o.profile != 1) return fail(c, PD_ERR_ARG, "profile must be 0 or 1");
     if (o.kernel < 0 || o.kernel > 2) return fail(c, PD_ERR_ARG, "kernel must be 0, 1 or 2");
+    if (o.extension != 0 && o.extension != 1) return fail(c, PD_ERR_ARG, "extension must be 0 or 1");
+    if (o.extension && (o.precision != PD_FP64 || o.form != PD_MATRIX_FREE || o.kernel == 2))
+        return fail(c, PD_ERR_UNSUPPORTED, "the finite extension runs with PD_FP64, PD_MATRIX_FREE and the gather kernels");
     if (o.kernel == 2 && o.form == PD_MATRIX_FREE) {
         pd_state_dev tmp = *st;
         const pdk::StepArgs ta = make_args(p, &tmp);
@@ -453,7 +464,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
                                        (uint64_t)(uintptr_t)st->fe32, (uint64_t)(uintptr_t)st->fe64,
                                        (uint64_t)(uintptr_t)st->qv32,
                                        (uint64_t)(uintptr_t)K, (uint64_t)(uintptr_t)F,
-                                       (uint64_t)(uintptr_t)R};
+                                       (uint64_t)(uintptr_t)R, (uint64_t)o.extension};
             for (uint64_t f : fields) key = mix(key, f);
             if (R) {
                 uint64_t dtb;
@@ -547,6 +558,23 @@ pd_status pd_fac_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int6
     if (opts) o = *opts;
     o.form = PD_FACTORED;
     return step_impl(c, p, st, nsteps, &o, nullptr, F, nullptr, rep);
+}
+
+pd_status pd_force_finite(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, double *f, double *theta) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!f) return fail(c, PD_ERR_ARG, "f is NULL");
+    if (!p->aux) return fail(c, PD_ERR_ARG, "aux is NULL (call pd_state_init first)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pdk::StepArgs a = make_args(p, st);
+    a.f_out = reinterpret_cast<double4 *>(f);
+    a.theta_out = theta;
+    HIP_TRY(c, pdk::launch_fin_pass1(a, st->cur, false, 256, c->stream));
+    a.theta_out = nullptr;
+    HIP_TRY(c, pdk::launch_fin_pass2(a, st->cur, false, 256, c->stream));
+    return PD_OK;
 }
 
 pd_status pd_adr_step(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int64_t nsteps,

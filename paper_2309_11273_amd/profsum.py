@@ -38,6 +38,7 @@ KERNEL_SOURCES = {
     "k_fac_dilatation": ["factored.hip", "factored.h", "tile_common.h"],
     "k_fac_force": ["factored.hip", "factored.h", "tile_common.h"],
     "k_fac_rows": ["factored.hip", "factored.h", "tile_common.h"],
+    "k_fin_pass1": ["finite.hip", "finite.h"], "k_fin_pass2": ["finite.hip", "finite.h"],
     "k_adr_sums": ["adr.hip", "adr.h"], "k_adr_reduce": ["adr.hip", "adr.h"], "k_adr_update": ["adr.hip", "adr.h"],
 }
 

@@ -327,6 +327,15 @@ class Solver:
         torch.cuda.synchronize(self.dev)
         return self._to_caller(f), self._rows_to_caller(th)
 
+    def force_finite(self):
+        """Force and dilatation with the finite extension (Eqs. 1.10, 1.13)."""
+        f = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=self.dev)
+        th = torch.zeros(self.n_pad, dtype=torch.float64, device=self.dev)
+        self.ctx.check("pd_force_finite", A.load().pd_force_finite(self.ctx.h, C.byref(self.P), C.byref(self.S),
+                                                                     _tp(f), _tp(th)))
+        torch.cuda.synchronize(self.dev)
+        return self._to_caller(f), self._rows_to_caller(th)
+
     def autotune(self, precision: str = "fp32", trial_steps: int = 20, cache: Optional[str] = None) -> dict:
         """Pick the fastest kernel variant / block size (pd_autotune).  With a
         cache path, results are stored in a JSON file keyed by
@@ -373,13 +382,14 @@ class Solver:
 
     def step(self, nsteps: int, precision: str = "fp64", form: str = "mf", graph_chunk: int = 0,
              block: int = 0, check_every: int = 0, report: bool = True, profile: bool = False,
-             kernel: str = "auto"):
+             kernel: str = "auto", extension: str = "linear"):
         o = A.pd_step_opts()
         o.precision = {"fp64": A.PD_FP64, "fp32": A.PD_FP32_RECHECK}[precision]
         o.form = {"mf": A.PD_MATRIX_FREE, "bsr": A.PD_BSR, "fac": A.PD_FACTORED}[form]
         o.graph_chunk, o.block, o.check_every = int(graph_chunk), int(block), int(check_every)
         o.profile = 1 if profile else 0
         o.kernel = {"auto": 0, "gather": 1, "tiled": 2}[kernel]
+        o.extension = {"linear": 0, "finite": 1}[extension]
         rep = A.pd_step_report()
         if form == "fac":
             Fp = C.byref(self.F) if self.F is not None else None
@@ -533,9 +543,10 @@ class Solver:
                                                                    C.byref(self.R)))
 
     def adr_step(self, nsteps: int, graph_chunk: int = 0, kernel: str = "auto", report: bool = True,
-                 profile: bool = False, check_every: int = 0):
+                 profile: bool = False, check_every: int = 0, extension: str = "linear"):
         o = A.pd_step_opts()
         o.precision, o.form = A.PD_FP64, A.PD_MATRIX_FREE
+        o.extension = {"linear": 0, "finite": 1}[extension]
         o.graph_chunk, o.check_every = int(graph_chunk), int(check_every)
         o.profile = 1 if profile else 0
         o.kernel = {"auto": 0, "gather": 1, "tiled": 2}[kernel]

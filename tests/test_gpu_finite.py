@@ -1,0 +1,206 @@
+"""Parity of the finite-deformation force (Eqs. 1.10, 1.13: e = |Y| - x,
+pair force along Y/|Y|) on the GPU, through the C ABI, with the FP64 CPU
+reference in the same mode: one force evaluation at a finite rotation,
+objectivity, FP64 trajectories with breaking (displacement rel-L2 <= 1e-10,
+identical broken-bond sets and damage), graph replay, the relaxation, and
+the full cylinder for a few steps."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import Oracle  # noqa: E402
+from pd_inputs import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_11273_amd.solver import Context
+    return Context(0)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def solver(w, ctx, **kw):
+    from paper_2309_11273_amd.solver import Solver
+    return Solver(w, ctx=ctx, **kw)
+
+
+def finite_oracle(w):
+    o = Oracle(w)
+    o.set_finite(True)
+    return o
+
+
+def rotation(axis, ang):
+    a = np.asarray(axis, float)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + np.sin(ang) * K + (1 - np.cos(ang)) * K @ K
+
+
+def workloads():
+    wide = W.plate2d(nx=48, ny=24, dt=1.2e-7, sigma=5e6, G0=None, notch_row=11, notch_tip=23.37, steps=200)
+    wide.delta = 5.015 * wide.dx
+    r2 = W.impact3d(nx=36, ny=36, nz=9, dt=1.6e-7, steps=200)
+    r2.delta = 2.015 * r2.dx
+    return {
+        "cantilever": W.cantilever3d(),
+        "plate_notched": W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37,
+                                   steps=300),
+        "plane_strain": W.plate2d(nx=30, ny=22, dt=1.2e-7, mode="plane_strain", E=190e9, nu=0.25,
+                                  rho=7800.0, G0=None, steps=100),
+        "plate_16x4": W.plate2d(nx=64, ny=20, dt=1.347e-7, sigma=2e6, notch_row=9, notch_tip=31.37, steps=200),
+        "plate_wide": wide,
+        "impact": W.impact3d(nx=36, ny=36, nz=9, dt=2.6e-7, steps=200),
+        "impact_r2": r2,
+        "cylinder": W.cylinder3d(dx=2.5e-3, dt=2.4e-7, twist_rate=8.0, steps=200),
+        "batch": W.batch2d(n_plates=3, steps=200, dt=np.array([1.0e-7, 1.1e-7, 0.9e-7])),
+    }
+
+
+def break_random(s, o, w, rng, frac):
+    bi, bj, _ = s.bond_status()
+    rho = o.rho()
+    drop = rng.random(o.nb) < frac
+    rho2 = rho.copy()
+    rho2[drop] = 0
+    o.set_rho(rho2)
+    mask = s.mask_host()
+    rows, ks, ci, cj, _ = s.fam.bond_table()
+    key = np.minimum(ci, cj).astype(np.int64) * w.n + np.maximum(ci, cj)
+    idx = np.searchsorted(bi.astype(np.int64) * w.n + bj, key)
+    clear = drop[idx]
+    widx = s.fam.slice_ptr[rows // 64] // 64 + ks
+    for wi, lane in zip(widx[clear], (rows % 64)[clear]):
+        mask[wi] &= ~np.uint64(1 << int(lane))
+    return mask
+
+
+@pytest.mark.parametrize("name", ["cantilever", "plate_notched", "plane_strain", "impact", "impact_r2", "cylinder",
+                                  "batch", "plate_wide", "plate_16x4"])
+def test_force_matches_reference(ctx, name):
+    """A 20 degree rotation plus 1 % strain noise and 10 % broken bonds."""
+    w = workloads()[name]
+    o = finite_oracle(w)
+    rng = np.random.default_rng(17)
+    X = w.positions()
+    axis = (0, 0, 1) if w.dim == 2 else (1, 2, 3)
+    u = X @ (rotation(axis, 0.35) - np.eye(3)).T + rng.standard_normal((w.n, 3)) * 1e-2 * w.dx
+    if w.dim == 2:
+        u[:, 2] = 0
+    s = solver(w, ctx, u0=u)
+    mask = break_random(s, o, w, rng, 0.1)
+    s.reset(u0=u, mask=mask)
+    f, th = s.force_finite()
+    fo, tho = o.force(u)
+    assert np.abs(f - fo).max() <= 1e-12 * np.abs(fo).max()
+    assert np.abs(th - tho).max() <= 1e-12 * np.abs(tho).max()
+
+
+@pytest.mark.parametrize("name", ["cantilever", "plate_notched", "cylinder"])
+def test_rigid_rotation_gives_zero_force(ctx, name):
+    w = workloads()[name]
+    X = w.positions()
+    axis = (0, 0, 1) if w.dim == 2 else (1, 2, 3)
+    u = X @ (rotation(axis, np.pi / 3) - np.eye(3)).T + np.array([0.3, -0.2, 0.1 if w.dim == 3 else 0.0])
+    s = solver(w, ctx, u0=1e-3 * X)
+    f_stretch, _ = s.force_finite()
+    s.reset(u0=u)
+    f, th = s.force_finite()
+    f_lin, _ = s.force()
+    scale = np.abs(f_stretch).max()
+    assert np.abs(f).max() <= 1e-10 * scale
+    assert np.abs(th).max() <= 1e-12
+    assert np.abs(f_lin).max() >= 1e2 * scale
+
+
+@pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("plane_strain", 100),
+                                        ("impact", 200), ("impact_r2", 200), ("cylinder", 200), ("batch", 200),
+                                        ("plate_wide", 200), ("plate_16x4", 200)])
+def test_trajectory(ctx, name, steps):
+    w = workloads()[name]
+    o = finite_oracle(w)
+    s = solver(w, ctx)
+    uo, vo = o.initial_state()
+    done = 0
+    for target in (steps // 4, steps // 2, steps):
+        s.step(target - done, precision="fp64", extension="finite")
+        o.run(target - done, uo, vo)
+        done = target
+        u, v = s.read()
+        assert rel(u, uo) <= FP64_TOL, (name, target, rel(u, uo))
+        assert rel(v, vo) <= FP64_TOL * 10, (name, target, rel(v, vo))
+        _, _, st = s.bond_status()
+        assert np.array_equal(st, o.rho()), (name, target, int((st != o.rho()).sum()))
+    assert s.step_count() == steps
+    np.testing.assert_allclose(s.damage(), o.damage(), rtol=0, atol=1e-15)
+
+
+def test_finite_and_linearized_trajectories_differ(ctx):
+    """The cylinder twist (rotations of the end layers) separates the two
+    models; each follows its own reference."""
+    w = workloads()["cylinder"]
+    a = solver(w, ctx)
+    b = solver(w, ctx)
+    a.step(200, precision="fp64", extension="finite")
+    b.step(200, precision="fp64")
+    assert rel(a.read()[0], b.read()[0]) > 1e-6
+
+
+def test_graph_replay_equals_eager(ctx):
+    w = workloads()["impact"]
+    a = solver(w, ctx)
+    b = solver(w, ctx)
+    a.step(120, precision="fp64", extension="finite")
+    for _ in range(3):
+        b.step(40, precision="fp64", extension="finite", graph_chunk=10)
+    assert np.array_equal(a.read()[0], b.read()[0])
+    assert np.array_equal(a.mask_host(), b.mask_host())
+
+
+def test_options_are_checked(ctx):
+    from paper_2309_11273_amd import _abi as A
+    w = workloads()["cantilever"]
+    s = solver(w, ctx)
+    for kw in (dict(precision="fp32"), dict(precision="fp64", kernel="tiled")):
+        with pytest.raises(A.PDError):
+            s.step(1, extension="finite", **kw)
+
+
+def test_relaxation_with_finite_extension(ctx):
+    """The first twenty relaxation iterates of the cantilever with the
+    finite model follow the reference."""
+    w = W.cantilever3d()
+    o = finite_oracle(w)
+    st = o.adr_start()
+    s = solver(w, ctx)
+    s.adr_setup()
+    for target in (5, 20):
+        done = s.adr_stats()["iterations"]
+        s.adr_step(target - done, extension="finite")
+        o.adr_run(target - done, st)
+        u, _ = s.read()
+        assert rel(u, st["u"]) <= FP64_TOL, (target, rel(u, st["u"]))
+
+
+def test_full_size_cylinder_short_run(ctx):
+    w = W.workload("cylinder3d")
+    s = solver(w, ctx)
+    s.step(4, precision="fp64", extension="finite", graph_chunk=2)
+    u, _ = s.read()
+    o = finite_oracle(w)
+    uo, vo = o.initial_state()
+    o.run(4, uo, vo)
+    assert rel(u, uo) <= FP64_TOL
+    assert np.array_equal(s.bond_status()[2], o.rho())
