@@ -161,3 +161,70 @@ def factored_run(w, nsteps, u, v, s0, dt, rho_bond=None, step0=0, rebuild_ktheta
         VEL += dt * ACC
         U += dt * VEL
     return rho.astype(np.uint8)
+
+
+def sparse_operator(w, o, rho_bond=None):
+    """F_int = (K^v + K^d) U (Eq. 2.14) as a scipy sparse matrix, 3N x 3N,
+    assembled from the same per-bond blocks as matrices() (Eqs. 2.7-2.10)
+    for larger grids: the bonds, bond geometry and weighted volumes come
+    from the loop reference o.  A broken bond contributes to none of the
+    four matrices."""
+    import scipy.sparse as sparse
+
+    bi, bj = o.bonds()
+    x, M = o.bond_geom()
+    m = o.m()
+    n, nb = w.n, len(bi)
+    V = np.asarray(w.vol, dtype=np.float64)
+    rho = np.ones(nb) if rho_bond is None else np.asarray(rho_bond, dtype=np.float64)
+    spec = np.asarray(w.specimen)[bi]
+    A = np.empty(nb)
+    Kc = np.empty(nb)
+    G = np.empty(nb)
+    for k, mat in enumerate(w.materials):
+        c = constants(w.mode_id(), mat.E, mat.nu)
+        sel = spec == k
+        A[sel], Kc[sel], G[sel] = c["A"], c["K"], c["G"]
+    b = np.arange(nb)
+    comp = np.arange(3)
+    # Eq. 2.7
+    rows = np.repeat(b, 6)
+    cols = np.concatenate([3 * bi[:, None] + comp, 3 * bj[:, None] + comp], axis=1).ravel()
+    vals = (np.concatenate([-M, M], axis=1) * rho[:, None]).ravel()
+    CE = sparse.csr_matrix((vals, (rows, cols)), shape=(nb, 3 * n))
+    # Eq. 2.10
+    CTH = sparse.csr_matrix((np.concatenate([A * x * V[bj] / m[bi], A * x * V[bi] / m[bj]]) * np.tile(rho, 2),
+                             (np.concatenate([bi, bj]), np.concatenate([b, b]))), shape=(n, nb))
+    # Eq. 2.8
+    cb = (Kc - G / 3.0) * x * V[bi] * V[bj] * rho
+    r8, c8, v8 = [], [], []
+    for node_row, sgn in ((bi, 1.0), (bj, -1.0)):
+        for node_col, mcol in ((bi, m[bi]), (bj, m[bj])):
+            r8.append(3 * node_row[:, None] + comp)
+            c8.append(np.repeat(node_col[:, None], 3, axis=1))
+            v8.append(sgn * (cb / mcol)[:, None] * M)
+    KTH = sparse.csr_matrix((np.concatenate(v8).ravel(), (np.concatenate(r8).ravel(), np.concatenate(c8).ravel())),
+                            shape=(3 * n, n))
+    # Eq. 2.9
+    g = G * V[bi] * V[bj] * (1.0 / m[bi] + 1.0 / m[bj]) * rho
+    KE = sparse.csr_matrix((np.concatenate([g[:, None] * M, -g[:, None] * M]).ravel(),
+                            (np.concatenate([3 * bi[:, None] + comp, 3 * bj[:, None] + comp]).ravel(),
+                             np.concatenate([np.repeat(b[:, None], 3, axis=1)] * 2).ravel())),
+                           shape=(3 * n, nb))
+    return (KTH @ (CTH @ CE) + KE @ CE).tocsr()
+
+
+def static_solution(w, o, u0=None, rho_bond=None):
+    """Static equilibrium F_int(u) + F_ext = 0 on the free components, the
+    prescribed components held at their values in u0 (zero if None): a
+    direct sparse solve of K_ff du_f = F_ext,f + F_int(u0)_f with K = -F_int'
+    (Eq. 2.14).  Returns u (n x 3)."""
+    import scipy.sparse.linalg as spla
+
+    L = sparse_operator(w, o, rho_bond)
+    u = np.zeros(3 * w.n) if u0 is None else np.asarray(u0, dtype=np.float64).reshape(-1).copy()
+    free = free_dofs(w)
+    b = np.asarray(w.fext, dtype=np.float64).reshape(-1) + L @ u
+    Kff = (-L)[free][:, free].tocsc()
+    u[free] += spla.spsolve(Kff, b[free])
+    return u.reshape(w.n, 3)

@@ -718,7 +718,8 @@ int orc_adr_run(orc_model *o, int64_t nsteps, double *u, double *v, double *fpre
         dilatation_and_force(o, f);
         int first = (*iter == 0);
         double num = 0.0, den = 0.0, res = 0.0;
-        #pragma omp parallel for schedule(static) reduction(+ : num, den, res)
+        /* serial, in component order: the damping is sensitive to rounding,
+         * so the reference sums in one fixed order */
         for (int64_t q = 0; q < 3 * n; q++) {
             f[q] += fext[q] * r;
             if (bc[q / 3] & (1u << (q % 3))) continue;
