@@ -199,6 +199,24 @@ def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto", extension=
     return time.perf_counter() - t0
 
 
+def time_static(s, steps, warmup):
+    """Wall time of 'steps' conjugate-gradient iterations (HIP events on the
+    library's stream), less that of a solve with none (the start phase)."""
+    import torch
+    s.static_solve(tol=1e-300, max_iter=max(1, warmup), check_every=max(1, warmup))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    u0 = s.uv[s.S.cur].clone()
+    ev[0].record()
+    s.static_solve(tol=1e-300, max_iter=1, check_every=1)
+    ev[1].record()
+    s.uv[s.S.cur].copy_(u0)
+    ev[2].record()
+    s.static_solve(tol=1e-300, max_iter=steps + 1, check_every=steps + 1)
+    ev[3].record()
+    torch.cuda.synchronize()
+    return (ev[2].elapsed_time(ev[3]) - ev[0].elapsed_time(ev[1])) * 1e-3
+
+
 def time_adr(s, steps, warmup, chunk, kernel="auto", extension="linear"):
     import torch
     s.adr_step(warmup, graph_chunk=chunk, report=False, kernel=kernel, extension=extension)
@@ -241,6 +259,9 @@ def main():
     ap.add_argument("--extension", default="linear", choices=["linear", "finite"],
                     help="finite: e = |x M + u_j - u_i| - x with the force along the deformed bond "
                          "(FP64 gather kernels)")
+    ap.add_argument("--static", action="store_true",
+                    help="time conjugate-gradient iterations of the static solve with the assembled "
+                         "double block-sparse K (one K product per iteration)")
     ap.add_argument("--adr", action="store_true",
                     help="time iterations of the adaptive dynamic relaxation (FP64 matrix-free force, "
                          "fictitious time step 1) instead of explicit steps")
@@ -297,6 +318,34 @@ def main():
         args.precision = "fp64"
         s.adr_setup(1.0)
 
+    if args.static:
+        args.precision = "fp64"
+        # the static problem: prescribed components displaced by what 100
+        # explicit steps of their prescribed velocity move them, plus the
+        # external load
+        dts = np.asarray(w.dt, dtype=np.float64).reshape(-1)
+        s.reset(u0=w.v0 * (100.0 * (dts[np.asarray(w.specimen)][:, None] if dts.size > 1 else float(dts[0]))))
+        s.build_K(fp32=False)
+        s.assemble_K()
+        el = time_static(s, args.steps, args.warmup)
+        ms_it = 1e3 * el / args.steps
+        kb = int(s.K_sizes.nnzb)
+        dim = int(sz.dim)
+        byt = kb * (8 * dim * dim + 4) + int(sz.n_pad) * (8 + 512)
+        gbs = byt / (ms_it * 1e-3) / 1e9
+        out = {"metric": "bond-updates/s per explicit step", "value": n_bonds * args.steps / el,
+               "unit": "bond-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": ms_it, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64", "data": "synthetic",
+               "config": {"workload": desc + "; static solve (prescribed components displaced by 100 explicit "
+                                      "steps of their velocity), conjugate-gradient iterations (one K product each)",
+                          "nodes": int(sz.n), "unique_bonds": n_bonds, "K_blocks": kb},
+               "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                            "kernel": "one CG iteration (block product + vector kernels)",
+                            "kernel_ms": round(ms_it, 5), "algorithmic_bytes": byt}}
+        print(json.dumps(out), flush=True)
+        return
     if args.adr:
         el = time_adr(s, args.steps, args.warmup, args.graph_chunk, args.kernel, args.extension)
     else:

@@ -596,6 +596,40 @@ pd_status pd_adr_step(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st,
                       const pd_step_opts *opts, pd_adr_dev *R, pd_step_report *rep);
 
 /* ------------------------------------------------------------------------ */
+/* static solve with the block-sparse stiffness (Eq. 2.14)                  */
+/* ------------------------------------------------------------------------ */
+
+/* The paper notes that the global stiffness of Eq. 2.14 is too wide for a
+ * direct implicit solve and suggests an iterative one.  pd_static_solve
+ * finds static equilibrium f(u) + F_ext = 0 by preconditioned conjugate
+ * gradients (block Jacobi) on the free components: from the current u0 of
+ * st (prescribed components held), K_ff du = F_ext + f(u0) with
+ * K = -df/du (the double-precision K of pd_assemble_K, for the bond status
+ * it was assembled with), then u = u0 + du is written to st->uv[st->cur].
+ * The full external load is used (no ramp).  Synchronises every
+ * opts->check_every iterations to test |r| <= tol |r0|. */
+typedef struct pd_cg_opts {
+    double tol;            /* relative residual |r| / |r0| to stop at (> 0)           */
+    int32_t max_iter;      /* iteration limit (> 0)                                   */
+    int32_t check_every;   /* iterations between convergence checks (> 0)             */
+} pd_cg_opts;
+
+typedef struct pd_cg_report {
+    int32_t iterations;    /* iterations done                                          */
+    int32_t converged;     /* 1 if the tolerance was met                               */
+    double rel_residual;   /* |r| / |r0| at the end                                    */
+} pd_cg_report;
+
+/* Doubles of device workspace pd_static_solve needs for n_pad rows. */
+int64_t pd_static_workspace(int64_t n_pad);
+
+/* Errors: PD_ERR_ARG (NULL pointers, bad options), PD_ERR_STATE (K not
+ * assembled), PD_ERR_UNSUPPORTED (K stores float values), PD_ERR_UNSTABLE
+ * (non-finite solution), PD_ERR_HIP. */
+pd_status pd_static_solve(pd_ctx *ctx, const pd_problem_dev *prob, const struct pd_bsr_dev *K, pd_state_dev *st,
+                          const pd_cg_opts *opts, double *work, pd_cg_report *rep);
+
+/* ------------------------------------------------------------------------ */
 /* outputs                                                                  */
 /* ------------------------------------------------------------------------ */
 

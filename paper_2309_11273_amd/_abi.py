@@ -103,6 +103,14 @@ class pd_adr_dev(C.Structure):
     _fields_ = [("dt", dbl), ("lambda_", P), ("f_prev", P), ("f_int", P), ("partial", P), ("stats", P)]
 
 
+class pd_cg_opts(C.Structure):
+    _fields_ = [("tol", dbl), ("max_iter", i32), ("check_every", i32)]
+
+
+class pd_cg_report(C.Structure):
+    _fields_ = [("iterations", i32), ("converged", i32), ("rel_residual", dbl)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "pd_version": (C.c_char_p, []),
@@ -139,6 +147,9 @@ SIGNATURES = {
     "pd_adr_density": (i32, [P, C.POINTER(pd_problem_dev), P, C.POINTER(pd_adr_dev)]),
     "pd_adr_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i64,
                           C.POINTER(pd_step_opts), C.POINTER(pd_adr_dev), C.POINTER(pd_step_report)]),
+    "pd_static_workspace": (i64, [i64]),
+    "pd_static_solve": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_bsr_dev), C.POINTER(pd_state_dev),
+                              C.POINTER(pd_cg_opts), P, C.POINTER(pd_cg_report)]),
     "pd_damage": (i32, [P, C.POINTER(pd_problem_dev), P, P]),
     "pd_energy": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), P,
                         C.POINTER(dbl), C.POINTER(dbl)]),

@@ -19,7 +19,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpd.so")
 
 HIP_SOURCES = ["api.hip", "kernels.hip", "kernels_f32.hip", "kernels_tiled.hip", "kernels_tiled64.hip", "bsr.hip",
-               "factored.hip", "adr.hip", "finite.hip"]
+               "factored.hip", "adr.hip", "finite.hip",
+               "cg.hip"]
 CXX_SOURCES = ["family.cpp"]
 
 ARCH = "gfx950"

@@ -10,6 +10,7 @@
 #include <string>
 
 #include "adr.h"
+#include "cg.h"
 #include "factored.h"
 #include "finite.h"
 #include "kernels.h"
@@ -690,6 +691,50 @@ pd_status pd_bsr_apply(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *K, 
     pdk::StepArgs a = make_args(p, st);
     a.f_out = reinterpret_cast<double4 *>(f);
     HIP_TRY(c, pdk::launch_bsr_spmv(a, p, K, st->cur, false, c->stream));
+    return PD_OK;
+}
+
+int64_t pd_static_workspace(int64_t n_pad) { return n_pad > 0 ? pdk::cg_workspace_doubles(n_pad) : 0; }
+
+pd_status pd_static_solve(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *K, pd_state_dev *st,
+                          const pd_cg_opts *o, double *work, pd_cg_report *rep) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_bsr(c, p, K)) != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!K->assembled) return fail(c, PD_ERR_STATE, "K is not assembled");
+    if (K->fp32) return fail(c, PD_ERR_UNSUPPORTED, "the static solve needs K in double");
+    if (!o || !work) return fail(c, PD_ERR_ARG, "NULL options or workspace");
+    if (!(o->tol > 0.0) || o->max_iter <= 0 || o->check_every <= 0) return fail(c, PD_ERR_ARG, "bad solver options");
+    if (reinterpret_cast<uintptr_t>(work) % 32 != 0) return fail(c, PD_ERR_ARG, "workspace must be 32-byte aligned");
+    if (!p->aux || !p->fext) return fail(c, PD_ERR_ARG, "aux/fext are NULL (call pd_state_init first)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pdk::StepArgs a = make_args(p, st);
+    const int cur = st->cur;
+    HIP_TRY(c, pdk::launch_cg_start(a, K, work, cur, c->stream));
+    const double *scal = pdk::cg_scalars(work, p->n_pad);
+    double h[8] = {0};
+    int it = 0;
+    bool conv = false;
+    HIP_TRY(c, hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    conv = h[4] == 0.0;  // zero residual: u0 is already in equilibrium
+    while (!conv && it < o->max_iter) {
+        const int chunk = std::min(o->check_every, o->max_iter - it);
+        for (int k = 0; k < chunk; k++) HIP_TRY(c, pdk::launch_cg_iteration(a, K, work, c->stream));
+        it += chunk;
+        HIP_TRY(c, hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (!std::isfinite(h[5])) return fail(c, PD_ERR_UNSTABLE, "non-finite residual in the static solve");
+        conv = h[5] <= o->tol;
+    }
+    HIP_TRY(c, pdk::launch_cg_finish(a, K, work, cur, c->stream));
+    if (rep) {
+        rep->iterations = (int32_t)h[6];
+        rep->converged = conv ? 1 : 0;
+        rep->rel_residual = h[5];
+    }
     return PD_OK;
 }
 

@@ -457,6 +457,20 @@ class Solver:
         self.ctx.check("pd_assemble_K", A.load().pd_assemble_K(self.ctx.h, C.byref(self.P), _tp(self.mask),
                                                                  C.byref(self.K)))
 
+    def static_solve(self, tol: float = 1e-12, max_iter: int = 20000, check_every: int = 50) -> dict:
+        """Static equilibrium from the current state with the assembled
+        double K (pd_static_solve); the solution replaces u."""
+        L = A.load()
+        nw = int(L.pd_static_workspace(self.n_pad))
+        if getattr(self, "_cg_work", None) is None or self._cg_work.numel() < nw:
+            self._cg_work = torch.zeros(nw, dtype=torch.float64, device=self.dev)
+        o = A.pd_cg_opts(float(tol), int(max_iter), int(check_every))
+        rep = A.pd_cg_report()
+        self.ctx.check("pd_static_solve", L.pd_static_solve(self.ctx.h, C.byref(self.P), C.byref(self.K),
+                                                              C.byref(self.S), C.byref(o), _tp(self._cg_work),
+                                                              C.byref(rep)))
+        return dict(iterations=rep.iterations, converged=bool(rep.converged), rel_residual=rep.rel_residual)
+
     def bsr_apply(self):
         f = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=self.dev)
         self.ctx.check("pd_bsr_apply", A.load().pd_bsr_apply(self.ctx.h, C.byref(self.P), C.byref(self.K),
