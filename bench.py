@@ -371,6 +371,18 @@ def main():
         if args.adr:
             # pass 2 runs without its update here; the relaxation's own kernels
             roofline["relaxation_kernels_ms"] = round(prof["ms_extra"] / ps, 5)
+    elif args.form == "bsr":
+        # the block product with the update dominates; per block the values
+        # (9 or 4 entries) and a column index, per row u, v, aux and the update
+        dim = int(sz.dim)
+        vb = 4 if args.precision == "fp32" else 8
+        kb = int(s.K_sizes.nnzb)
+        byt = kb * (dim * dim * vb + 4) + int(sz.n) * (8 + 32 + 68 + 64) + 32 * n_loaded
+        gbs = byt / (ms2 * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_bsr_spmv",
+                    "kernel_ms": round(ms2, 5), "algorithmic_bytes": byt, "K_blocks": kb,
+                    "break_mark_ms": round(ms1, 5), "reassembly_ms": round(prof["ms_extra"] / ps, 5)}
     elif args.form == "fac":
         # pass 1: E product + breaking; extra: K_theta re-assembly check + Theta
         # product; pass 2: F product + update

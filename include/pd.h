@@ -444,7 +444,10 @@ typedef struct pd_bsr_dev {
     int32_t reach;          /* from pd_bsr_pattern                                     */
     const int64_t *row_ptr; /* [device] n_pad+1                                        */
     const int32_t *col;     /* [device] nnzb                                           */
-    void *vals;             /* [device] nnzb*dim*dim, row-major blocks                 */
+    void *vals;             /* [device] nnzb*dim*dim; the blocks of row i fill entries
+                               [row_ptr[i], row_ptr[i+1]) * dim*dim, entry (r, s) of the
+                               row's block slot t at row_ptr[i]*dim*dim
+                               + (r*dim + s)*nblk_i + t (component-major by row)       */
     double *bc;             /* [device] n_pad*8 scratch: per-node sums B_i, C_i        */
     uint32_t *dirty;        /* [device] n_pad flags of rows to re-assemble (zeroed)     */
     int32_t assembled;      /* set by pd_assemble_K                                    */

@@ -15,6 +15,12 @@
 // pattern reaches two bonds (2 delta).  Using differences keeps the product
 // free of the rigid-motion cancellation of K u when u is large.
 //
+// Storage: the values of row i occupy the range [row_ptr[i], row_ptr[i+1])
+// of blocks, entry (r, s) of block slot t at
+// vals[row_ptr[i] * NV + (r * DIM + s) * nblk_i + t] (component-major within
+// the row), so the 64 lanes of a wave that take consecutive blocks of one
+// row read consecutive values for each entry.
+//
 // Assembly: one workgroup per row accumulates its blocks in LDS.  The
 // one-bond terms touch distinct blocks; the two-bond terms are added one
 // neighbour j at a time (distinct q for a fixed j, barrier between j), so
@@ -181,8 +187,11 @@ __global__ void k_bsr_assemble(StepArgs a, BsrArgs b, int all, int par) {
         __syncthreads();
     }
     for (int t = tid; t < nblk * NV; t += nt) {
-        if (FP32V) reinterpret_cast<float *>(b.vals)[(size_t)rp0 * NV + t] = (float)acc[t];
-        else reinterpret_cast<double *>(b.vals)[(size_t)rp0 * NV + t] = acc[t];
+        // acc holds block-major entries; the row is stored component-major
+        const int k = t / nblk, slot = t - k * nblk;
+        const double v = acc[(size_t)slot * NV + k];
+        if (FP32V) reinterpret_cast<float *>(b.vals)[(size_t)rp0 * NV + t] = (float)v;
+        else reinterpret_cast<double *>(b.vals)[(size_t)rp0 * NV + t] = v;
     }
     if (!all && tid == 0) b.dirty[i] = 0u;
 }
@@ -260,20 +269,22 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(StepArgs a, BsrArgs b, int cur
     const double4 *__restrict__ uv = a.uv[cur];
     const double4 ui = uv[row];
     const int64_t rp0 = b.row_ptr[row], rp1 = b.row_ptr[row + 1];
+    const int64_t nblk = rp1 - rp0;
     double f[3] = {0, 0, 0};
     float ff[3] = {0, 0, 0};
-    for (int64_t t = rp0 + lane; t < rp1; t += 64) {
-        const double4 uq = uv[b.col[t]];
+#pragma unroll 2
+    for (int64_t t = lane; t < nblk; t += 64) {
+        const double4 uq = uv[b.col[rp0 + t]];
         const double d[3] = {uq.x - ui.x, uq.y - ui.y, DIM == 3 ? uq.z - ui.z : 0.0};
         if (FP32V) {
-            const float *K = reinterpret_cast<const float *>(b.vals) + (size_t)t * NV;
+            const float *K = reinterpret_cast<const float *>(b.vals) + (size_t)rp0 * NV + t;
             const float df[3] = {(float)d[0], (float)d[1], (float)d[2]};
             for (int r = 0; r < DIM; r++)
-                for (int s = 0; s < DIM; s++) ff[r] += K[r * DIM + s] * df[s];
+                for (int s = 0; s < DIM; s++) ff[r] += K[(r * DIM + s) * nblk] * df[s];
         } else {
-            const double *K = reinterpret_cast<const double *>(b.vals) + (size_t)t * NV;
+            const double *K = reinterpret_cast<const double *>(b.vals) + (size_t)rp0 * NV + t;
             for (int r = 0; r < DIM; r++)
-                for (int s = 0; s < DIM; s++) f[r] += K[r * DIM + s] * d[s];
+                for (int s = 0; s < DIM; s++) f[r] += K[(r * DIM + s) * nblk] * d[s];
         }
     }
     if (FP32V)

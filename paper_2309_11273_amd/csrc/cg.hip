@@ -53,14 +53,16 @@ __device__ __forceinline__ void row_product(const CgArgs &c, int64_t row, const 
     constexpr int NV = DIM * DIM;
     const int lane = threadIdx.x & 63;
     const double4 vi = v[row];
-    const int64_t rp0 = c.row_ptr[row], rp1 = c.row_ptr[row + 1];
+    const int64_t rp0 = c.row_ptr[row], nblk = c.row_ptr[row + 1] - rp0;
     double f[3] = {0.0, 0.0, 0.0};
-    for (int64_t t = rp0 + lane; t < rp1; t += 64) {
-        const double4 vq = v[c.col[t]];
+#pragma unroll 2
+    for (int64_t t = lane; t < nblk; t += 64) {
+        const double4 vq = v[c.col[rp0 + t]];
         const double d[3] = {vq.x - vi.x, vq.y - vi.y, DIM == 3 ? vq.z - vi.z : 0.0};
-        const double *K = c.vals + (size_t)t * NV;
+        // entry (a, b) of the block at (a DIM + b) nblk (component-major rows)
+        const double *K = c.vals + (size_t)rp0 * NV + t;
         for (int a = 0; a < DIM; a++)
-            for (int b = 0; b < DIM; b++) f[a] += K[a * DIM + b] * d[b];
+            for (int b = 0; b < DIM; b++) f[a] += K[(a * DIM + b) * nblk] * d[b];
     }
     for (int o = 32; o > 0; o >>= 1)
         for (int a = 0; a < 3; a++) f[a] += __shfl_xor(f[a], o);
@@ -92,10 +94,11 @@ __global__ __launch_bounds__(256) void k_cg_dinv(StepArgs a, CgArgs c) {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= a.n_pad) return;
     double D[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t t = c.row_ptr[row]; t < c.row_ptr[row + 1]; t++) {
-        const double *K = c.vals + (size_t)t * NV;
+    const int64_t rp0 = c.row_ptr[row], nblk = c.row_ptr[row + 1] - rp0;
+    for (int64_t t = 0; t < nblk; t++) {
+        const double *K = c.vals + (size_t)rp0 * NV + t;
         for (int i = 0; i < DIM; i++)
-            for (int j = 0; j < DIM; j++) D[3 * i + j] += K[i * DIM + j];
+            for (int j = 0; j < DIM; j++) D[3 * i + j] += K[(i * DIM + j) * nblk];
     }
     if (DIM == 2) D[8] = 1.0;
     const double c00 = D[4] * D[8] - D[5] * D[7], c01 = D[5] * D[6] - D[3] * D[8], c02 = D[3] * D[7] - D[4] * D[6];
