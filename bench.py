@@ -199,6 +199,23 @@ def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto", extension=
     return time.perf_counter() - t0
 
 
+def batch_baseline(n_plates, steps, chunk):
+    """Wall time of 'steps' FP64 steps of every plate of the batch, one plate
+    after the other, each with its own solver, context and captured graph."""
+    import torch
+    from paper_2309_11273_amd.solver import Context, Solver
+    from pd_inputs import workloads as W
+    solvers = [Solver(W.batch2d(n_plates=1, first=k), ctx=Context(0), fp32_state=False) for k in range(n_plates)]
+    for s in solvers:
+        s.step(chunk, precision="fp64", graph_chunk=chunk, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps, precision="fp64", graph_chunk=chunk, report=False)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
 def time_static(s, steps, warmup):
     """Wall time of 'steps' conjugate-gradient iterations (HIP events on the
     library's stream), less that of a solve with none (the start phase)."""
@@ -259,6 +276,9 @@ def main():
     ap.add_argument("--extension", default="linear", choices=["linear", "finite"],
                     help="finite: e = |x M + u_j - u_i| - x with the force along the deformed bond "
                          "(FP64 gather kernels)")
+    ap.add_argument("--batch-baseline", action="store_true",
+                    help="batch2d only: also time the plain FP64 path run one plate at a time (each plate "
+                         "its own solver and graph), the baseline the batched form is compared with")
     ap.add_argument("--static", action="store_true",
                     help="time conjugate-gradient iterations of the static solve with the assembled "
                          "double block-sparse K (one K product per iteration)")
@@ -430,6 +450,12 @@ def main():
         out["fp32_speedup_vs_fp64"] = value / out["fp64"]["value"]
     del s
     torch.cuda.empty_cache()
+    if args.batch_baseline and args.workload == "batch2d":
+        el_b = batch_baseline(w.n_specimens, args.steps, args.graph_chunk)
+        out["batch_baseline"] = {"kind": "plain FP64, one plate at a time",
+                                 "ms_per_step": 1e3 * el_b / args.steps, "value": n_bonds * args.steps / el_b,
+                                 "batched_speedup": value / (n_bonds * args.steps / el_b)}
+        torch.cuda.empty_cache()
     if args.copy_mb > 0:
         src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
