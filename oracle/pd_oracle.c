@@ -51,7 +51,11 @@
  * critical stretch from the energy released across a crack; the two-node
  * oscillator and the break step in closed form; the discrete energy invariant
  * of the update; the cantilever's first bending frequency; notch cuts against
- * sampled crossings of every bond segment.
+ * sampled crossings of every bond segment; for the finite model, zero force
+ * under a finite rigid rotation, the force as the energy gradient and the
+ * first-order agreement with the linearized model; for the relaxation, a
+ * density that bounds every row of |K|, convergence to the direct static
+ * solution and damping that approaches twice the slowest frequency.
  * Parity unpinned: the 2D critical stretch (Eq. 1.28, taken as printed; the
  * paper prints no value of it, and it is not what the 2D stored energy gives),
  * and the crack paths of the fracture workloads (nothing outside this file
