@@ -97,15 +97,10 @@ __device__ __forceinline__ int map_index(const int4 &d, int reach) {
     return (d.x + reach) * S + (d.y + reach);
 }
 
+// one row of the assembly, the whole workgroup (LDS smem)
 template <int DIM, bool FP32V>
-__global__ void k_bsr_assemble(StepArgs a, BsrArgs b, int all, int par) {
+__device__ void assemble_row(const StepArgs &a, const BsrArgs &b, int64_t i, int all, double *smem) {
     constexpr int NV = DIM * DIM;
-    extern __shared__ double smem[];
-    const int64_t i = blockIdx.x;
-    if (!all) {
-        if (a.ctl->dirty[par] == 0) return;
-        if (!b.dirty[i]) return;
-    }
     const int tid = threadIdx.x, nt = blockDim.x;
     const int64_t rp0 = b.row_ptr[i];
     const int nblk = (int)(b.row_ptr[i + 1] - rp0);
@@ -194,6 +189,24 @@ __global__ void k_bsr_assemble(StepArgs a, BsrArgs b, int all, int par) {
         else reinterpret_cast<double *>(b.vals)[(size_t)rp0 * NV + t] = v;
     }
     if (!all && tid == 0) b.dirty[i] = 0u;
+}
+
+// all = 1: one workgroup per row.  all = 0 (after a step): a fixed grid
+// strides over the rows and re-assembles those flagged; when no bond broke
+// every workgroup returns at once.
+template <int DIM, bool FP32V>
+__global__ void k_bsr_assemble(StepArgs a, BsrArgs b, int all, int par) {
+    extern __shared__ double smem[];
+    if (all) {
+        assemble_row<DIM, FP32V>(a, b, blockIdx.x, 1, smem);
+        return;
+    }
+    if (a.ctl->dirty[par] == 0) return;
+    for (int64_t i = blockIdx.x; i < a.n_pad; i += gridDim.x) {
+        if (!b.dirty[i]) continue;
+        assemble_row<DIM, FP32V>(a, b, i, 0, smem);
+        __syncthreads();
+    }
 }
 
 // pass 1 variant for the block form: breaking only, marking the rows that
@@ -360,7 +373,7 @@ hipError_t launch_bsr_prep_assemble(const StepArgs &a, const pd_problem_dev *p, 
     if (e != hipSuccess) return e;
     const size_t lds = bsr_assemble_lds(a.dim, K->max_row_blocks, K->reach);
     const int nt = a.dim == 3 ? 128 : 64;
-    const dim3 g((unsigned)a.n_pad);
+    const dim3 g((unsigned)(all ? a.n_pad : std::min<int64_t>(a.n_pad, 2048)));
     if (a.dim == 3) {
         if (K->fp32) hipLaunchKernelGGL((k_bsr_assemble<3, true>), g, dim3(nt), lds, s, a, b, (int)all, par);
         else hipLaunchKernelGGL((k_bsr_assemble<3, false>), g, dim3(nt), lds, s, a, b, (int)all, par);
