@@ -213,16 +213,24 @@ def test_bsr_apply_matches_matrix_free(ctx):
         assert rel(f_k, f_mf) <= 1e-12, (name, rel(f_k, f_mf))
 
 
-@pytest.mark.parametrize("name,steps", [("plate_notched", 300), ("impact", 200)])
-def test_bsr_trajectory(ctx, name, steps):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,steps", [("plate_notched", 300), ("impact", 200), ("cylinder", 200),
+                                        ("plane_strain", 100)])
+def test_bsr_trajectory(ctx, name, steps, precision):
+    """The block-sparse form (K in double or float values; breaking decided
+    in double in both) at n/4, n/2, n steps."""
     w = small_workloads()[name]
     o = Oracle(w)
     s = solver(w, ctx)
-    s.build_K(fp32=False)
+    s.build_K(fp32=precision == "fp32")
     s.assemble_K()
     uo, vo = o.initial_state()
-    s.step(steps, precision="fp64", form="bsr")
-    o.run(steps, uo, vo)
-    u, _ = s.read()
-    assert rel(u, uo) <= FP64_TOL, rel(u, uo)
-    assert np.array_equal(s.bond_status()[2], o.rho())
+    tol = FP64_TOL if precision == "fp64" else FP32_TOL
+    done = 0
+    for target in (steps // 4, steps // 2, steps):
+        s.step(target - done, precision=precision, form="bsr")
+        o.run(target - done, uo, vo)
+        done = target
+        u, _ = s.read()
+        assert rel(u, uo) <= tol, (target, rel(u, uo))
+        assert np.array_equal(s.bond_status()[2], o.rho()), target
