@@ -244,22 +244,35 @@ def time_adr(s, steps, warmup, chunk, kernel="auto", extension="linear"):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(w, budget_s: float):
+def cpu_baseline(w, budget_s: float, mode: str = "step"):
+    """The CPU reference timed on a bounded sample of the same workload and
+    the same operation: explicit steps (mode "step"; also the reference of
+    the factored form, which applies the same operator), explicit steps of
+    the finite model ("finite"), or relaxation iterations ("adr")."""
     from oracle import Oracle
     from oracle.oracle import num_threads
     o = Oracle(w)
-    u, v = o.initial_state()
-    o.run(1, u, v)  # first touch
+    if mode == "finite":
+        o.set_finite(True)
+    if mode == "adr":
+        st = o.adr_start()
+        advance = lambda: o.adr_run(1, st)  # noqa: E731
+    else:
+        u, v = o.initial_state()
+        advance = lambda: o.run(1, u, v)  # noqa: E731
+    advance()  # first touch
     n, t0 = 0, time.perf_counter()
     while True:
-        o.run(1, u, v)
+        advance()
         n += 1
         el = time.perf_counter() - t0
         if el >= budget_s or n >= 1000:
             break
+    what = {"step": "explicit steps", "finite": "explicit steps of the finite model",
+            "adr": "relaxation iterations"}[mode]
     return dict(value=o.nb * n / el, unit="bond-updates/s", cores=num_threads(), kind="oracle",
-                sample=f"{w.name}: {n} explicit steps of the full workload ({o.nb} unique bonds) "
-                       f"after one untimed step, FP64 loop reference with OpenMP over nodes")
+                sample=f"{w.name}: {n} {what} of the full workload ({o.nb} unique bonds) "
+                       f"after one untimed one, FP64 loop reference with OpenMP over nodes")
 
 
 def main():
@@ -465,8 +478,9 @@ def main():
         out["copy_reference_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
         torch.cuda.empty_cache()
-    if not args.no_cpu and not args.adr:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    if not args.no_cpu:
+        mode = "adr" if args.adr else ("finite" if args.extension == "finite" else "step")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, mode)
     print(json.dumps(out), flush=True)
 
 
