@@ -211,7 +211,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     const int rx = rsent ? 0 : r0;
     const int ry = rsent ? 0 : __builtin_amdgcn_readlane(own.y, lr);
     const int rz = rsent ? 0 : __builtin_amdgcn_readlane(own.z, lr);
-    __syncthreads();
+    tile_sync<TPW>();
     bool sent = false;
     {
         uint32_t rw[MS];
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
                     DIM == 3 ? idiff(v[i].z, rz) : 0.0f, Vv, GQ * r[i] * Vv);
         }
     }
-    const bool anysent = __syncthreads_or(sent);
+    const bool anysent = tile_sync_or<TPW>(sent);
     if (BREAK && valid && tile == 0 && gt == 0) {
         ctl->s1 = ctl->s2;
         ctl->qs[cur ^ 1] = shadow_scale_t(ctl->umax_bits[cur]);
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         fe = a.fe32[row];
         if (UPDATE) v = a.vel[row];
     }
-    __syncthreads();
+    tile_sync<TPW>();
     {
         uint32_t rw[MS];
 #pragma unroll
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
             }
         }
     }
-    __syncthreads();
+    tile_sync<TPW>();
     const int my = own_slot1<DIM>(a.tile, a.reach, B1, lane);
     const float qi = DIM == 3 ? hb[my] : reinterpret_cast<const float2 *>(hb)[my].x;
     float fx = 0.f, fy = 0.f, fz = 0.f;

@@ -139,6 +139,32 @@ __device__ __forceinline__ int64_t halo_row_of(int m, const int *tn) {
     return nt < 0 ? -1 : (int64_t)nt * 64 + (m & 63);
 }
 
+// Barrier between the staging and the sweep of a tile.  With one tile per
+// workgroup (TPW = 1) the four waves share the tile's LDS; with one tile per
+// wave (TPW = 4) a wave reads only what it wrote itself, and its LDS
+// operations complete in order, so a wavefront-scope fence suffices and the
+// waves of a workgroup need not wait for each other.
+template <int TPW>
+__device__ __forceinline__ void tile_sync() {
+    if constexpr (TPW == 1) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <int TPW>
+__device__ __forceinline__ bool tile_sync_or(bool p) {
+    if constexpr (TPW == 1) {
+        return __syncthreads_or(p);
+    } else {
+        tile_sync<TPW>();
+        return __ballot(p) != 0ull;
+    }
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs of the chip, each with its
 // own L2.  Tile of workgroup b: every XCD gets a contiguous range of tiles,
 // so neighbouring tiles, whose halo boxes overlap, are staged through the
