@@ -304,8 +304,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
-                    help="after the run, launch a plain read+write kernel over this many MiB (a known-size "
-                         "reference for HBM byte counters)")
+                    help="size in MiB of the plain read+write kernel timed after the run (the HBM ceiling "
+                         "and the known-size reference for the byte counters); 0 = 1024")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -469,15 +469,24 @@ def main():
                                  "ms_per_step": 1e3 * el_b / args.steps, "value": n_bonds * args.steps / el_b,
                                  "batched_speedup": value / (n_bonds * args.steps / el_b)}
         torch.cuda.empty_cache()
-    if args.copy_mb > 0:
-        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 2.0, out=dst)
-        torch.cuda.synchronize()
-        out["copy_reference_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
-        del src, dst
-        torch.cuda.empty_cache()
+    # the practical HBM ceiling: a plain read-and-write kernel of known size
+    # (also the reference the byte counters are scaled by)
+    mb = args.copy_mb if args.copy_mb > 0 else 1024
+    src = torch.ones(mb << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 2.0, out=dst)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        torch.mul(src, 2.0, out=dst)
+    ev1.record()
+    torch.cuda.synchronize()
+    moved = 10 * 2 * src.numel() * 4
+    out["copy_reference"] = {"read_bytes": src.numel() * 4, "write_bytes": dst.numel() * 4,
+                             "gbs": round(moved / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)}
+    del src, dst
+    torch.cuda.empty_cache()
     if not args.no_cpu:
         mode = "adr" if args.adr else ("finite" if args.extension == "finite" else "step")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, mode)
