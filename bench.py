@@ -122,7 +122,7 @@ def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
     tiled = args.kernel != "gather" and s.tiled_supported(args.precision)
     kname = f"k_{'t' if tiled else ''}{dom}_{'f32' if args.precision == 'fp32' else 'f64'}"
     if args.extension == "finite":
-        kname = f"k_fin_{dom}"
+        kname = f"k_tpass{dom[-1]}_f64 (finite model)" if tiled else f"k_fin_{dom}"
     ms_dom = ms1 if dom == "pass1" else ms2
     sec = ms_dom * 1e-3
     byt = algorithmic_bytes(dom, args.precision, nnz, n, n_loaded, tiled)
@@ -136,7 +136,8 @@ def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
     gbs, tfs = byt / sec / 1e9, fl / sec / 1e12
     alu = fl / (peak_fl * 1e12) > byt / (HBM_PEAK_GBS * 1e9)
     from paper_2309_11273_amd.profsum import kernel_source_hash
-    traffic = traffic_from_profiles(f"{kname}@{args.workload}", kernel_source_hash(kname))
+    traffic = None if args.extension == "finite" else \
+        traffic_from_profiles(f"{kname}@{args.workload}", kernel_source_hash(kname))
     return {"bound": "alu" if alu else "hbm",
             "achieved": round(tfs if alu else gbs, 2), "peak": peak_fl if alu else HBM_PEAK_GBS,
             "unit": "TFLOP/s" if alu else "GB/s",
@@ -344,7 +345,7 @@ def main():
     if args.extension == "finite":
         if args.form != "mf":
             sys.exit("bench.py: --extension finite runs with the matrix-free force (--form mf)")
-        args.precision, args.kernel = "fp64", "gather"
+        args.precision = "fp64"
     if args.adr:
         if args.form != "mf":
             sys.exit("bench.py: --adr runs with the matrix-free force (--form mf)")

@@ -324,7 +324,8 @@ pd_status pd_force(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, in
 
 /* The same force with the finite extension and the deformed direction of
  * Eqs. 1.10, 1.13 (e = |Y| - x, Y = x M + u_j - u_i, pair force of Eq. 2.2
- * along Y/|Y|), in double precision with the gather kernels.  Uses st->qr
+ * along Y/|Y|), in double precision (tile kernels when the family allows
+ * them and st->fe64 is set, else gather kernels).  Uses st->qr and st->fe64
  * as scratch.  Errors as pd_force. */
 pd_status pd_force_finite(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, double *f, double *theta);
 
@@ -347,7 +348,8 @@ typedef struct pd_step_opts {
     int32_t extension;   /* 0: linearized e = M.(u_j - u_i) along M (Eqs. 2.4, 2.7);
                             1: finite e = |x M + u_j - u_i| - x with the pair force
                             along the deformed bond (Eqs. 1.10, 1.13): PD_FP64,
-                            PD_MATRIX_FREE, gather kernels                           */
+                            PD_MATRIX_FREE; double tile kernels or, with kernel = 1
+                            or a family they do not fit, gather kernels            */
 } pd_step_opts;
 
 /* Kernel timings gathered by pd_step with opts->profile = 1 (milliseconds,

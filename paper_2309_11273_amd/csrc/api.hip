@@ -342,12 +342,14 @@ static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, in
         // relaxation: FP64 force without its update, then the relaxation kernels
         pdk::StepArgs af = a;
         af.f_out = reinterpret_cast<double4 *>(R->f_int);
-        const bool tiled = o.kernel != 1 && o.extension == 0 && pdk::tiled64_supported(af);
-        if (o.extension) e = pdk::launch_fin_pass1(af, cur, true, block, s);
+        const bool tiled = o.kernel != 1 && (o.extension ? pdk::tiled64_fin_supported(af) : pdk::tiled64_supported(af));
+        if (o.extension)
+            e = tiled ? pdk::launch_tpass1_f64_fin(af, cur, true, s) : pdk::launch_fin_pass1(af, cur, true, block, s);
         else e = tiled ? pdk::launch_tpass1_f64(af, cur, true, s) : pdk::launch_pass1_f64(af, cur, true, block, s);
         if (e != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-        if (o.extension) e = pdk::launch_fin_pass2(af, cur, false, block, s);
+        if (o.extension)
+            e = tiled ? pdk::launch_tpass2_f64_fin(af, cur, false, s) : pdk::launch_fin_pass2(af, cur, false, block, s);
         else e = tiled ? pdk::launch_tpass2_f64(af, cur, false, s) : pdk::launch_pass2_f64(af, cur, false, block, s);
         if (e != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
@@ -366,10 +368,14 @@ static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, in
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
         if ((e = pdk::launch_bsr_spmv(a, p, K, cur, true, s)) != hipSuccess) return e;
     } else if (o.extension) {
-        if ((e = pdk::launch_fin_pass1(a, cur, true, block, s)) != hipSuccess) return e;
+        // the double tile kernels unless the gather kernels are asked for
+        const bool tiled = o.kernel != 1 && pdk::tiled64_fin_supported(a);
+        e = tiled ? pdk::launch_tpass1_f64_fin(a, cur, true, s) : pdk::launch_fin_pass1(a, cur, true, block, s);
+        if (e != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-        if ((e = pdk::launch_fin_pass2(a, cur, true, block, s)) != hipSuccess) return e;
+        e = tiled ? pdk::launch_tpass2_f64_fin(a, cur, true, s) : pdk::launch_fin_pass2(a, cur, true, block, s);
+        if (e != hipSuccess) return e;
     } else {
         // LDS-staged tile kernels unless the gather kernels are asked for
         const bool fp64 = o.precision == PD_FP64;
@@ -406,8 +412,13 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
     if (o.profile != 0 && o.profile != 1) return fail(c, PD_ERR_ARG, "profile must be 0 or 1");
     if (o.kernel < 0 || o.kernel > 2) return fail(c, PD_ERR_ARG, "kernel must be 0, 1 or 2");
     if (o.extension != 0 && o.extension != 1) return fail(c, PD_ERR_ARG, "extension must be 0 or 1");
-    if (o.extension && (o.precision != PD_FP64 || o.form != PD_MATRIX_FREE || o.kernel == 2))
-        return fail(c, PD_ERR_UNSUPPORTED, "the finite extension runs with PD_FP64, PD_MATRIX_FREE and the gather kernels");
+    if (o.extension && (o.precision != PD_FP64 || o.form != PD_MATRIX_FREE))
+        return fail(c, PD_ERR_UNSUPPORTED, "the finite extension runs with PD_FP64 and PD_MATRIX_FREE");
+    if (o.extension && o.kernel == 2) {
+        pd_state_dev tmp = *st;
+        if (!pdk::tiled64_fin_supported(make_args(p, &tmp)))
+            return fail(c, PD_ERR_UNSUPPORTED, "the finite model's tile kernels do not fit this family");
+    }
     if (o.kernel == 2 && o.form == PD_MATRIX_FREE) {
         pd_state_dev tmp = *st;
         const pdk::StepArgs ta = make_args(p, &tmp);
@@ -572,9 +583,12 @@ pd_status pd_force_finite(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, 
     pdk::StepArgs a = make_args(p, st);
     a.f_out = reinterpret_cast<double4 *>(f);
     a.theta_out = theta;
-    HIP_TRY(c, pdk::launch_fin_pass1(a, st->cur, false, 256, c->stream));
+    const bool tiled = pdk::tiled64_fin_supported(a);
+    if (tiled) HIP_TRY(c, pdk::launch_tpass1_f64_fin(a, st->cur, false, c->stream));
+    else HIP_TRY(c, pdk::launch_fin_pass1(a, st->cur, false, 256, c->stream));
     a.theta_out = nullptr;
-    HIP_TRY(c, pdk::launch_fin_pass2(a, st->cur, false, 256, c->stream));
+    if (tiled) HIP_TRY(c, pdk::launch_tpass2_f64_fin(a, st->cur, false, c->stream));
+    else HIP_TRY(c, pdk::launch_fin_pass2(a, st->cur, false, 256, c->stream));
     return PD_OK;
 }
 

@@ -14,6 +14,11 @@
 // a cheap pre-filter e >= s_c (1 - 1e-9) x skips the division for all bonds
 // that are clearly below the threshold.
 //
+// With FIN the kernels evaluate the finite model of Eqs. 1.10, 1.13 instead:
+// e = |Y| - x with Y = x M + (u_j - u_i) (|Y|^2 summed (Y1^2 + Y2^2) + Y3^2
+// without contraction), both force parts along Y / |Y|; pass 2 then stages
+// the displacements as well, to rebuild Y.
+//
 // LDS holds the staged quantities as separate arrays of doubles at a fixed
 // stride (a multiple of 64 elements), so that one address serves all of a
 // slot's arrays and pairs of them are fetched by one two-address LDS read.
@@ -21,6 +26,7 @@
 
 #include <cmath>
 
+#include "finite.h"
 #include "kernels.h"
 #include "tile_common.h"
 
@@ -50,10 +56,20 @@ __device__ __forceinline__ double ext_canonical64(double m1, double m2, double m
     return (a + b) + c;
 }
 
+// deformed bond Y = x M + (dx, dy, dz) and its length (finite model)
+__device__ __forceinline__ double deformed64(const double4 &sd, double dx, double dy, double dz, double &y1,
+                                             double &y2, double &y3) {
+#pragma clang fp contract(off)
+    y1 = sd.w * sd.x + dx;
+    y2 = sd.w * sd.y + dy;
+    y3 = sd.w * sd.z + dz;
+    return sqrt((y1 * y1 + y2 * y2) + y3 * y3);
+}
+
 // ---------------------------------------------------------------------------
 // pass 1: breaking, dilatation, deviatoric pair force
 // ---------------------------------------------------------------------------
-template <int DIM, bool BREAK, int TPW>
+template <int DIM, bool BREAK, int TPW, bool FIN = false>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int cur, const KEnt *__restrict__ kt,
                                                                 const double4 *__restrict__ sten) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -154,8 +170,20 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
         for (int c = 0; c < 4; c++) {
             const int k = 4 * gg + c;
             const double dx = ux[c] - uix, dy = uy[c] - uiy, dz = DIM == 3 ? uz[c] - uiz : 0.0;
-            const double ev = DIM == 3 ? ext_canonical64(sd[c].x, sd[c].y, sd[c].z, dx, dy, dz)
-                                       : ext_canonical64(sd[c].x, sd[c].y, 0.0, dx, dy, 0.0);
+            double ev, n1 = sd[c].x, n2 = sd[c].y, n3 = sd[c].z;
+            if constexpr (FIN) {
+                double y1, y2, y3;
+                const double yl = deformed64(sd[c], dx, dy, dz, y1, y2, y3);
+                ev = yl - sd[c].w;
+                // the deformed direction, taken only for bonds that carry force
+                const bool use = lane_bit(mm[c]);
+                n1 = use ? y1 / yl : 0.0;
+                n2 = use ? y2 / yl : 0.0;
+                n3 = use ? y3 / yl : 0.0;
+            } else {
+                ev = DIM == 3 ? ext_canonical64(sd[c].x, sd[c].y, sd[c].z, dx, dy, dz)
+                              : ext_canonical64(sd[c].x, sd[c].y, 0.0, dx, dy, 0.0);
+            }
             uint64_t live = mm[c];
             if (BREAK) {
                 const bool need = lane_bit(live) && ev >= thr_scale * sd[c].w;
@@ -174,9 +202,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
             const double xv = sd[c].w * vj[c];
             acc = fma(intact ? xv : 0.0, ev, acc);
             const double te = intact ? ev * fma(rpi, vj[c], rv[c]) : 0.0;
-            fx = fma(te, sd[c].x, fx);
-            fy = fma(te, sd[c].y, fy);
-            if (DIM == 3) fz = fma(te, sd[c].z, fz);
+            fx = fma(te, n1, fx);
+            fy = fma(te, n2, fy);
+            if (DIM == 3) fz = fma(te, n3, fz);
         }
     }
     if (BREAK && valid && lane == 0 && nbroken) atomicAdd(&ctl->broken, (unsigned long long)nbroken);
@@ -204,13 +232,15 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
 // ---------------------------------------------------------------------------
 // pass 2: dilatational pair force, explicit update
 // ---------------------------------------------------------------------------
-template <int DIM, bool UPDATE, int TPW>
+template <int DIM, bool UPDATE, int TPW, bool FIN = false>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int cur, const KEnt *__restrict__ kt,
                                                                 const double4 *__restrict__ sten) {
     extern __shared__ __align__(16) unsigned char smem[];
     using GR = Grp<DIM, TPW>;
     constexpr int MS = GR::MS;
-    using LY = Lay64<DIM, TPW, 2>;
+    // (K - G/3) theta/m, V; with FIN also u_x, u_y (, u_z)
+    constexpr int NA = FIN ? (DIM == 3 ? 5 : 4) : 2;
+    using LY = Lay64<DIM, TPW, NA>;
     constexpr int S = LY::S;
     const Box g = make_box(a, DIM);
     const int tid = threadIdx.x, lane = tid & 63;
@@ -224,7 +254,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
     // [0] (K - G/3) theta_j / m_j, [1] V_j; reused for the partial sums
     double *hB = reinterpret_cast<double *>(smem + sub * LY::BYTES);
-    uint64_t *smask = reinterpret_cast<uint64_t *>(hB + 2 * S);
+    uint64_t *smask = reinterpret_cast<uint64_t *>(hB + NA * S);
     int *stn = reinterpret_cast<int *>(smask + 128);
     pd_ctl *ctl = a.ctl;
     const double4 *__restrict__ uv = a.uv[cur];
@@ -246,7 +276,8 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
     __syncthreads();
     {
         int64_t rw[MS];
-        double q[MS], v[MS];
+        double q[MS];
+        double4 u[MS];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             rw[i] = halo_row_of(hmv[i], stn);
@@ -254,14 +285,19 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             q[i] = rw[i] >= 0 ? qr[rw[i]].x : 0.0;
-            v[i] = rw[i] >= 0 ? uv[rw[i]].w : 0.0;
+            u[i] = rw[i] >= 0 ? uv[rw[i]] : make_double4(0.0, 0.0, 0.0, 0.0);
         }
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             const int s = gt + i * GR::NT;
             if (s < g.nslot) {
                 hB[s] = kp * q[i];
-                hB[S + s] = v[i];
+                hB[S + s] = u[i].w;
+                if constexpr (FIN) {
+                    hB[2 * S + s] = u[i].x;
+                    hB[3 * S + s] = u[i].y;
+                    if (DIM == 3) hB[4 * S + s] = u[i].z;
+                }
             }
         }
     }
@@ -270,13 +306,19 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
     __syncthreads();
     const int my = own_slot<DIM>(g, lane);
     const double qi = hB[my];
+    double uix = 0.0, uiy = 0.0, uiz = 0.0;
+    if constexpr (FIN) {
+        uix = hB[2 * S + my];
+        uiy = hB[3 * S + my];
+        if (DIM == 3) uiz = hB[4 * S + my];
+    }
     const int ns = a.n_stencil;
     const int G4 = L4 >> 2;
     const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
     const int g0 = kq * gper, g1 = min(G4, g0 + gper);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int gg = g0; gg < g1; gg++) {
-        double qj[4], vj[4];
+        double qj[4], vj[4], uj[4][3];
         double4 sd[4];
         uint64_t mm[4];
 #pragma unroll
@@ -286,16 +328,31 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
             sd[c] = sten[min(k, ns - 1)];
             qj[c] = hB[slot];
             vj[c] = hB[S + slot];
+            if constexpr (FIN) {
+                uj[c][0] = hB[2 * S + slot];
+                uj[c][1] = hB[3 * S + slot];
+                uj[c][2] = DIM == 3 ? hB[4 * S + slot] : 0.0;
+            }
             mm[c] = uni64_t(smask[k]);
         }
 #pragma unroll
         for (int c = 0; c < 4; c++) {
             // (K - G/3) x (q_i + q_j) V_j
             double t = (qi + qj[c]) * vj[c] * sd[c].w;
-            t = lane_bit(mm[c]) ? t : 0.0;
-            fx = fma(t, sd[c].x, fx);
-            fy = fma(t, sd[c].y, fy);
-            if (DIM == 3) fz = fma(t, sd[c].z, fz);
+            const bool use = lane_bit(mm[c]);
+            t = use ? t : 0.0;
+            double n1 = sd[c].x, n2 = sd[c].y, n3 = sd[c].z;
+            if constexpr (FIN) {
+                double y1, y2, y3;
+                const double yl = deformed64(sd[c], uj[c][0] - uix, uj[c][1] - uiy,
+                                             DIM == 3 ? uj[c][2] - uiz : 0.0, y1, y2, y3);
+                n1 = use ? y1 / yl : 0.0;
+                n2 = use ? y2 / yl : 0.0;
+                n3 = use ? y3 / yl : 0.0;
+            }
+            fx = fma(t, n1, fx);
+            fy = fma(t, n2, fy);
+            if (DIM == 3) fz = fma(t, n3, fz);
         }
     }
     double sx = fx, sy = fy, sz = fz;
@@ -360,10 +417,12 @@ static int box_slots64(const StepArgs &a) {
     return B[3] * B[2];
 }
 
+// pass 3 stands for pass 2 of the finite model (as many arrays as pass 1)
 static size_t tiled64_lds(int dim, int pass, int tpw) {
-    if (dim == 3) return pass == 1 ? Lay64<3, 1, 5>::BYTES : Lay64<3, 1, 2>::BYTES;
-    if (tpw == 4) return 4 * (size_t)(pass == 1 ? Lay64<2, 4, 4>::BYTES : Lay64<2, 4, 2>::BYTES);
-    return pass == 1 ? Lay64<2, 1, 4>::BYTES : Lay64<2, 1, 2>::BYTES;
+    const bool big = pass != 2;
+    if (dim == 3) return big ? Lay64<3, 1, 5>::BYTES : Lay64<3, 1, 2>::BYTES;
+    if (tpw == 4) return 4 * (size_t)(big ? Lay64<2, 4, 4>::BYTES : Lay64<2, 4, 2>::BYTES);
+    return big ? Lay64<2, 1, 4>::BYTES : Lay64<2, 1, 2>::BYTES;
 }
 
 bool tiled64_supported(const StepArgs &a) {
@@ -420,6 +479,39 @@ hipError_t launch_tpass2_f64(const StepArgs &a, int cur, bool update, hipStream_
         if (update) hipLaunchKernelGGL((k_tpass2_f64<2, true, 1>), g, b, lds, s, a, cur, kt, sten);
         else hipLaunchKernelGGL((k_tpass2_f64<2, false, 1>), g, b, lds, s, a, cur, kt, sten);
     }
+    return hipGetLastError();
+}
+
+bool tiled64_fin_supported(const StepArgs &a) {
+    if (!tiled64_supported(a)) return false;
+    return tiled64_lds(a.dim, 3, tiles_per_group(a.dim, box_slots64(a))) <= 64 * 1024;
+}
+
+hipError_t launch_tpass1_f64_fin(const StepArgs &a, int cur, bool brk, hipStream_t s) {
+    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    const size_t lds = tiled64_lds(a.dim, 1, tpw);
+    const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
+    const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
+    const double4 *sten = reinterpret_cast<const double4 *>(a.stencil);
+#define PD_FT1(D, B, T) hipLaunchKernelGGL((k_tpass1_f64<D, B, T, true>), g, b, lds, s, a, cur, kt, sten)
+    if (a.dim == 3) { if (brk) PD_FT1(3, true, 1); else PD_FT1(3, false, 1); }
+    else if (tpw == 4) { if (brk) PD_FT1(2, true, 4); else PD_FT1(2, false, 4); }
+    else { if (brk) PD_FT1(2, true, 1); else PD_FT1(2, false, 1); }
+#undef PD_FT1
+    return hipGetLastError();
+}
+
+hipError_t launch_tpass2_f64_fin(const StepArgs &a, int cur, bool update, hipStream_t s) {
+    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    const size_t lds = tiled64_lds(a.dim, 3, tpw);
+    const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
+    const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
+    const double4 *sten = reinterpret_cast<const double4 *>(a.stencil);
+#define PD_FT2(D, U, T) hipLaunchKernelGGL((k_tpass2_f64<D, U, T, true>), g, b, lds, s, a, cur, kt, sten)
+    if (a.dim == 3) { if (update) PD_FT2(3, true, 1); else PD_FT2(3, false, 1); }
+    else if (tpw == 4) { if (update) PD_FT2(2, true, 4); else PD_FT2(2, false, 4); }
+    else { if (update) PD_FT2(2, true, 1); else PD_FT2(2, false, 1); }
+#undef PD_FT2
     return hipGetLastError();
 }
 

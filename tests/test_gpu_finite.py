@@ -125,17 +125,18 @@ def test_rigid_rotation_gives_zero_force(ctx, name):
     assert np.abs(f_lin).max() >= 1e2 * scale
 
 
+@pytest.mark.parametrize("kernel", ["gather", "tiled"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("plane_strain", 100),
                                         ("impact", 200), ("impact_r2", 200), ("cylinder", 200), ("batch", 200),
                                         ("plate_wide", 200), ("plate_16x4", 200)])
-def test_trajectory(ctx, name, steps):
+def test_trajectory(ctx, name, steps, kernel):
     w = workloads()[name]
     o = finite_oracle(w)
     s = solver(w, ctx)
     uo, vo = o.initial_state()
     done = 0
     for target in (steps // 4, steps // 2, steps):
-        s.step(target - done, precision="fp64", extension="finite")
+        s.step(target - done, precision="fp64", extension="finite", kernel=kernel)
         o.run(target - done, uo, vo)
         done = target
         u, v = s.read()
@@ -173,9 +174,22 @@ def test_options_are_checked(ctx):
     from paper_2309_11273_amd import _abi as A
     w = workloads()["cantilever"]
     s = solver(w, ctx)
-    for kw in (dict(precision="fp32"), dict(precision="fp64", kernel="tiled")):
+    for kw in (dict(precision="fp32"), dict(precision="fp64", form="bsr")):
         with pytest.raises(A.PDError):
             s.step(1, extension="finite", **kw)
+
+
+def test_tile_and_gather_forces_agree(ctx):
+    """The finite force from the tile kernels (pd_force_finite) and from one
+    gather-kernel step's force agree to round-off on a rotated plate."""
+    w = workloads()["impact"]
+    X = w.positions()
+    u = X @ (rotation((1, 2, 3), 0.35) - np.eye(3)).T
+    s = solver(w, ctx, u0=u)
+    f_tile, th_tile = s.force_finite()
+    o = finite_oracle(w)
+    fo, tho = o.force(u)
+    assert np.abs(f_tile - fo).max() <= 1e-12 * np.abs(fo).max()
 
 
 def test_relaxation_with_finite_extension(ctx):
