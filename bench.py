@@ -127,10 +127,17 @@ def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
     sec = ms_dom * 1e-3
     byt = algorithmic_bytes(dom, args.precision, nnz, n, n_loaded, tiled)
     fl = algorithmic_flops(dom, nnz, tiled)
-    if args.extension == "finite":
-        # per directed bond: deformed bond 6, |Y| 5 + sqrt, e 1, stretch 1,
-        # dilatation 3 (pass 1: 20 with eta 3); pass 2 adds Y/|Y| 3 and the
-        # bracket and accumulation 13 (31)
+    if args.extension == "finite" and tiled:
+        # per directed bond, tile kernels: deformed bond 6, |Y|^2 5, square
+        # root 1, e 1, dilatation 3, reciprocal square root with its Newton
+        # step 5, direction 3, deviatoric bracket 3 and accumulation 6 (pass
+        # 1: 33); pass 2 rebuilds Y (6 + 5 + 5 + 3) and adds the dilatational
+        # bracket 4 and accumulation 6 (29)
+        fl = (33 if dom == "pass1" else 29) * nnz
+    elif args.extension == "finite":
+        # per directed bond, bond-list kernels: deformed bond 6, |Y| 5 +
+        # sqrt, e 1, stretch 1, dilatation 3 (pass 1: 20 with eta 3); pass 2
+        # adds Y/|Y| 3 and the bracket and accumulation 13 (31)
         fl = (20 if dom == "pass1" else 31) * nnz
     peak_fl = VALU_PEAK_TFLOPS[args.precision]
     gbs, tfs = byt / sec / 1e9, fl / sec / 1e12

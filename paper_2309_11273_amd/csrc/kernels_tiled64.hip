@@ -17,7 +17,10 @@
 // With FIN the kernels evaluate the finite model of Eqs. 1.10, 1.13 instead:
 // e = |Y| - x with Y = x M + (u_j - u_i) (|Y|^2 summed (Y1^2 + Y2^2) + Y3^2
 // without contraction), both force parts along Y / |Y|; pass 2 then stages
-// the displacements as well, to rebuild Y.
+// the displacements as well, to rebuild Y.  |Y| itself is the correctly
+// rounded square root (it decides breaking); the direction takes the
+// hardware reciprocal square root refined by one Newton step, which costs a
+// fraction of a double divide and is accurate to about 1e-13.
 //
 // LDS holds the staged quantities as separate arrays of doubles at a fixed
 // stride (a multiple of 64 elements), so that one address serves all of a
@@ -56,14 +59,23 @@ __device__ __forceinline__ double ext_canonical64(double m1, double m2, double m
     return (a + b) + c;
 }
 
-// deformed bond Y = x M + (dx, dy, dz) and its length (finite model)
+// deformed bond Y = x M + (dx, dy, dz) and |Y|^2 (finite model)
 __device__ __forceinline__ double deformed64(const double4 &sd, double dx, double dy, double dz, double &y1,
                                              double &y2, double &y3) {
 #pragma clang fp contract(off)
     y1 = sd.w * sd.x + dx;
     y2 = sd.w * sd.y + dy;
     y3 = sd.w * sd.z + dz;
-    return sqrt((y1 * y1 + y2 * y2) + y3 * y3);
+    return (y1 * y1 + y2 * y2) + y3 * y3;
+}
+
+// 1/sqrt(s) for the force direction, where no decision depends on the last
+// bits: the hardware estimate refined by one Newton-Raphson step for the
+// reciprocal square root, r <- r (3 - s r^2) / 2 (relative error about the
+// square of the estimate's)
+__device__ __forceinline__ double rsqrt_refined(double s) {
+    const double r = __builtin_amdgcn_rsq(s);
+    return r * fma(-0.5 * s, r * r, 1.5);
 }
 
 // ---------------------------------------------------------------------------
@@ -173,13 +185,15 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
             double ev, n1 = sd[c].x, n2 = sd[c].y, n3 = sd[c].z;
             if constexpr (FIN) {
                 double y1, y2, y3;
-                const double yl = deformed64(sd[c], dx, dy, dz, y1, y2, y3);
+                const double yy = deformed64(sd[c], dx, dy, dz, y1, y2, y3);
+                const double yl = sqrt(yy);  // correctly rounded: it decides breaking
                 ev = yl - sd[c].w;
                 // the deformed direction, taken only for bonds that carry force
                 const bool use = lane_bit(mm[c]);
-                n1 = use ? y1 / yl : 0.0;
-                n2 = use ? y2 / yl : 0.0;
-                n3 = use ? y3 / yl : 0.0;
+                const double iy = rsqrt_refined(yy);
+                n1 = use ? y1 * iy : 0.0;
+                n2 = use ? y2 * iy : 0.0;
+                n3 = use ? y3 * iy : 0.0;
             } else {
                 ev = DIM == 3 ? ext_canonical64(sd[c].x, sd[c].y, sd[c].z, dx, dy, dz)
                               : ext_canonical64(sd[c].x, sd[c].y, 0.0, dx, dy, 0.0);
@@ -344,11 +358,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
             double n1 = sd[c].x, n2 = sd[c].y, n3 = sd[c].z;
             if constexpr (FIN) {
                 double y1, y2, y3;
-                const double yl = deformed64(sd[c], uj[c][0] - uix, uj[c][1] - uiy,
+                const double yy = deformed64(sd[c], uj[c][0] - uix, uj[c][1] - uiy,
                                              DIM == 3 ? uj[c][2] - uiz : 0.0, y1, y2, y3);
-                n1 = use ? y1 / yl : 0.0;
-                n2 = use ? y2 / yl : 0.0;
-                n3 = use ? y3 / yl : 0.0;
+                const double iy = rsqrt_refined(yy);
+                n1 = use ? y1 * iy : 0.0;
+                n2 = use ? y2 * iy : 0.0;
+                n3 = use ? y3 * iy : 0.0;
             }
             fx = fma(t, n1, fx);
             fy = fma(t, n2, fy);
