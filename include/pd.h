@@ -601,11 +601,14 @@ pd_status pd_adr_step(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st,
                       const pd_step_opts *opts, pd_adr_dev *R, pd_step_report *rep);
 
 /* ------------------------------------------------------------------------ */
-/* static solve with the block-sparse stiffness (Eq. 2.14)                  */
+/* static solve and implicit step with the block-sparse stiffness (Eq. 2.14) */
 /* ------------------------------------------------------------------------ */
 
-/* The paper notes that the global stiffness of Eq. 2.14 is too wide for a
- * direct implicit solve and suggests an iterative one.  pd_static_solve
+/* Remark 1 (Sec. 3.3) notes that the band of the global stiffness of
+ * Eq. 2.14 is wide, which makes an implicit solve costly in memory and time
+ * (it turns to coupling with finite elements instead).  Here K stays in the
+ * block-sparse form and is only multiplied: no factorisation, no fill-in.
+ * pd_static_solve
  * finds static equilibrium f(u) + F_ext = 0 by preconditioned conjugate
  * gradients (block Jacobi) on the free components: from the current u0 of
  * st (prescribed components held), K_ff du = F_ext + f(u0) with
@@ -633,6 +636,43 @@ int64_t pd_static_workspace(int64_t n_pad);
  * (non-finite solution), PD_ERR_HIP. */
 pd_status pd_static_solve(pd_ctx *ctx, const pd_problem_dev *prob, const struct pd_bsr_dev *K, pd_state_dev *st,
                           const pd_cg_opts *opts, double *work, pd_cg_report *rep);
+
+/* Implicit dynamics with the assembled double K: nsteps steps of the
+ * average-acceleration Newmark rule (beta = 1/4, gamma = 1/2, unconditionally
+ * stable for the linear model), the implicit counterpart of the explicit
+ * update of Eq. 2.11 whose cost Remark 1 (Sec. 3.3) weighs, solved
+ * iteratively as above.  Lumped mass m_i = rho V_i.  Per step, from (u_n, v_n) in st:
+ *   with opts->breaking = 1, the critical-stretch test of Eqs. 1.17, 1.30 at
+ *   u_n marks broken bonds in prob->mask and K is re-assembled around them;
+ *   a_n = (F_ext + f(u_n)) / m on the free components;
+ *   u* = u_n with the prescribed components advanced by dt v_n;
+ *   (K_ff + 4/dt^2 M) du = F_ext + f(u*) + M (4 v_n / dt + a_n) on the free
+ *   components, by the block-Jacobi preconditioned CG of pd_static_solve
+ *   (opts->cg; |r| <= tol |r0| per step);
+ *   u_{n+1} = u* + du, v_{n+1} = v_n + dt/2 (a_n + a_{n+1}) with
+ *   a_{n+1} = 4/dt^2 (du - dt v_n) - a_n on the free components (prescribed
+ *   velocities kept).
+ * The full external load is used (no ramp); st->cur flips every step.
+ * work [device] pd_newmark_workspace(n_pad) doubles, 32-byte aligned, owned
+ * by the caller, no state kept in it between calls.  rep (may be NULL):
+ * iterations summed over the steps, converged = 1 if every step met the
+ * tolerance, rel_residual the largest final one.  Synchronises every
+ * opts->cg.check_every iterations.  Errors: PD_ERR_ARG (NULL pointers,
+ * dt <= 0, bad options, nsteps < 0), PD_ERR_STATE (K not assembled),
+ * PD_ERR_UNSUPPORTED (K stores float values), PD_ERR_UNSTABLE (non-finite
+ * residual), PD_ERR_HIP. */
+typedef struct pd_newmark_opts {
+    double dt;             /* time step (> 0)                                          */
+    pd_cg_opts cg;         /* solver of each step                                      */
+    int32_t breaking;      /* 1: breaking test and re-assembly at the start of a step  */
+    int32_t reserved;      /* 0                                                        */
+} pd_newmark_opts;
+
+/* Doubles of device workspace pd_newmark_step needs for n_pad rows. */
+int64_t pd_newmark_workspace(int64_t n_pad);
+
+pd_status pd_newmark_step(pd_ctx *ctx, const pd_problem_dev *prob, const struct pd_bsr_dev *K, pd_state_dev *st,
+                          int32_t nsteps, const pd_newmark_opts *opts, double *work, pd_cg_report *rep);
 
 /* ------------------------------------------------------------------------ */
 /* outputs                                                                  */

@@ -228,3 +228,56 @@ def static_solution(w, o, u0=None, rho_bond=None):
     Kff = (-L)[free][:, free].tocsc()
     u[free] += spla.spsolve(Kff, b[free])
     return u.reshape(w.n, 3)
+
+
+def newmark_run(w, o, u, v, dt, nsteps, rho_bond=None, breaking=False):
+    """Implicit dynamics by the average-acceleration Newmark rule (beta = 1/4,
+    gamma = 1/2) with the lumped mass rho V and the stiffness of Eq. 2.14.
+    Per step, from (u_n, v_n):
+
+    * with ``breaking``, the critical-stretch test of Eqs. 1.17, 1.30 at u_n
+      (linearized extension (M1 eta1 + M2 eta2) + M3 eta3 over x >= s_c)
+      takes broken bonds out of the operator;
+    * a_n from the equation of motion M a_n = F_ext + F_int(u_n) on the free
+      components;
+    * u* = u_n with the prescribed components advanced by dt v_n;
+    * a direct sparse solve of (K_ff + 4/dt^2 M_ff) du_f =
+      F_ext + F_int(u*) + M (4 v_n / dt + a_n) on the free components;
+    * u_{n+1} = u* + du, a_{n+1} = 4/dt^2 (du - dt v_n) - a_n and
+      v_{n+1} = v_n + dt/2 (a_n + a_{n+1}) on the free components.
+
+    Returns (u, v, rho_bond); u and v are n x 3."""
+    import scipy.sparse as sparse
+    import scipy.sparse.linalg as spla
+
+    u = np.asarray(u, dtype=np.float64).reshape(-1).copy()
+    v = np.asarray(v, dtype=np.float64).reshape(-1).copy()
+    rho = (o.rho() if rho_bond is None else np.asarray(rho_bond)).astype(np.float64).copy()
+    free = free_dofs(w)
+    pres = np.array([3 * p + c for p in range(w.n) for c in range(w.dim) if (int(w.bc[p]) >> c) & 1],
+                    dtype=np.int64)
+    mass = mass_vector(w)
+    F = np.asarray(w.fext, dtype=np.float64).reshape(-1)
+    k = 4.0 / (dt * dt)
+    bi, bj = o.bonds()
+    x, M = o.bond_geom()
+    s0 = np.asarray(o.s0)[np.asarray(w.specimen)[bi]]
+    for _ in range(nsteps):
+        if breaking:
+            U = u.reshape(-1, 3)
+            eta = U[bj] - U[bi]
+            e = (M[:, 0] * eta[:, 0] + M[:, 1] * eta[:, 1]) + M[:, 2] * eta[:, 2]
+            rho[(rho > 0) & (e / x >= s0)] = 0.0
+        L = sparse_operator(w, o, rho)
+        a = np.zeros_like(u)
+        a[free] = (F + L @ u)[free] / mass[free]
+        us = u.copy()
+        us[pres] += dt * v[pres]
+        b = F + L @ us + mass * (4.0 / dt * v + a)
+        Aff = ((-L) + sparse.diags(k * mass))[free][:, free].tocsc()
+        du = spla.spsolve(Aff, b[free])
+        u = us
+        u[free] += du
+        a_new = k * (du - dt * v[free]) - a[free]
+        v[free] = v[free] + 0.5 * dt * (a[free] + a_new)
+    return u.reshape(w.n, 3), v.reshape(w.n, 3), rho

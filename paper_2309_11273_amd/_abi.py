@@ -111,6 +111,10 @@ class pd_cg_report(C.Structure):
     _fields_ = [("iterations", i32), ("converged", i32), ("rel_residual", dbl)]
 
 
+class pd_newmark_opts(C.Structure):
+    _fields_ = [("dt", dbl), ("cg", pd_cg_opts), ("breaking", i32), ("reserved", i32)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "pd_version": (C.c_char_p, []),
@@ -148,6 +152,9 @@ SIGNATURES = {
     "pd_adr_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i64,
                           C.POINTER(pd_step_opts), C.POINTER(pd_adr_dev), C.POINTER(pd_step_report)]),
     "pd_static_workspace": (i64, [i64]),
+    "pd_newmark_workspace": (i64, [i64]),
+    "pd_newmark_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_bsr_dev), C.POINTER(pd_state_dev), i32,
+                              C.POINTER(pd_newmark_opts), P, C.POINTER(pd_cg_report)]),
     "pd_static_solve": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_bsr_dev), C.POINTER(pd_state_dev),
                               C.POINTER(pd_cg_opts), P, C.POINTER(pd_cg_report)]),
     "pd_damage": (i32, [P, C.POINTER(pd_problem_dev), P, P]),

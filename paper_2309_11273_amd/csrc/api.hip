@@ -736,7 +736,7 @@ pd_status pd_static_solve(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
     conv = h[4] == 0.0;  // zero residual: u0 is already in equilibrium
     while (!conv && it < o->max_iter) {
         const int chunk = std::min(o->check_every, o->max_iter - it);
-        for (int k = 0; k < chunk; k++) HIP_TRY(c, pdk::launch_cg_iteration(a, K, work, c->stream));
+        for (int k = 0; k < chunk; k++) HIP_TRY(c, pdk::launch_cg_iteration(a, K, work, 0.0, c->stream));
         it += chunk;
         HIP_TRY(c, hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -748,6 +748,67 @@ pd_status pd_static_solve(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
         rep->iterations = (int32_t)h[6];
         rep->converged = conv ? 1 : 0;
         rep->rel_residual = h[5];
+    }
+    return PD_OK;
+}
+
+int64_t pd_newmark_workspace(int64_t n_pad) { return n_pad < 0 ? -1 : pdk::nm_workspace_doubles(n_pad); }
+
+pd_status pd_newmark_step(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *K, pd_state_dev *st, int32_t nsteps,
+                          const pd_newmark_opts *o, double *work, pd_cg_report *rep) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_bsr(c, p, K)) != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!K->assembled) return fail(c, PD_ERR_STATE, "K is not assembled");
+    if (K->fp32) return fail(c, PD_ERR_UNSUPPORTED, "the implicit step needs K in double");
+    if (!o || !work) return fail(c, PD_ERR_ARG, "NULL options or workspace");
+    if (nsteps < 0) return fail(c, PD_ERR_ARG, "nsteps < 0");
+    if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(c, PD_ERR_ARG, "dt must be positive and finite");
+    if (!(o->cg.tol > 0.0) || o->cg.max_iter <= 0 || o->cg.check_every <= 0)
+        return fail(c, PD_ERR_ARG, "bad solver options");
+    if (o->breaking != 0 && o->breaking != 1) return fail(c, PD_ERR_ARG, "breaking must be 0 or 1");
+    if (reinterpret_cast<uintptr_t>(work) % 32 != 0) return fail(c, PD_ERR_ARG, "workspace must be 32-byte aligned");
+    if (!p->aux || !p->fext) return fail(c, PD_ERR_ARG, "aux/fext are NULL (call pd_state_init first)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const double *scal = pdk::cg_scalars(work, p->n_pad);
+    int total = 0;
+    bool all_conv = true;
+    double worst = 0.0;
+    for (int n = 0; n < nsteps; n++) {
+        pdk::StepArgs a = make_args(p, st);
+        const int cur = st->cur;
+        if (o->breaking) {
+            // critical stretch at u_n, then K re-assembled around new breaks
+            HIP_TRY(c, pdk::launch_break_mark(a, p, K, cur, c->stream));
+            HIP_TRY(c, pdk::launch_bsr_prep_assemble(a, p, K, false, cur, c->stream));
+        }
+        HIP_TRY(c, pdk::launch_nm_start(a, K, work, o->dt, cur, c->stream));
+        double h[8] = {0};
+        int it = 0;
+        HIP_TRY(c, hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        bool conv = h[4] == 0.0;
+        while (!conv && it < o->cg.max_iter) {
+            const int chunk = std::min(o->cg.check_every, o->cg.max_iter - it);
+            for (int k = 0; k < chunk; k++) HIP_TRY(c, pdk::launch_cg_iteration(a, K, work, o->dt, c->stream));
+            it += chunk;
+            HIP_TRY(c, hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (!std::isfinite(h[5])) return fail(c, PD_ERR_UNSTABLE, "non-finite residual in the implicit step");
+            conv = h[5] <= o->cg.tol;
+        }
+        HIP_TRY(c, pdk::launch_nm_finish(a, K, work, o->dt, cur, c->stream));
+        st->cur = cur ^ 1;
+        total += (int)h[6];
+        all_conv = all_conv && conv;
+        worst = std::max(worst, conv && h[4] == 0.0 ? 0.0 : h[5]);
+    }
+    if (rep) {
+        rep->iterations = total;
+        rep->converged = all_conv ? 1 : 0;
+        rep->rel_residual = worst;
     }
     return PD_OK;
 }

@@ -15,6 +15,20 @@
 // z = P D^-1 P r with the r.z and r.r sums; beta; p = z + beta p.  Sums are
 // per-workgroup partials (a fixed tree) added in a fixed order by one
 // workgroup, so a solve gives the same bits on every run.
+//
+// Implicit dynamics (the counterpart of the explicit update of Eq. 2.11,
+// whose cost with the wide-band K Remark 1 of Sec. 3.3 weighs): the
+// average-acceleration Newmark rule (beta = 1/4, gamma = 1/2) with the lumped
+// mass m_i = rho V_i.  One step from (u_n, v_n):
+//   a_n = M^-1 (F_ext + f(u_n))               on the free components,
+//   u*  = u_n, prescribed components advanced by dt v_n,
+//   (K_ff + (4/dt^2) M) du_f = F_ext + f(u*) + M (4 v_n / dt + a_n)   (free),
+//   u_{n+1} = u* + du,  a_{n+1} = (4/dt^2)(du - dt v_n) - a_n,
+//   v_{n+1} = v_n + dt/2 (a_n + a_{n+1})      on the free components.
+// The solve is the same preconditioned CG with the mass term added to the
+// operator and to the block-Jacobi diagonal.  a_n is taken from the equation
+// of motion at the start of each step (it equals the previous step's a_{n+1}
+// when that solve converged and no bond broke).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,6 +47,11 @@ struct CgArgs {
     double *dinv;  // 12 per row: the 3x3 inverse (row-major), 3 unused
     double *partial;
     double *scal;  // rz, alpha, beta, rr, rr0, rel, iterations
+    // implicit dynamics: lumped mass per row (nullptr for the static solve),
+    // the operator's mass factor 4/dt^2, a_n per row
+    double *mass;
+    double shift;
+    double4 *acc;
 };
 
 __device__ __forceinline__ double block_sum256(double v, double *sh) {
@@ -86,19 +105,30 @@ __device__ __forceinline__ double4 precondition(const double *Di, double4 r, uin
 
 }  // namespace
 
-// D_i = sum_q Kt_iq and its inverse (identity where D_i is singular, e.g.
-// padding rows); one thread per row
+// D_i = sum_q Kt_iq (plus the Newmark mass term) and its inverse (identity
+// where D_i is singular, e.g. padding rows); one wave per row, the lanes
+// striding over the row's blocks like the block product
 template <int DIM>
 __global__ __launch_bounds__(256) void k_cg_dinv(StepArgs a, CgArgs c) {
     constexpr int NV = DIM * DIM;
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= a.n_pad) return;
+    const int lane = threadIdx.x & 63;
     double D[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t rp0 = c.row_ptr[row], nblk = c.row_ptr[row + 1] - rp0;
-    for (int64_t t = 0; t < nblk; t++) {
+    for (int64_t t = lane; t < nblk; t += 64) {
         const double *K = c.vals + (size_t)rp0 * NV + t;
         for (int i = 0; i < DIM; i++)
             for (int j = 0; j < DIM; j++) D[3 * i + j] += K[(i * DIM + j) * nblk];
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int k = 0; k < 9; k++) D[k] += __shfl_xor(D[k], o);
+    if (lane != 0) return;
+    if (c.mass) {
+        const double sm = c.shift * c.mass[row];
+        D[0] += sm;
+        D[4] += sm;
+        D[8] += sm;
     }
     if (DIM == 2) D[8] = 1.0;
     const double c00 = D[4] * D[8] - D[5] * D[7], c01 = D[5] * D[6] - D[3] * D[8], c02 = D[3] * D[7] - D[4] * D[6];
@@ -143,7 +173,8 @@ __global__ __launch_bounds__(256) void k_cg_residual(StepArgs a, CgArgs c, int c
     c.r[row] = masked(r, aux);
 }
 
-// q = K p = -(difference product of p) on the free components
+// q = K p = -(difference product of p) on the free components, plus
+// (4/dt^2) M p for implicit dynamics
 template <int DIM>
 __global__ __launch_bounds__(256) void k_cg_matvec(StepArgs a, CgArgs c) {
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -151,7 +182,99 @@ __global__ __launch_bounds__(256) void k_cg_matvec(StepArgs a, CgArgs c) {
     double f[3];
     row_product<DIM>(c, row, c.p, f);
     if ((threadIdx.x & 63) != 0) return;
-    c.q[row] = masked(make_double4(-f[0], -f[1], -f[2], 0.0), a.aux[row]);
+    double4 q = make_double4(-f[0], -f[1], -f[2], 0.0);
+    if (c.mass) {
+        const double sm = c.shift * c.mass[row];
+        const double4 pr = c.p[row];
+        q.x += sm * pr.x;
+        q.y += sm * pr.y;
+        q.z += sm * pr.z;
+    }
+    c.q[row] = masked(q, a.aux[row]);
+}
+
+// Newmark start: m_i = rho V_i and a_n = (F_ext + f(u_n)) / m_i on the free
+// components (zero for padding rows, whose mass is zero)
+template <int DIM>
+__global__ __launch_bounds__(256) void k_nm_accel(StepArgs a, CgArgs c, int cur) {
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= a.n_pad) return;
+    double f[3];
+    row_product<DIM>(c, row, a.uv[cur], f);
+    if ((threadIdx.x & 63) != 0) return;
+    const uint32_t aux = a.aux[row];
+    const double m = a.spec[aux >> 8].rho * a.uv[cur][row].w;
+    double4 g = make_double4(f[0], f[1], f[2], 0.0);
+    if (aux & 8u) {
+        const double4 fe = a.fext[row];
+        g.x += fe.x;
+        g.y += fe.y;
+        g.z += fe.z;
+    }
+    const double im = m > 0.0 ? 1.0 / m : 0.0;
+    c.mass[row] = m;
+    c.acc[row] = masked(make_double4(g.x * im, g.y * im, g.z * im, 0.0), aux);
+}
+
+// u* = u_n with the prescribed components advanced by dt v_n, into the other
+// displacement buffer
+__global__ __launch_bounds__(256) void k_nm_predict(StepArgs a, double dt, int cur) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= a.n_pad) return;
+    if (row == 0) a.ctl->s1 = a.ctl->s2;
+    const uint32_t aux = a.aux[row];
+    double4 u = a.uv[cur][row];
+    const double4 v = a.vel[row];
+    if (aux & 1u) u.x += dt * v.x;
+    if (aux & 2u) u.y += dt * v.y;
+    if (aux & 4u) u.z += dt * v.z;
+    a.uv[cur ^ 1][row] = u;
+}
+
+// right-hand side F_ext + f(u*) + M (4 v_n / dt + a_n) on the free components
+template <int DIM>
+__global__ __launch_bounds__(256) void k_nm_rhs(StepArgs a, CgArgs c, double dt, int cur) {
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= a.n_pad) return;
+    double f[3];
+    row_product<DIM>(c, row, a.uv[cur ^ 1], f);
+    if ((threadIdx.x & 63) != 0) return;
+    const uint32_t aux = a.aux[row];
+    const double m = c.mass[row];
+    const double4 v = a.vel[row], an = c.acc[row];
+    const double k4 = 4.0 / dt;
+    double4 r = make_double4(f[0] + m * (k4 * v.x + an.x), f[1] + m * (k4 * v.y + an.y),
+                             f[2] + m * (k4 * v.z + an.z), 0.0);
+    if (aux & 8u) {
+        const double4 fe = a.fext[row];
+        r.x += fe.x;
+        r.y += fe.y;
+        r.z += fe.z;
+    }
+    c.r[row] = masked(r, aux);
+}
+
+// u_{n+1} = u* + du, a_{n+1} and v_{n+1} on the free components; the
+// prescribed velocities are kept
+__global__ __launch_bounds__(256) void k_nm_finish(StepArgs a, CgArgs c, double dt, int cur) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= a.n_pad) return;
+    if (row == 0) a.ctl->s2 = a.ctl->s1 + 1;
+    const uint32_t aux = a.aux[row];
+    const double4 du = c.x[row], an = c.acc[row];
+    double4 u = a.uv[cur ^ 1][row];
+    u.x += du.x;
+    u.y += du.y;
+    u.z += du.z;
+    a.uv[cur ^ 1][row] = u;
+    double4 v = a.vel[row];
+    const double h = 0.5 * dt;
+    if (!(aux & 1u)) v.x += h * (an.x + (c.shift * (du.x - dt * v.x) - an.x));
+    if (!(aux & 2u)) v.y += h * (an.y + (c.shift * (du.y - dt * v.y) - an.y));
+    if (!(aux & 4u)) v.z += h * (an.z + (c.shift * (du.z - dt * v.z) - an.z));
+    a.vel[row] = v;
+    if (!(isfinite(u.x) && isfinite(u.y) && isfinite(u.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z)))
+        atomicOr(&a.ctl->flags, PD_CTL_NONFINITE);
 }
 
 // mode 0 (start): x = 0, z = M r, p = z, sums r.z and r.r
@@ -259,7 +382,15 @@ int64_t cg_workspace_doubles(int64_t n_pad) {
     return 5 * 4 * n_pad + 12 * n_pad + 2 * nb + 16;
 }
 
-static CgArgs cg_args(const pd_bsr_dev *K, double *work, int64_t n_pad) {
+// the Newmark arrays start at a 32-byte boundary after the solver's (a_n is
+// read as double4)
+static int64_t nm_base(int64_t n_pad) { return (cg_workspace_doubles(n_pad) + 3) & ~int64_t(3); }
+
+int64_t nm_workspace_doubles(int64_t n_pad) { return nm_base(n_pad) + 5 * n_pad; }
+
+// dt > 0: the Newmark operator K + (4/dt^2) M, with a_n and the mass after
+// the solver's arrays
+static CgArgs cg_args(const pd_bsr_dev *K, double *work, int64_t n_pad, double dt = 0.0) {
     CgArgs c{};
     c.row_ptr = K->row_ptr;
     c.col = K->col;
@@ -280,6 +411,12 @@ static CgArgs cg_args(const pd_bsr_dev *K, double *work, int64_t n_pad) {
     c.partial = w;
     w += 2 * ((n_pad + 255) / 256);
     c.scal = w;
+    if (dt > 0.0) {
+        double *e = work + nm_base(n_pad);
+        c.acc = reinterpret_cast<double4 *>(e);
+        c.mass = e + 4 * n_pad;
+        c.shift = 4.0 / (dt * dt);
+    }
     return c;
 }
 
@@ -287,10 +424,10 @@ hipError_t launch_cg_start(const StepArgs &a, const pd_bsr_dev *K, double *work,
     const CgArgs c = cg_args(K, work, a.n_pad);
     const unsigned nrow = (unsigned)((a.n_pad + 255) / 256), nwave = (unsigned)((a.n_pad + 3) / 4);
     if (a.dim == 3) {
-        hipLaunchKernelGGL((k_cg_dinv<3>), dim3(nrow), dim3(256), 0, s, a, c);
+        hipLaunchKernelGGL((k_cg_dinv<3>), dim3(nwave), dim3(256), 0, s, a, c);
         hipLaunchKernelGGL((k_cg_residual<3>), dim3(nwave), dim3(256), 0, s, a, c, cur);
     } else {
-        hipLaunchKernelGGL((k_cg_dinv<2>), dim3(nrow), dim3(256), 0, s, a, c);
+        hipLaunchKernelGGL((k_cg_dinv<2>), dim3(nwave), dim3(256), 0, s, a, c);
         hipLaunchKernelGGL((k_cg_residual<2>), dim3(nwave), dim3(256), 0, s, a, c, cur);
     }
     hipLaunchKernelGGL(k_cg_vec, dim3(nrow), dim3(256), 0, s, a, c, 0);
@@ -298,8 +435,34 @@ hipError_t launch_cg_start(const StepArgs &a, const pd_bsr_dev *K, double *work,
     return hipGetLastError();
 }
 
-hipError_t launch_cg_iteration(const StepArgs &a, const pd_bsr_dev *K, double *work, hipStream_t s) {
-    const CgArgs c = cg_args(K, work, a.n_pad);
+hipError_t launch_nm_start(const StepArgs &a, const pd_bsr_dev *K, double *work, double dt, int cur,
+                           hipStream_t s) {
+    const CgArgs c = cg_args(K, work, a.n_pad, dt);
+    const unsigned nrow = (unsigned)((a.n_pad + 255) / 256), nwave = (unsigned)((a.n_pad + 3) / 4);
+    if (a.dim == 3) hipLaunchKernelGGL((k_nm_accel<3>), dim3(nwave), dim3(256), 0, s, a, c, cur);
+    else hipLaunchKernelGGL((k_nm_accel<2>), dim3(nwave), dim3(256), 0, s, a, c, cur);
+    hipLaunchKernelGGL(k_nm_predict, dim3(nrow), dim3(256), 0, s, a, dt, cur);
+    if (a.dim == 3) {
+        hipLaunchKernelGGL((k_nm_rhs<3>), dim3(nwave), dim3(256), 0, s, a, c, dt, cur);
+        hipLaunchKernelGGL((k_cg_dinv<3>), dim3(nwave), dim3(256), 0, s, a, c);
+    } else {
+        hipLaunchKernelGGL((k_nm_rhs<2>), dim3(nwave), dim3(256), 0, s, a, c, dt, cur);
+        hipLaunchKernelGGL((k_cg_dinv<2>), dim3(nwave), dim3(256), 0, s, a, c);
+    }
+    hipLaunchKernelGGL(k_cg_vec, dim3(nrow), dim3(256), 0, s, a, c, 0);
+    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(256), 0, s, c, (int)nrow, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_nm_finish(const StepArgs &a, const pd_bsr_dev *K, double *work, double dt, int cur,
+                            hipStream_t s) {
+    const CgArgs c = cg_args(K, work, a.n_pad, dt);
+    hipLaunchKernelGGL(k_nm_finish, dim3((unsigned)((a.n_pad + 255) / 256)), dim3(256), 0, s, a, c, dt, cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_iteration(const StepArgs &a, const pd_bsr_dev *K, double *work, double dt, hipStream_t s) {
+    const CgArgs c = cg_args(K, work, a.n_pad, dt);
     const unsigned nrow = (unsigned)((a.n_pad + 255) / 256), nwave = (unsigned)((a.n_pad + 3) / 4);
     if (a.dim == 3) hipLaunchKernelGGL((k_cg_matvec<3>), dim3(nwave), dim3(256), 0, s, a, c);
     else hipLaunchKernelGGL((k_cg_matvec<2>), dim3(nwave), dim3(256), 0, s, a, c);

@@ -471,6 +471,22 @@ class Solver:
                                                               C.byref(rep)))
         return dict(iterations=rep.iterations, converged=bool(rep.converged), rel_residual=rep.rel_residual)
 
+    def newmark_step(self, nsteps: int, dt: float, breaking: bool = False, tol: float = 1e-12,
+                     max_iter: int = 20000, check_every: int = 50) -> dict:
+        """nsteps implicit average-acceleration Newmark steps with the
+        assembled double K (pd_newmark_step); the state advances in place."""
+        L = A.load()
+        nw = int(L.pd_newmark_workspace(self.n_pad))
+        if getattr(self, "_nm_work", None) is None or self._nm_work.numel() < nw:
+            self._nm_work = torch.zeros(nw, dtype=torch.float64, device=self.dev)
+        o = A.pd_newmark_opts(float(dt), A.pd_cg_opts(float(tol), int(max_iter), int(check_every)),
+                              1 if breaking else 0, 0)
+        rep = A.pd_cg_report()
+        self.ctx.check("pd_newmark_step", L.pd_newmark_step(self.ctx.h, C.byref(self.P), C.byref(self.K),
+                                                              C.byref(self.S), int(nsteps), C.byref(o),
+                                                              _tp(self._nm_work), C.byref(rep)))
+        return dict(iterations=rep.iterations, converged=bool(rep.converged), rel_residual=rep.rel_residual)
+
     def bsr_apply(self):
         f = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=self.dev)
         self.ctx.check("pd_bsr_apply", A.load().pd_bsr_apply(self.ctx.h, C.byref(self.P), C.byref(self.K),

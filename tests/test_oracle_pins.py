@@ -818,3 +818,99 @@ def test_notch_cuts_match_sampled_crossings(case):
         assert len(mism) <= 0.03 * cut_o.sum()
     else:
         assert not mism, mism[:10]
+
+
+# ---------------------------------------------------------------------------
+# implicit dynamics (average-acceleration Newmark) with the stiffness of Eq. 2.14
+# ---------------------------------------------------------------------------
+
+def _unloaded(w):
+    import copy
+    w2 = copy.copy(w)
+    w2.fext = np.zeros_like(np.asarray(w.fext, dtype=np.float64))
+    return w2
+
+
+def test_newmark_follows_the_discrete_rotation_of_every_mode():
+    """For M a + K u = 0 the average-acceleration rule turns each mode by the
+    angle theta = 2 atan(omega dt / 2) per step (its amplification matrix has
+    eigenvalues exp(+-i theta)): from u_0 = phi and v_0 = 0 it gives
+    cos(n theta) phi, from u_0 = 0 and v_0 = phi it gives sin(n theta) / omega
+    phi.  The modes come from the generalised eigenproblem (K_ff, M_ff);
+    dt is 40x the explicit limit, so theta is far from omega dt."""
+    import scipy.linalg as sla
+    w = _unloaded(W.cantilever3d())
+    o = Oracle(w)
+    rho = o.rho()
+    L = dense.sparse_operator(w, o, rho).toarray()
+    free = dense.free_dofs(w)
+    mass = dense.mass_vector(w)
+    K = -L[np.ix_(free, free)]
+    lam, Phi = sla.eigh(K, np.diag(mass[free]))
+    om = np.sqrt(np.maximum(lam, 0.0))
+    dt = 40 * 2.0 / om.max()
+    theta = 2.0 * np.arctan(om * dt / 2.0)
+    rng = np.random.default_rng(11)
+    u0 = np.zeros(3 * w.n)
+    v0 = np.zeros(3 * w.n)
+    u0[free] = rng.standard_normal(free.size) * 1e-6
+    v0[free] = rng.standard_normal(free.size) * 1e-3
+    c = Phi.T @ (mass[free] * u0[free])
+    d = Phi.T @ (mass[free] * v0[free])
+    n = 7
+    u, v, _ = dense.newmark_run(w, o, u0.reshape(-1, 3), v0.reshape(-1, 3), dt, n, rho_bond=rho)
+    exact = Phi @ (np.cos(n * theta) * c + np.sin(n * theta) / om * d)
+    got = u.reshape(-1)[free]
+    assert np.linalg.norm(got - exact) <= 1e-9 * np.linalg.norm(exact)
+    # a plain-trapezoid mistake (theta = omega dt) would be far off
+    wrong = Phi @ (np.cos(n * om * dt) * c + np.sin(n * om * dt) / om * d)
+    assert np.linalg.norm(wrong - exact) > 1e-2 * np.linalg.norm(exact)
+
+
+def test_newmark_conserves_energy_and_holds_static_equilibrium():
+    """Without load the rule conserves 1/2 v.M v + 1/2 u.K u exactly (up to
+    the solves' rounding) at any dt; with the cantilever's load, a start at
+    rest in the static solution stays there (F_ext + F_int(u) = 0, a = 0)."""
+    w = _unloaded(W.cantilever3d())
+    o = Oracle(w)
+    rho = o.rho()
+    L = dense.sparse_operator(w, o, rho)
+    mass = dense.mass_vector(w)
+    free = dense.free_dofs(w)
+    rng = np.random.default_rng(5)
+    u = np.zeros(3 * w.n)
+    v = np.zeros(3 * w.n)
+    u[free] = rng.standard_normal(free.size) * 1e-6
+    v[free] = rng.standard_normal(free.size) * 1e-3
+
+    def energy(u, v):
+        u, v = u.reshape(-1), v.reshape(-1)
+        return 0.5 * v @ (mass * v) - 0.5 * u @ (L @ u)
+
+    E0 = energy(u, v)
+    dt = 3.0 * w.dt if np.ndim(w.dt) == 0 else 3.0 * float(np.asarray(w.dt).reshape(-1)[0])
+    for _ in range(4):
+        u, v, _ = dense.newmark_run(w, o, u, v, dt, 5, rho_bond=rho)
+        assert abs(energy(u, v) - E0) <= 1e-10 * E0
+
+    wl = W.cantilever3d()
+    ol = Oracle(wl)
+    us = dense.static_solution(wl, ol, rho_bond=ol.rho())
+    u2, v2, _ = dense.newmark_run(wl, ol, us, np.zeros_like(us), 50 * dt, 3, rho_bond=ol.rho())
+    assert np.abs(u2 - us).max() <= 1e-9 * np.abs(us).max()
+    assert np.abs(v2).max() <= 1e-9 * np.abs(us).max() / dt
+
+
+def test_newmark_carries_a_rigid_translation():
+    """K annihilates rigid translations: with every node, the prescribed ones
+    included, moving at one velocity and no load, the step gives
+    u_n = n dt V and keeps v = V (the prescribed components are advanced by
+    dt v, the free ones by the solve)."""
+    w = _unloaded(W.cantilever3d())
+    o = Oracle(w)
+    Vr = np.array([0.3, -0.2, 0.1])
+    v0 = np.tile(Vr, (w.n, 1))
+    dt = 10.0 * float(np.asarray(w.dt).reshape(-1)[0])
+    u, v, _ = dense.newmark_run(w, o, np.zeros((w.n, 3)), v0, dt, 6, rho_bond=o.rho())
+    assert np.abs(u - 6 * dt * Vr).max() <= 1e-12 * 6 * dt
+    assert np.abs(v - Vr).max() <= 1e-10
