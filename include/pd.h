@@ -620,6 +620,12 @@ typedef struct pd_cg_opts {
     double tol;            /* relative residual |r| / |r0| to stop at (> 0)           */
     int32_t max_iter;      /* iteration limit (> 0)                                   */
     int32_t check_every;   /* iterations between convergence checks (> 0)             */
+    int32_t matrix_free;   /* 0: products with the stored K; 1: every product K x    */
+                           /* (the CG's, and those of pd_newmark_step's a_n and right- */
+                           /* hand side) taken as -f(x) by the double force kernels    */
+                           /* (the force of Eq. 2.2 is linear in u); K then serves     */
+                           /* the preconditioner's diagonal only                       */
+    int32_t reserved;      /* 0                                                        */
 } pd_cg_opts;
 
 typedef struct pd_cg_report {

@@ -104,7 +104,7 @@ class pd_adr_dev(C.Structure):
 
 
 class pd_cg_opts(C.Structure):
-    _fields_ = [("tol", dbl), ("max_iter", i32), ("check_every", i32)]
+    _fields_ = [("tol", dbl), ("max_iter", i32), ("check_every", i32), ("matrix_free", i32), ("reserved", i32)]
 
 
 class pd_cg_report(C.Structure):

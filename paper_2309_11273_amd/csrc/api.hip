@@ -720,7 +720,8 @@ pd_status pd_static_solve(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
     if (!K->assembled) return fail(c, PD_ERR_STATE, "K is not assembled");
     if (K->fp32) return fail(c, PD_ERR_UNSUPPORTED, "the static solve needs K in double");
     if (!o || !work) return fail(c, PD_ERR_ARG, "NULL options or workspace");
-    if (!(o->tol > 0.0) || o->max_iter <= 0 || o->check_every <= 0) return fail(c, PD_ERR_ARG, "bad solver options");
+    if (!(o->tol > 0.0) || o->max_iter <= 0 || o->check_every <= 0 || (o->matrix_free != 0 && o->matrix_free != 1))
+        return fail(c, PD_ERR_ARG, "bad solver options");
     if (reinterpret_cast<uintptr_t>(work) % 32 != 0) return fail(c, PD_ERR_ARG, "workspace must be 32-byte aligned");
     if (!p->aux || !p->fext) return fail(c, PD_ERR_ARG, "aux/fext are NULL (call pd_state_init first)");
     HIP_TRY(c, hipSetDevice(c->device));
@@ -736,7 +737,8 @@ pd_status pd_static_solve(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
     conv = h[4] == 0.0;  // zero residual: u0 is already in equilibrium
     while (!conv && it < o->max_iter) {
         const int chunk = std::min(o->check_every, o->max_iter - it);
-        for (int k = 0; k < chunk; k++) HIP_TRY(c, pdk::launch_cg_iteration(a, K, work, 0.0, c->stream));
+        for (int k = 0; k < chunk; k++)
+            HIP_TRY(c, pdk::launch_cg_iteration(a, K, work, 0.0, cur, o->matrix_free != 0, c->stream));
         it += chunk;
         HIP_TRY(c, hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -766,7 +768,8 @@ pd_status pd_newmark_step(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
     if (!o || !work) return fail(c, PD_ERR_ARG, "NULL options or workspace");
     if (nsteps < 0) return fail(c, PD_ERR_ARG, "nsteps < 0");
     if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(c, PD_ERR_ARG, "dt must be positive and finite");
-    if (!(o->cg.tol > 0.0) || o->cg.max_iter <= 0 || o->cg.check_every <= 0)
+    if (!(o->cg.tol > 0.0) || o->cg.max_iter <= 0 || o->cg.check_every <= 0 ||
+        (o->cg.matrix_free != 0 && o->cg.matrix_free != 1))
         return fail(c, PD_ERR_ARG, "bad solver options");
     if (o->breaking != 0 && o->breaking != 1) return fail(c, PD_ERR_ARG, "breaking must be 0 or 1");
     if (reinterpret_cast<uintptr_t>(work) % 32 != 0) return fail(c, PD_ERR_ARG, "workspace must be 32-byte aligned");
@@ -784,7 +787,7 @@ pd_status pd_newmark_step(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
             HIP_TRY(c, pdk::launch_break_mark(a, p, K, cur, c->stream));
             HIP_TRY(c, pdk::launch_bsr_prep_assemble(a, p, K, false, cur, c->stream));
         }
-        HIP_TRY(c, pdk::launch_nm_start(a, K, work, o->dt, cur, c->stream));
+        HIP_TRY(c, pdk::launch_nm_start(a, K, work, o->dt, cur, o->cg.matrix_free != 0, c->stream));
         double h[8] = {0};
         int it = 0;
         HIP_TRY(c, hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->stream));
@@ -792,7 +795,8 @@ pd_status pd_newmark_step(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
         bool conv = h[4] == 0.0;
         while (!conv && it < o->cg.max_iter) {
             const int chunk = std::min(o->cg.check_every, o->cg.max_iter - it);
-            for (int k = 0; k < chunk; k++) HIP_TRY(c, pdk::launch_cg_iteration(a, K, work, o->dt, c->stream));
+            for (int k = 0; k < chunk; k++)
+                HIP_TRY(c, pdk::launch_cg_iteration(a, K, work, o->dt, cur, o->cg.matrix_free != 0, c->stream));
             it += chunk;
             HIP_TRY(c, hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));

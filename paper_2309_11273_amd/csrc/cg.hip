@@ -52,6 +52,9 @@ struct CgArgs {
     double *mass;
     double shift;
     double4 *acc;
+    // the state's displacements (volume V in .w): p carries V in .w too, so
+    // that the force kernels can take p as a displacement field
+    const double4 *uvc;
 };
 
 __device__ __forceinline__ double block_sum256(double v, double *sh) {
@@ -193,14 +196,38 @@ __global__ __launch_bounds__(256) void k_cg_matvec(StepArgs a, CgArgs c) {
     c.q[row] = masked(q, a.aux[row]);
 }
 
+// matrix-free product: the force kernels have written f(p) (the restoring
+// force of the direction taken as a displacement field, Eq. 2.2 summed) into
+// q; q = -f(p) on the free components, plus (4/dt^2) M p for the implicit step
+__global__ __launch_bounds__(256) void k_cg_mf_fix(StepArgs a, CgArgs c) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= a.n_pad) return;
+    const double4 f = c.q[row];
+    double4 q = make_double4(-f.x, -f.y, -f.z, 0.0);
+    if (c.mass) {
+        const double sm = c.shift * c.mass[row];
+        const double4 pr = c.p[row];
+        q.x += sm * pr.x;
+        q.y += sm * pr.y;
+        q.z += sm * pr.z;
+    }
+    c.q[row] = masked(q, a.aux[row]);
+}
+
 // Newmark start: m_i = rho V_i and a_n = (F_ext + f(u_n)) / m_i on the free
 // components (zero for padding rows, whose mass is zero)
-template <int DIM>
+// (MF: f(u_n) already in q, written by the force kernels)
+template <int DIM, bool MF>
 __global__ __launch_bounds__(256) void k_nm_accel(StepArgs a, CgArgs c, int cur) {
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= a.n_pad) return;
     double f[3];
-    row_product<DIM>(c, row, a.uv[cur], f);
+    if (MF) {
+        const double4 fq = c.q[row];
+        f[0] = fq.x, f[1] = fq.y, f[2] = fq.z;
+    } else {
+        row_product<DIM>(c, row, a.uv[cur], f);
+    }
     if ((threadIdx.x & 63) != 0) return;
     const uint32_t aux = a.aux[row];
     const double m = a.spec[aux >> 8].rho * a.uv[cur][row].w;
@@ -232,12 +259,18 @@ __global__ __launch_bounds__(256) void k_nm_predict(StepArgs a, double dt, int c
 }
 
 // right-hand side F_ext + f(u*) + M (4 v_n / dt + a_n) on the free components
-template <int DIM>
+// (MF: f(u*) already in q)
+template <int DIM, bool MF>
 __global__ __launch_bounds__(256) void k_nm_rhs(StepArgs a, CgArgs c, double dt, int cur) {
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= a.n_pad) return;
     double f[3];
-    row_product<DIM>(c, row, a.uv[cur ^ 1], f);
+    if (MF) {
+        const double4 fq = c.q[row];
+        f[0] = fq.x, f[1] = fq.y, f[2] = fq.z;
+    } else {
+        row_product<DIM>(c, row, a.uv[cur ^ 1], f);
+    }
     if ((threadIdx.x & 63) != 0) return;
     const uint32_t aux = a.aux[row];
     const double m = c.mass[row];
@@ -308,7 +341,7 @@ __global__ __launch_bounds__(256) void k_cg_vec(StepArgs a, CgArgs c, int mode) 
             }
             const double4 z = precondition(c.dinv + 12 * row, r, aux);
             c.z[row] = z;
-            if (mode == 0) c.p[row] = z;
+            if (mode == 0) c.p[row] = make_double4(z.x, z.y, z.z, c.uvc[row].w);
             s0 = r.x * z.x + r.y * z.y + r.z * z.z;
             s1 = r.x * r.x + r.y * r.y + r.z * r.z;
         }
@@ -361,6 +394,7 @@ __global__ __launch_bounds__(256) void k_cg_direction(StepArgs a, CgArgs c) {
     p.x = z.x + be * p.x;
     p.y = z.y + be * p.y;
     p.z = z.z + be * p.z;
+    p.w = c.uvc[row].w;
     c.p[row] = p;
 }
 
@@ -390,8 +424,10 @@ int64_t nm_workspace_doubles(int64_t n_pad) { return nm_base(n_pad) + 5 * n_pad;
 
 // dt > 0: the Newmark operator K + (4/dt^2) M, with a_n and the mass after
 // the solver's arrays
-static CgArgs cg_args(const pd_bsr_dev *K, double *work, int64_t n_pad, double dt = 0.0) {
+static CgArgs cg_args(const StepArgs &a, const pd_bsr_dev *K, double *work, int cur, double dt = 0.0) {
+    const int64_t n_pad = a.n_pad;
     CgArgs c{};
+    c.uvc = a.uv[cur];
     c.row_ptr = K->row_ptr;
     c.col = K->col;
     c.vals = reinterpret_cast<const double *>(K->vals);
@@ -421,7 +457,7 @@ static CgArgs cg_args(const pd_bsr_dev *K, double *work, int64_t n_pad, double d
 }
 
 hipError_t launch_cg_start(const StepArgs &a, const pd_bsr_dev *K, double *work, int cur, hipStream_t s) {
-    const CgArgs c = cg_args(K, work, a.n_pad);
+    const CgArgs c = cg_args(a, K, work, cur);
     const unsigned nrow = (unsigned)((a.n_pad + 255) / 256), nwave = (unsigned)((a.n_pad + 3) / 4);
     if (a.dim == 3) {
         hipLaunchKernelGGL((k_cg_dinv<3>), dim3(nwave), dim3(256), 0, s, a, c);
@@ -435,20 +471,41 @@ hipError_t launch_cg_start(const StepArgs &a, const pd_bsr_dev *K, double *work,
     return hipGetLastError();
 }
 
-hipError_t launch_nm_start(const StepArgs &a, const pd_bsr_dev *K, double *work, double dt, int cur,
+// restoring force f(uv[buf]) (Eq. 2.2 summed, no breaking, no update) into
+// q by the double force kernels
+static hipError_t force_into_q(const StepArgs &a, const CgArgs &c, int buf, hipStream_t s) {
+    StepArgs af = a;
+    af.f_out = c.q;
+    af.theta_out = nullptr;
+    const bool tiled = tiled64_supported(af);
+    hipError_t e = tiled ? launch_tpass1_f64(af, buf, false, s) : launch_pass1_f64(af, buf, false, 256, s);
+    if (e != hipSuccess) return e;
+    return tiled ? launch_tpass2_f64(af, buf, false, s) : launch_pass2_f64(af, buf, false, 256, s);
+}
+
+hipError_t launch_nm_start(const StepArgs &a, const pd_bsr_dev *K, double *work, double dt, int cur, bool mf,
                            hipStream_t s) {
-    const CgArgs c = cg_args(K, work, a.n_pad, dt);
+    const CgArgs c = cg_args(a, K, work, cur, dt);
     const unsigned nrow = (unsigned)((a.n_pad + 255) / 256), nwave = (unsigned)((a.n_pad + 3) / 4);
-    if (a.dim == 3) hipLaunchKernelGGL((k_nm_accel<3>), dim3(nwave), dim3(256), 0, s, a, c, cur);
-    else hipLaunchKernelGGL((k_nm_accel<2>), dim3(nwave), dim3(256), 0, s, a, c, cur);
+    hipError_t e;
+    if (mf && (e = force_into_q(a, c, cur, s)) != hipSuccess) return e;
+#define PD_NM(KN, ...)                                                                                 \
+    do {                                                                                               \
+        if (a.dim == 3) {                                                                              \
+            if (mf) hipLaunchKernelGGL((KN<3, true>), dim3(nwave), dim3(256), 0, s, __VA_ARGS__);      \
+            else hipLaunchKernelGGL((KN<3, false>), dim3(nwave), dim3(256), 0, s, __VA_ARGS__);        \
+        } else {                                                                                       \
+            if (mf) hipLaunchKernelGGL((KN<2, true>), dim3(nwave), dim3(256), 0, s, __VA_ARGS__);      \
+            else hipLaunchKernelGGL((KN<2, false>), dim3(nwave), dim3(256), 0, s, __VA_ARGS__);        \
+        }                                                                                              \
+    } while (0)
+    PD_NM(k_nm_accel, a, c, cur);
     hipLaunchKernelGGL(k_nm_predict, dim3(nrow), dim3(256), 0, s, a, dt, cur);
-    if (a.dim == 3) {
-        hipLaunchKernelGGL((k_nm_rhs<3>), dim3(nwave), dim3(256), 0, s, a, c, dt, cur);
-        hipLaunchKernelGGL((k_cg_dinv<3>), dim3(nwave), dim3(256), 0, s, a, c);
-    } else {
-        hipLaunchKernelGGL((k_nm_rhs<2>), dim3(nwave), dim3(256), 0, s, a, c, dt, cur);
-        hipLaunchKernelGGL((k_cg_dinv<2>), dim3(nwave), dim3(256), 0, s, a, c);
-    }
+    if (mf && (e = force_into_q(a, c, cur ^ 1, s)) != hipSuccess) return e;
+    PD_NM(k_nm_rhs, a, c, dt, cur);
+#undef PD_NM
+    if (a.dim == 3) hipLaunchKernelGGL((k_cg_dinv<3>), dim3(nwave), dim3(256), 0, s, a, c);
+    else hipLaunchKernelGGL((k_cg_dinv<2>), dim3(nwave), dim3(256), 0, s, a, c);
     hipLaunchKernelGGL(k_cg_vec, dim3(nrow), dim3(256), 0, s, a, c, 0);
     hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(256), 0, s, c, (int)nrow, 0);
     return hipGetLastError();
@@ -456,16 +513,33 @@ hipError_t launch_nm_start(const StepArgs &a, const pd_bsr_dev *K, double *work,
 
 hipError_t launch_nm_finish(const StepArgs &a, const pd_bsr_dev *K, double *work, double dt, int cur,
                             hipStream_t s) {
-    const CgArgs c = cg_args(K, work, a.n_pad, dt);
+    const CgArgs c = cg_args(a, K, work, cur, dt);
     hipLaunchKernelGGL(k_nm_finish, dim3((unsigned)((a.n_pad + 255) / 256)), dim3(256), 0, s, a, c, dt, cur);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_iteration(const StepArgs &a, const pd_bsr_dev *K, double *work, double dt, hipStream_t s) {
-    const CgArgs c = cg_args(K, work, a.n_pad, dt);
+hipError_t launch_cg_iteration(const StepArgs &a, const pd_bsr_dev *K, double *work, double dt, int cur, bool mf,
+                               hipStream_t s) {
+    const CgArgs c = cg_args(a, K, work, cur, dt);
     const unsigned nrow = (unsigned)((a.n_pad + 255) / 256), nwave = (unsigned)((a.n_pad + 3) / 4);
-    if (a.dim == 3) hipLaunchKernelGGL((k_cg_matvec<3>), dim3(nwave), dim3(256), 0, s, a, c);
-    else hipLaunchKernelGGL((k_cg_matvec<2>), dim3(nwave), dim3(256), 0, s, a, c);
+    if (mf) {
+        // K p = -f(p): the double force kernels (no breaking, no update) on
+        // p as the displacement field, then the sign, mask and mass term
+        StepArgs am = a;
+        am.uv[0] = c.p;
+        am.f_out = c.q;
+        am.theta_out = nullptr;
+        const bool tiled = tiled64_supported(am);
+        hipError_t e = tiled ? launch_tpass1_f64(am, 0, false, s) : launch_pass1_f64(am, 0, false, 256, s);
+        if (e != hipSuccess) return e;
+        e = tiled ? launch_tpass2_f64(am, 0, false, s) : launch_pass2_f64(am, 0, false, 256, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cg_mf_fix, dim3(nrow), dim3(256), 0, s, am, c);
+    } else if (a.dim == 3) {
+        hipLaunchKernelGGL((k_cg_matvec<3>), dim3(nwave), dim3(256), 0, s, a, c);
+    } else {
+        hipLaunchKernelGGL((k_cg_matvec<2>), dim3(nwave), dim3(256), 0, s, a, c);
+    }
     hipLaunchKernelGGL(k_cg_vec, dim3(nrow), dim3(256), 0, s, a, c, 1);
     hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(256), 0, s, c, (int)nrow, 1);
     hipLaunchKernelGGL(k_cg_vec, dim3(nrow), dim3(256), 0, s, a, c, 2);
@@ -475,7 +549,7 @@ hipError_t launch_cg_iteration(const StepArgs &a, const pd_bsr_dev *K, double *w
 }
 
 hipError_t launch_cg_finish(const StepArgs &a, const pd_bsr_dev *K, double *work, int cur, hipStream_t s) {
-    const CgArgs c = cg_args(K, work, a.n_pad);
+    const CgArgs c = cg_args(a, K, work, cur);
     hipLaunchKernelGGL(k_cg_finish, dim3((unsigned)((a.n_pad + 255) / 256)), dim3(256), 0, s, a, c, cur);
     return hipGetLastError();
 }

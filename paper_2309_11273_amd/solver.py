@@ -457,14 +457,16 @@ class Solver:
         self.ctx.check("pd_assemble_K", A.load().pd_assemble_K(self.ctx.h, C.byref(self.P), _tp(self.mask),
                                                                  C.byref(self.K)))
 
-    def static_solve(self, tol: float = 1e-12, max_iter: int = 20000, check_every: int = 50) -> dict:
+    def static_solve(self, tol: float = 1e-12, max_iter: int = 20000, check_every: int = 50,
+                     matrix_free: bool = False) -> dict:
         """Static equilibrium from the current state with the assembled
-        double K (pd_static_solve); the solution replaces u."""
+        double K (pd_static_solve); the solution replaces u.  matrix_free:
+        the CG products by the double force kernels."""
         L = A.load()
         nw = int(L.pd_static_workspace(self.n_pad))
         if getattr(self, "_cg_work", None) is None or self._cg_work.numel() < nw:
             self._cg_work = torch.zeros(nw, dtype=torch.float64, device=self.dev)
-        o = A.pd_cg_opts(float(tol), int(max_iter), int(check_every))
+        o = A.pd_cg_opts(float(tol), int(max_iter), int(check_every), 1 if matrix_free else 0, 0)
         rep = A.pd_cg_report()
         self.ctx.check("pd_static_solve", L.pd_static_solve(self.ctx.h, C.byref(self.P), C.byref(self.K),
                                                               C.byref(self.S), C.byref(o), _tp(self._cg_work),
@@ -472,14 +474,15 @@ class Solver:
         return dict(iterations=rep.iterations, converged=bool(rep.converged), rel_residual=rep.rel_residual)
 
     def newmark_step(self, nsteps: int, dt: float, breaking: bool = False, tol: float = 1e-12,
-                     max_iter: int = 20000, check_every: int = 50) -> dict:
+                     max_iter: int = 20000, check_every: int = 50, matrix_free: bool = False) -> dict:
         """nsteps implicit average-acceleration Newmark steps with the
         assembled double K (pd_newmark_step); the state advances in place."""
         L = A.load()
         nw = int(L.pd_newmark_workspace(self.n_pad))
         if getattr(self, "_nm_work", None) is None or self._nm_work.numel() < nw:
             self._nm_work = torch.zeros(nw, dtype=torch.float64, device=self.dev)
-        o = A.pd_newmark_opts(float(dt), A.pd_cg_opts(float(tol), int(max_iter), int(check_every)),
+        o = A.pd_newmark_opts(float(dt), A.pd_cg_opts(float(tol), int(max_iter), int(check_every),
+                                                    1 if matrix_free else 0, 0),
                               1 if breaking else 0, 0)
         rep = A.pd_cg_report()
         self.ctx.check("pd_newmark_step", L.pd_newmark_step(self.ctx.h, C.byref(self.P), C.byref(self.K),

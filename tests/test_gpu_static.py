@@ -48,8 +48,9 @@ def clamped_plate():
     return w
 
 
+@pytest.mark.parametrize("mf", [False, True], ids=["stored_K", "matrix_free"])
 @pytest.mark.parametrize("name", ["cantilever", "plate_clamped"])
-def test_static_solution_matches_direct_solve(ctx, name):
+def test_static_solution_matches_direct_solve(ctx, name, mf):
     w = W.cantilever3d() if name == "cantilever" else clamped_plate()
     o = Oracle(w)
     ref = dense.static_solution(w, o, rho_bond=o.rho())
@@ -58,13 +59,14 @@ def test_static_solution_matches_direct_solve(ctx, name):
     ev = np.linalg.eigvalsh(-L[np.ix_(free, free)])
     cond = ev[-1] / ev[0]
     s = static_solver(w, ctx)
-    rep = s.static_solve(tol=1e-13, max_iter=20000)
+    rep = s.static_solve(tol=1e-13, max_iter=20000, matrix_free=mf)
     assert rep["converged"], rep
     u, _ = s.read()
     assert rel(u, ref) <= max(1e-10, 10 * cond * rep["rel_residual"]), (rel(u, ref), cond, rep)
 
 
-def test_cylinder_torsion_static(ctx):
+@pytest.mark.parametrize("mf", [False, True], ids=["stored_K", "matrix_free"])
+def test_cylinder_torsion_static(ctx, mf):
     """Small cylinder (dx = 5 mm) with its end layers turned by a prescribed
     rotation: the interior equilibrium against the direct solve."""
     w = W.cylinder3d(dx=5e-3, dt=2.4e-7, twist_rate=8.0, steps=10)
@@ -72,7 +74,7 @@ def test_cylinder_torsion_static(ctx):
     o = Oracle(w)
     ref = dense.static_solution(w, o, u0=u0, rho_bond=o.rho())
     s = static_solver(w, ctx, u0=u0)
-    rep = s.static_solve(tol=1e-13, max_iter=50000)
+    rep = s.static_solve(tol=1e-13, max_iter=50000, matrix_free=mf)
     assert rep["converged"], rep
     u, _ = s.read()
     assert rel(u, ref) <= 1e-8, (rel(u, ref), rep)
