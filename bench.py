@@ -224,19 +224,19 @@ def batch_baseline(n_plates, steps, chunk):
     return time.perf_counter() - t0
 
 
-def time_static(s, steps, warmup, mf=False):
+def time_static(s, steps, warmup, mf=False, use_k=True):
     """Wall time of 'steps' conjugate-gradient iterations (HIP events on the
     library's stream), less that of a solve with none (the start phase)."""
     import torch
-    s.static_solve(tol=1e-300, max_iter=max(1, warmup), check_every=max(1, warmup), matrix_free=mf)
+    s.static_solve(tol=1e-300, max_iter=max(1, warmup), check_every=max(1, warmup), matrix_free=mf, use_K=use_k)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     u0 = s.uv[s.S.cur].clone()
     ev[0].record()
-    s.static_solve(tol=1e-300, max_iter=1, check_every=1, matrix_free=mf)
+    s.static_solve(tol=1e-300, max_iter=1, check_every=1, matrix_free=mf, use_K=use_k)
     ev[1].record()
     s.uv[s.S.cur].copy_(u0)
     ev[2].record()
-    s.static_solve(tol=1e-300, max_iter=steps + 1, check_every=steps + 1, matrix_free=mf)
+    s.static_solve(tol=1e-300, max_iter=steps + 1, check_every=steps + 1, matrix_free=mf, use_K=use_k)
     ev[3].record()
     torch.cuda.synchronize()
     return (ev[2].elapsed_time(ev[3]) - ev[0].elapsed_time(ev[1])) * 1e-3
@@ -309,6 +309,9 @@ def main():
     ap.add_argument("--matrix-free", action="store_true",
                     help="with --static / --implicit: CG products K p = -f(p) by the double force kernels "
                          "instead of the stored K (K then only gives the preconditioner's diagonal)")
+    ap.add_argument("--no-stored-k", action="store_true",
+                    help="with --matrix-free: assemble no K at all (the preconditioner's diagonal summed "
+                         "from the bonds)")
     ap.add_argument("--adr", action="store_true",
                     help="time iterations of the adaptive dynamic relaxation (FP64 matrix-free force, "
                          "fictitious time step 1) instead of explicit steps")
@@ -372,11 +375,13 @@ def main():
         # external load
         dts = np.asarray(w.dt, dtype=np.float64).reshape(-1)
         s.reset(u0=w.v0 * (100.0 * (dts[np.asarray(w.specimen)][:, None] if dts.size > 1 else float(dts[0]))))
-        s.build_K(fp32=False)
-        s.assemble_K()
-        el = time_static(s, args.steps, args.warmup, args.matrix_free)
+        use_k = not (args.matrix_free and args.no_stored_k)
+        if use_k:
+            s.build_K(fp32=False)
+            s.assemble_K()
+        el = time_static(s, args.steps, args.warmup, args.matrix_free, use_k)
         ms_it = 1e3 * el / args.steps
-        kb = int(s.K_sizes.nnzb)
+        kb = int(s.K_sizes.nnzb) if use_k else 0
         dim = int(sz.dim)
         # per iteration: the stored K's blocks and column indices, or the two
         # double force passes (84 + 172 B/node, 1/8 B/bond each), plus the
@@ -391,7 +396,8 @@ def main():
                "config": {"workload": desc + "; static solve (prescribed components displaced by 100 explicit "
                                       "steps of their velocity), conjugate-gradient iterations (one K product each)",
                           "nodes": int(sz.n), "unique_bonds": n_bonds, "K_blocks": kb,
-                          "operator": "matrix-free (double force kernels)" if args.matrix_free else "stored K"},
+                          "operator": ("matrix-free (double force kernels)" + ("" if use_k else ", no stored K"))
+                          if args.matrix_free else "stored K"},
                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                             "kernel": "one CG iteration (block product + vector kernels)",
@@ -401,19 +407,22 @@ def main():
     if args.implicit:
         import torch
         args.precision = "fp64"
-        s.build_K(fp32=False)
-        s.assemble_K()
+        use_k = not (args.matrix_free and args.no_stored_k)
+        if use_k:
+            s.build_K(fp32=False)
+            s.assemble_K()
         dts = np.asarray(w.dt, dtype=np.float64).reshape(-1)
         dt_imp = 10.0 * float(dts.min())
-        s.newmark_step(args.warmup, dt_imp, tol=1e-10, check_every=10, matrix_free=args.matrix_free)
+        s.newmark_step(args.warmup, dt_imp, tol=1e-10, check_every=10, matrix_free=args.matrix_free, use_K=use_k)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rep = s.newmark_step(args.steps, dt_imp, tol=1e-10, check_every=10, matrix_free=args.matrix_free)
+        rep = s.newmark_step(args.steps, dt_imp, tol=1e-10, check_every=10, matrix_free=args.matrix_free,
+                             use_K=use_k)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         ms_step = 1e3 * el / args.steps
         its = rep["iterations"] / max(1, args.steps)
-        kb = int(s.K_sizes.nnzb)
+        kb = int(s.K_sizes.nnzb) if use_k else 0
         dim = int(sz.dim)
         byt = (int(sz.n_pad) * (84 + 172 + 520) + nnz // 4) if args.matrix_free else \
             kb * (8 * dim * dim + 4) + int(sz.n_pad) * (8 + 512)
@@ -425,7 +434,8 @@ def main():
                "config": {"workload": desc + "; implicit Newmark steps (average acceleration, dt = 10x the "
                                       "explicit step), CG to 1e-10 per step", "nodes": int(sz.n),
                           "unique_bonds": n_bonds, "K_blocks": kb, "cg_iterations_per_step": round(its, 2),
-                          "operator": "matrix-free (double force kernels)" if args.matrix_free else "stored K",
+                          "operator": ("matrix-free (double force kernels)" + ("" if use_k else ", no stored K"))
+                          if args.matrix_free else "stored K",
                           "converged": rep["converged"]},
                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,

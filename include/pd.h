@@ -624,7 +624,9 @@ typedef struct pd_cg_opts {
                            /* (the CG's, and those of pd_newmark_step's a_n and right- */
                            /* hand side) taken as -f(x) by the double force kernels    */
                            /* (the force of Eq. 2.2 is linear in u); K then serves     */
-                           /* the preconditioner's diagonal only                       */
+                           /* the preconditioner's diagonal only, and may be NULL:     */
+                           /* the diagonal blocks are then summed from the bonds and   */
+                           /* the implicit step's breaking test is the force pass's   */
     int32_t reserved;      /* 0                                                        */
 } pd_cg_opts;
 
@@ -637,9 +639,9 @@ typedef struct pd_cg_report {
 /* Doubles of device workspace pd_static_solve needs for n_pad rows. */
 int64_t pd_static_workspace(int64_t n_pad);
 
-/* Errors: PD_ERR_ARG (NULL pointers, bad options), PD_ERR_STATE (K not
- * assembled), PD_ERR_UNSUPPORTED (K stores float values), PD_ERR_UNSTABLE
- * (non-finite solution), PD_ERR_HIP. */
+/* Errors: PD_ERR_ARG (NULL pointers, K NULL without matrix_free, bad
+ * options), PD_ERR_STATE (K not assembled), PD_ERR_UNSUPPORTED (K stores
+ * float values), PD_ERR_UNSTABLE (non-finite solution), PD_ERR_HIP. */
 pd_status pd_static_solve(pd_ctx *ctx, const pd_problem_dev *prob, const struct pd_bsr_dev *K, pd_state_dev *st,
                           const pd_cg_opts *opts, double *work, pd_cg_report *rep);
 
@@ -663,8 +665,9 @@ pd_status pd_static_solve(pd_ctx *ctx, const pd_problem_dev *prob, const struct 
  * by the caller, no state kept in it between calls.  rep (may be NULL):
  * iterations summed over the steps, converged = 1 if every step met the
  * tolerance, rel_residual the largest final one.  Synchronises every
- * opts->cg.check_every iterations.  Errors: PD_ERR_ARG (NULL pointers,
- * dt <= 0, bad options, nsteps < 0), PD_ERR_STATE (K not assembled),
+ * opts->cg.check_every iterations.  K may be NULL with
+ * opts->cg.matrix_free = 1.  Errors: PD_ERR_ARG (NULL pointers, K NULL
+ * without matrix_free, dt <= 0, bad options, nsteps < 0), PD_ERR_STATE (K not assembled),
  * PD_ERR_UNSUPPORTED (K stores float values), PD_ERR_UNSTABLE (non-finite
  * residual), PD_ERR_HIP. */
 typedef struct pd_newmark_opts {

@@ -715,11 +715,12 @@ pd_status pd_static_solve(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
     if (!c) return PD_ERR_ARG;
     pd_status s = check_problem(c, p);
     if (s != PD_OK) return s;
-    if ((s = check_bsr(c, p, K)) != PD_OK) return s;
-    if ((s = check_state(c, st, false)) != PD_OK) return s;
-    if (!K->assembled) return fail(c, PD_ERR_STATE, "K is not assembled");
-    if (K->fp32) return fail(c, PD_ERR_UNSUPPORTED, "the static solve needs K in double");
     if (!o || !work) return fail(c, PD_ERR_ARG, "NULL options or workspace");
+    if (!K && o->matrix_free != 1) return fail(c, PD_ERR_ARG, "K is NULL (allowed with matrix_free = 1 only)");
+    if (K && (s = check_bsr(c, p, K)) != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (K && !K->assembled) return fail(c, PD_ERR_STATE, "K is not assembled");
+    if (K && K->fp32) return fail(c, PD_ERR_UNSUPPORTED, "the static solve needs K in double");
     if (!(o->tol > 0.0) || o->max_iter <= 0 || o->check_every <= 0 || (o->matrix_free != 0 && o->matrix_free != 1))
         return fail(c, PD_ERR_ARG, "bad solver options");
     if (reinterpret_cast<uintptr_t>(work) % 32 != 0) return fail(c, PD_ERR_ARG, "workspace must be 32-byte aligned");
@@ -727,7 +728,7 @@ pd_status pd_static_solve(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
     HIP_TRY(c, hipSetDevice(c->device));
     pdk::StepArgs a = make_args(p, st);
     const int cur = st->cur;
-    HIP_TRY(c, pdk::launch_cg_start(a, K, work, cur, c->stream));
+    HIP_TRY(c, pdk::launch_cg_start(a, K, work, cur, o->matrix_free != 0, c->stream));
     const double *scal = pdk::cg_scalars(work, p->n_pad);
     double h[8] = {0};
     int it = 0;
@@ -761,11 +762,12 @@ pd_status pd_newmark_step(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
     if (!c) return PD_ERR_ARG;
     pd_status s = check_problem(c, p);
     if (s != PD_OK) return s;
-    if ((s = check_bsr(c, p, K)) != PD_OK) return s;
-    if ((s = check_state(c, st, false)) != PD_OK) return s;
-    if (!K->assembled) return fail(c, PD_ERR_STATE, "K is not assembled");
-    if (K->fp32) return fail(c, PD_ERR_UNSUPPORTED, "the implicit step needs K in double");
     if (!o || !work) return fail(c, PD_ERR_ARG, "NULL options or workspace");
+    if (!K && o->cg.matrix_free != 1) return fail(c, PD_ERR_ARG, "K is NULL (allowed with matrix_free = 1 only)");
+    if (K && (s = check_bsr(c, p, K)) != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (K && !K->assembled) return fail(c, PD_ERR_STATE, "K is not assembled");
+    if (K && K->fp32) return fail(c, PD_ERR_UNSUPPORTED, "the implicit step needs K in double");
     if (nsteps < 0) return fail(c, PD_ERR_ARG, "nsteps < 0");
     if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(c, PD_ERR_ARG, "dt must be positive and finite");
     if (!(o->cg.tol > 0.0) || o->cg.max_iter <= 0 || o->cg.check_every <= 0 ||
@@ -784,8 +786,16 @@ pd_status pd_newmark_step(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
         const int cur = st->cur;
         if (o->breaking) {
             // critical stretch at u_n, then K re-assembled around new breaks
-            HIP_TRY(c, pdk::launch_break_mark(a, p, K, cur, c->stream));
-            HIP_TRY(c, pdk::launch_bsr_prep_assemble(a, p, K, false, cur, c->stream));
+            if (K) {
+                HIP_TRY(c, pdk::launch_break_mark(a, p, K, cur, c->stream));
+                HIP_TRY(c, pdk::launch_bsr_prep_assemble(a, p, K, false, cur, c->stream));
+            } else {
+                // no stored K: the double force pass 1 with its breaking test
+                // (its dilatation and force outputs are scratch here)
+                const bool tiled = pdk::tiled64_supported(a);
+                HIP_TRY(c, tiled ? pdk::launch_tpass1_f64(a, cur, true, c->stream)
+                                 : pdk::launch_pass1_f64(a, cur, true, 256, c->stream));
+            }
         }
         HIP_TRY(c, pdk::launch_nm_start(a, K, work, o->dt, cur, o->cg.matrix_free != 0, c->stream));
         double h[8] = {0};

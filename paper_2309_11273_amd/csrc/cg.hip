@@ -106,6 +106,40 @@ __device__ __forceinline__ double4 precondition(const double *Di, double4 r, uin
     return masked(z, aux);
 }
 
+// the inverse of a diagonal block D (row-major 3x3; identity where D is
+// singular, e.g. padding rows) into dinv
+template <int DIM>
+__device__ __forceinline__ void store_block_inverse(const CgArgs &c, int64_t row, double D[9]) {
+    if (DIM == 2) D[8] = 1.0;
+    const double c00 = D[4] * D[8] - D[5] * D[7], c01 = D[5] * D[6] - D[3] * D[8], c02 = D[3] * D[7] - D[4] * D[6];
+    const double det = D[0] * c00 + D[1] * c01 + D[2] * c02;
+    double inv[9];
+    double scale = 0.0;
+    for (int k = 0; k < 9; k++) scale = fmax(scale, fabs(D[k]));
+    if (!(fabs(det) > 1e-300) || !(fabs(det) > 1e-12 * scale * scale * scale)) {
+        for (int k = 0; k < 9; k++) inv[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    } else {
+        const double id = 1.0 / det;
+        inv[0] = c00 * id;
+        inv[1] = (D[2] * D[7] - D[1] * D[8]) * id;
+        inv[2] = (D[1] * D[5] - D[2] * D[4]) * id;
+        inv[3] = c01 * id;
+        inv[4] = (D[0] * D[8] - D[2] * D[6]) * id;
+        inv[5] = (D[2] * D[3] - D[0] * D[5]) * id;
+        inv[6] = c02 * id;
+        inv[7] = (D[1] * D[6] - D[0] * D[7]) * id;
+        inv[8] = (D[0] * D[4] - D[1] * D[3]) * id;
+    }
+    if (DIM == 2) inv[2] = inv[5] = inv[6] = inv[7] = inv[8] = 0.0;
+    for (int k = 0; k < 9; k++) c.dinv[12 * row + k] = inv[k];
+}
+
+__device__ __forceinline__ uint64_t wave_u64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 }  // namespace
 
 // D_i = sum_q Kt_iq (plus the Newmark mass term) and its inverse (identity
@@ -133,37 +167,74 @@ __global__ __launch_bounds__(256) void k_cg_dinv(StepArgs a, CgArgs c) {
         D[4] += sm;
         D[8] += sm;
     }
-    if (DIM == 2) D[8] = 1.0;
-    const double c00 = D[4] * D[8] - D[5] * D[7], c01 = D[5] * D[6] - D[3] * D[8], c02 = D[3] * D[7] - D[4] * D[6];
-    const double det = D[0] * c00 + D[1] * c01 + D[2] * c02;
-    double inv[9];
-    double scale = 0.0;
-    for (int k = 0; k < 9; k++) scale = fmax(scale, fabs(D[k]));
-    if (!(fabs(det) > 1e-300) || !(fabs(det) > 1e-12 * scale * scale * scale)) {
-        for (int k = 0; k < 9; k++) inv[k] = (k % 4 == 0) ? 1.0 : 0.0;
-    } else {
-        const double id = 1.0 / det;
-        inv[0] = c00 * id;
-        inv[1] = (D[2] * D[7] - D[1] * D[8]) * id;
-        inv[2] = (D[1] * D[5] - D[2] * D[4]) * id;
-        inv[3] = c01 * id;
-        inv[4] = (D[0] * D[8] - D[2] * D[6]) * id;
-        inv[5] = (D[2] * D[3] - D[0] * D[5]) * id;
-        inv[6] = c02 * id;
-        inv[7] = (D[1] * D[6] - D[0] * D[7]) * id;
-        inv[8] = (D[0] * D[4] - D[1] * D[3]) * id;
+    store_block_inverse<DIM>(c, row, D);
+}
+
+// The diagonal block of K = -df/du without the stored K, from the force of
+// Eq. 2.2 with q = theta / m (Eq. 1.8: q_i = A r_i^2 sum_k x V_k e_ik,
+// r = 1/m, w = 1):
+//   f_i = V_i sum_j V_j [kp x (q_i + q_j) + G e_ij (r_i + r_j)] M_ij,
+// and u_i enters e_ij (de_ij/du_i = -M), q_i (dq_i/du_i = -A r_i^2 b_i,
+// b_i = sum_j x V_j M_ij) and every neighbour's q_j (through e_ji:
+// dq_j/du_i = -A r_j^2 x V_i M_ij), so
+//   D_i = V_i [kp A r_i^2 b_i b_i^T
+//              + sum_j V_j (kp A r_j^2 V_i x^2 + G (r_i + r_j)) M M^T]
+// over the intact bonds; plus the Newmark mass term.  One wave per 64-row
+// slice, each lane its own row, bond words and status bits as in the
+// bond-list kernels.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_cg_dinv_mf(StepArgs a, CgArgs c) {
+    const int lane = threadIdx.x & 63;
+    const int64_t slice = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (slice >= a.n_slices) return;
+    const int64_t row = slice * 64 + lane;
+    const int64_t base = a.slice_ptr[slice];
+    const int64_t L = (a.slice_ptr[slice + 1] - base) >> 6;
+    const double Vi = c.uvc[row].w, ri = a.qr[row].y;
+    const pd_spec sp = a.spec[a.aux[row] >> 8];
+    double S[6] = {0, 0, 0, 0, 0, 0}, b[3] = {0, 0, 0};
+    for (int64_t k = 0; k < L; k++) {
+        const uint64_t m64 = wave_u64(a.mask[(base >> 6) + k]);
+        if (!((m64 >> lane) & 1ull)) continue;
+        const uint32_t w = a.words[pd_widx(base, k, lane)];
+        const int64_t j = w >> 7;
+        const double *st = a.stencil + 4 * (w & 127u);
+        const double x = st[3], Vj = c.uvc[j].w, rj = a.qr[j].y;
+        const double cj = Vj * (sp.kp * sp.A * rj * rj * Vi * x * x + sp.G * (ri + rj));
+        S[0] += cj * st[0] * st[0];
+        S[1] += cj * st[0] * st[1];
+        S[2] += cj * st[0] * st[2];
+        S[3] += cj * st[1] * st[1];
+        S[4] += cj * st[1] * st[2];
+        S[5] += cj * st[2] * st[2];
+        for (int q = 0; q < 3; q++) b[q] += Vj * x * st[q];
     }
-    if (DIM == 2) inv[2] = inv[5] = inv[6] = inv[7] = inv[8] = 0.0;
-    for (int k = 0; k < 9; k++) c.dinv[12 * row + k] = inv[k];
+    const double g = sp.kp * sp.A * ri * ri;
+    double D[9] = {Vi * (S[0] + g * b[0] * b[0]), Vi * (S[1] + g * b[0] * b[1]), Vi * (S[2] + g * b[0] * b[2]),
+                   Vi * (S[1] + g * b[1] * b[0]), Vi * (S[3] + g * b[1] * b[1]), Vi * (S[4] + g * b[1] * b[2]),
+                   Vi * (S[2] + g * b[2] * b[0]), Vi * (S[4] + g * b[2] * b[1]), Vi * (S[5] + g * b[2] * b[2])};
+    if (c.mass) {
+        const double sm = c.shift * c.mass[row];
+        D[0] += sm;
+        D[4] += sm;
+        D[8] += sm;
+    }
+    store_block_inverse<DIM>(c, row, D);
 }
 
 // r = F_ext + f(u0) on the free components (one wave per row)
-template <int DIM>
+// (MF: f(u0) already in q, written by the force kernels)
+template <int DIM, bool MF>
 __global__ __launch_bounds__(256) void k_cg_residual(StepArgs a, CgArgs c, int cur) {
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= a.n_pad) return;
     double f[3];
-    row_product<DIM>(c, row, a.uv[cur], f);
+    if (MF) {
+        const double4 fq = c.q[row];
+        f[0] = fq.x, f[1] = fq.y, f[2] = fq.z;
+    } else {
+        row_product<DIM>(c, row, a.uv[cur], f);
+    }
     if ((threadIdx.x & 63) != 0) return;
     const uint32_t aux = a.aux[row];
     double4 r = make_double4(f[0], f[1], f[2], 0.0);
@@ -428,9 +499,11 @@ static CgArgs cg_args(const StepArgs &a, const pd_bsr_dev *K, double *work, int 
     const int64_t n_pad = a.n_pad;
     CgArgs c{};
     c.uvc = a.uv[cur];
-    c.row_ptr = K->row_ptr;
-    c.col = K->col;
-    c.vals = reinterpret_cast<const double *>(K->vals);
+    if (K) {
+        c.row_ptr = K->row_ptr;
+        c.col = K->col;
+        c.vals = reinterpret_cast<const double *>(K->vals);
+    }
     double *w = work;
     c.r = reinterpret_cast<double4 *>(w);
     w += 4 * n_pad;
@@ -456,21 +529,6 @@ static CgArgs cg_args(const StepArgs &a, const pd_bsr_dev *K, double *work, int 
     return c;
 }
 
-hipError_t launch_cg_start(const StepArgs &a, const pd_bsr_dev *K, double *work, int cur, hipStream_t s) {
-    const CgArgs c = cg_args(a, K, work, cur);
-    const unsigned nrow = (unsigned)((a.n_pad + 255) / 256), nwave = (unsigned)((a.n_pad + 3) / 4);
-    if (a.dim == 3) {
-        hipLaunchKernelGGL((k_cg_dinv<3>), dim3(nwave), dim3(256), 0, s, a, c);
-        hipLaunchKernelGGL((k_cg_residual<3>), dim3(nwave), dim3(256), 0, s, a, c, cur);
-    } else {
-        hipLaunchKernelGGL((k_cg_dinv<2>), dim3(nwave), dim3(256), 0, s, a, c);
-        hipLaunchKernelGGL((k_cg_residual<2>), dim3(nwave), dim3(256), 0, s, a, c, cur);
-    }
-    hipLaunchKernelGGL(k_cg_vec, dim3(nrow), dim3(256), 0, s, a, c, 0);
-    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(256), 0, s, c, (int)nrow, 0);
-    return hipGetLastError();
-}
-
 // restoring force f(uv[buf]) (Eq. 2.2 summed, no breaking, no update) into
 // q by the double force kernels
 static hipError_t force_into_q(const StepArgs &a, const CgArgs &c, int buf, hipStream_t s) {
@@ -482,6 +540,38 @@ static hipError_t force_into_q(const StepArgs &a, const CgArgs &c, int buf, hipS
     if (e != hipSuccess) return e;
     return tiled ? launch_tpass2_f64(af, buf, false, s) : launch_pass2_f64(af, buf, false, 256, s);
 }
+
+// block-Jacobi diagonal: from the stored K when there is one, else from the
+// bonds (k_cg_dinv_mf)
+static void launch_dinv(const StepArgs &a, const pd_bsr_dev *K, const CgArgs &c, hipStream_t s) {
+    const unsigned nwave = (unsigned)((a.n_pad + 3) / 4), nsl = (unsigned)((a.n_slices + 3) / 4);
+    if (K) {
+        if (a.dim == 3) hipLaunchKernelGGL((k_cg_dinv<3>), dim3(nwave), dim3(256), 0, s, a, c);
+        else hipLaunchKernelGGL((k_cg_dinv<2>), dim3(nwave), dim3(256), 0, s, a, c);
+    } else {
+        if (a.dim == 3) hipLaunchKernelGGL((k_cg_dinv_mf<3>), dim3(nsl), dim3(256), 0, s, a, c);
+        else hipLaunchKernelGGL((k_cg_dinv_mf<2>), dim3(nsl), dim3(256), 0, s, a, c);
+    }
+}
+
+hipError_t launch_cg_start(const StepArgs &a, const pd_bsr_dev *K, double *work, int cur, bool mf, hipStream_t s) {
+    const CgArgs c = cg_args(a, K, work, cur);
+    const unsigned nrow = (unsigned)((a.n_pad + 255) / 256), nwave = (unsigned)((a.n_pad + 3) / 4);
+    hipError_t e;
+    if (mf && (e = force_into_q(a, c, cur, s)) != hipSuccess) return e;
+    launch_dinv(a, K, c, s);
+    if (a.dim == 3) {
+        if (mf) hipLaunchKernelGGL((k_cg_residual<3, true>), dim3(nwave), dim3(256), 0, s, a, c, cur);
+        else hipLaunchKernelGGL((k_cg_residual<3, false>), dim3(nwave), dim3(256), 0, s, a, c, cur);
+    } else {
+        if (mf) hipLaunchKernelGGL((k_cg_residual<2, true>), dim3(nwave), dim3(256), 0, s, a, c, cur);
+        else hipLaunchKernelGGL((k_cg_residual<2, false>), dim3(nwave), dim3(256), 0, s, a, c, cur);
+    }
+    hipLaunchKernelGGL(k_cg_vec, dim3(nrow), dim3(256), 0, s, a, c, 0);
+    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(256), 0, s, c, (int)nrow, 0);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_nm_start(const StepArgs &a, const pd_bsr_dev *K, double *work, double dt, int cur, bool mf,
                            hipStream_t s) {
@@ -504,8 +594,7 @@ hipError_t launch_nm_start(const StepArgs &a, const pd_bsr_dev *K, double *work,
     if (mf && (e = force_into_q(a, c, cur ^ 1, s)) != hipSuccess) return e;
     PD_NM(k_nm_rhs, a, c, dt, cur);
 #undef PD_NM
-    if (a.dim == 3) hipLaunchKernelGGL((k_cg_dinv<3>), dim3(nwave), dim3(256), 0, s, a, c);
-    else hipLaunchKernelGGL((k_cg_dinv<2>), dim3(nwave), dim3(256), 0, s, a, c);
+    launch_dinv(a, K, c, s);
     hipLaunchKernelGGL(k_cg_vec, dim3(nrow), dim3(256), 0, s, a, c, 0);
     hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(256), 0, s, c, (int)nrow, 0);
     return hipGetLastError();

@@ -458,23 +458,26 @@ class Solver:
                                                                  C.byref(self.K)))
 
     def static_solve(self, tol: float = 1e-12, max_iter: int = 20000, check_every: int = 50,
-                     matrix_free: bool = False) -> dict:
+                     matrix_free: bool = False, use_K: bool = True) -> dict:
         """Static equilibrium from the current state with the assembled
         double K (pd_static_solve); the solution replaces u.  matrix_free:
-        the CG products by the double force kernels."""
+        the CG products by the double force kernels; use_K=False (with
+        matrix_free) passes no K at all."""
         L = A.load()
         nw = int(L.pd_static_workspace(self.n_pad))
         if getattr(self, "_cg_work", None) is None or self._cg_work.numel() < nw:
             self._cg_work = torch.zeros(nw, dtype=torch.float64, device=self.dev)
         o = A.pd_cg_opts(float(tol), int(max_iter), int(check_every), 1 if matrix_free else 0, 0)
         rep = A.pd_cg_report()
-        self.ctx.check("pd_static_solve", L.pd_static_solve(self.ctx.h, C.byref(self.P), C.byref(self.K),
+        Kp = C.byref(self.K) if use_K else None
+        self.ctx.check("pd_static_solve", L.pd_static_solve(self.ctx.h, C.byref(self.P), Kp,
                                                               C.byref(self.S), C.byref(o), _tp(self._cg_work),
                                                               C.byref(rep)))
         return dict(iterations=rep.iterations, converged=bool(rep.converged), rel_residual=rep.rel_residual)
 
     def newmark_step(self, nsteps: int, dt: float, breaking: bool = False, tol: float = 1e-12,
-                     max_iter: int = 20000, check_every: int = 50, matrix_free: bool = False) -> dict:
+                     max_iter: int = 20000, check_every: int = 50, matrix_free: bool = False,
+                     use_K: bool = True) -> dict:
         """nsteps implicit average-acceleration Newmark steps with the
         assembled double K (pd_newmark_step); the state advances in place."""
         L = A.load()
@@ -485,7 +488,8 @@ class Solver:
                                                     1 if matrix_free else 0, 0),
                               1 if breaking else 0, 0)
         rep = A.pd_cg_report()
-        self.ctx.check("pd_newmark_step", L.pd_newmark_step(self.ctx.h, C.byref(self.P), C.byref(self.K),
+        Kp = C.byref(self.K) if use_K else None
+        self.ctx.check("pd_newmark_step", L.pd_newmark_step(self.ctx.h, C.byref(self.P), Kp,
                                                               C.byref(self.S), int(nsteps), C.byref(o),
                                                               _tp(self._nm_work), C.byref(rep)))
         return dict(iterations=rep.iterations, converged=bool(rep.converged), rel_residual=rep.rel_residual)

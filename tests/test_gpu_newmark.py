@@ -48,8 +48,8 @@ def base_dt(w):
     return float(np.asarray(w.dt).reshape(-1)[0])
 
 
-@pytest.mark.parametrize("mf", [False, True], ids=["stored_K", "matrix_free"])
-def test_cantilever_matches_direct_newmark(ctx, mf):
+@pytest.mark.parametrize("op", ["stored_K", "matrix_free", "no_K"])
+def test_cantilever_matches_direct_newmark(ctx, op):
     """12 steps at 20x the explicit time step under the tip load; the CG
     products with the stored K or by the double force kernels."""
     w = W.cantilever3d()
@@ -66,16 +66,16 @@ def test_cantilever_matches_direct_newmark(ctx, mf):
     uo, vo = o.initial_state()
     ur, vr, _ = dense.newmark_run(w, o, uo, vo, dt, n)
     s = implicit_solver(w, ctx)
-    rep = s.newmark_step(n, dt, tol=TOL, matrix_free=mf)
+    rep = s.newmark_step(n, dt, tol=TOL, matrix_free=op != "stored_K", use_K=op != "no_K")
     assert rep["converged"], rep
     u, v = s.read()
     assert rel(u, ur) <= BAR, rel(u, ur)
     assert rel(v, vr) <= BAR, rel(v, vr)
 
 
-@pytest.mark.parametrize("mf", [False, True], ids=["stored_K", "matrix_free"])
+@pytest.mark.parametrize("op", ["stored_K", "matrix_free", "no_K"])
 @pytest.mark.parametrize("name", ["plate_notched", "cylinder"])
-def test_trajectory_with_breaking(ctx, name, mf):
+def test_trajectory_with_breaking(ctx, name, op):
     """Breaking tested at the start of every step, K re-assembled around new
     breaks: the notched plate under a traction that opens the notch (5x the
     explicit step), and a small cylinder whose end layers turn at a
@@ -93,7 +93,7 @@ def test_trajectory_with_breaking(ctx, name, mf):
     done = 0
     for target in stops:
         uo, vo, rho = dense.newmark_run(w, o, uo, vo, dt, target - done, rho_bond=rho, breaking=True)
-        rep = s.newmark_step(target - done, dt, breaking=True, tol=TOL, matrix_free=mf)
+        rep = s.newmark_step(target - done, dt, breaking=True, tol=TOL, matrix_free=op != "stored_K", use_K=op != "no_K")
         done = target
         u, v = s.read()
         assert rel(u, uo) <= BAR, (target, rel(u, uo), rep)
