@@ -755,7 +755,7 @@ pd_status pd_static_solve(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
     return PD_OK;
 }
 
-int64_t pd_newmark_workspace(int64_t n_pad) { return n_pad < 0 ? -1 : pdk::nm_workspace_doubles(n_pad); }
+int64_t pd_newmark_workspace(int64_t n_pad) { return n_pad > 0 ? pdk::nm_workspace_doubles(n_pad) : 0; }
 
 pd_status pd_newmark_step(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *K, pd_state_dev *st, int32_t nsteps,
                           const pd_newmark_opts *o, double *work, pd_cg_report *rep) {

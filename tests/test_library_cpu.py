@@ -428,6 +428,23 @@ def test_argument_errors(lib):
     assert lib.pd_damage(None, C.byref(pr), None, None) == -1
     ps = A.pd_profile_stats()
     assert lib.pd_profile_read(None, C.byref(ps), 0) == -1
+    o = A.pd_newmark_opts(1e-6, A.pd_cg_opts(1e-10, 10, 5, 1, 0), 0, 0)
+    rep = A.pd_cg_report()
+    assert lib.pd_newmark_step(None, C.byref(pr), None, C.byref(st), 1, C.byref(o), None, C.byref(rep)) == -1
+    assert lib.pd_static_solve(None, C.byref(pr), None, C.byref(st), C.byref(o.cg), None, C.byref(rep)) == -1
+
+
+def test_solver_workspace_sizes(lib):
+    """The static solve's workspace holds five double4 vectors, the 3x3
+    block inverses (12 doubles a row), two partial sums per 256 rows and 16
+    scalars; the implicit step's adds a_n (double4) and the mass per row
+    after a 32-byte boundary."""
+    for n in (64, 128, 256 * 7 + 64, 911360):
+        nb = (n + 255) // 256
+        st = 5 * 4 * n + 12 * n + 2 * nb + 16
+        assert lib.pd_static_workspace(n) == st
+        assert lib.pd_newmark_workspace(n) == ((st + 3) // 4) * 4 + 5 * n
+    assert lib.pd_newmark_workspace(-1) == 0 and lib.pd_static_workspace(0) == 0
 
 
 # --------------------------------------------------------------------------
