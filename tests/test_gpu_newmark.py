@@ -133,3 +133,25 @@ def test_newmark_checks(ctx):
             s.newmark_step(1, dt)
     with pytest.raises(A.PDError):
         s.newmark_step(-1, base_dt(w))
+
+
+def test_full_cylinder_conserves_energy(ctx):
+    """The 911,319-node cylinder, no load, ends held fixed, random free
+    velocities: the average-acceleration rule conserves kinetic plus strain
+    energy (pd_energy) at any size, here with no stored K and 10x the
+    explicit step; the drift is the solves' tolerance, not the rule's."""
+    from paper_2309_11273_amd.solver import Solver
+    w = W.cylinder3d()
+    w.fext = np.zeros((w.n, 3))
+    rng = np.random.default_rng(9)
+    v0 = rng.standard_normal((w.n, 3)) * 1e-3
+    v0[np.asarray(w.bc) != 0] = 0.0
+    w.v0 = v0
+    s = Solver(w, ctx=ctx)
+    k0, e0 = s.energy()
+    assert e0 == 0.0 and k0 > 0.0
+    rep = s.newmark_step(5, 10 * base_dt(w), tol=1e-12, check_every=10, matrix_free=True, use_K=False)
+    assert rep["converged"], rep
+    k1, e1 = s.energy()
+    assert e1 > 0.0
+    assert abs((k1 + e1) - k0) <= 1e-8 * k0, ((k1 + e1) / k0 - 1.0, rep)
