@@ -207,6 +207,59 @@ def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto", extension=
     return time.perf_counter() - t0
 
 
+def golden_compare(s, name, step):
+    """Error against the CPU reference at 'step' of the full workload, from
+    the reference's stored full-length outputs (tests/golden/, written by the
+    reference alone): relative L2 of the displacement over the stored node
+    sample and the bonds on whose status the two runs differ.  None if no
+    stored output covers this workload and step."""
+    import hashlib
+
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path, allow_pickle=False)
+    meta = json.loads(str(g["meta"]))
+    if step not in meta["snapshots"]:
+        return None
+    k = meta["snapshots"].index(step)
+    u, _ = s.read()
+    idx = g["sample"]
+    ur = g[f"u{k}"]
+    keys_g = s.broken_keys()
+    n_ref = int(g[f"brk_count{k}"])
+    sha = hashlib.sha256(np.ascontiguousarray(np.sort(keys_g), dtype="<i8").tobytes()).hexdigest()
+    out = {"step": step, "rel_l2_u_sample": float(np.linalg.norm(u[idx] - ur) / np.linalg.norm(ur)),
+           "sample_nodes": int(idx.size), "broken_oracle": n_ref, "broken_gpu": int(keys_g.size),
+           "broken_sets_identical": bool(keys_g.size == n_ref and sha == str(g[f"brk_sha{k}"])),
+           "first_break_step_oracle": meta.get("first_break_step")}
+    if f"brk_dkeys{k}" in g.files:
+        keys_o = np.cumsum(g[f"brk_dkeys{k}"].astype(np.int64))
+        out["bonds_differ"] = int(np.setxor1d(keys_o, keys_g).size)
+    return out
+
+
+def run_window(s, w, args, precision, preroll, chunk, extension="linear", kernel="auto"):
+    """Untimed pre-roll, warm-up, then the timed steps; returns the wall time
+    of the timed steps and the step counter at their end."""
+    import torch
+    if preroll > 0:
+        s.step(preroll, precision=precision, form=args.form, graph_chunk=chunk, report=False, kernel=kernel,
+               extension=extension)
+    el = time_gpu(s, args.steps, args.warmup, precision, args.form, chunk, kernel, extension)
+    torch.cuda.synchronize()
+    return el, preroll + args.warmup + args.steps
+
+
+def default_preroll(args, w):
+    """Untimed steps before the warm-up so that the timed window ends where
+    the workload's run ends (for the cylinder: inside its fracture phase)."""
+    if args.preroll >= 0:
+        return args.preroll
+    return max(0, int(w.steps) - args.warmup - args.steps)
+
+
 def batch_baseline(n_plates, steps, chunk):
     """Wall time of 'steps' FP64 steps of every plate of the batch, one plate
     after the other, each with its own solver, context and captured graph."""
@@ -283,6 +336,82 @@ def cpu_baseline(w, budget_s: float, mode: str = "step"):
                        f"after one untimed one, FP64 loop reference with OpenMP over nodes")
 
 
+def leg_roofline(s, args, nnz, n, n_loaded):
+    """Kernel durations of the FP32 tile path (HIP events, eager steps) and
+    the roofline of its dominant kernel."""
+    s.profile_read(reset=True)
+    s.step(args.profile_steps, precision="fp32", profile=True, report=False)
+    prof = s.profile_read(reset=True)
+    ps = max(1, prof["steps"])
+    ms1, ms2 = prof["ms_pass1"] / ps, prof["ms_pass2"] / ps
+    a = argparse.Namespace(kernel="auto", precision="fp32", extension="linear", workload=args.workload)
+    return roofline_entry(s, a, "pass2" if ms2 >= ms1 else "pass1", ms1, ms2, nnz, n, n_loaded)
+
+
+def batched_leg(args):
+    """The 256-plate batch: FP32 force path, all plates in one launch per
+    pass (graph replay), against plain FP64 run one plate at a time (each
+    plate its own solver and graph), both over the same timed steps at the
+    end of the 1000-step run."""
+    import numpy as np
+    import torch
+    from paper_2309_11273_amd.solver import Solver
+    w, desc = make_workload("batch2d")
+    t0 = time.perf_counter()
+    s = Solver(w, device=0)
+    setup = time.perf_counter() - t0
+    sz = s.fam.sizes
+    nb, nnz = int(sz.n_bonds), int(sz.nnz)
+    n_loaded = int(np.count_nonzero(np.abs(w.fext).sum(1)))
+    a = argparse.Namespace(**vars(args))
+    a.workload, a.form = "batch2d", "mf"
+    pre = default_preroll(a, w)
+    el, end = run_window(s, w, a, "fp32", pre, args.graph_chunk)
+    err = golden_compare(s, "batch2d", end)
+    st = s.step(0, precision="fp32")
+    roof = leg_roofline(s, a, nnz, int(sz.n), n_loaded)
+    s.reset()
+    el64, _ = run_window(s, w, a, "fp64", pre, args.graph_chunk)
+    del s
+    torch.cuda.empty_cache()
+    el_b = batch_baseline(w.n_specimens, args.steps, args.graph_chunk)
+    v32 = nb * args.steps / el
+    return {"workload": desc, "nodes": int(sz.n), "unique_bonds": nb, "setup_s": round(setup, 2),
+            "timed_window": [pre + args.warmup, pre + args.warmup + args.steps],
+            "fp32_batched": {"value": v32, "ms_per_step": 1e3 * el / args.steps,
+                             "broken_bonds_after_run": int(st["broken_total"]) // 2,
+                             "fp64_rechecks": int(st["rechecks"]), "roofline": roof, "error_vs_oracle": err},
+            "fp64_batched": {"value": nb * args.steps / el64, "ms_per_step": 1e3 * el64 / args.steps},
+            "fp64_one_plate_at_a_time": {"value": nb * args.steps / el_b, "ms_per_step": 1e3 * el_b / args.steps},
+            "fp32_batched_speedup_vs_fp64_one_at_a_time": v32 / (nb * args.steps / el_b),
+            "fp32_batched_speedup_vs_fp64_batched": el64 / el}
+
+
+def cylinder_dx05_leg(args):
+    """The cylinder at dx = 0.5 mm (1,572,000 nodes), FP32 force path, timed
+    at the end of its 5000-step run, with its own roofline."""
+    import numpy as np
+    from paper_2309_11273_amd.solver import Solver
+    w, desc = make_workload("cylinder3d_dx05")
+    t0 = time.perf_counter()
+    s = Solver(w, device=0)
+    setup = time.perf_counter() - t0
+    sz = s.fam.sizes
+    nb, nnz = int(sz.n_bonds), int(sz.nnz)
+    a = argparse.Namespace(**vars(args))
+    a.workload, a.form = "cylinder3d_dx05", "mf"
+    pre = default_preroll(a, w)
+    el, end = run_window(s, w, a, "fp32", pre, args.graph_chunk)
+    err = golden_compare(s, "cylinder3d_dx05", end)
+    st = s.step(0, precision="fp32")
+    roof = leg_roofline(s, a, nnz, int(sz.n), 0)
+    return {"workload": desc, "nodes": int(sz.n), "unique_bonds": nb, "setup_s": round(setup, 2),
+            "timed_window": [pre + args.warmup, pre + args.warmup + args.steps],
+            "value": nb * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+            "broken_bonds_after_run": int(st["broken_total"]) // 2, "fp64_rechecks": int(st["rechecks"]),
+            "roofline": roof, "error_vs_oracle": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +449,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--preroll", type=int, default=-1,
+                    help="untimed steps before the warm-up; -1 (default): the workload's step count minus "
+                         "warm-up and timed steps, so the timed window ends where the run does (the "
+                         "cylinder's fracture phase) and the state can be compared with the stored "
+                         "full-length reference outputs")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="default run only: skip the batched (256 plates) and dx = 0.5 mm cylinder legs")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="size in MiB of the plain read+write kernel timed after the run (the HBM ceiling "
                          "and the known-size reference for the byte counters); 0 = 1024")
@@ -444,13 +580,19 @@ def main():
                             "kernel_ms": round(ms_step, 5), "algorithmic_bytes": int(byt * its)}}
         print(json.dumps(out), flush=True)
         return
+    preroll = 0
+    err_vs_oracle = None
     if args.adr:
         el = time_adr(s, args.steps, args.warmup, args.graph_chunk, args.kernel, args.extension)
     else:
-        el = time_gpu(s, args.steps, args.warmup, args.precision, args.form, args.graph_chunk, args.kernel,
-                      args.extension)
+        preroll = default_preroll(args, w)
+        el, end_step = run_window(s, w, args, args.precision, preroll, args.graph_chunk, args.extension,
+                                  args.kernel)
+        if args.extension == "linear":
+            err_vs_oracle = golden_compare(s, args.workload, end_step)
     ms_per_step = 1e3 * el / args.steps
     value = n_bonds * args.steps / el
+    st_end = s.step(0, precision=args.precision, form=args.form) if not args.adr else None
 
     # kernel durations with HIP events on the launch stream
     s.profile_read(reset=True)
@@ -489,7 +631,7 @@ def main():
     else:
         roofline = None
 
-    st = s.adr_step(0) if args.adr else s.step(0, precision=args.precision, form=args.form)
+    st = s.adr_step(0) if args.adr else st_end
     if args.adr:
         st["rechecks"] = 0
     out = {
@@ -511,23 +653,36 @@ def main():
                            + (", finite extension (Eqs. 1.10, 1.13)" if args.extension == "finite" else "")
                            + (", adaptive dynamic relaxation iterations" if args.adr else ""),
                    "state_dtype": "f64", "graph_chunk": args.graph_chunk, "setup_s": round(setup_s, 2),
+                   "untimed_steps_before_warmup": preroll,
+                   "timed_window": [preroll + args.warmup, preroll + args.warmup + args.steps],
                    "broken_bonds_after_run": int(st["broken_total"]) // 2,
-                   "fp64_rechecks": int(st["rechecks"])},
+                   "fp64_rechecks": int(st["rechecks"]),
+                   "min_recheck_margin": st.get("min_margin")},
         "roofline": roofline,
+        "error_vs_oracle": err_vs_oracle,
     }
     if not args.no_fp64 and args.precision == "fp32":
         s.reset()
-        el64 = time_gpu(s, args.steps, args.warmup, "fp64", args.form if args.form == "mf" else "mf",
-                        args.graph_chunk)
+        el64, end64 = run_window(s, w, args, "fp64", preroll, args.graph_chunk)
+        err64 = golden_compare(s, args.workload, end64)
+        st64 = s.step(0, precision="fp64")
         s.profile_read(reset=True)
         s.step(args.profile_steps, precision="fp64", profile=True, report=False)
         p64 = s.profile_read(reset=True)
         ps = max(1, p64["steps"])
         out["fp64"] = {"value": n_bonds * args.steps / el64, "ms_per_step": 1e3 * el64 / args.steps,
-                       "pass1_ms": p64["ms_pass1"] / ps, "pass2_ms": p64["ms_pass2"] / ps}
+                       "pass1_ms": p64["ms_pass1"] / ps, "pass2_ms": p64["ms_pass2"] / ps,
+                       "broken_bonds_after_run": int(st64["broken_total"]) // 2, "error_vs_oracle": err64}
         out["fp32_speedup_vs_fp64"] = value / out["fp64"]["value"]
     del s
     torch.cuda.empty_cache()
+    legs = (args.workload == "cylinder3d" and args.form == "mf" and args.precision == "fp32" and not args.adr
+            and args.extension == "linear" and not args.no_legs)
+    if legs:
+        out["batched"] = batched_leg(args)
+        torch.cuda.empty_cache()
+        out["cylinder3d_dx05"] = cylinder_dx05_leg(args)
+        torch.cuda.empty_cache()
     if args.batch_baseline and args.workload == "batch2d":
         el_b = batch_baseline(w.n_specimens, args.steps, args.graph_chunk)
         out["batch_baseline"] = {"kind": "plain FP64, one plate at a time",

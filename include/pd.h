@@ -350,6 +350,21 @@ typedef struct pd_step_opts {
                             along the deformed bond (Eqs. 1.10, 1.13): PD_FP64,
                             PD_MATRIX_FREE; double tile kernels or, with kernel = 1
                             or a family they do not fit, gather kernels            */
+    int32_t energy_check;/* 1: at every check (every check_every steps, and at the end
+                            of the call) compute the kinetic energy 1/2 sum rho V v.v
+                            and the strain energy sum V_i W_i of Eq. 1.20 (in double,
+                            from the double state, with the extension of the step;
+                            fixed-order reductions, so the values are the same on
+                            every run), and stop with PD_ERR_UNSTABLE when their sum
+                            exceeds energy_growth times the sum of the previous
+                            check of this state (pd_state_init clears the history).
+                            The first use allocates a small reduction buffer in the
+                            context (4 doubles per 256 rows).  0: no energies      */
+    int32_t pad0;
+    double energy_growth;/* growth factor of the energy check; <= 0 means 1e3. An
+                            explicit step beyond the stability limit multiplies the
+                            energy of its unstable mode several times per step, while
+                            loading grows it like a low power of time          */
 } pd_step_opts;
 
 /* Kernel timings gathered by pd_step with opts->profile = 1 (milliseconds,
@@ -397,6 +412,14 @@ typedef struct pd_step_report {
     int32_t nonfinite;      /* 1 if a non-finite displacement was produced            */
     int32_t pad0;
     double umax;            /* max |u| component at the end                           */
+    double min_margin;      /* smallest |s - s_c| / s_c (Eqs. 1.17, 1.30) among the bonds
+                               whose breaking the FP32 path decided in double precision
+                               (rechecks and shadow fallbacks) since pd_state_init,
+                               rounded to float; +inf if none (and on the FP64 paths,
+                               whose every decision is taken in double)               */
+    double kinetic;         /* energies of the last energy check (opts.energy_check),  */
+    double strain;          /* Eq. 1.20; 0 if none since pd_state_init                 */
+    int64_t energy_step;    /* step counter at that check; -1 if none                  */
 } pd_step_report;
 
 /* Advance 'nsteps' explicit steps.  Each step n (t_n = n dt):
@@ -412,10 +435,18 @@ typedef struct pd_step_report {
  *   4. update (Eqs. 2.11, 2.12): a = (f + F_ext r(n)) / (rho V), zero on
  *      prescribed components; v += dt a; u += dt v.
  * 'rep' (may be NULL) is filled after synchronising the stream; with
- * rep == NULL and check_every == 0 the call is fully asynchronous.
+ * rep == NULL, check_every == 0 and energy_check == 0 the call is fully
+ * asynchronous.  The FP32_RECHECK matrix-free path keeps its fixed-point
+ * displacement shadow, the shadow scale and the row constants D_i in the
+ * state between calls, so a trajectory is the same bits however its steps
+ * are split across calls (for one kernel kind); they are rebuilt from the
+ * double state whenever another path, pd_state_init, a solve or a kernel
+ * kind change has touched the state since.  After changing the state or
+ * the bond status from the host, call pd_state_init.
  * Errors: PD_ERR_ARG, PD_ERR_UNSUPPORTED (PD_BSR without K, unknown
  * option, PD_FACTORED: use pd_fac_step), PD_ERR_UNSTABLE (non-finite state
- * seen at a check), PD_ERR_HIP. */
+ * seen at a check, or energy growth beyond opts.energy_growth at an energy
+ * check; the state is left as the last step produced it), PD_ERR_HIP. */
 struct pd_bsr_dev;
 pd_status pd_step(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st, int64_t nsteps,
                   const pd_step_opts *opts, struct pd_bsr_dev *K, pd_step_report *rep);
@@ -692,8 +723,11 @@ pd_status pd_newmark_step(pd_ctx *ctx, const pd_problem_dev *prob, const struct 
 pd_status pd_damage(pd_ctx *ctx, const pd_problem_dev *prob, const uint64_t *mask, double *phi);
 
 /* Energies of the current state (synchronises): kinetic 1/2 sum rho V v.v
- * and strain 1/2 sum u.(-f(u)) (the quadratic energy whose gradient is
- * Eq. 2.2).  f_scratch [device] n_pad*4. */
+ * and strain sum V_i W_i with W_i of Eq. 1.20 (in the constants of Eqs.
+ * 1.8, 1.15, 1.16, linearized extension; for this quadratic energy it equals
+ * 1/2 u.(-f(u)), its gradient being the force of Eq. 2.2), in double with
+ * fixed-order reductions (the same bits on every run).  f_scratch [device]
+ * n_pad*4 doubles, 32-byte aligned: work space of the reductions. */
 pd_status pd_energy(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st,
                     double *f_scratch, double *kinetic, double *strain);
 

@@ -54,6 +54,9 @@ def lib():
         L.orc_n_close.restype = i64
         L.orc_n_close.argtypes = [P]
         L.orc_reset_margin.argtypes = [P]
+        L.orc_track_bond_margins.argtypes = [P, i32]
+        L.orc_get_bond_margins.restype = i32
+        L.orc_get_bond_margins.argtypes = [P, P]
         L.orc_constants.argtypes = [i32, dbl, dbl, P]
         L.orc_critical_stretch.restype = dbl
         L.orc_critical_stretch.argtypes = [i32, dbl, dbl, dbl, dbl, i32]
@@ -197,6 +200,17 @@ class Oracle:
 
     def reset_margin(self):
         lib().orc_reset_margin(self.h)
+
+    def track_bond_margins(self, on: bool = True):
+        """Start (or stop) recording, per bond, the smallest |s - s_c| / s_c
+        seen while the bond was intact."""
+        lib().orc_track_bond_margins(self.h, 1 if on else 0)
+
+    def bond_margins(self) -> np.ndarray:
+        out = np.empty(self.nb)
+        if lib().orc_get_bond_margins(self.h, _p(out)) != 0:
+            raise RuntimeError("bond margins are not tracked (call track_bond_margins first)")
+        return out
 
     # ---- operators -----------------------------------------------------
     def force(self, u: np.ndarray):

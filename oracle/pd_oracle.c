@@ -109,6 +109,9 @@ typedef struct {
     /* breaking diagnostics of the last run */
     double min_margin;  /* min |s - s_c| / s_c over evaluated intact bonds */
     int64_t n_close6;   /* evaluations with margin < 1e-6 */
+    double *bmargin;    /* nb running min of |s - s_c| / s_c per bond over the
+                           evaluations made while it was intact (the breaking
+                           evaluation included); NULL = not tracked */
 } orc_model;
 
 /* ------------------------------------------------------------------------ */
@@ -305,7 +308,7 @@ void orc_free(orc_model *o) {
     if (!o) return;
     free(o->X); free(o->lat); free(o->V); free(o->sp);
     free(o->bi); free(o->bj); free(o->xl); free(o->M); free(o->rho); free(o->brk); free(o->e); free(o->My);
-    free(o->aptr); free(o->abond); free(o->m); free(o->theta);
+    free(o->aptr); free(o->abond); free(o->m); free(o->theta); free(o->bmargin);
     free(o);
 }
 
@@ -329,6 +332,23 @@ void orc_set_step(orc_model *o, int64_t s) { o->step = s; }
 double orc_min_margin(const orc_model *o) { return o->min_margin; }
 int64_t orc_n_close(const orc_model *o) { return o->n_close6; }
 void orc_reset_margin(orc_model *o) { o->min_margin = INFINITY; o->n_close6 = 0; }
+
+/* Per-bond breaking margins (a diagnostic: how close each bond came to the
+ * critical stretch of Eq. 1.30; the arithmetic of a step is unchanged).
+ * on != 0 starts tracking from +inf, on == 0 stops and frees the array. */
+void orc_track_bond_margins(orc_model *o, int on) {
+    free(o->bmargin);
+    o->bmargin = NULL;
+    if (!on) return;
+    o->bmargin = (double *)malloc(sizeof(double) * (o->nb + 1));
+    for (int64_t b = 0; b < o->nb; b++) o->bmargin[b] = INFINITY;
+}
+/* Copies the running minima into out[nb]; returns 0, or -1 if not tracked. */
+int orc_get_bond_margins(const orc_model *o, double *out) {
+    if (!o->bmargin) return -1;
+    memcpy(out, o->bmargin, sizeof(double) * o->nb);
+    return 0;
+}
 
 /* ------------------------------------------------------------------------ */
 /* material constants and critical stretch                                  */
@@ -509,6 +529,7 @@ static void break_bonds(orc_model *o, const double *u, int64_t step) {
         double margin = fabs(s - s0) / s0;
         if (margin < mm) mm = margin;
         if (margin < 1e-6) close++;
+        if (o->bmargin && margin < o->bmargin[b]) o->bmargin[b] = margin;
         if (s >= s0) { o->rho[b] = 0; o->brk[b] = (int32_t)step; }
     }
     if (mm < o->min_margin) o->min_margin = mm;

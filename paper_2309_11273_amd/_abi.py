@@ -62,7 +62,8 @@ class pd_state_dev(C.Structure):
 
 class pd_step_opts(C.Structure):
     _fields_ = [("precision", i32), ("form", i32), ("graph_chunk", i32), ("block", i32),
-                ("check_every", i32), ("profile", i32), ("kernel", i32), ("extension", i32)]
+                ("check_every", i32), ("profile", i32), ("kernel", i32), ("extension", i32),
+                ("energy_check", i32), ("pad0", i32), ("energy_growth", dbl)]
 
 
 class pd_profile_stats(C.Structure):
@@ -76,7 +77,8 @@ class pd_tune_result(C.Structure):
 
 class pd_step_report(C.Structure):
     _fields_ = [("step", i64), ("broken_total", i64), ("rechecks", i64), ("nonfinite", i32),
-                ("pad0", i32), ("umax", dbl)]
+                ("pad0", i32), ("umax", dbl), ("min_margin", dbl), ("kinetic", dbl), ("strain", dbl),
+                ("energy_step", i64)]
 
 
 class pd_bsr_sizes(C.Structure):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "adr.h"
 #include "cg.h"
@@ -24,10 +25,12 @@ struct pd_ctx {
     std::string err;
     pd_ctl *host_ctl = nullptr;        // pinned copy of the control block
     hipGraphExec_t gexec = nullptr;
-    uint64_t gkey = 0;
+    std::vector<unsigned char> gkey;  // launch parameters the graph was captured with
     int gsteps = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // profiling events
     pd_profile_stats prof{};
+    double4 *part = nullptr;           // partials of the fixed-order reductions
+    int64_t part_n = 0;
 };
 
 namespace {
@@ -74,6 +77,7 @@ pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
     a.slice_ptr = p->slice_ptr;
     a.words = p->words;
     a.stencil = p->stencil;
+    a.inv_m = p->inv_m;
     a.spec = p->spec;
     a.aux = p->aux;
     a.fext = reinterpret_cast<const double4 *>(p->fext);
@@ -111,9 +115,20 @@ pd_status check_state(pd_ctx *c, const pd_state_dev *st, bool need_f32) {
     return PD_OK;
 }
 
-uint64_t mix(uint64_t h, uint64_t v) {
-    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
-    return h;
+
+// The context's reduction buffer, grown to hold the partials of n_pad rows.
+pd_status need_parts(pd_ctx *c, int64_t n_pad) {
+    const int64_t n = pdk::reduce_parts(n_pad) + 1;
+    if (n <= c->part_n) return PD_OK;
+    if (c->part) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipFree(c->part));
+        c->part = nullptr;
+        c->part_n = 0;
+    }
+    HIP_TRY(c, hipMalloc(reinterpret_cast<void **>(&c->part), sizeof(double4) * n));
+    c->part_n = n;
+    return PD_OK;
 }
 
 }  // namespace
@@ -156,6 +171,7 @@ pd_status pd_ctx_destroy(pd_ctx *c) {
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+    if (c->part) (void)hipFree(c->part);
     delete c;
     return PD_OK;
 }
@@ -318,7 +334,7 @@ pd_status pd_force(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int32_t
         else HIP_TRY(c, pdk::launch_pass2_f64(a, st->cur, false, 256, c->stream));
     } else {
         const bool tiled = pdk::tiled_supported(a);
-        HIP_TRY(c, pdk::launch_shadow_prep(a, st->cur, c->stream));
+        HIP_TRY(c, pdk::launch_shadow_prep(a, st->cur, tiled, true, c->stream));
         if (tiled) HIP_TRY(c, pdk::launch_tpass1_f32(a, st->cur, false, c->stream));
         else HIP_TRY(c, pdk::launch_pass1_f32(a, st->cur, false, 256, c->stream));
         a.theta_out = nullptr;
@@ -452,11 +468,15 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
         if (o.precision != PD_FP64)
             return fail(c, PD_ERR_UNSUPPORTED, "the factored form stores double values (precision PD_FP64)");
     }
+    if (o.energy_check != 0 && o.energy_check != 1) return fail(c, PD_ERR_ARG, "energy_check must be 0 or 1");
+    if (std::isnan(o.energy_growth)) return fail(c, PD_ERR_ARG, "energy_growth is NaN");
     HIP_TRY(c, hipSetDevice(c->device));
+    const double growth = o.energy_growth > 0.0 ? o.energy_growth : 1e3;
+    if (o.energy_check && (s = need_parts(c, p->n_pad)) != PD_OK) return s;
     pdk::StepArgs a = make_args(p, st);
     int cur = st->cur;
     if (o.precision == PD_FP32_RECHECK && o.form == PD_MATRIX_FREE)
-        HIP_TRY(c, pdk::launch_shadow_prep(a, cur, c->stream));
+        HIP_TRY(c, pdk::launch_shadow_prep(a, cur, o.kernel != 1 && pdk::tiled_supported(a), false, c->stream));
 
     int64_t done = 0;
     const int64_t check = o.check_every > 0 ? o.check_every : nsteps;
@@ -464,28 +484,27 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
         int64_t todo = std::min<int64_t>(check, nsteps - done);
         int64_t chunk = (o.graph_chunk > 0 && !o.profile) ? ((int64_t)o.graph_chunk + 1) / 2 * 2 : 0;
         if (chunk > 0 && todo >= chunk) {
-            uint64_t key = 1469598103934665603ull;
-            const uint64_t fields[] = {(uint64_t)(uintptr_t)p->words, (uint64_t)(uintptr_t)p->spec,
-                                       (uint64_t)(uintptr_t)p->aux, (uint64_t)(uintptr_t)st->uv[0],
-                                       (uint64_t)(uintptr_t)st->uv[1], (uint64_t)(uintptr_t)st->mask,
-                                       (uint64_t)(uintptr_t)st->ctl, (uint64_t)(uintptr_t)st->ush[0],
-                                       (uint64_t)(uintptr_t)st->vel, (uint64_t)o.precision,
-                                       (uint64_t)o.block, (uint64_t)cur, (uint64_t)chunk,
-                                       (uint64_t)p->ramp_steps, (uint64_t)(uintptr_t)p->fext,
-                                       (uint64_t)(uintptr_t)st->qr, (uint64_t)o.kernel, (uint64_t)o.form,
-                                       (uint64_t)(uintptr_t)st->fe32, (uint64_t)(uintptr_t)st->fe64,
-                                       (uint64_t)(uintptr_t)st->qv32,
-                                       (uint64_t)(uintptr_t)K, (uint64_t)(uintptr_t)F,
-                                       (uint64_t)(uintptr_t)R, (uint64_t)o.extension};
-            for (uint64_t f : fields) key = mix(key, f);
-            if (R) {
-                uint64_t dtb;
-                std::memcpy(&dtb, &R->dt, 8);
-                const uint64_t rf[] = {dtb, (uint64_t)(uintptr_t)R->lambda, (uint64_t)(uintptr_t)R->f_prev,
-                                       (uint64_t)(uintptr_t)R->f_int, (uint64_t)(uintptr_t)R->partial,
-                                       (uint64_t)(uintptr_t)R->stats};
-                for (uint64_t f : rf) key = mix(key, f);
-            }
+            // Everything a captured launch bakes in by value: the argument
+            // block, the problem descriptor, the options, the starting
+            // buffer, the chunk and the operator descriptors (by content, not
+            // by address).  Compared byte for byte, so a new problem or a
+            // rebuilt operator never replays a stale graph.
+            std::vector<unsigned char> key;
+            auto add = [&key](const void *q, size_t nb) {
+                const unsigned char *b = static_cast<const unsigned char *>(q);
+                key.insert(key.end(), b, b + nb);
+            };
+            add(&a, sizeof(a));
+            add(p, sizeof(*p));
+            add(&o, sizeof(o));
+            add(&cur, sizeof(cur));
+            add(&chunk, sizeof(chunk));
+            const unsigned char present[3] = {(unsigned char)(K != nullptr), (unsigned char)(F != nullptr),
+                                              (unsigned char)(R != nullptr)};
+            add(present, sizeof(present));
+            if (K) add(K, sizeof(*K));
+            if (F) add(F, sizeof(*F));
+            if (R) add(R, sizeof(*R));
             if (!c->gexec || c->gkey != key) {
                 if (c->gexec) {
                     (void)hipGraphExecDestroy(c->gexec);
@@ -529,13 +548,24 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
             cur ^= 1;
             done++;
         }
-        if (o.check_every > 0) {
+        const bool last = done == nsteps;
+        if (o.check_every > 0 || (o.energy_check && last)) {
             st->cur = cur;
+            if (o.energy_check)
+                HIP_TRY(c, pdk::launch_energy(a, cur, o.extension != 0, c->part, nullptr, 0,
+                                              reinterpret_cast<pd_ctl *>(st->ctl), c->stream));
             HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
-            if (c->host_ctl->flags & PD_CTL_NONFINITE)
-                return fail(c, PD_ERR_UNSTABLE, "non-finite displacement before step %lld",
-                            (long long)c->host_ctl->s2);
+            const pd_ctl *h = c->host_ctl;
+            if (h->flags & PD_CTL_NONFINITE)
+                return fail(c, PD_ERR_UNSTABLE, "non-finite displacement before step %lld", (long long)h->s2);
+            if (o.energy_check) {
+                const double now = h->en[0] + h->en[1], before = h->en[2];
+                if (before > 0.0 && !(now <= growth * before))
+                    return fail(c, PD_ERR_UNSTABLE,
+                                "energy grew from %.6g to %.6g (more than %.3g times) by step %lld", before, now,
+                                growth, (long long)h->s2);
+            }
         }
     }
     st->cur = cur;
@@ -551,6 +581,17 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
         unsigned int bits = h->umax_bits[cur];
         std::memcpy(&um, &bits, 4);
         rep->umax = (double)um;
+        if (h->margin_key) {
+            float mg;
+            const unsigned int mb = ~h->margin_key;
+            std::memcpy(&mg, &mb, 4);
+            rep->min_margin = (double)mg;
+        } else {
+            rep->min_margin = INFINITY;
+        }
+        rep->kinetic = h->en[0];
+        rep->strain = h->en[1];
+        rep->energy_step = h->en[3] > 0.0 ? (int64_t)h->en[3] - 1 : -1;
         if (rep->nonfinite) return fail(c, PD_ERR_UNSTABLE, "non-finite displacement");
     }
     return PD_OK;
@@ -747,6 +788,7 @@ pd_status pd_static_solve(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
         conv = h[5] <= o->tol;
     }
     HIP_TRY(c, pdk::launch_cg_finish(a, K, work, cur, c->stream));
+    HIP_TRY(c, pdk::launch_shadow_invalidate(reinterpret_cast<pd_ctl *>(st->ctl), c->stream));
     if (rep) {
         rep->iterations = (int32_t)h[6];
         rep->converged = conv ? 1 : 0;
@@ -814,6 +856,7 @@ pd_status pd_newmark_step(pd_ctx *c, const pd_problem_dev *p, const pd_bsr_dev *
             conv = h[5] <= o->cg.tol;
         }
         HIP_TRY(c, pdk::launch_nm_finish(a, K, work, o->dt, cur, c->stream));
+        HIP_TRY(c, pdk::launch_shadow_invalidate(reinterpret_cast<pd_ctl *>(st->ctl), c->stream));
         st->cur = cur ^ 1;
         total += (int)h[6];
         all_conv = all_conv && conv;
@@ -909,17 +952,23 @@ pd_status pd_damage(pd_ctx *c, const pd_problem_dev *p, const uint64_t *mask, do
 pd_status pd_energy(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, double *f_scratch, double *kinetic,
                     double *strain) {
     if (!c) return PD_ERR_ARG;
-    if (!f_scratch || !kinetic || !strain) return fail(c, PD_ERR_ARG, "NULL output");
-    pd_status s = pd_force(c, p, st, PD_FP64, f_scratch, nullptr);
+    pd_status s = check_problem(c, p);
     if (s != PD_OK) return s;
-    pd_ctl *ctl = reinterpret_cast<pd_ctl *>(st->ctl);
-    HIP_TRY(c, pdk::launch_energy(p->n_pad, reinterpret_cast<const double4 *>(st->uv[st->cur]),
-                                  reinterpret_cast<const double4 *>(st->vel),
-                                  reinterpret_cast<const double4 *>(f_scratch), p->aux, p->spec, ctl, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!f_scratch || !kinetic || !strain) return fail(c, PD_ERR_ARG, "NULL output");
+    if (reinterpret_cast<uintptr_t>(f_scratch) % 32 != 0) return fail(c, PD_ERR_ARG, "f_scratch must be 32-byte aligned");
+    if (!p->aux) return fail(c, PD_ERR_ARG, "aux is NULL (call pd_state_init first)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const pdk::StepArgs a = make_args(p, st);
+    // partials, then the four sums, inside the caller's n_pad*4 doubles
+    double4 *part = reinterpret_cast<double4 *>(f_scratch);
+    double *out = f_scratch + 4 * pdk::reduce_parts(p->n_pad);
+    HIP_TRY(c, pdk::launch_energy(a, st->cur, false, part, out, 4, nullptr, c->stream));
+    double h[4];
+    HIP_TRY(c, hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    *strain = -0.5 * c->host_ctl->red[0];
-    *kinetic = 0.5 * c->host_ctl->red[1];
+    *kinetic = h[0];
+    *strain = h[1];
     return PD_OK;
 }
 
@@ -931,15 +980,18 @@ pd_status pd_stable_dt(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, dou
     if ((s = check_state(c, st, false)) != PD_OK) return s;
     if (!f_scratch || !dt_crit || iters < 1 || !p->aux) return fail(c, PD_ERR_ARG, "bad arguments");
     HIP_TRY(c, hipSetDevice(c->device));
+    if ((s = need_parts(c, p->n_pad)) != PD_OK) return s;
     double4 *x = reinterpret_cast<double4 *>(st->uv[st->cur]);
     double4 *y = reinterpret_cast<double4 *>(st->uv[st->cur ^ 1]);
     pd_ctl *ctl = reinterpret_cast<pd_ctl *>(st->ctl);
+    // u and v are overwritten: the FP32 shadow no longer describes them
+    HIP_TRY(c, pdk::launch_shadow_invalidate(ctl, c->stream));
     HIP_TRY(c, pdk::launch_pi_init(p->n_pad, p->dim, p->aux, x, seed, c->stream));
     double lam = 0.0;
     for (int it = 0; it < iters; it++) {
         if ((s = pd_force(c, p, st, PD_FP64, f_scratch, nullptr)) != PD_OK) return s;
         HIP_TRY(c, pdk::launch_pi_step(p->n_pad, p->dim, p->aux, p->spec, x,
-                                       reinterpret_cast<const double4 *>(f_scratch), y, ctl, c->stream));
+                                       reinterpret_cast<const double4 *>(f_scratch), y, ctl, c->part, c->stream));
         if (it == iters - 1) {
             HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -16,6 +16,7 @@ struct StepArgs {
     const int64_t *slice_ptr;
     const uint32_t *words;
     const double *stencil;
+    const double *inv_m;
     const pd_spec *spec;
     const uint32_t *aux;
     const double4 *fext;
@@ -79,7 +80,7 @@ hipError_t launch_pass1_f64(const StepArgs &a, int cur, bool brk, int block, hip
 hipError_t launch_pass2_f64(const StepArgs &a, int cur, bool update, int block, hipStream_t s);
 hipError_t launch_pass1_f32(const StepArgs &a, int cur, bool brk, int block, hipStream_t s);
 hipError_t launch_pass2_f32(const StepArgs &a, int cur, bool update, int block, hipStream_t s);
-hipError_t launch_shadow_prep(const StepArgs &a, int cur, hipStream_t s);
+hipError_t launch_shadow_prep(const StepArgs &a, int cur, bool tiled, bool force, hipStream_t s);
 bool tiled_supported(const StepArgs &a);
 hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s);
 hipError_t launch_tpass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s);
@@ -91,8 +92,13 @@ hipError_t launch_state_init(const InitArgs &a, hipStream_t s);
 hipError_t launch_state_read(const int32_t *perm, int64_t n_pad, const double4 *uv, const double4 *vel,
                              double *u_out, double *v_out, hipStream_t s);
 hipError_t launch_damage(const DamageArgs &a, hipStream_t s);
-hipError_t launch_energy(int64_t n_pad, const double4 *uv, const double4 *vel, const double4 *f,
-                         const uint32_t *aux, const pd_spec *spec, pd_ctl *ctl, hipStream_t s);
+// partials (double4 each) of the fixed-order reductions for n_pad rows
+int64_t reduce_parts(int64_t n_pad);
+// kinetic and strain energy (Eq. 1.20) of state buffer cur into out[0..nout-1]
+// (nout <= 4; out[2..3] = 0), or with rec != NULL recorded as the state's
+// energy check; part holds reduce_parts(n_pad) partials
+hipError_t launch_energy(const StepArgs &a, int cur, bool finite, double4 *part, double *out, int nout, pd_ctl *rec,
+                         hipStream_t s);
 hipError_t launch_pi_init(int64_t n_pad, int dim, const uint32_t *aux, double4 *uv, uint64_t seed,
                           hipStream_t s);
 size_t bsr_assemble_lds(int dim, int max_row_blocks, int reach);
@@ -104,6 +110,7 @@ hipError_t launch_break_mark(const StepArgs &a, const pd_problem_dev *p, const p
 hipError_t launch_bsr_spmv(const StepArgs &a, const pd_problem_dev *p, const pd_bsr_dev *K, int cur, bool update,
                            hipStream_t s);
 hipError_t launch_pi_step(int64_t n_pad, int dim, const uint32_t *aux, const pd_spec *spec, double4 *uv,
-                          const double4 *f, double4 *y, pd_ctl *ctl, hipStream_t s);
+                          const double4 *f, double4 *y, pd_ctl *ctl, double4 *part, hipStream_t s);
+hipError_t launch_shadow_invalidate(pd_ctl *ctl, hipStream_t s);
 
 }  // namespace pdk

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 
 #include "kernels.h"
 
@@ -211,18 +212,12 @@ __global__ __launch_bounds__(256) void k_pass2_f64(StepArgs a, int cur) {
 // ---------------------------------------------------------------------------
 __global__ void k_state_init(InitArgs a) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the control block: step counter (words 0, 1) set, every other word cleared
+    if (r >= 2 && r < (int64_t)(sizeof(pd_ctl) / 8)) reinterpret_cast<unsigned long long *>(a.ctl)[r] = 0ull;
+    static_assert(offsetof(pd_ctl, s2) == 8, "step counter in the first two words");
     if (r == 0) {
-        pd_ctl *c = a.ctl;
-        c->s1 = a.start_step;
-        c->s2 = a.start_step;
-        c->broken = 0;
-        c->rechecks = 0;
-        c->flags = 0;
-        c->umax_bits[0] = c->umax_bits[1] = 0;
-        c->qs[0] = c->qs[1] = 0.0;
-        c->fallbacks = 0;
-        for (int k = 0; k < 8; k++) c->red[k] = 0.0;
-        c->dirty[0] = c->dirty[1] = 0;
+        a.ctl->s1 = a.start_step;
+        a.ctl->s2 = a.start_step;
     }
     if (r >= a.n_pad) return;
     const int32_t p = a.perm[r];
@@ -288,39 +283,109 @@ __global__ __launch_bounds__(256) void k_damage(DamageArgs a) {
     a.phi[row] = den > 0.0 ? 1.0 - num / den : 0.0;
 }
 
-// Block-wide sums of u.f, rho V v.v for the energies; one double atomic per
-// block into red[0], red[1].
-__global__ __launch_bounds__(256) void k_energy(int64_t n_pad, const double4 *uv, const double4 *vel,
-                                                const double4 *f, const uint32_t *aux, const pd_spec *spec,
-                                                double *red) {
-    __shared__ double s0[256], s1[256];
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double uf = 0.0, kin = 0.0;
-    if (r < n_pad) {
-        const double4 u = uv[r], v = vel[r], ff = f[r];
-        const pd_spec sp = spec[aux[r] >> 8];
-        uf = u.x * ff.x + u.y * ff.y + u.z * ff.z;
-        kin = sp.rho * u.w * (v.x * v.x + v.y * v.y + v.z * v.z);
-    }
-    s0[threadIdx.x] = uf;
-    s1[threadIdx.x] = kin;
+// ---------------------------------------------------------------------------
+// energies (Eq. 1.20) and the power iteration, reduced in a fixed order
+// ---------------------------------------------------------------------------
+// Sums over a block of 256 threads, NQ values each, in a fixed tree: the
+// result does not depend on the order in which waves run.  Thread 0 holds
+// the totals afterwards.  Every thread of the block must call it.
+template <int NQ>
+__device__ __forceinline__ void block_sum_fixed(double (&v)[NQ], double (*sh)[256]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < NQ; q++) sh[q][t] = v[q];
     __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            s0[threadIdx.x] += s0[threadIdx.x + o];
-            s1[threadIdx.x] += s1[threadIdx.x + o];
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+#pragma unroll
+            for (int q = 0; q < NQ; q++) sh[q][t] += sh[q][t + o];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        atomicAdd(&red[0], s0[0]);
-        atomicAdd(&red[1], s1[0]);
+#pragma unroll
+    for (int q = 0; q < NQ; q++) v[q] = sh[q][0];
+}
+
+// Per row: the kinetic energy 1/2 rho V_i v.v and V_i W_i with the strain
+// energy density of Eq. 1.20 in the constants of Eqs. 1.8, 1.15, 1.16,
+//   W_i = (K - G/3) / (2 A) theta_i^2 + G / (2 m_i) sum_j rho_ij e_ij^2 V_j,
+//   theta_i = (A / m_i) sum_j rho_ij x e_ij V_j               (Eq. 2.3, w = 1),
+// with the linearized extension (Eqs. 2.4, 2.7) or, FIN, the finite one
+// (e = |x M + u_j - u_i| - x, Eq. 1.10).  One partial (kinetic, strain) per
+// block of four slices.
+template <int DIM, bool FIN>
+__global__ __launch_bounds__(256) void k_energy_rows(StepArgs a, int cur, double4 *part) {
+    __shared__ double4 sst[128];
+    __shared__ double red[2][256];
+    load_stencil_lds(sst, a.stencil, a.n_stencil);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t slice = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    double v[2] = {0.0, 0.0};
+    if (slice < a.n_slices) {
+        const int64_t row = slice * 64 + lane;
+        const double4 *__restrict__ uv = a.uv[cur];
+        const double4 ui = uv[row];
+        const int64_t base = a.slice_ptr[slice];
+        const int64_t L = (a.slice_ptr[slice + 1] - base) >> 6;
+        double at = 0.0, ae = 0.0;
+        for (int64_t k = 0; k < L; k++) {
+            const uint64_t m64 = uniform64(a.mask[(base >> 6) + k]);
+            if (!((m64 >> lane) & 1ull)) continue;
+            const uint32_t w = a.words[pd_widx(base, k, lane)];
+            const double4 uj = uv[w >> 7];
+            const double4 sd = sst[w & 127u];
+            const double h0 = uj.x - ui.x, h1 = uj.y - ui.y, h2 = DIM == 3 ? uj.z - ui.z : 0.0;
+            double e;
+            if (FIN) {
+                const double y0 = sd.w * sd.x + h0, y1 = sd.w * sd.y + h1, y2 = sd.w * sd.z + h2;
+                e = sqrt((y0 * y0 + y1 * y1) + y2 * y2) - sd.w;
+            } else {
+                e = ext_canonical(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, h0, h1, h2);
+            }
+            at += sd.w * e * uj.w;
+            ae += e * e * uj.w;
+        }
+        if (ui.w > 0.0) {
+            const pd_spec sp = a.spec[a.aux[row] >> 8];
+            const double r = a.inv_m[row];
+            const double th = sp.A * r * at;
+            const double W = sp.kp / (2.0 * sp.A) * th * th + 0.5 * sp.G * r * ae;
+            const double4 vv = a.vel[row];
+            v[0] = 0.5 * sp.rho * ui.w * (vv.x * vv.x + vv.y * vv.y + vv.z * vv.z);
+            v[1] = ui.w * W;
+        }
+    }
+    block_sum_fixed<2>(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double4(v[0], v[1], 0.0, 0.0);
+}
+
+// One block adds n partials: thread t takes t, t + 256, ... in index order,
+// then the fixed tree.  Writes the four sums to out, or, with rec, records
+// them as the energy check of the state (the previous check's total kept).
+__global__ __launch_bounds__(256) void k_sum_partials(const double4 *part, int64_t n, double *out, int nout,
+                                                      pd_ctl *rec) {
+    __shared__ double red[4][256];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double4 p = part[i];
+        v[0] += p.x;
+        v[1] += p.y;
+        v[2] += p.z;
+        v[3] += p.w;
+    }
+    block_sum_fixed<4>(v, red);
+    if (threadIdx.x != 0) return;
+    if (rec) {
+        rec->en[2] = rec->en[0] + rec->en[1];
+        rec->en[0] = v[0];
+        rec->en[1] = v[1];
+        rec->en[3] = (double)(rec->s2 + 1);  // 0 = no check yet
+    } else {
+        for (int q = 0; q < nout; q++) out[q] = v[q];
     }
 }
 
-__global__ void k_zero_red(pd_ctl *ctl) {
-    if (threadIdx.x < 8) ctl->red[threadIdx.x] = 0.0;
-}
 
 // Power iteration helpers for the stable time step.
 // x := seeded random vector on free components (counter-based hash).
@@ -340,13 +405,13 @@ __global__ void k_pi_init(int64_t n_pad, int dim, const uint32_t *aux, double4 *
     uv[r] = make_double4(x[0], x[1], x[2], u.w);
 }
 
-// y = M^-1 (-f) on free components; accumulate x.Kx, x.Mx, y.My.
+// y = M^-1 (-f) on free components; block partials of x.Kx, x.Mx, y.My.
 __global__ __launch_bounds__(256) void k_pi_step(int64_t n_pad, int dim, const uint32_t *aux, const pd_spec *spec,
                                                  const double4 *uv, const double4 *f, double4 *y,
-                                                 double *red) {
+                                                 double4 *part) {
     __shared__ double s[3][256];
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double xkx = 0, xmx = 0, ymy = 0;
+    double acc[3] = {0.0, 0.0, 0.0};
     if (r < n_pad) {
         const double4 x = uv[r], ff = f[r];
         const uint32_t ax = aux[r];
@@ -356,24 +421,15 @@ __global__ __launch_bounds__(256) void k_pi_step(int64_t n_pad, int dim, const u
             if ((ax >> c) & 1u) continue;
             if (!(mass > 0.0)) continue;
             const double kx = -fv[c];
-            xkx += xv[c] * kx;
-            xmx += xv[c] * mass * xv[c];
+            acc[0] += xv[c] * kx;
+            acc[1] += xv[c] * mass * xv[c];
             yv[c] = kx / mass;
-            ymy += yv[c] * yv[c] * mass;
+            acc[2] += yv[c] * yv[c] * mass;
         }
         y[r] = make_double4(yv[0], yv[1], yv[2], x.w);
     }
-    s[0][threadIdx.x] = xkx;
-    s[1][threadIdx.x] = xmx;
-    s[2][threadIdx.x] = ymy;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int q = 0; q < 3; q++) s[q][threadIdx.x] += s[q][threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 3; q++) atomicAdd(&red[q], s[q][0]);
+    block_sum_fixed<3>(acc, s);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double4(acc[0], acc[1], acc[2], 0.0);
 }
 
 __global__ void k_pi_scale(int64_t n_pad, const double4 *y, double4 *uv, const double *red) {
@@ -435,11 +491,20 @@ hipError_t launch_damage(const DamageArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_energy(int64_t n_pad, const double4 *uv, const double4 *vel, const double4 *f,
-                         const uint32_t *aux, const pd_spec *spec, pd_ctl *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_red, dim3(1), dim3(64), 0, s, ctl);
-    const int64_t nb = (n_pad + 255) / 256;
-    hipLaunchKernelGGL(k_energy, dim3((unsigned)nb), dim3(256), 0, s, n_pad, uv, vel, f, aux, spec, ctl->red);
+int64_t reduce_parts(int64_t n_pad) { return (n_pad + 255) / 256; }
+
+hipError_t launch_energy(const StepArgs &a, int cur, bool finite, double4 *part, double *out, int nout, pd_ctl *rec,
+                         hipStream_t s) {
+    const int64_t nb = reduce_parts(a.n_pad);
+    const dim3 g((unsigned)nb), b(256);
+    if (a.dim == 3) {
+        if (finite) hipLaunchKernelGGL((k_energy_rows<3, true>), g, b, 0, s, a, cur, part);
+        else hipLaunchKernelGGL((k_energy_rows<3, false>), g, b, 0, s, a, cur, part);
+    } else {
+        if (finite) hipLaunchKernelGGL((k_energy_rows<2, true>), g, b, 0, s, a, cur, part);
+        else hipLaunchKernelGGL((k_energy_rows<2, false>), g, b, 0, s, a, cur, part);
+    }
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, nb, out, nout, rec);
     return hipGetLastError();
 }
 
@@ -451,10 +516,10 @@ hipError_t launch_pi_init(int64_t n_pad, int dim, const uint32_t *aux, double4 *
 }
 
 hipError_t launch_pi_step(int64_t n_pad, int dim, const uint32_t *aux, const pd_spec *spec, double4 *uv,
-                          const double4 *f, double4 *y, pd_ctl *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_red, dim3(1), dim3(64), 0, s, ctl);
-    const int64_t nb = (n_pad + 255) / 256;
-    hipLaunchKernelGGL(k_pi_step, dim3((unsigned)nb), dim3(256), 0, s, n_pad, dim, aux, spec, uv, f, y, ctl->red);
+                          const double4 *f, double4 *y, pd_ctl *ctl, double4 *part, hipStream_t s) {
+    const int64_t nb = reduce_parts(n_pad);
+    hipLaunchKernelGGL(k_pi_step, dim3((unsigned)nb), dim3(256), 0, s, n_pad, dim, aux, spec, uv, f, y, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, nb, ctl->red, 3, (pd_ctl *)nullptr);
     hipLaunchKernelGGL(k_pi_scale, dim3((unsigned)nb), dim3(256), 0, s, n_pad, y, uv, ctl->red);
     return hipGetLastError();
 }

@@ -76,6 +76,14 @@ __device__ __forceinline__ int quantise(double u, double invQ, bool &bad) {
     return (int)rint(t);
 }
 
+// Wave minimum of a non-negative margin, merged into *key as ~(float bits)
+// (larger key = smaller margin; a zero key means no margin yet).  Called by
+// every lane of the wave.
+__device__ __forceinline__ void margin_merge_g(float m, unsigned int *key) {
+    for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0 && m < __builtin_inff()) atomicMax(key, ~__float_as_uint(m));
+}
+
 // Wave maximum of a non-negative float, merged into *dst.  The atomic is
 // issued only when the wave's value exceeds what is already there (a plain
 // read that may be stale, which only costs an extra atomic), so tens of
@@ -101,13 +109,39 @@ __device__ __forceinline__ void load_stencil_scaled(float4 *sst, const double *s
 // ---------------------------------------------------------------------------
 // set-up at the start of a call: shadow scale and shadow, D_i
 // ---------------------------------------------------------------------------
-__global__ void k_zero_umax(pd_ctl *ctl, int k) {
-    if (threadIdx.x == 0) ctl->umax_bits[k] = 0u;
+// The shadow, its scale and D_i persist between calls: the set-up is skipped
+// when they still describe the current state (same buffer, same step
+// counter, same kind of set-up), so a trajectory does not depend on how its
+// steps are split across calls.  'force' redoes it regardless.
+__global__ void k_shadow_begin(pd_ctl *ctl, int k, int kind, int force) {
+    if (threadIdx.x == 0) {
+        const bool current = !force && ctl->sh_kind == kind && ctl->sh_cur == k && ctl->sh_step == ctl->s2;
+        ctl->sh_skip = current ? 1 : 0;
+        if (!current) ctl->umax_bits[k] = 0u;
+    }
+}
+
+__global__ void k_shadow_invalidate(pd_ctl *ctl) {
+    if (threadIdx.x == 0) ctl->sh_kind = 0;
+}
+
+hipError_t launch_shadow_invalidate(pd_ctl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_shadow_invalidate, dim3(1), dim3(64), 0, s, ctl);
+    return hipGetLastError();
+}
+
+__global__ void k_shadow_end(pd_ctl *ctl, int k, int kind) {
+    if (threadIdx.x == 0) {
+        ctl->sh_kind = kind;
+        ctl->sh_cur = k;
+        ctl->sh_step = ctl->s2;
+    }
 }
 
 // grid-stride maximum: one block maximum (and at most one atomic) per block
 __global__ __launch_bounds__(256) void k_umax(int64_t n_pad, const double4 *uv, pd_ctl *ctl, int k) {
     __shared__ float wm[4];
+    if (ctl->sh_skip) return;
     float m = 0.0f;
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n_pad; r += (int64_t)gridDim.x * 256) {
         const double4 u = uv[r];
@@ -128,6 +162,7 @@ __global__ __launch_bounds__(256) void k_umax(int64_t n_pad, const double4 *uv, 
 
 __global__ __launch_bounds__(256) void k_shadow_write(int64_t n_pad, const double4 *uv, int4 *ush, pd_ctl *ctl,
                                                       int k) {
+    if (ctl->sh_skip) return;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double Q = shadow_scale(ctl->umax_bits[k]);
     if (r == 0) ctl->qs[k] = Q;
@@ -147,6 +182,7 @@ __global__ __launch_bounds__(256) void k_shadow_write(int64_t n_pad, const doubl
 // D_i = sum over intact bonds of x M V_j (double precision)
 template <int DIM>
 __global__ __launch_bounds__(256) void k_dsum(StepArgs a, int cur) {
+    if (a.ctl->sh_skip) return;
     const int lane = threadIdx.x & 63;
     const int64_t slice = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (slice >= a.n_slices) return;
@@ -204,6 +240,7 @@ __global__ __launch_bounds__(256) void k_pass1_f32(StepArgs a, int cur) {
     float acc = 0.0f;
     uint32_t nbroken = 0, nrecheck = 0, nfall = 0;
     double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;  // x M V_j of the bonds this row breaks now
+    float mmin = __builtin_inff();           // smallest |s - s_c| / s_c decided in double
     const uint4 *__restrict__ wg = reinterpret_cast<const uint4 *>(a.words + base) + lane;
     const uint4 *__restrict__ mg = reinterpret_cast<const uint4 *>(a.mask + (base >> 6));
     const int64_t G = L >> 2;
@@ -239,6 +276,7 @@ __global__ __launch_bounds__(256) void k_pass1_f32(StepArgs a, int cur) {
                 const double e64 = ext_canonical32(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, uj.x - ui.x,
                                                    uj.y - ui.y, DIM == 3 ? uj.z - ui.z : 0.0);
                 if (intact) nfall++;
+                if (BREAK && intact) mmin = fminf(mmin, (float)(fabs(e64 / sd.w - s0) / s0));
                 if (BREAK && intact && e64 / sd.w >= s0) {
                     intact = false;
                     broke = true;
@@ -262,6 +300,7 @@ __global__ __launch_bounds__(256) void k_pass1_f32(StepArgs a, int cur) {
                     const double e64 = ext_canonical32(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, uj.x - ui.x,
                                                        uj.y - ui.y, DIM == 3 ? uj.z - ui.z : 0.0);
                     nrecheck++;
+                    mmin = fminf(mmin, (float)(fabs(e64 / sd.w - s0) / s0));
                     if (e64 / sd.w >= s0) {
                         intact = false;
                         broke = true;
@@ -304,6 +343,7 @@ __global__ __launch_bounds__(256) void k_pass1_f32(StepArgs a, int cur) {
         }
         if (lane == 0 && rc) atomicAdd(&ctl->rechecks, rc);
         if (lane == 0 && fb) atomicAdd(&ctl->fallbacks, fb);
+        if (rc | fb) margin_merge_g(mmin, &ctl->margin_key);
     }
 }
 
@@ -400,7 +440,12 @@ __global__ __launch_bounds__(256) void k_pass2_f32(StepArgs a, int cur) {
         return;
     }
     const int64_t n = ctl->s1;
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->s2 = n + 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->s2 = n + 1;
+        // the next shadow written below describes the new state
+        ctl->sh_step = n + 1;
+        ctl->sh_cur = cur ^ 1;
+    }
     const double Qn = ctl->qs[cur ^ 1];
     double r = 1.0;
     if (a.ramp_steps > 0) r = n >= a.ramp_steps ? 1.0 : (double)n / (double)a.ramp_steps;
@@ -442,17 +487,23 @@ __global__ __launch_bounds__(256) void k_pass2_f32(StepArgs a, int cur) {
     if (__ballot(bad) && lane == 0) atomicOr(&ctl->flags, PD_CTL_FALLBACK);
 }
 
-hipError_t launch_shadow_prep(const StepArgs &a, int cur, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_umax, dim3(1), dim3(64), 0, s, a.ctl, cur);
+hipError_t launch_shadow_prep(const StepArgs &a, int cur, bool tiled, bool force, hipStream_t s) {
+    const int kind = tiled ? 1 : 2;
+    hipLaunchKernelGGL(k_shadow_begin, dim3(1), dim3(64), 0, s, a.ctl, cur, kind, force ? 1 : 0);
     const int64_t nb = (a.n_pad + 255) / 256;
     hipLaunchKernelGGL(k_umax, dim3((unsigned)(nb < 1024 ? nb : 1024)), dim3(256), 0, s, a.n_pad, a.uv[cur], a.ctl,
                        cur);
     hipLaunchKernelGGL(k_shadow_write, dim3((unsigned)nb), dim3(256), 0, s, a.n_pad, a.uv[cur], a.ush[cur], a.ctl,
                        cur);
-    if (tiled_supported(a)) return launch_tdsum(a, cur, s);
-    const dim3 g((unsigned)((a.n_slices + 3) / 4));
-    if (a.dim == 3) hipLaunchKernelGGL((k_dsum<3>), g, dim3(256), 0, s, a, cur);
-    else hipLaunchKernelGGL((k_dsum<2>), g, dim3(256), 0, s, a, cur);
+    hipError_t e;
+    if (tiled) {
+        if ((e = launch_tdsum(a, cur, s)) != hipSuccess) return e;
+    } else {
+        const dim3 g((unsigned)((a.n_slices + 3) / 4));
+        if (a.dim == 3) hipLaunchKernelGGL((k_dsum<3>), g, dim3(256), 0, s, a, cur);
+        else hipLaunchKernelGGL((k_dsum<2>), g, dim3(256), 0, s, a, cur);
+    }
+    hipLaunchKernelGGL(k_shadow_end, dim3(1), dim3(64), 0, s, a.ctl, cur, kind);
     return hipGetLastError();
 }
 

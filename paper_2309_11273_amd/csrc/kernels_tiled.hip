@@ -263,6 +263,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     float acc = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
     uint32_t nbroken = 0, nrecheck = 0, nfall = 0;
     double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
+    float mmin = __builtin_inff();  // smallest |s - s_c| / s_c decided in double
 
     // double bond strain e / x of bond k of this row (canonical order, from
     // the double state); a break takes the bond out of the row's D_i
@@ -273,6 +274,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         const double e64 = ext_canonical_t(sd.x, sd.y, DIM == 3 ? sd.z : 0.0, uj.x - ui.x, uj.y - ui.y,
                                            DIM == 3 ? uj.z - ui.z : 0.0);
         const double st = e64 / sd.w;
+        if (BREAK) mmin = fminf(mmin, (float)(fabs(st - s0) / s0));
         if (BREAK && st >= s0) {
             broke = true;
             const double xv = sd.w * uj.w;
@@ -409,6 +411,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         if (lane == 0 && nbroken) atomicAdd(&ctl->broken, (unsigned long long)nbroken);
         if (lane == 0 && nrecheck) atomicAdd(&ctl->rechecks, (unsigned long long)nrecheck);
         if (lane == 0 && nfall) atomicAdd(&ctl->fallbacks, (unsigned long long)nfall);
+        if (nrecheck | nfall) margin_merge(mmin, &ctl->margin_key);
     }
     float tot[4] = {acc, fx, fy, fz};
     double d[3] = {dd0, dd1, dd2};
@@ -627,7 +630,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         return;
     }
     const int64_t n = ctl->s1;
-    if (tile == 0 && gt == 0) ctl->s2 = n + 1;
+    if (tile == 0 && gt == 0) {
+        ctl->s2 = n + 1;
+        // the next shadow written below describes the new state
+        ctl->sh_step = n + 1;
+        ctl->sh_cur = cur ^ 1;
+    }
     const double Qn = ctl->qs[cur ^ 1];
     double r = 1.0;
     if (a.ramp_steps > 0) r = n >= a.ramp_steps ? 1.0 : (double)n / (double)a.ramp_steps;
@@ -679,6 +687,7 @@ template <int DIM>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tdsum(StepArgs a, int cur, const KEnt *__restrict__ kt,
                                                            const double4 *__restrict__ sten) {
     extern __shared__ __align__(16) unsigned char smem[];
+    if (a.ctl->sh_skip) return;
     constexpr int MS = StageCap<DIM>::value;
     const Box g = make_box(a, DIM);
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);

@@ -16,14 +16,28 @@ struct pd_ctl {
     unsigned long long rechecks;  // FP64 rechecks made by the FP32 path
     unsigned int flags;           // bit 0: non-finite state, bit 1: shadow fallback used
     unsigned int umax_bits[2];    // float bits of max |u| of shadow buffer k
-    unsigned int pad0;
+    unsigned int margin_key;      // smallest |s - s_c| / s_c of a bond decided in double by
+                                  // the FP32 path, stored as ~(float bits); 0 = none yet
     double qs[2];                 // fixed-point scale of shadow buffer k (power of two)
     unsigned long long fallbacks; // shadow entries that fell back to FP64
-    double red[8];                // reductions (energies, power iteration)
+    double red[8];                // reductions (power iteration)
     unsigned long long dirty[2];  // rows marked for re-assembly, by step parity
-    unsigned long long pad1[10];
+    // FP32 path: the shadow, its scale and D_i are kept between calls.  They
+    // describe uv[sh_cur] at step counter sh_step, built by the tile (1) or
+    // gather (2) set-up (sh_kind; 0 = nothing valid).  Every other path that
+    // advances the state advances s2 without sh_step, which invalidates them.
+    int64_t sh_step;
+    int32_t sh_kind;
+    int32_t sh_cur;
+    int32_t sh_skip;              // set-up of the current call skipped (shadow current)
+    int32_t pad2;
+    // energy checks of pd_step: kinetic and strain energy of the last check,
+    // the total of the check before it, the step counter of the last check
+    double en[4];
+    unsigned long long pad1[6];
 };
 static_assert(sizeof(pd_ctl) <= PD_CTL_BYTES, "control block too large");
+static_assert(sizeof(pd_ctl) % 8 == 0, "control block is cleared in 8-byte words");
 
 #define PD_CTL_NONFINITE 1u
 #define PD_CTL_FALLBACK 2u

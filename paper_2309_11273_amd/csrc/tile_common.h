@@ -81,6 +81,14 @@ __device__ __forceinline__ float big_abs(float v) {
     return m >= 16777216.0f ? m : 0.0f;
 }
 
+// Wave minimum of a non-negative breaking margin, merged into *key as
+// ~(float bits) (a larger key is a smaller margin; zero means none yet).
+// Called by every lane of the wave.
+__device__ __forceinline__ void margin_merge(float m, unsigned int *key) {
+    for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0 && m < __builtin_inff()) atomicMax(key, ~__float_as_uint(m));
+}
+
 // lane's bit of a wave-uniform 64-bit word, used as the condition mask as is
 __device__ __forceinline__ bool lane_bit(uint64_t uniform_word) {
     return __builtin_amdgcn_inverse_ballot_w64(uniform_word);

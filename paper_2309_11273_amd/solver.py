@@ -145,6 +145,46 @@ class FamilyHost:
         j = (words >> 7).astype(np.int64)
         return rows.astype(np.int64), ks.astype(np.int64), self.perm[rows], self.perm[j], (words & 127)
 
+    def status_index(self, bi: np.ndarray, bj: np.ndarray):
+        """Where the status bit of each unique bond (caller nodes bi < bj)
+        sits: (mask word index, bit lane) of its directed copy i -> j."""
+        rows, ks, ci, cj, _ = self.bond_table()
+        fwd = ci < cj
+        n = int(max(int(ci.max(initial=0)), int(cj.max(initial=0)))) + 1
+        key = ci[fwd].astype(np.int64) * n + cj[fwd]
+        want = np.asarray(bi, np.int64) * n + np.asarray(bj, np.int64)
+        order = np.argsort(key, kind="stable")
+        pos = order[np.clip(np.searchsorted(key[order], want), 0, max(0, key.size - 1))]
+        if key.size == 0 or not np.array_equal(key[pos], want):
+            raise KeyError("a bond is not in the family")
+        r, k = rows[fwd][pos], ks[fwd][pos]
+        return self.slice_ptr[r // 64] // 64 + k, (r % 64).astype(np.uint64)
+
+    def cleared_keys(self, mask0: np.ndarray, mask: np.ndarray) -> np.ndarray:
+        """Sorted keys i * n + j (caller nodes, i < j) of the bonds whose
+        status bits are set in mask0 and clear in mask; raises if the two
+        directed copies of such a bond disagree."""
+        cleared = mask0 & ~mask
+        wi = np.nonzero(cleared)[0]
+        if wi.size == 0:
+            return np.zeros(0, np.int64)
+        bits = (cleared[wi][:, None] >> np.arange(64, dtype=np.uint64)[None, :]) & np.uint64(1)
+        wsel, lane = np.nonzero(bits)
+        word = wi[wsel].astype(np.int64)
+        first = self.slice_ptr // 64
+        sl = np.searchsorted(first, word, side="right") - 1
+        k = word - first[sl]
+        widx = self.slice_ptr[sl] + (k >> 2) * 256 + lane * 4 + (k & 3)
+        row = sl * 64 + lane
+        ci = self.perm[row].astype(np.int64)
+        cj = self.perm[(self.words[widx] >> 7).astype(np.int64)].astype(np.int64)
+        n = self.n
+        key = np.minimum(ci, cj) * n + np.maximum(ci, cj)
+        u, cnt = np.unique(key, return_counts=True)
+        if np.any(cnt != 2):
+            raise AssertionError("directed bond copies disagree on their status")
+        return u
+
     def bond_status(self, mask: np.ndarray):
         """Status of every unique bond, sorted by caller (i, j) with i < j.
 
@@ -295,6 +335,11 @@ class Solver:
         self.ctx.check("pd_get_step", A.load().pd_get_step(self.ctx.h, C.byref(self.S), C.byref(out)))
         return int(out.value)
 
+    def broken_keys(self) -> np.ndarray:
+        """Sorted keys i * n + j (caller nodes, i < j) of the bonds broken by
+        the steps since the initial status (notch cuts excluded)."""
+        return self.fam.cleared_keys(self.mask0, self.mask_host())
+
     def mask_host(self) -> np.ndarray:
         torch.cuda.synchronize(self.dev)
         return self.mask.cpu().numpy().view(np.uint64).copy()
@@ -382,7 +427,8 @@ class Solver:
 
     def step(self, nsteps: int, precision: str = "fp64", form: str = "mf", graph_chunk: int = 0,
              block: int = 0, check_every: int = 0, report: bool = True, profile: bool = False,
-             kernel: str = "auto", extension: str = "linear"):
+             kernel: str = "auto", extension: str = "linear", energy_check: bool = False,
+             energy_growth: float = 0.0):
         o = A.pd_step_opts()
         o.precision = {"fp64": A.PD_FP64, "fp32": A.PD_FP32_RECHECK}[precision]
         o.form = {"mf": A.PD_MATRIX_FREE, "bsr": A.PD_BSR, "fac": A.PD_FACTORED}[form]
@@ -390,6 +436,8 @@ class Solver:
         o.profile = 1 if profile else 0
         o.kernel = {"auto": 0, "gather": 1, "tiled": 2}[kernel]
         o.extension = {"linear": 0, "finite": 1}[extension]
+        o.energy_check = 1 if energy_check else 0
+        o.energy_growth = float(energy_growth)
         rep = A.pd_step_report()
         if form == "fac":
             Fp = C.byref(self.F) if self.F is not None else None
@@ -403,7 +451,8 @@ class Solver:
         if not report:
             return None
         return dict(step=rep.step, broken_total=rep.broken_total, rechecks=rep.rechecks,
-                    nonfinite=rep.nonfinite, umax=rep.umax)
+                    nonfinite=rep.nonfinite, umax=rep.umax, min_margin=rep.min_margin, kinetic=rep.kinetic,
+                    strain=rep.strain, energy_step=rep.energy_step)
 
     def damage(self) -> np.ndarray:
         phi = torch.zeros(self.n_pad, dtype=torch.float64, device=self.dev)

@@ -528,3 +528,47 @@ def test_xcd_tile_order_is_a_bijection():
         t = x * q + np.minimum(x, r) + b // 8
         assert np.array_equal(np.sort(t), b)
 
+
+
+@pytest.mark.parametrize("case", ["plate", "cylinder"])
+def test_cleared_keys_and_status_index(lib, case):
+    """The host helpers that map bond-status bits back to caller bonds:
+    clearing both directed copies of chosen reference bonds reports exactly
+    those bonds, and the status index of every reference bond points at a
+    bit of its own directed copy."""
+    if case == "plate":
+        w = W.plate2d(nx=30, ny=18, dt=1e-7, notch_row=8, notch_tip=14.37, steps=10)
+    else:
+        w = W.cylinder3d(dx=5e-3, dt=2.4e-7, twist_rate=10.0, steps=10)
+    fam = _family(w)
+    o = Oracle(w, search="brute")
+    bi, bj = o.bonds()
+    rows, ks, ci, cj, _ = fam.bond_table()
+    widx, lane = fam.status_index(bi, bj)
+    # the indexed bit belongs to a directed entry i -> j of that bond
+    word_of = {}
+    first = fam.slice_ptr // 64
+    for r, k, a, b in zip(rows, ks, ci, cj):
+        word_of[(int(first[r // 64] + k), int(r % 64))] = (int(a), int(b))
+    for q in np.random.default_rng(0).choice(bi.size, 200, replace=False):
+        assert word_of[(int(widx[q]), int(lane[q]))] == (int(bi[q]), int(bj[q]))
+    rng = np.random.default_rng(1)
+    pick = np.sort(rng.choice(bi.size, 25, replace=False))
+    m = fam.mask.copy()
+    for q in pick:
+        for a, b in ((bi[q], bj[q]), (bj[q], bi[q])):
+            sel = np.nonzero((ci == a) & (cj == b))[0][0]
+            r, k = rows[sel], ks[sel]
+            m[first[r // 64] + k] &= ~np.uint64(1 << int(r % 64))
+    keys = fam.cleared_keys(fam.mask, m)
+    want = bi[pick].astype(np.int64) * w.n + bj[pick]
+    # bonds already cut by the notch were 0 in the initial status
+    init = ((fam.mask[widx[pick]] >> lane[pick]) & np.uint64(1)).astype(bool)
+    assert np.array_equal(keys, np.sort(want[init]))
+    # one copy only: the helper refuses
+    q = pick[init][0]
+    sel = np.nonzero((ci == bi[q]) & (cj == bj[q]))[0][0]
+    m2 = fam.mask.copy()
+    m2[first[rows[sel] // 64] + ks[sel]] &= ~np.uint64(1 << int(rows[sel] % 64))
+    with pytest.raises(AssertionError):
+        fam.cleared_keys(fam.mask, m2)
