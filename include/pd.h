@@ -731,6 +731,22 @@ pd_status pd_damage(pd_ctx *ctx, const pd_problem_dev *prob, const uint64_t *mas
 pd_status pd_energy(pd_ctx *ctx, const pd_problem_dev *prob, pd_state_dev *st,
                     double *f_scratch, double *kinetic, double *strain);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * energies of pd_energy, the same bits, written to out [device] (2 doubles:
+ * kinetic, strain), with no allocation and no synchronisation (stream-
+ * ordered on the context's stream, so it can be captured).  The reduction
+ * partials live in a fixed array of the library on each GPU (65536 entries
+ * of 32 bytes, 2 MiB, held until the process ends), which limits n_pad to
+ * PD_NOALLOC_MAX_ROWS rows (PD_ERR_SIZE beyond, before any device work).
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (from several streams, contexts or threads) race, and the caller must
+ * order them.  Errors: PD_ERR_ARG (NULL or misaligned out, state without
+ * aux), PD_ERR_SIZE, PD_ERR_HIP. */
+#define PD_NOALLOC_PARTS 65536
+#define PD_NOALLOC_MAX_ROWS (PD_NOALLOC_PARTS * 256LL)
+pd_status pd_energy_noalloc(pd_ctx *ctx, const pd_problem_dev *prob, const pd_state_dev *st, double *out);
+
 /* Largest stable time step 2/omega_max of the explicit update for
  * specimen-uniform material, omega_max^2 = largest eigenvalue of
  * M^-1 K on the free degrees of freedom, by power iteration from a

@@ -136,6 +136,7 @@ SIGNATURES = {
     "pd_get_step": (i32, [P, C.POINTER(pd_state_dev), C.POINTER(i64)]),
     "pd_tile_kernels_apply": (i32, [C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i32, C.POINTER(i32)]),
     "pd_force": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i32, P, P]),
+    "pd_energy_noalloc": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), P]),
     "pd_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i64,
                       C.POINTER(pd_step_opts), C.POINTER(pd_bsr_dev), C.POINTER(pd_step_report)]),
     "pd_bsr_pattern": (i32, [C.POINTER(pd_family_sizes), C.POINTER(pd_family_host),

@@ -31,7 +31,16 @@ struct pd_ctx {
     pd_profile_stats prof{};
     double4 *part = nullptr;           // partials of the fixed-order reductions
     int64_t part_n = 0;
+    double4 *scratch_dev = nullptr;    // this device's address of 'scratch' (pd_energy_noalloc)
 };
+
+// Reduction partials of pd_energy_noalloc: a fixed array on every GPU the
+// library runs on (2 MiB, held until the process ends), so that the call
+// allocates nothing.  Host code reaches it only through the per-device
+// address that pd_ctx_create looks up (scratch_dev); every call on one GPU
+// shares it.  Each call writes the partials it reads, so nothing in it has
+// to start at zero.
+static __device__ __align__(256) double4 scratch[PD_NOALLOC_PARTS];
 
 namespace {
 
@@ -149,6 +158,12 @@ pd_status pd_ctx_create(pd_ctx **out, int device, void *stream) {
     pd_ctx *c = new pd_ctx();
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(stream);
+    // this device's copy of the no-allocation scratch array (device current)
+    if (hipGetSymbolAddress(reinterpret_cast<void **>(&c->scratch_dev), HIP_SYMBOL(scratch)) != hipSuccess ||
+        !c->scratch_dev) {
+        delete c;
+        return PD_ERR_HIP;
+    }
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return PD_ERR_HIP;
@@ -969,6 +984,25 @@ pd_status pd_energy(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, double
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     *kinetic = h[0];
     *strain = h[1];
+    return PD_OK;
+}
+
+pd_status pd_energy_noalloc(pd_ctx *c, const pd_problem_dev *p, const pd_state_dev *st, double *out) {
+    if (!c) return PD_ERR_ARG;
+    pd_status s = check_problem(c, p);
+    if (s != PD_OK) return s;
+    if ((s = check_state(c, st, false)) != PD_OK) return s;
+    if (!out) return fail(c, PD_ERR_ARG, "out is NULL");
+    if (reinterpret_cast<uintptr_t>(out) % 8 != 0) return fail(c, PD_ERR_ARG, "out must be 8-byte aligned");
+    if (!p->aux) return fail(c, PD_ERR_ARG, "aux is NULL (call pd_state_init first)");
+    if (pdk::reduce_parts(p->n_pad) > PD_NOALLOC_PARTS)
+        return fail(c, PD_ERR_SIZE, "n_pad %lld exceeds the %lld rows of the fixed reduction array",
+                    (long long)p->n_pad, (long long)PD_NOALLOC_MAX_ROWS);
+    if (!c->scratch_dev) return fail(c, PD_ERR_STATE, "no scratch address for this device");
+    HIP_TRY(c, hipSetDevice(c->device));
+    pd_state_dev tmp = *st;
+    const pdk::StepArgs a = make_args(p, &tmp);
+    HIP_TRY(c, pdk::launch_energy(a, st->cur, false, c->scratch_dev, out, 2, nullptr, c->stream));
     return PD_OK;
 }
 

@@ -467,6 +467,15 @@ class Solver:
                                                          C.byref(k), C.byref(s)))
         return k.value, s.value
 
+    def energy_noalloc(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """pd_energy_noalloc: (kinetic, strain) into a device tensor of two
+        doubles, enqueued on the context's stream without synchronising."""
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=self.dev)
+        self.ctx.check("pd_energy_noalloc", A.load().pd_energy_noalloc(self.ctx.h, C.byref(self.P),
+                                                                         C.byref(self.S), _tp(out)))
+        return out
+
     def stable_dt(self, iters: int = 500, seed: int = 0) -> float:
         f = torch.zeros(self.n_pad * 4, dtype=torch.float64, device=self.dev)
         out = C.c_double()
