@@ -710,6 +710,14 @@ def main():
     if not args.no_cpu:
         mode = "adr" if args.adr else ("finite" if args.extension == "finite" else "step")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, mode)
+        # the same reference on one core (a shorter sample: the rate per core)
+        from oracle.oracle import num_threads, set_num_threads
+        nt = num_threads()
+        set_num_threads(1)
+        try:
+            out["cpu_baseline_1core"] = cpu_baseline(w, max(5.0, args.cpu_seconds / 2), mode)
+        finally:
+            set_num_threads(nt)
     print(json.dumps(out), flush=True)
 
 

@@ -573,7 +573,8 @@ extern "C" pd_status pd_bsr_pattern(const pd_family_sizes *sz, const pd_family_h
     for (int64_t r = 0; r < n_pad; r++) row_ptr[r + 1] = row_ptr[r] + (int64_t)rows[r].size();
     parallel_for(n_pad, [&](int64_t a, int64_t b) {
         for (int64_t r = a; r < b; r++)
-            std::memcpy(col + row_ptr[r], rows[r].data(), sizeof(int32_t) * rows[r].size());
+            if (!rows[r].empty())  // padding rows have no blocks (and no data pointer)
+                std::memcpy(col + row_ptr[r], rows[r].data(), sizeof(int32_t) * rows[r].size());
     });
     return PD_OK;
 }
