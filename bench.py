@@ -121,6 +121,8 @@ def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
     kernel source."""
     tiled = args.kernel != "gather" and s.tiled_supported(args.precision)
     kname = f"k_{'t' if tiled else ''}{dom}_{'f32' if args.precision == 'fp32' else 'f64'}"
+    if tiled and args.kernel == "super" and args.precision == "fp32":
+        kname += " (super-tiles)"
     if args.extension == "finite":
         kname = f"k_tpass{dom[-1]}_f64 (finite model)" if tiled else f"k_fin_{dom}"
     ms_dom = ms1 if dom == "pass1" else ms2
@@ -144,7 +146,7 @@ def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
     alu = fl / (peak_fl * 1e12) > byt / (HBM_PEAK_GBS * 1e9)
     from paper_2309_11273_amd.profsum import kernel_source_hash
     traffic = None if args.extension == "finite" else \
-        traffic_from_profiles(f"{kname}@{args.workload}", kernel_source_hash(kname))
+        traffic_from_profiles(f"{kname}@{args.workload}", kernel_source_hash(kname.split(" ")[0]))
     return {"bound": "alu" if alu else "hbm",
             "achieved": round(tfs if alu else gbs, 2), "peak": peak_fl if alu else HBM_PEAK_GBS,
             "unit": "TFLOP/s" if alu else "GB/s",
@@ -422,7 +424,9 @@ def main():
     ap.add_argument("--form", default="mf", choices=["mf", "bsr", "fac"],
                     help="mf: matrix-free tile kernels; bsr: block-sparse K; fac: the paper's four "
                          "factored matrices (double values, so --precision fp64)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tiled"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tiled", "super"],
+                    help="matrix-free kernels: auto (library default), gather (bond list), tiled (one tile "
+                         "per workgroup), super (FP32: four tiles per workgroup sharing one halo box)")
     ap.add_argument("--extension", default="linear", choices=["linear", "finite"],
                     help="finite: e = |x M + u_j - u_i| - x with the force along the deformed bond "
                          "(FP64 gather kernels)")

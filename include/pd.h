@@ -223,6 +223,38 @@ typedef struct pd_family_host {
 pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, int32_t ncuts,
                           pd_family_sizes *sizes, pd_family_host *bufs);
 
+/* Super-tiles of a 3D family of 4x4x4 tiles with stencil reach <= 3: the
+ * tiles grouped 2 x 2 x 1 (same specimen, same tile layer), so that one
+ * workgroup stages one halo box for four tiles (8 x 8 x 4 lattice points plus
+ * the reach on every side) and each of its four waves sweeps the whole
+ * stencil for its own tile.  Two-phase like pd_build_family (with
+ * st_tiles == NULL only *out is set).  Outputs [host]:
+ *   st_tiles [4 n_st]   tile of quadrant q (x offset 4 (q & 1), y offset
+ *                       4 (q >> 1)) of super-tile s at 4 s + q, -1 if none;
+ *                       super-tiles in (specimen, z, y, x) order
+ *   st_nbr  [48 n_st]   tile at tile offset (dx, dy, dz) in {-1..2}^2 x {-1..1}
+ *                       from the super-tile's first tile, index
+ *                       (dx + 1) + 4 (dy + 1) + 16 (dz + 1), -1 if none
+ *   st_pos  [n_pos]     the box points some stencil entry of some tile point
+ *                       reaches, x fastest: (slot << 12) | (64 d + l), d the
+ *                       st_nbr index of the point's tile and l its place in it,
+ *                       slot = x + 16 y + 228 z in the box (pitches chosen so
+ *                       that the 64 lanes of a tile reading the same offset hit
+ *                       64 distinct LDS banks)
+ *   st_ktab [128*8]     per stencil entry: M1/x, M2/x, x^2, x M1, x M2 as float,
+ *                       the int32 offset of the neighbour in that box, M3/x,
+ *                       x M3 as float (zero beyond n_stencil)
+ * Errors: PD_ERR_ARG (NULL arguments), PD_ERR_UNSUPPORTED (not 3D, tiles
+ * other than 4x4x4, or reach above 3). */
+typedef struct pd_st_sizes {
+    int64_t n_st;            /* super-tiles                                        */
+    int32_t n_pos;           /* reached box points                                 */
+    int32_t pad0;
+} pd_st_sizes;
+
+pd_status pd_build_supertiles(const pd_family_sizes *sizes, const pd_family_host *fam, pd_st_sizes *out,
+                              int32_t *st_tiles, int32_t *st_nbr, int32_t *st_pos, uint32_t *st_ktab);
+
 /* ------------------------------------------------------------------------ */
 /* device descriptors                                                       */
 /* ------------------------------------------------------------------------ */
@@ -255,6 +287,14 @@ typedef struct pd_problem_dev {
     const int32_t *halo_pos;    /* [device] n_box, pd_family_host.halo_pos         */
     int32_t n_pos;              /* pd_family_sizes.n_box                           */
     int32_t pad1;
+    /* super-tiles (pd_build_supertiles; NULL st_tiles: not used)                 */
+    const int32_t *st_tiles;    /* [device] 4 n_st                                 */
+    const int32_t *st_nbr;      /* [device] 48 n_st                                */
+    const int32_t *st_pos;      /* [device] st_n_pos                               */
+    const uint32_t *st_ktab;    /* [device] 128*8 words                            */
+    int64_t n_st;
+    int32_t st_n_pos;
+    int32_t pad2;
 } pd_problem_dev;
 
 /* Device control block (step counter, diagnostics).  Size in bytes: */
@@ -344,7 +384,10 @@ typedef struct pd_step_opts {
     int32_t kernel;      /* matrix-free kernels: 0 = LDS-staged tile kernels when the
                             family allows them (tile edges >= stencil reach; FP64 also
                             needs st->fe64), else gather kernels; 1 = gather kernels;
-                            2 = tile kernels (error if not possible)                   */
+                            2 = tile kernels, one tile per workgroup (error if not
+                            possible); 3 = FP32 super-tile kernels (four tiles per
+                            workgroup, pd_build_supertiles; error if not possible;
+                            the FP64 path then uses the tile kernels)               */
     int32_t extension;   /* 0: linearized e = M.(u_j - u_i) along M (Eqs. 2.4, 2.7);
                             1: finite e = |x M + u_j - u_i| - x with the pair force
                             along the deformed bond (Eqs. 1.10, 1.13): PD_FP64,

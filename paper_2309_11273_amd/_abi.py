@@ -52,7 +52,13 @@ class pd_problem_dev(C.Structure):
                 ("n_specimens", i32), ("pad0", i32), ("slice_ptr", P), ("words", P), ("stencil", P),
                 ("vol", P), ("inv_m", P), ("lat4", P), ("spec", P), ("aux", P), ("fext", P),
                 ("ramp_steps", i64), ("stencil_off", P), ("tile_nbr", P), ("tile", i32 * 3), ("reach", i32),
-                ("ktab", P), ("halo_map", P), ("halo_pos", P), ("n_pos", i32), ("pad1", i32)]
+                ("ktab", P), ("halo_map", P), ("halo_pos", P), ("n_pos", i32), ("pad1", i32),
+                ("st_tiles", P), ("st_nbr", P), ("st_pos", P), ("st_ktab", P), ("n_st", i64),
+                ("st_n_pos", i32), ("pad2", i32)]
+
+
+class pd_st_sizes(C.Structure):
+    _fields_ = [("n_st", i64), ("n_pos", i32), ("pad0", i32)]
 
 
 class pd_state_dev(C.Structure):
@@ -139,6 +145,8 @@ SIGNATURES = {
     "pd_energy_noalloc": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), P]),
     "pd_step": (i32, [P, C.POINTER(pd_problem_dev), C.POINTER(pd_state_dev), i64,
                       C.POINTER(pd_step_opts), C.POINTER(pd_bsr_dev), C.POINTER(pd_step_report)]),
+    "pd_build_supertiles": (i32, [C.POINTER(pd_family_sizes), C.POINTER(pd_family_host), C.POINTER(pd_st_sizes),
+                                  P, P, P, P]),
     "pd_bsr_pattern": (i32, [C.POINTER(pd_family_sizes), C.POINTER(pd_family_host),
                              C.POINTER(pd_bsr_sizes), P, P]),
     "pd_assemble_K": (i32, [P, C.POINTER(pd_problem_dev), P, C.POINTER(pd_bsr_dev)]),

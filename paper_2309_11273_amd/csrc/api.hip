@@ -111,6 +111,12 @@ pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
     a.halo_map = p->halo_map;
     a.halo_pos = p->halo_pos;
     a.n_pos = p->n_pos;
+    a.st_tiles = p->st_tiles;
+    a.st_nbr = p->st_nbr;
+    a.st_pos = p->st_pos;
+    a.st_ktab = p->st_ktab;
+    a.n_st = p->n_st;
+    a.st_n_pos = p->st_n_pos;
     return a;
 }
 
@@ -408,15 +414,19 @@ static hipError_t enqueue_step(const pdk::StepArgs &a, const pd_step_opts &o, in
         e = tiled ? pdk::launch_tpass2_f64_fin(a, cur, true, s) : pdk::launch_fin_pass2(a, cur, true, block, s);
         if (e != hipSuccess) return e;
     } else {
-        // LDS-staged tile kernels unless the gather kernels are asked for
+        // LDS-staged tile kernels unless the gather kernels are asked for;
+        // the FP32 super-tile kernels when asked for (kernel 3)
         const bool fp64 = o.precision == PD_FP64;
         const bool tiled = o.kernel != 1 && (fp64 ? pdk::tiled64_supported(a) : pdk::tiled_supported(a));
+        const bool super = !fp64 && o.kernel == 3 && pdk::supertiles_supported(a);
         if (fp64) e = tiled ? pdk::launch_tpass1_f64(a, cur, true, s) : pdk::launch_pass1_f64(a, cur, true, block, s);
+        else if (super) e = pdk::launch_spass1_f32(a, cur, true, s);
         else e = tiled ? pdk::launch_tpass1_f32(a, cur, true, s) : pdk::launch_pass1_f32(a, cur, true, block, s);
         if (e != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
         if (fp64) e = tiled ? pdk::launch_tpass2_f64(a, cur, true, s) : pdk::launch_pass2_f64(a, cur, true, block, s);
+        else if (super) e = pdk::launch_spass2_f32(a, cur, true, s);
         else e = tiled ? pdk::launch_tpass2_f32(a, cur, true, s) : pdk::launch_pass2_f32(a, cur, true, block, s);
         if (e != hipSuccess) return e;
     }
@@ -441,7 +451,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
         return fail(c, PD_ERR_ARG, "block must be 0, 64, 128 or 256");
     if (o.graph_chunk < 0 || o.check_every < 0) return fail(c, PD_ERR_ARG, "negative option");
     if (o.profile != 0 && o.profile != 1) return fail(c, PD_ERR_ARG, "profile must be 0 or 1");
-    if (o.kernel < 0 || o.kernel > 2) return fail(c, PD_ERR_ARG, "kernel must be 0, 1 or 2");
+    if (o.kernel < 0 || o.kernel > 3) return fail(c, PD_ERR_ARG, "kernel must be 0, 1, 2 or 3");
     if (o.extension != 0 && o.extension != 1) return fail(c, PD_ERR_ARG, "extension must be 0 or 1");
     if (o.extension && (o.precision != PD_FP64 || o.form != PD_MATRIX_FREE))
         return fail(c, PD_ERR_UNSUPPORTED, "the finite extension runs with PD_FP64 and PD_MATRIX_FREE");
@@ -450,7 +460,13 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
         if (!pdk::tiled64_fin_supported(make_args(p, &tmp)))
             return fail(c, PD_ERR_UNSUPPORTED, "the finite model's tile kernels do not fit this family");
     }
-    if (o.kernel == 2 && o.form == PD_MATRIX_FREE) {
+    if (o.kernel == 3 && o.form == PD_MATRIX_FREE && o.precision == PD_FP32_RECHECK && !o.extension) {
+        pd_state_dev tmp = *st;
+        if (!pdk::supertiles_supported(make_args(p, &tmp)))
+            return fail(c, PD_ERR_UNSUPPORTED,
+                        "super-tile kernels need 3D 4x4x4 tiles, reach <= 3 and the tables of pd_build_supertiles");
+    }
+    if ((o.kernel == 2 || o.kernel == 3) && o.form == PD_MATRIX_FREE) {
         pd_state_dev tmp = *st;
         const pdk::StepArgs ta = make_args(p, &tmp);
         if (o.precision == PD_FP32_RECHECK ? !pdk::tiled_supported(ta) : !pdk::tiled64_supported(ta))
@@ -902,6 +918,10 @@ pd_status pd_autotune(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int3
         pdk::StepArgs a = make_args(p, st);
         if (precision == PD_FP32_RECHECK ? pdk::tiled_supported(a) : pdk::tiled64_supported(a)) {
             ck[nc] = 2;
+            cb[nc++] = 0;
+        }
+        if (precision == PD_FP32_RECHECK && pdk::supertiles_supported(a)) {
+            ck[nc] = 3;
             cb[nc++] = 0;
         }
     }

@@ -9,6 +9,7 @@
 // a small set of lattice offsets: the geometry is stored once per offset
 // (the "stencil") and each bond stores the neighbour row and the offset id.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdint>
@@ -645,5 +646,118 @@ extern "C" pd_status pd_fac_pattern(const pd_family_sizes *sz, const pd_family_h
             }
         }
     });
+    return PD_OK;
+}
+
+// Super-tiles: 2 x 2 x 1 groups of 4x4x4 tiles sharing one halo box.  The
+// tile coordinates follow from the tile origins: per specimen the smallest
+// origin is the tile grid's origin.
+extern "C" pd_status pd_build_supertiles(const pd_family_sizes *sz, const pd_family_host *fam, pd_st_sizes *out,
+                                         int32_t *st_tiles, int32_t *st_nbr, int32_t *st_pos, uint32_t *st_ktab) {
+    if (!sz || !fam || !out || !fam->tile_org || !fam->stencil || !fam->stencil_off) return PD_ERR_ARG;
+    if (sz->dim != 3 || sz->tile[0] != 4 || sz->tile[1] != 4 || sz->tile[2] != 4 || sz->reach < 1 ||
+        sz->reach > 3 || sz->n_stencil < 1 || sz->n_stencil > 124)
+        return PD_ERR_UNSUPPORTED;
+    const int64_t nt = sz->n_tiles;
+    const int R = sz->reach;
+    const int ns = sz->n_stencil;
+    const int P0 = 16, P1 = 228;  // box pitches; x, y extents 8 + 2R <= 14
+    // tile coordinates per specimen
+    std::unordered_map<int32_t, std::array<int32_t, 3>> lo;
+    for (int64_t t = 0; t < nt; t++) {
+        const int32_t sp = fam->tile_org[4 * t + 3];
+        auto it = lo.find(sp);
+        if (it == lo.end()) {
+            lo[sp] = {fam->tile_org[4 * t], fam->tile_org[4 * t + 1], fam->tile_org[4 * t + 2]};
+        } else {
+            for (int c = 0; c < 3; c++) it->second[c] = std::min(it->second[c], fam->tile_org[4 * t + c]);
+        }
+    }
+    auto tkey = [](int64_t sp, int64_t x, int64_t y, int64_t z) {
+        return (uint64_t)((sp << 48) | ((z + 1) << 32) | ((y + 1) << 16) | (x + 1));
+    };
+    std::unordered_map<uint64_t, int32_t> tile_at;
+    std::vector<uint64_t> skeys;
+    tile_at.reserve((size_t)nt * 2);
+    for (int64_t t = 0; t < nt; t++) {
+        const int32_t sp = fam->tile_org[4 * t + 3];
+        const auto &l = lo[sp];
+        int32_t tc[3];
+        for (int c = 0; c < 3; c++) tc[c] = (fam->tile_org[4 * t + c] - l[c]) / 4;
+        tile_at[tkey(sp, tc[0], tc[1], tc[2])] = (int32_t)t;
+        skeys.push_back(((uint64_t)sp << 48) | ((uint64_t)tc[2] << 32) | ((uint64_t)(tc[1] >> 1) << 16) |
+                        (uint64_t)(tc[0] >> 1));
+    }
+    std::sort(skeys.begin(), skeys.end());
+    skeys.erase(std::unique(skeys.begin(), skeys.end()), skeys.end());
+    // reached points of the box (8 + 2R) x (8 + 2R) x (4 + 2R)
+    const int e0 = 8 + 2 * R, e1 = 8 + 2 * R, e2 = 4 + 2 * R;
+    std::vector<uint8_t> reached((size_t)e0 * e1 * e2, 0);
+    for (int q = 0; q < 4; q++)
+        for (int l = 0; l < 64; l++)
+            for (int s = -1; s < ns; s++) {
+                int32_t o[3] = {0, 0, 0};
+                if (s >= 0)
+                    for (int c = 0; c < 3; c++) o[c] = fam->stencil_off[3 * s + c];
+                const int bx = 4 * (q & 1) + (l & 3) + o[0] + R, by = 4 * (q >> 1) + ((l >> 2) & 3) + o[1] + R,
+                          bz = (l >> 4) + o[2] + R;
+                if (bx < 0 || by < 0 || bz < 0 || bx >= e0 || by >= e1 || bz >= e2) return PD_ERR_UNSUPPORTED;
+                reached[bx + e0 * (by + e1 * bz)] = 1;
+            }
+    int32_t npos = 0;
+    for (uint8_t r : reached) npos += r;
+    out->n_st = (int64_t)skeys.size();
+    out->n_pos = npos;
+    out->pad0 = 0;
+    if (!st_tiles) return PD_OK;
+    if (!st_nbr || !st_pos || !st_ktab) return PD_ERR_ARG;
+    for (size_t s = 0; s < skeys.size(); s++) {
+        const int64_t sp = (int64_t)(skeys[s] >> 48), z = (int64_t)((skeys[s] >> 32) & 0xffff),
+                      sy = (int64_t)((skeys[s] >> 16) & 0xffff), sx = (int64_t)(skeys[s] & 0xffff);
+        auto find = [&](int64_t x, int64_t y, int64_t zz) -> int32_t {
+            if (x < 0 || y < 0 || zz < 0) return -1;
+            auto it = tile_at.find(tkey(sp, x, y, zz));
+            return it == tile_at.end() ? -1 : it->second;
+        };
+        for (int q = 0; q < 4; q++) st_tiles[4 * s + q] = find(2 * sx + (q & 1), 2 * sy + (q >> 1), z);
+        for (int dz = 0; dz < 3; dz++)
+            for (int dy = 0; dy < 4; dy++)
+                for (int dx = 0; dx < 4; dx++)
+                    st_nbr[48 * s + dx + 4 * dy + 16 * dz] = find(2 * sx - 1 + dx, 2 * sy - 1 + dy, z - 1 + dz);
+    }
+    int32_t np = 0;
+    for (int bz = 0; bz < e2; bz++)
+        for (int by = 0; by < e1; by++)
+            for (int bx = 0; bx < e0; bx++) {
+                if (!reached[bx + e0 * (by + e1 * bz)]) continue;
+                const int p[3] = {bx - R, by - R, bz - R};
+                int d[3], l[3];
+                for (int c = 0; c < 3; c++) {
+                    d[c] = (p[c] + 4) / 4;  // tile offset + 1 (p >= -3)
+                    l[c] = p[c] - 4 * (d[c] - 1);
+                }
+                const int32_t slot = bx + P0 * by + P1 * bz;
+                st_pos[np++] = (slot << 12) | (64 * (d[0] + 4 * d[1] + 16 * d[2]) + l[0] + 4 * (l[1] + 4 * l[2]));
+            }
+    auto fbits = [](double v) {
+        const float f = (float)v;
+        uint32_t b;
+        std::memcpy(&b, &f, 4);
+        return b;
+    };
+    for (int q = 0; q < 128 * 8; q++) st_ktab[q] = 0u;
+    for (int s = 0; s < ns; s++) {
+        const double *S = fam->stencil + 4 * s;  // M1, M2, M3, x
+        const int32_t *o = fam->stencil_off + 3 * s;
+        uint32_t *k1 = st_ktab + 8 * s;
+        k1[0] = fbits(S[0] / S[3]);
+        k1[1] = fbits(S[1] / S[3]);
+        k1[2] = fbits(S[3] * S[3]);
+        k1[3] = fbits(S[3] * S[0]);
+        k1[4] = fbits(S[3] * S[1]);
+        k1[5] = (uint32_t)(o[0] + P0 * o[1] + P1 * o[2]);
+        k1[6] = fbits(S[2] / S[3]);
+        k1[7] = fbits(S[3] * S[2]);
+    }
     return PD_OK;
 }

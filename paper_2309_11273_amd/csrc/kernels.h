@@ -45,6 +45,13 @@ struct StepArgs {
     const int16_t *halo_map;
     const int32_t *halo_pos;
     int32_t n_pos;
+    // super-tiles (four tiles per workgroup sharing one box; NULL: not used)
+    const int32_t *st_tiles;
+    const int32_t *st_nbr;
+    const int32_t *st_pos;
+    const uint32_t *st_ktab;
+    int64_t n_st;
+    int32_t st_n_pos;
 };
 
 struct InitArgs {
@@ -82,6 +89,9 @@ hipError_t launch_pass1_f32(const StepArgs &a, int cur, bool brk, int block, hip
 hipError_t launch_pass2_f32(const StepArgs &a, int cur, bool update, int block, hipStream_t s);
 hipError_t launch_shadow_prep(const StepArgs &a, int cur, bool tiled, bool force, hipStream_t s);
 bool tiled_supported(const StepArgs &a);
+bool supertiles_supported(const StepArgs &a);
+hipError_t launch_spass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s);
+hipError_t launch_spass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s);
 hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s);
 hipError_t launch_tpass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s);
 hipError_t launch_tdsum(const StepArgs &a, int cur, hipStream_t s);

@@ -61,15 +61,20 @@ namespace pdk {
 // from one address, which keeps the box of a one-wave tile small.
 template <int DIM, int TPW>
 struct Lay1 {
-    static constexpr int S = DIM == 3 ? 1472 : (TPW == 4 ? 336 : 1024);
+    // super-tile box: 16 x 14 x 10 slots at pitches 16 and 228 (2280 slots)
+    static constexpr int S = TPW == 0 ? 2304 : (DIM == 3 ? 1472 : (TPW == 4 ? 336 : 1024));
     // box points staged per thread: 3D boxes of up to 1024 points (R <= 3),
-    // 2D up to 256 per wave (TPW = 4) or 512 per workgroup
-    static constexpr int MP = DIM == 3 ? 4 : (TPW == 4 ? 4 : 2);
+    // super-tile boxes up to 2048, 2D up to 256 per wave (TPW = 4) or 512
+    // per workgroup
+    static constexpr int MP = TPW == 0 ? 8 : (DIM == 3 ? 4 : (TPW == 4 ? 4 : 2));
     static constexpr int BOX = DIM == 3 ? 5 * S * 4 : 2 * S * 8;
     static constexpr int SUMS = TPW == 1 ? PD_TILE_WAVES * 64 * (4 * 4 + 3 * 8) : 0;
     static constexpr int AREA = BOX > SUMS ? BOX : SUMS;
-    static constexpr int BYTES = AREA + 32 * 4;
+    // then the neighbour tiles (27, or 48 for a super-tile) and, for a
+    // super-tile, the shared reference point
+    static constexpr int BYTES = AREA + (TPW == 0 ? 64 : 32) * 4;
     static_assert(DIM == 2 || (S % 64 == 0 && 4 * S * 4 / 256 <= 255), "array offsets fit the st64 encoding");
+    static_assert(TPW != 0 || (DIM == 3 && 228 * 10 <= S), "super-tile box fits the stride");
 };
 
 // access to the staged pass-1 box of Lay1
@@ -156,19 +161,23 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     constexpr int MS = LY::MP;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int gt = TPW == 1 ? tid : lane;  // thread within its tile's group
+    const int gt = TPW <= 1 ? tid : lane;  // thread within its box's group
     const int sub = TPW == 1 ? 0 : wv;     // tile of the workgroup this wave serves
     const int kq = TPW == 1 ? wv : 0;      // stencil part of this wave
+    constexpr int HB = TPW == 0 ? 12 : 11;  // bits of the point code in a box-point entry
+    constexpr int NNB = TPW == 0 ? 48 : 27;  // neighbour tiles of the box
     bool valid;
-    const int64_t tile = group_tile<TPW>(a.n_slices, sub, valid);
+    int64_t stid = 0;
+    const int64_t tile = TPW == 0 ? super_tile(a, sub, stid, valid) : group_tile<TPW>(a.n_slices, sub, valid);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
-    unsigned char *reg = smem + sub * LY::BYTES;
+    unsigned char *reg = smem + (TPW == 4 ? sub * LY::BYTES : 0);
     const View1<DIM, S> box{reinterpret_cast<float *>(reg)};
     int *stn = reinterpret_cast<int *>(reg + LY::AREA);
     int32_t B1[4];
     pd_tile_box1(a.tile, a.reach, DIM, B1);
-    const int npts = a.n_pos;  // box points the stencil reaches
+    const int npts = TPW == 0 ? a.st_n_pos : a.n_pos;  // box points the stencil reaches
+    const int32_t *hpos = TPW == 0 ? a.st_pos : a.halo_pos;
     pd_ctl *ctl = a.ctl;
     const double Q = ctl->qs[cur];
     const int4 *__restrict__ sh = a.ush[cur];
@@ -188,9 +197,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
 #pragma unroll
     for (int i = 0; i < MS; i++) {
         act[i] = (gt & ~63) + i * GR::NT < npts;
-        hp[i] = act[i] ? a.halo_pos[min(gt + i * GR::NT, npts - 1)] : 0;
+        hp[i] = act[i] ? hpos[min(gt + i * GR::NT, npts - 1)] : 0;
     }
-    if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
+    if (gt < NNB) stn[gt] = TPW == 0 ? a.st_nbr[48 * stid + gt] : a.tile_nbr[27 * tile + gt];
     const int G4 = L4 >> 2;
     const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
     const int g0 = kq * gper, g1 = min(G4, g0 + gper);
@@ -208,16 +217,32 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     const int lr = ((nodes >> lc) & 1ull) || !nodes ? lc : (int)__builtin_ctzll(nodes);
     const int r0 = __builtin_amdgcn_readlane(own.x, lr);
     const bool rsent = r0 == PD_SENTINEL_T;
-    const int rx = rsent ? 0 : r0;
-    const int ry = rsent ? 0 : __builtin_amdgcn_readlane(own.y, lr);
-    const int rz = rsent ? 0 : __builtin_amdgcn_readlane(own.z, lr);
+    int rx = rsent ? 0 : r0;
+    int ry = rsent ? 0 : __builtin_amdgcn_readlane(own.y, lr);
+    int rz = rsent ? 0 : __builtin_amdgcn_readlane(own.z, lr);
+    int *rfl = stn + NNB;
+    if constexpr (TPW == 0) {
+        // one reference for the shared box: that of the first quadrant with a
+        // tile (a wave without a tile took that tile's rows, so any wave with
+        // the first tile can write it)
+        if (valid && lane == 0 && tile == first_st_tile(a, stid)) {
+            rfl[0] = rx;
+            rfl[1] = ry;
+            rfl[2] = rz;
+        }
+    }
     tile_sync<TPW>();
+    if constexpr (TPW == 0) {
+        rx = rfl[0];
+        ry = rfl[1];
+        rz = rfl[2];
+    }
     bool sent = false;
     {
         uint32_t rw[MS];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            const int h = hp[i] & 2047;
+            const int h = hp[i] & ((1 << HB) - 1);
             const int nt = act[i] ? stn[h >> 6] : 0;
             // no tile in that direction: any row of this tile (finite values on a
             // point no intact bond reaches)
@@ -237,17 +262,20 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
             const bool st = v[i].x == PD_SENTINEL_T;
             sent |= st;
             const float Vv = __int_as_float(v[i].w);
-            box.put(hp[i] >> 11, st ? __builtin_inff() : idiff(v[i].x, rx), idiff(v[i].y, ry),
+            box.put(hp[i] >> HB, st ? __builtin_inff() : idiff(v[i].x, rx), idiff(v[i].y, ry),
                     DIM == 3 ? idiff(v[i].z, rz) : 0.0f, Vv, GQ * r[i] * Vv);
         }
     }
     const bool anysent = tile_sync_or<TPW>(sent);
-    if (BREAK && valid && tile == 0 && gt == 0) {
+    // a super-tile quadrant without a tile has nothing more to do (no later
+    // workgroup barrier in this mode)
+    if (TPW == 0 && !valid) return;
+    if (BREAK && valid && tile == 0 && (TPW == 1 ? gt == 0 : lane == 0)) {
         ctl->s1 = ctl->s2;
         ctl->qs[cur ^ 1] = shadow_scale_t(ctl->umax_bits[cur]);
         ctl->umax_bits[cur ^ 1] = 0u;
     }
-    const int my = own_slot1<DIM>(a.tile, a.reach, B1, lane);
+    const int my = TPW == 0 ? own_slot_st(a.reach, sub, lane) : own_slot1<DIM>(a.tile, a.reach, B1, lane);
     float aix, aiy, aiz;
     box.pos(my, aix, aiy, aiz);
     const float big_i = big_abs(aix) + big_abs(aiy) + big_abs(aiz);
@@ -471,7 +499,7 @@ struct Lay2 {
     static constexpr int S = Lay1<DIM, TPW>::S;
     static constexpr int BOX = 2 * S * 4;
     static constexpr int SUMS = TPW == 1 ? 3 * PD_TILE_WAVES * 64 * 4 : 0;
-    static constexpr int BYTES = BOX + SUMS + 32 * 4;
+    static constexpr int BYTES = BOX + SUMS + (TPW == 0 ? 64 : 32) * 4;
 };
 
 template <int DIM, bool UPDATE, int TPW>
@@ -484,20 +512,24 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     constexpr int MS = Lay1<DIM, TPW>::MP;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int gt = TPW == 1 ? tid : lane;
+    const int gt = TPW <= 1 ? tid : lane;
     const int sub = TPW == 1 ? 0 : wv;
     const int kq = TPW == 1 ? wv : 0;
+    constexpr int HB = TPW == 0 ? 12 : 11;
+    constexpr int NNB = TPW == 0 ? 48 : 27;
     bool valid;
-    const int64_t tile = group_tile<TPW>(a.n_slices, sub, valid);
+    int64_t stid = 0;
+    const int64_t tile = TPW == 0 ? super_tile(a, sub, stid, valid) : group_tile<TPW>(a.n_slices, sub, valid);
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
-    unsigned char *reg = smem + sub * LY::BYTES;
+    unsigned char *reg = smem + (TPW == 4 ? sub * LY::BYTES : 0);
     float *hb = reinterpret_cast<float *>(reg);  // [2][S]: (K - G/3) theta_j/m_j, V_j
     float *red = reinterpret_cast<float *>(reg + LY::BOX);  // TPW = 1: [3][waves][64]
     int *stn = reinterpret_cast<int *>(reg + LY::BOX + LY::SUMS);
     int32_t B1[4];
     pd_tile_box1(a.tile, a.reach, DIM, B1);
-    const int npts = a.n_pos;  // box points the stencil reaches
+    const int npts = TPW == 0 ? a.st_n_pos : a.n_pos;  // box points the stencil reaches
+    const int32_t *hpos = TPW == 0 ? a.st_pos : a.halo_pos;
     pd_ctl *ctl = a.ctl;
     const float2 *__restrict__ qvs = a.qv32;
     const int64_t row = tile * 64 + lane;
@@ -508,9 +540,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
 #pragma unroll
     for (int i = 0; i < MS; i++) {
         act[i] = (gt & ~63) + i * GR::NT < npts;
-        hp[i] = act[i] ? a.halo_pos[min(gt + i * GR::NT, npts - 1)] : 0;
+        hp[i] = act[i] ? hpos[min(gt + i * GR::NT, npts - 1)] : 0;
     }
-    if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
+    if (gt < NNB) stn[gt] = TPW == 0 ? a.st_nbr[48 * stid + gt] : a.tile_nbr[27 * tile + gt];
     const int G4 = L4 >> 2;
     const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
     const int g0 = kq * gper, g1 = min(G4, g0 + gper);
@@ -535,7 +567,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         uint32_t rw[MS];
 #pragma unroll
         for (int i = 0; i < MS; i++) {
-            const int h = hp[i] & 2047;
+            const int h = hp[i] & ((1 << HB) - 1);
             const int nt = act[i] ? stn[h >> 6] : 0;
             rw[i] = (uint32_t)(nt < 0 ? (int)tile : nt) * 64u + (uint32_t)(h & 63);
         }
@@ -546,7 +578,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             if (!act[i]) continue;
-            const int slot = hp[i] >> 11;
+            const int slot = hp[i] >> HB;
             if constexpr (DIM == 3) {
                 hb[slot] = kp * qv[i].x;
                 hb[S + slot] = qv[i].y;
@@ -556,7 +588,8 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         }
     }
     tile_sync<TPW>();
-    const int my = own_slot1<DIM>(a.tile, a.reach, B1, lane);
+    if (TPW == 0 && !valid) return;  // no later workgroup barrier in this mode
+    const int my = TPW == 0 ? own_slot_st(a.reach, sub, lane) : own_slot1<DIM>(a.tile, a.reach, B1, lane);
     const float qi = DIM == 3 ? hb[my] : reinterpret_cast<const float2 *>(hb)[my].x;
     float fx = 0.f, fy = 0.f, fz = 0.f;
     {
@@ -630,7 +663,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
         return;
     }
     const int64_t n = ctl->s1;
-    if (tile == 0 && gt == 0) {
+    if (tile == 0 && (TPW == 1 ? gt == 0 : lane == 0)) {
         ctl->s2 = n + 1;
         // the next shadow written below describes the new state
         ctl->sh_step = n + 1;
@@ -808,6 +841,35 @@ bool tiled_supported(const StepArgs &a) {
     if (np > cap1) return false;
     if (a.n_pad >= (int64_t(1) << 31)) return false;  // 32-bit row numbers in the staging
     return tiled_lds(a, 1, tpw) <= 64 * 1024 && tiled_lds(a, 2, tpw) <= 64 * 1024;
+}
+
+bool supertiles_supported(const StepArgs &a) {
+    if (!tiled_supported(a)) return false;  // the tile path's tables and limits
+    if (!a.st_tiles || !a.st_nbr || !a.st_pos || !a.st_ktab || a.n_st < 1 || a.n_st >= (int64_t(1) << 31))
+        return false;
+    if (a.dim != 3 || a.tile[0] != 4 || a.tile[1] != 4 || a.tile[2] != 4 || a.reach < 1 || a.reach > 3) return false;
+    if (a.st_n_pos < 1 || a.st_n_pos > Grp<3, 0>::CAP || a.st_n_pos > (8 + 2 * a.reach) * (8 + 2 * a.reach) * (4 + 2 * a.reach))
+        return false;
+    return Lay1<3, 0>::BYTES <= 64 * 1024 && Lay2<3, 0>::BYTES <= 64 * 1024;
+}
+
+hipError_t launch_spass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s) {
+    const dim3 g((unsigned)a.n_st), b(PD_TILE_THREADS);
+    const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
+    const KEnt1 *kn = reinterpret_cast<const KEnt1 *>(a.st_ktab);
+    constexpr size_t lds = Lay1<3, 0>::BYTES;
+    if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true, 0>), g, b, lds, s, a, cur, kt, kn);
+    else hipLaunchKernelGGL((k_tpass1_f32<3, false, 0>), g, b, lds, s, a, cur, kt, kn);
+    return hipGetLastError();
+}
+
+hipError_t launch_spass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s) {
+    const dim3 g((unsigned)a.n_st), b(PD_TILE_THREADS);
+    const KEnt1 *kn = reinterpret_cast<const KEnt1 *>(a.st_ktab);
+    constexpr size_t lds = Lay2<3, 0>::BYTES;
+    if (update) hipLaunchKernelGGL((k_tpass2_f32<3, true, 0>), g, b, lds, s, a, cur, kn);
+    else hipLaunchKernelGGL((k_tpass2_f32<3, false, 0>), g, b, lds, s, a, cur, kn);
+    return hipGetLastError();
 }
 
 hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s) {

@@ -154,7 +154,7 @@ __device__ __forceinline__ int64_t halo_row_of(int m, const int *tn) {
 // waves of a workgroup need not wait for each other.
 template <int TPW>
 __device__ __forceinline__ void tile_sync() {
-    if constexpr (TPW == 1) {
+    if constexpr (TPW <= 1) {  // one tile (TPW 1) or one super-tile (TPW 0) per workgroup
         __syncthreads();
     } else {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -165,7 +165,7 @@ __device__ __forceinline__ void tile_sync() {
 
 template <int TPW>
 __device__ __forceinline__ bool tile_sync_or(bool p) {
-    if constexpr (TPW == 1) {
+    if constexpr (TPW <= 1) {
         return __syncthreads_or(p);
     } else {
         tile_sync<TPW>();
@@ -192,16 +192,50 @@ struct StageCap {
 //   TPW = 1: the four waves split the stencil of one tile in quarters and add
 //            their partial sums in LDS (3D: a long stencil, a large halo box);
 //   TPW = 4: every wave takes a whole tile of its own (2D: a short stencil,
-//            whose quarters would leave each wave too little work per box).
+//            whose quarters would leave each wave too little work per box);
+//   TPW = 0: a super-tile, four 4x4x4 tiles side by side (2 x 2 x 1) that
+//            share one halo box staged by the whole workgroup; every wave
+//            sweeps the whole stencil for its own tile (3D).
 // SPLIT waves share a tile; NT threads stage its box, MS slots each, so a box
 // holds at most NT * MS slots (TPW = 4: 256).
 template <int DIM, int TPW>
 struct Grp {
-    static constexpr int SPLIT = PD_TILE_WAVES / TPW;
-    static constexpr int NT = 64 * SPLIT;
-    static constexpr int MS = TPW == 1 ? StageCap<DIM>::value : 4;
+    static constexpr int SPLIT = TPW == 0 ? 1 : PD_TILE_WAVES / TPW;
+    static constexpr int NT = TPW == 0 ? PD_TILE_THREADS : 64 * SPLIT;
+    static constexpr int MS = TPW == 0 ? 8 : (TPW == 1 ? StageCap<DIM>::value : 4);
     static constexpr int CAP = NT * MS;
 };
+
+// super-tile of this workgroup and the tile of this wave in it (quadrant
+// 'sub'); a wave whose quadrant holds no tile reads the first tile of the
+// super-tile and must not write
+__device__ __forceinline__ int64_t super_tile(const StepArgs &a, int sub, int64_t &st, bool &valid) {
+    st = xcd_tile(blockIdx.x, a.n_st);
+    const int t = a.st_tiles[4 * st + sub];
+    valid = t >= 0;
+    if (valid) return t;
+    for (int q = 0; q < 4; q++) {
+        const int u = a.st_tiles[4 * st + q];
+        if (u >= 0) return u;
+    }
+    return 0;
+}
+
+// first tile of a super-tile (the quadrant whose wave writes the box's
+// shared reference point)
+__device__ __forceinline__ int64_t first_st_tile(const StepArgs &a, int64_t st) {
+    for (int q = 0; q < 4; q++) {
+        const int u = a.st_tiles[4 * st + q];
+        if (u >= 0) return u;
+    }
+    return 0;
+}
+
+// slot of lane l of quadrant q's tile in the super-tile box (pitches 16 and
+// 228, reach R on every side)
+__device__ __forceinline__ int own_slot_st(int R, int sub, int lane) {
+    return ((lane & 3) + 4 * (sub & 1) + R) + 16 * (((lane >> 2) & 3) + 4 * (sub >> 1) + R) + 228 * ((lane >> 4) + R);
+}
 
 // tile of this wave; waves of the last workgroup past the last tile (TPW > 1)
 // redo the last tile and must not write

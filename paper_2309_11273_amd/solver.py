@@ -118,6 +118,28 @@ class FamilyHost:
         A.check("pd_build_family", L.pd_build_family(C.byref(body), C.cast(carr, C.c_void_p), len(cuts),
                                                      C.byref(sizes), C.byref(hb)))
 
+        self.supertiles()
+
+    def supertiles(self):
+        """pd_build_supertiles: st_tiles, st_nbr, st_pos, st_ktab (None where the
+        family has no super-tiles: not 3D 4x4x4 tiles with reach <= 3)."""
+        self.st_tiles = self.st_nbr = self.st_pos = self.st_ktab = None
+        self.n_st, self.st_n_pos = 0, 0
+        L = A.load()
+        ss = A.pd_st_sizes()
+        st = L.pd_build_supertiles(C.byref(self.sizes), C.byref(self._hb), C.byref(ss), None, None, None, None)
+        if st == -5:  # PD_ERR_UNSUPPORTED
+            return
+        A.check("pd_build_supertiles", st)
+        self.st_tiles = np.empty(4 * ss.n_st, np.int32)
+        self.st_nbr = np.empty(48 * ss.n_st, np.int32)
+        self.st_pos = np.empty(ss.n_pos, np.int32)
+        self.st_ktab = np.empty(128 * 8, np.uint32)
+        A.check("pd_build_supertiles", L.pd_build_supertiles(C.byref(self.sizes), C.byref(self._hb), C.byref(ss),
+                                                             _np(self.st_tiles), _np(self.st_nbr),
+                                                             _np(self.st_pos), _np(self.st_ktab)))
+        self.n_st, self.st_n_pos = int(ss.n_st), int(ss.n_pos)
+
     @property
     def n(self):
         return int(self.sizes.n)
@@ -267,6 +289,12 @@ class Solver:
         for c in range(3):
             P.tile[c] = int(s.tile[c])
         P.reach = int(s.reach)
+        if self.fam.st_tiles is not None:
+            self.st_tiles, self.st_nbr = t(self.fam.st_tiles), t(self.fam.st_nbr)
+            self.st_pos, self.st_ktab = t(self.fam.st_pos), t(self.fam.st_ktab.view(np.int32))
+            P.st_tiles, P.st_nbr = _tp(self.st_tiles), _tp(self.st_nbr)
+            P.st_pos, P.st_ktab = _tp(self.st_pos), _tp(self.st_ktab)
+            P.n_st, P.st_n_pos = self.fam.n_st, self.fam.st_n_pos
         self.P = P
         # state
         self.uv = [torch.zeros(self.n_pad * 4, dtype=torch.float64, device=d) for _ in range(2)]
@@ -400,7 +428,7 @@ class Solver:
         prec = {"fp64": A.PD_FP64, "fp32": A.PD_FP32_RECHECK}[precision]
         self.ctx.check("pd_autotune", A.load().pd_autotune(self.ctx.h, C.byref(self.P), C.byref(self.S), prec,
                                                              int(trial_steps), C.byref(r)))
-        res = dict(kernel={0: "auto", 1: "gather", 2: "tiled"}[r.kernel], block=int(r.block),
+        res = dict(kernel={0: "auto", 1: "gather", 2: "tiled", 3: "super"}[r.kernel], block=int(r.block),
                    ms_per_step=r.ms_per_step,
                    candidates=[dict(kernel=int(r.cand_kernel[i]), block=int(r.cand_block[i]),
                                     ms=r.cand_ms[i]) for i in range(r.n_candidates)])
@@ -434,7 +462,7 @@ class Solver:
         o.form = {"mf": A.PD_MATRIX_FREE, "bsr": A.PD_BSR, "fac": A.PD_FACTORED}[form]
         o.graph_chunk, o.block, o.check_every = int(graph_chunk), int(block), int(check_every)
         o.profile = 1 if profile else 0
-        o.kernel = {"auto": 0, "gather": 1, "tiled": 2}[kernel]
+        o.kernel = {"auto": 0, "gather": 1, "tiled": 2, "super": 3}[kernel]
         o.extension = {"linear": 0, "finite": 1}[extension]
         o.energy_check = 1 if energy_check else 0
         o.energy_growth = float(energy_growth)
@@ -644,7 +672,7 @@ class Solver:
         o.extension = {"linear": 0, "finite": 1}[extension]
         o.graph_chunk, o.check_every = int(graph_chunk), int(check_every)
         o.profile = 1 if profile else 0
-        o.kernel = {"auto": 0, "gather": 1, "tiled": 2}[kernel]
+        o.kernel = {"auto": 0, "gather": 1, "tiled": 2, "super": 3}[kernel]
         rep = A.pd_step_report()
         self.ctx.check("pd_adr_step", A.load().pd_adr_step(self.ctx.h, C.byref(self.P), C.byref(self.S),
                                                              int(nsteps), C.byref(o), C.byref(self.R),

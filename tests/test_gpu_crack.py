@@ -100,7 +100,7 @@ def strains(reference, u):
     return ((M[:, 0] * h[:, 0] + M[:, 1] * h[:, 1]) + M[:, 2] * h[:, 2]) / reference["xl"]
 
 
-@pytest.mark.parametrize("kernel", ["tiled", "gather"])
+@pytest.mark.parametrize("kernel", ["tiled", "gather", "super"])
 def test_fp32_cracking_cylinder(ctx, reference, kernel):
     """The FP32 force path one step at a time beside the reference.
 

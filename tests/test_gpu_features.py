@@ -89,12 +89,15 @@ def test_graph_replay_equals_eager_all_paths(ctx, precision, form):
     assert np.array_equal(a.mask_host(), b.mask_host())
 
 
-@pytest.mark.parametrize("kernel", ["tiled", "gather"])
+@pytest.mark.parametrize("kernel", ["tiled", "gather", "super"])
 def test_fp32_split_calls_equal_one_call(ctx, kernel):
     """An FP32 trajectory is the same bits however its steps are split into
     calls (1 + 7 + 30 + 62 eager steps against 100 in one call), on a plate
     that breaks bonds."""
-    w = W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37, steps=100)
+    if kernel == "super":  # 3D only: the cracking-free impact plate with its 16.5 m/s edge
+        w = W.impact3d(nx=36, ny=36, nz=9, dt=2.6e-7, steps=100)
+    else:
+        w = W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37, steps=100)
     a = solver(w, ctx)
     b = solver(w, ctx)
     a.step(100, precision="fp32", kernel=kernel)
@@ -103,6 +106,8 @@ def test_fp32_split_calls_equal_one_call(ctx, kernel):
     assert np.array_equal(a.read()[0], b.read()[0])
     assert np.array_equal(a.mask_host(), b.mask_host())
     assert b.bond_status()[2].size and int((b.bond_status()[2] == 0).sum()) > 0
+    if kernel == "super":
+        assert a.fam.st_tiles is not None
 
 
 def test_fp32_shadow_rebuilt_after_other_paths(ctx):

@@ -146,14 +146,18 @@ def test_plate_full_size_fp64(ctx):
         assert np.array_equal(s.bond_status()[2], o.rho())
 
 
-@pytest.mark.parametrize("kernel", ["gather", "tiled"])
+@pytest.mark.parametrize("kernel", ["gather", "tiled", "super"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("impact", 200),
                                         ("impact_r2", 200), ("cylinder", 200), ("batch", 200), ("plate_wide", 200),
                                         ("plate_16x4", 200)])
 def test_fp32_recheck_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
+    if kernel == "super" and w.dim != 3:
+        pytest.skip("super-tiles are 3D")
     o = Oracle(w)
     s = solver(w, ctx)
+    if kernel == "super" and s.fam.st_tiles is None:
+        pytest.skip("no super-tiles for this family (tile shape or reach)")
     uo, vo = o.initial_state()
     s.step(steps, precision="fp32", kernel=kernel)
     o.run(steps, uo, vo)
@@ -188,14 +192,14 @@ def test_deterministic_and_block_invariant(ctx):
     for u, m in outs[1:]:
         assert np.array_equal(u, outs[0][0])
         assert np.array_equal(m, outs[0][1])
-    for prec in ("fp64", "fp32"):
+    for prec, kern in (("fp64", "tiled"), ("fp32", "tiled"), ("fp32", "super")):
         runs = []
         for _ in range(2):
             s = solver(w, ctx)
-            s.step(100, precision=prec, kernel="tiled")
+            s.step(100, precision=prec, kernel=kern)
             runs.append((s.read()[0], s.mask_host()))
-        assert np.array_equal(runs[0][0], runs[1][0]), prec
-        assert np.array_equal(runs[0][1], runs[1][1]), prec
+        assert np.array_equal(runs[0][0], runs[1][0]), (prec, kern)
+        assert np.array_equal(runs[0][1], runs[1][1]), (prec, kern)
 
 
 def test_bsr_apply_matches_matrix_free(ctx):

@@ -572,3 +572,68 @@ def test_cleared_keys_and_status_index(lib, case):
     m2[first[rows[sel] // 64] + ks[sel]] &= ~np.uint64(1 << int(rows[sel] % 64))
     with pytest.raises(AssertionError):
         fam.cleared_keys(fam.mask, m2)
+
+
+@pytest.mark.parametrize("case", ["cantilever", "impact_small", "cylinder_small", "short_reach"])
+def test_supertile_box_addressing_matches_bond_words(lib, case):
+    """Super-tiles group the 4x4x4 tiles 2 x 2 x 1: every tile is in exactly
+    one quadrant of one super-tile, at its place; the shared box (pitches 16
+    and 228) receives, at slot(l) + soff[k] of lane l of quadrant q, exactly
+    the row the bond word of bond k names; the lanes of a quadrant hit 64
+    distinct LDS banks; the table holds M/x, x^2, x M of every entry."""
+    if case == "short_reach":
+        w = W.impact3d(nx=24, ny=24, nz=8, dt=1e-7)
+        w.delta = 2.015 * w.dx
+    else:
+        w = CASES[case]()
+    f = _family(w)
+    s = f.sizes
+    R = int(s.reach)
+    assert f.st_tiles is not None and list(s.tile) == [4, 4, 4]
+    nst = f.n_st
+    st = f.st_tiles.reshape(nst, 4)
+    assert np.array_equal(np.sort(st[st >= 0]), np.arange(int(s.n_tiles)))
+    org = f.tile_org.reshape(-1, 4)
+    for q in range(4):
+        for sidx in np.nonzero(st[:, q] >= 0)[0][:50]:
+            t0 = st[sidx][st[sidx] >= 0][0]
+            t = st[sidx, q]
+            assert org[t, 3] == org[t0, 3] and org[t, 2] == org[t0, 2]
+    P0, P1 = 16, 228
+    for q in range(4):
+        lanes = [((l & 3) + 4 * (q & 1)) + P0 * (((l >> 2) & 3) + 4 * (q >> 1)) + P1 * (l >> 4) for l in range(64)]
+        assert len({v % 64 for v in lanes}) == 64
+    ns_ = int(s.n_stencil)
+    off = f.stencil_off.reshape(-1, 3)
+    kt = f.st_ktab.view(np.int32).reshape(128, 8)
+    kf = f.st_ktab.view(np.float32).reshape(128, 8)
+    soff = off[:, 0] + P0 * off[:, 1] + P1 * off[:, 2]
+    assert np.array_equal(kt[:ns_, 5], soff) and not kt[ns_:].any()
+    k1 = f.ktab[1536:].view(np.float32).reshape(128, 8)
+    assert np.array_equal(kf[:ns_, [0, 1, 2, 3, 4, 6, 7]], k1[:ns_, [0, 1, 2, 3, 4, 6, 7]])
+    hp = f.st_pos.astype(np.int64)
+    slots = hp >> 12
+    assert len(np.unique(slots)) == len(slots) and slots.max() < P1 * (4 + 2 * R)
+    rng = np.random.default_rng(2)
+    for sidx in rng.choice(nst, size=min(25, nst), replace=False):
+        nb = f.st_nbr[48 * sidx: 48 * sidx + 48]
+        rows = np.full(P1 * (4 + 2 * R), -1, np.int64)
+        nt = nb[(hp & 4095) >> 6]
+        rows[slots] = np.where(nt >= 0, nt * 64 + (hp & 63), -1)
+        for q in range(4):
+            t = st[sidx, q]
+            if t < 0:
+                continue
+            base = f.slice_ptr[t]
+            for lane in range(64):
+                my = ((lane & 3) + 4 * (q & 1) + R) + P0 * (((lane >> 2) & 3) + 4 * (q >> 1) + R) + P1 * ((lane >> 4) + R)
+                assert rows[my] == t * 64 + lane
+                for k in range(ns_):
+                    wd = f.words[base + (k // 4) * 256 + lane * 4 + (k % 4)]
+                    if (wd & 127) != 127:
+                        assert rows[my + soff[k]] == (wd >> 7)
+
+
+def test_supertiles_only_for_3d_4x4x4(lib):
+    f = _family(W.plate2d(nx=40, ny=20, dt=1e-7, notch_row=9, notch_tip=19.37))
+    assert f.st_tiles is None and f.n_st == 0
