@@ -197,14 +197,14 @@ def fac_roofline(ms, dim, nnz, nb, n, n_loaded, workload):
                             for k, v in ms.items()}}
 
 
-def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto", extension="linear"):
+def time_gpu(s, steps, warmup, precision, form, chunk, kernel="auto", extension="linear", block=0):
     import torch
     s.step(warmup, precision=precision, form=form, graph_chunk=chunk, report=False, kernel=kernel,
-           extension=extension)
+           extension=extension, block=block)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(steps, precision=precision, form=form, graph_chunk=chunk, report=False, kernel=kernel,
-           extension=extension)
+           extension=extension, block=block)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 
@@ -242,14 +242,14 @@ def golden_compare(s, name, step):
     return out
 
 
-def run_window(s, w, args, precision, preroll, chunk, extension="linear", kernel="auto"):
+def run_window(s, w, args, precision, preroll, chunk, extension="linear", kernel="auto", block=0):
     """Untimed pre-roll, warm-up, then the timed steps; returns the wall time
     of the timed steps and the step counter at their end."""
     import torch
     if preroll > 0:
         s.step(preroll, precision=precision, form=args.form, graph_chunk=chunk, report=False, kernel=kernel,
-               extension=extension)
-    el = time_gpu(s, args.steps, args.warmup, precision, args.form, chunk, kernel, extension)
+               extension=extension, block=block)
+    el = time_gpu(s, args.steps, args.warmup, precision, args.form, chunk, kernel, extension, block)
     torch.cuda.synchronize()
     return el, preroll + args.warmup + args.steps
 
@@ -350,6 +350,10 @@ def leg_roofline(s, args, nnz, n, n_loaded):
     return roofline_entry(s, a, "pass2" if ms2 >= ms1 else "pass1", ms1, ms2, nnz, n, n_loaded)
 
 
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def batched_leg(args):
     """The 256-plate batch: FP32 force path, all plates in one launch per
     pass (graph replay), against plain FP64 run one plate at a time (each
@@ -358,6 +362,7 @@ def batched_leg(args):
     import numpy as np
     import torch
     from paper_2309_11273_amd.solver import Solver
+    progress("batched leg: 256 plates")
     w, desc = make_workload("batch2d")
     t0 = time.perf_counter()
     s = Solver(w, device=0)
@@ -366,7 +371,7 @@ def batched_leg(args):
     nb, nnz = int(sz.n_bonds), int(sz.nnz)
     n_loaded = int(np.count_nonzero(np.abs(w.fext).sum(1)))
     a = argparse.Namespace(**vars(args))
-    a.workload, a.form = "batch2d", "mf"
+    a.workload, a.form, a.kernel = "batch2d", "mf", "auto"
     pre = default_preroll(a, w)
     el, end = run_window(s, w, a, "fp32", pre, args.graph_chunk)
     err = golden_compare(s, "batch2d", end)
@@ -376,6 +381,7 @@ def batched_leg(args):
     el64, _ = run_window(s, w, a, "fp64", pre, args.graph_chunk)
     del s
     torch.cuda.empty_cache()
+    progress("batched leg: FP64 one plate at a time")
     el_b = batch_baseline(w.n_specimens, args.steps, args.graph_chunk)
     v32 = nb * args.steps / el
     return {"workload": desc, "nodes": int(sz.n), "unique_bonds": nb, "setup_s": round(setup, 2),
@@ -394,6 +400,7 @@ def cylinder_dx05_leg(args):
     at the end of its 5000-step run, with its own roofline."""
     import numpy as np
     from paper_2309_11273_amd.solver import Solver
+    progress("cylinder dx 0.5 mm leg")
     w, desc = make_workload("cylinder3d_dx05")
     t0 = time.perf_counter()
     s = Solver(w, device=0)
@@ -401,7 +408,7 @@ def cylinder_dx05_leg(args):
     sz = s.fam.sizes
     nb, nnz = int(sz.n_bonds), int(sz.nnz)
     a = argparse.Namespace(**vars(args))
-    a.workload, a.form = "cylinder3d_dx05", "mf"
+    a.workload, a.form, a.kernel = "cylinder3d_dx05", "mf", "auto"
     pre = default_preroll(a, w)
     el, end = run_window(s, w, a, "fp32", pre, args.graph_chunk)
     err = golden_compare(s, "cylinder3d_dx05", end)
@@ -586,12 +593,20 @@ def main():
         return
     preroll = 0
     err_vs_oracle = None
+    tune = None
+    block = 0
+    if args.kernel == "auto" and args.form == "mf" and not args.adr and args.extension == "linear":
+        # the library's tuner picks the kernel kind (tile, super-tile, gather
+        # at 64/128/256 threads) on this workload; the timed run uses its pick
+        tune = s.autotune(args.precision, trial_steps=10)
+        args.kernel = tune["kernel"] if tune["kernel"] != "auto" else "tiled"
+        block = int(tune["block"])
     if args.adr:
         el = time_adr(s, args.steps, args.warmup, args.graph_chunk, args.kernel, args.extension)
     else:
         preroll = default_preroll(args, w)
         el, end_step = run_window(s, w, args, args.precision, preroll, args.graph_chunk, args.extension,
-                                  args.kernel)
+                                  args.kernel, block)
         if args.extension == "linear":
             err_vs_oracle = golden_compare(s, args.workload, end_step)
     ms_per_step = 1e3 * el / args.steps
@@ -604,7 +619,7 @@ def main():
         s.adr_step(args.profile_steps, profile=True, report=False, kernel=args.kernel, extension=args.extension)
     else:
         s.step(args.profile_steps, precision=args.precision, form=args.form, profile=True, report=False,
-               kernel=args.kernel, extension=args.extension)
+               kernel=args.kernel, extension=args.extension, block=block)
     prof = s.profile_read(reset=True)
     ps = max(1, prof["steps"])
     ms1, ms2 = prof["ms_pass1"] / ps, prof["ms_pass2"] / ps
@@ -665,6 +680,13 @@ def main():
         "roofline": roofline,
         "error_vs_oracle": err_vs_oracle,
     }
+    if tune is not None:
+        out["config"]["kernel"] = args.kernel + (f" ({block} threads per block)" if args.kernel == "gather" else "")
+        names = {1: "gather", 2: "tiled", 3: "super"}
+        out["autotune"] = {"pick": tune["kernel"], "block": tune["block"],
+                           "candidates_ms_per_step": {f"{names.get(c['kernel'], c['kernel'])}"
+                                                      f"{'/' + str(c['block']) if c['kernel'] == 1 else ''}":
+                                                      round(c["ms"], 5) for c in tune["candidates"]}}
     if not args.no_fp64 and args.precision == "fp32":
         s.reset()
         el64, end64 = run_window(s, w, args, "fp64", preroll, args.graph_chunk)
@@ -712,6 +734,7 @@ def main():
     del src, dst
     torch.cuda.empty_cache()
     if not args.no_cpu:
+        progress("CPU baseline")
         mode = "adr" if args.adr else ("finite" if args.extension == "finite" else "step")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, mode)
         # the same reference on one core (a shorter sample: the rate per core)

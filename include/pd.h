@@ -303,16 +303,20 @@ typedef struct pd_problem_dev {
 /* Solver state, [device] arrays in internal row order. */
 typedef struct pd_state_dev {
     double *uv[2];      /* n_pad*4: (u_x, u_y, u_z, V) ping-pong                   */
-    double *vel;        /* n_pad*4: (v_x, v_y, v_z, 0)                              */
+    double *vel;        /* n_pad*4 allocated: per row (v_x, v_y, v_z, 0) in 3D; in 2D
+                           (v_x, v_y) in the first n_pad*2 (the per-row vectors below
+                           marked "per row, by dim" follow the same rule)           */
     double *qr;         /* n_pad*2: (theta/m, 1/m)                                  */
     uint64_t *mask;     /* n_mask bond status bits (mutable: bonds break)           */
     int32_t *ush[2];    /* n_pad*4 fixed-point displacement shadow (FP32 path)      */
     float *qr32;        /* n_pad*2 (theta/m, 1/m) in FP32 (FP32 path)               */
-    double *dsum;       /* n_pad*4 sum over intact bonds of x M V_j (FP32 path)      */
+    double *dsum;       /* n_pad*4 sum over intact bonds of x M V_j, per row, by dim
+                           (FP32 path)                                               */
     float *fe32;        /* n_pad*4 deviatoric part of the pair force of the step,
-                           carried from pass 1 to pass 2 (FP32 LDS-staged path)      */
-    double *fe64;       /* n_pad*4 the same for the FP64 LDS-staged path (NULL: the
-                           FP64 path uses the gather kernels)                        */
+                           carried from pass 1 to pass 2, per row, by dim (FP32
+                           LDS-staged path)                                          */
+    double *fe64;       /* n_pad*4 the same for the FP64 LDS-staged path, per row, by
+                           dim (NULL: the FP64 path uses the gather kernels)        */
     float *qv32;        /* n_pad*2 (theta/m, V) of the step in FP32, written by the
                            FP32 LDS-staged pass 1 for its pass 2 (NULL: the FP32
                            path uses the gather kernels)                             */

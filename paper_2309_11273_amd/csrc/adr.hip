@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_adr_sums(StepArgs a, AdrArgs r, int cur
             F[2] += fe.z * rr;
         }
         const double4 u4 = a.uv[cur][row];
-        const double4 v4 = a.vel[row];
+        const double4 v4 = ldv(a.vel, DIM, row);
         const double u[3] = {u4.x, u4.y, u4.z}, v[3] = {v4.x, v4.y, v4.z};
         const double *lam = r.lambda + 4 * row;
         const double *fp = r.f_prev + 4 * row;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_adr_update(StepArgs a, AdrArgs r, int c
     const uint32_t aux = a.aux[row];
     const double4 F = reinterpret_cast<const double4 *>(r.f_prev)[row];
     const double4 lam = reinterpret_cast<const double4 *>(r.lambda)[row];
-    double4 v = a.vel[row];
+    double4 v = ldv(a.vel, DIM, row);
     double4 u = a.uv[cur][row];
     const double Fc[3] = {F.x, F.y, F.z}, lc[3] = {lam.x, lam.y, lam.z};
     double vc[3] = {v.x, v.y, v.z};
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_adr_update(StepArgs a, AdrArgs r, int c
     u.y = u.y + dt * v.y;
     u.z = u.z + dt * v.z;
     a.uv[cur ^ 1][row] = u;
-    a.vel[row] = v;
+    stv(a.vel, DIM, row, v);
     if (!(isfinite(u.x) && isfinite(u.y) && isfinite(u.z))) atomicOr(&a.ctl->flags, PD_CTL_NONFINITE);
 }
 

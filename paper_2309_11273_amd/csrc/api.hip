@@ -92,16 +92,16 @@ pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
     a.fext = reinterpret_cast<const double4 *>(p->fext);
     a.uv[0] = reinterpret_cast<double4 *>(st->uv[0]);
     a.uv[1] = reinterpret_cast<double4 *>(st->uv[1]);
-    a.vel = reinterpret_cast<double4 *>(st->vel);
+    a.vel = st->vel;
     a.qr = reinterpret_cast<double2 *>(st->qr);
     a.mask = st->mask;
     a.ctl = reinterpret_cast<pd_ctl *>(st->ctl);
     a.ush[0] = reinterpret_cast<int4 *>(st->ush[0]);
     a.ush[1] = reinterpret_cast<int4 *>(st->ush[1]);
     a.qr32 = reinterpret_cast<float2 *>(st->qr32);
-    a.dsum = reinterpret_cast<double4 *>(st->dsum);
-    a.fe32 = reinterpret_cast<float4 *>(st->fe32);
-    a.fe64 = reinterpret_cast<double4 *>(st->fe64);
+    a.dsum = st->dsum;
+    a.fe32 = st->fe32;
+    a.fe64 = st->fe64;
     a.qv32 = reinterpret_cast<float2 *>(st->qv32);
     a.stencil_off = p->stencil_off;
     a.tile_nbr = p->tile_nbr;
@@ -290,7 +290,8 @@ pd_status pd_state_init(pd_ctx *c, const pd_problem_dev *p, const int32_t *perm,
     a.aux = aux_out;
     a.fext = reinterpret_cast<double4 *>(fext_out);
     a.uv = reinterpret_cast<double4 *>(st->uv[st->cur]);
-    a.vel = reinterpret_cast<double4 *>(st->vel);
+    a.vel = st->vel;
+    a.dim = p->dim;
     a.qr = reinterpret_cast<double2 *>(st->qr);
     a.qr32 = reinterpret_cast<float2 *>(st->qr32);
     a.ctl = reinterpret_cast<pd_ctl *>(st->ctl);
@@ -310,8 +311,8 @@ pd_status pd_state_read(pd_ctx *c, const pd_problem_dev *p, const int32_t *perm,
     if (!perm) return fail(c, PD_ERR_ARG, "perm is NULL");
     if (n < 1 || n > p->n_pad) return fail(c, PD_ERR_SIZE, "n out of range");
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, pdk::launch_state_read(perm, p->n_pad, reinterpret_cast<const double4 *>(st->uv[st->cur]),
-                                      reinterpret_cast<const double4 *>(st->vel), u_out, v_out, c->stream));
+    HIP_TRY(c, pdk::launch_state_read(perm, p->n_pad, p->dim, reinterpret_cast<const double4 *>(st->uv[st->cur]),
+                                      st->vel, u_out, v_out, c->stream));
     return PD_OK;
 }
 

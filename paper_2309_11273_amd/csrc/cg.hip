@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_nm_predict(StepArgs a, double dt, int c
     if (row == 0) a.ctl->s1 = a.ctl->s2;
     const uint32_t aux = a.aux[row];
     double4 u = a.uv[cur][row];
-    const double4 v = a.vel[row];
+    const double4 v = ldv(a.vel, a.dim, row);
     if (aux & 1u) u.x += dt * v.x;
     if (aux & 2u) u.y += dt * v.y;
     if (aux & 4u) u.z += dt * v.z;
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_nm_rhs(StepArgs a, CgArgs c, double dt,
     if ((threadIdx.x & 63) != 0) return;
     const uint32_t aux = a.aux[row];
     const double m = c.mass[row];
-    const double4 v = a.vel[row], an = c.acc[row];
+    const double4 v = ldv(a.vel, DIM, row), an = c.acc[row];
     const double k4 = 4.0 / dt;
     double4 r = make_double4(f[0] + m * (k4 * v.x + an.x), f[1] + m * (k4 * v.y + an.y),
                              f[2] + m * (k4 * v.z + an.z), 0.0);
@@ -371,12 +371,12 @@ __global__ __launch_bounds__(256) void k_nm_finish(StepArgs a, CgArgs c, double 
     u.y += du.y;
     u.z += du.z;
     a.uv[cur ^ 1][row] = u;
-    double4 v = a.vel[row];
+    double4 v = ldv(a.vel, a.dim, row);
     const double h = 0.5 * dt;
     if (!(aux & 1u)) v.x += h * (an.x + (c.shift * (du.x - dt * v.x) - an.x));
     if (!(aux & 2u)) v.y += h * (an.y + (c.shift * (du.y - dt * v.y) - an.y));
     if (!(aux & 4u)) v.z += h * (an.z + (c.shift * (du.z - dt * v.z) - an.z));
-    a.vel[row] = v;
+    stv(a.vel, a.dim, row, v);
     if (!(isfinite(u.x) && isfinite(u.y) && isfinite(u.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z)))
         atomicOr(&a.ctl->flags, PD_CTL_NONFINITE);
 }

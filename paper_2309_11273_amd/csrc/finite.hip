@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void k_fin_pass2(StepArgs a, int cur) {
         fz += fe.z * r;
     }
     const double mass = sp.rho * ui.w;
-    double4 v = a.vel[row];
+    double4 v = ldv(a.vel, DIM, row);
     const double ax = (aux & 1u) ? 0.0 : fx / mass;
     const double ay = (aux & 2u) ? 0.0 : fy / mass;
     const double az = (aux & 4u) ? 0.0 : fz / mass;
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_fin_pass2(StepArgs a, int cur) {
     u.y = u.y + sp.dt * v.y;
     u.z = u.z + sp.dt * v.z;
     a.uv[cur ^ 1][row] = u;
-    a.vel[row] = v;
+    stv(a.vel, DIM, row, v);
     if (!(isfinite(u.x) && isfinite(u.y) && isfinite(u.z))) atomicOr(&a.ctl->flags, PD_CTL_NONFINITE);
 }
 

@@ -21,7 +21,7 @@ struct StepArgs {
     const uint32_t *aux;
     const double4 *fext;
     double4 *uv[2];
-    double4 *vel;
+    double *vel;        // per row: 3D double4 (v, 0), 2D double2 (ldv/stv)
     double2 *qr;
     uint64_t *mask;
     pd_ctl *ctl;
@@ -30,9 +30,9 @@ struct StepArgs {
     // FP32 path
     int4 *ush[2];
     float2 *qr32;
-    double4 *dsum;
-    float4 *fe32;
-    double4 *fe64;
+    double *dsum;       // per row, as vel
+    float *fe32;        // per row: 3D float4, 2D float2 (ldvf/stvf)
+    double *fe64;       // per row, as vel
     float2 *qv32;
     // BSR path
     uint32_t *dirty;
@@ -68,10 +68,11 @@ struct InitArgs {
     uint32_t *aux;
     double4 *fext;
     double4 *uv;
-    double4 *vel;
+    double *vel;
     double2 *qr;
     float2 *qr32;
     pd_ctl *ctl;
+    int32_t dim;
 };
 
 struct DamageArgs {
@@ -99,7 +100,7 @@ bool tiled64_supported(const StepArgs &a);
 hipError_t launch_tpass1_f64(const StepArgs &a, int cur, bool brk, hipStream_t s);
 hipError_t launch_tpass2_f64(const StepArgs &a, int cur, bool update, hipStream_t s);
 hipError_t launch_state_init(const InitArgs &a, hipStream_t s);
-hipError_t launch_state_read(const int32_t *perm, int64_t n_pad, const double4 *uv, const double4 *vel,
+hipError_t launch_state_read(const int32_t *perm, int64_t n_pad, int dim, const double4 *uv, const double *vel,
                              double *u_out, double *v_out, hipStream_t s);
 hipError_t launch_damage(const DamageArgs &a, hipStream_t s);
 // partials (double4 each) of the fixed-order reductions for n_pad rows

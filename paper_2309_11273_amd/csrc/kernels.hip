@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_pass2_f64(StepArgs a, int cur) {
         fz += fe.z * r;
     }
     const double mass = sp.rho * ui.w;
-    double4 v = a.vel[row];
+    double4 v = ldv(a.vel, DIM, row);
     const double ax = (aux & 1u) ? 0.0 : fx / mass;
     const double ay = (aux & 2u) ? 0.0 : fy / mass;
     const double az = (aux & 4u) ? 0.0 : fz / mass;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_pass2_f64(StepArgs a, int cur) {
     u.y = u.y + sp.dt * v.y;
     u.z = u.z + sp.dt * v.z;
     a.uv[cur ^ 1][row] = u;
-    a.vel[row] = v;
+    stv(a.vel, DIM, row, v);
     const bool bad = !(isfinite(u.x) && isfinite(u.y) && isfinite(u.z));
     if (__ballot(bad) && lane == 0) atomicOr(&a.ctl->flags, PD_CTL_NONFINITE);
 }
@@ -238,12 +238,12 @@ __global__ void k_state_init(InitArgs a) {
     a.fext[r] = make_double4(f[0], f[1], f[2], 0.0);
     const double V = a.vol[r];
     a.uv[r] = make_double4(u[0], u[1], u[2], V);
-    a.vel[r] = make_double4(v[0], v[1], v[2], 0.0);
+    stv(a.vel, a.dim, r, make_double4(v[0], v[1], v[2], 0.0));
     a.qr[r] = make_double2(0.0, a.inv_m[r]);
     if (a.qr32) a.qr32[r] = make_float2(0.0f, (float)a.inv_m[r]);
 }
 
-__global__ void k_state_read(const int32_t *perm, int64_t n_pad, const double4 *uv, const double4 *vel,
+__global__ void k_state_read(const int32_t *perm, int64_t n_pad, int dim, const double4 *uv, const double *vel,
                              double *u_out, double *v_out) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_pad) return;
@@ -256,7 +256,7 @@ __global__ void k_state_read(const int32_t *perm, int64_t n_pad, const double4 *
         u_out[3 * (int64_t)p + 2] = u.z;
     }
     if (v_out) {
-        const double4 v = vel[r];
+        const double4 v = ldv(vel, dim, r);
         v_out[3 * (int64_t)p] = v.x;
         v_out[3 * (int64_t)p + 1] = v.y;
         v_out[3 * (int64_t)p + 2] = v.z;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void k_energy_rows(StepArgs a, int cur, double
             const double r = a.inv_m[row];
             const double th = sp.A * r * at;
             const double W = sp.kp / (2.0 * sp.A) * th * th + 0.5 * sp.G * r * ae;
-            const double4 vv = a.vel[row];
+            const double4 vv = ldv(a.vel, DIM, row);
             v[0] = 0.5 * sp.rho * ui.w * (vv.x * vv.x + vv.y * vv.y + vv.z * vv.z);
             v[1] = ui.w * W;
         }
@@ -479,10 +479,10 @@ hipError_t launch_state_init(const InitArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_state_read(const int32_t *perm, int64_t n_pad, const double4 *uv, const double4 *vel,
+hipError_t launch_state_read(const int32_t *perm, int64_t n_pad, int dim, const double4 *uv, const double *vel,
                              double *u_out, double *v_out, hipStream_t s) {
     const int64_t nb = (n_pad + 255) / 256;
-    hipLaunchKernelGGL(k_state_read, dim3((unsigned)nb), dim3(256), 0, s, perm, n_pad, uv, vel, u_out, v_out);
+    hipLaunchKernelGGL(k_state_read, dim3((unsigned)nb), dim3(256), 0, s, perm, n_pad, dim, uv, vel, u_out, v_out);
     return hipGetLastError();
 }
 

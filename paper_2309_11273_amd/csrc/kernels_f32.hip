@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_dsum(StepArgs a, int cur) {
         d1 += xv * sd.y;
         if (DIM == 3) d2 += xv * sd.z;
     }
-    a.dsum[row] = make_double4(d0, d1, d2, 0.0);
+    stv(a.dsum, DIM, row, make_double4(d0, d1, d2, 0.0));
 }
 
 // ---------------------------------------------------------------------------
@@ -329,11 +329,11 @@ __global__ __launch_bounds__(256) void k_pass1_f32(StepArgs a, int cur) {
     if (a.theta_out) a.theta_out[row] = (double)sp.A * (double)qri.y * acc64;
     if (BREAK) {
         if (dd0 != 0.0 || dd1 != 0.0 || dd2 != 0.0) {
-            double4 D = a.dsum[row];
+            double4 D = ldv(a.dsum, DIM, row);
             D.x -= dd0;
             D.y -= dd1;
             D.z -= dd2;
-            a.dsum[row] = D;
+            stv(a.dsum, DIM, row, D);
         }
         if (lane == 0 && nbroken) atomicAdd(&ctl->broken, (unsigned long long)nbroken);
         unsigned long long rc = nrecheck, fb = nfall;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(256) void k_pass2_f32(StepArgs a, int cur) {
       }
     }
     const double4 ui = uv[row];
-    const double4 D = a.dsum[row];
+    const double4 D = ldv(a.dsum, DIM, row);
     // the direction was accumulated as M Q: divide by Q (a power of two);
     // add the row-constant dilatation term 2 (K - G/3) q_i D_i
     const double invQ = 1.0 / Q;
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void k_pass2_f32(StepArgs a, int cur) {
         Fz += fe.z * r;
     }
     const double mass = sp.rho * ui.w;
-    double4 v = a.vel[row];
+    double4 v = ldv(a.vel, DIM, row);
     const double ax = (aux & 1u) ? 0.0 : Fx / mass;
     const double ay = (aux & 2u) ? 0.0 : Fy / mass;
     const double az = (aux & 4u) ? 0.0 : Fz / mass;
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(256) void k_pass2_f32(StepArgs a, int cur) {
     u.y = u.y + sp.dt * v.y;
     u.z = u.z + sp.dt * v.z;
     a.uv[cur ^ 1][row] = u;
-    a.vel[row] = v;
+    stv(a.vel, DIM, row, v);
     const double invQn = 1.0 / Qn;
     bool bad = false;
     int4 s;

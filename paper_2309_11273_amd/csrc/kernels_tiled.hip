@@ -471,20 +471,20 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     }
     if (!valid) return;
     if (BREAK && (d[0] != 0.0 || d[1] != 0.0 || d[2] != 0.0)) {
-        double4 D = a.dsum[row];
+        double4 D = ldv(a.dsum, DIM, row);
         D.x -= d[0];
         D.y -= d[1];
         D.z -= d[2];
-        a.dsum[row] = D;
+        stv(a.dsum, DIM, row, D);
     }
     // theta_i / m_i = A r_i^2 sum_j x V_j e_j, the sum carried in units of Q;
     // pass 2 stages it with V_i
     const double accQ = (double)tot[0] * Q;
     const float qi = (float)((double)sp.A * (double)ri * (double)ri * accQ);
-    a.qr32[row].x = qi;
+    // (the gather kernels' qr32.x is not needed: pass 2 here reads qv32)
     a.qv32[row] = make_float2(qi, __int_as_float(own.w));
     if (a.theta_out) a.theta_out[row] = (double)sp.A * (double)ri * accQ;
-    a.fe32[row] = make_float4(tot[1], tot[2], tot[3], 0.0f);
+    stvf(a.fe32, DIM, row, make_float4(tot[1], tot[2], tot[3], 0.0f));
 }
 
 // ---------------------------------------------------------------------------
@@ -558,9 +558,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     float4 fe = make_float4(0.f, 0.f, 0.f, 0.f);
     if (kq == 0 && valid) {
         ui = a.uv[cur][row];
-        D = a.dsum[row];
-        fe = a.fe32[row];
-        if (UPDATE) v = a.vel[row];
+        D = ldv(a.dsum, DIM, row);
+        fe = ldvf(a.fe32, DIM, row);
+        if (UPDATE) v = ldv(a.vel, DIM, row);
     }
     tile_sync<TPW>();
     {
@@ -690,7 +690,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     u.y = u.y + sp.dt * v.y;
     u.z = u.z + sp.dt * v.z;
     a.uv[cur ^ 1][row] = u;
-    a.vel[row] = v;
+    stv(a.vel, DIM, row, v);
     const double invQn = inv_pow2(Qn);
     bool bad = false;
     int4 s;
@@ -784,7 +784,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tdsum(StepArgs a, int cur, 
         s1 += red[(PD_TILE_WAVES + q) * 64 + lane];
         s2 += red[(2 * PD_TILE_WAVES + q) * 64 + lane];
     }
-    a.dsum[tile * 64 + lane] = make_double4(s0, s1, s2, 0.0);
+    stv(a.dsum, DIM, tile * 64 + lane, make_double4(s0, s1, s2, 0.0));
 }
 
 static size_t tdsum_lds(const StepArgs &a) {

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
     // theta_i = A / m_i * acc; store theta_i / m_i
     a.qr[row].x = sp.A * ri * tot[0] * ri;
     if (a.theta_out) a.theta_out[row] = sp.A * ri * tot[0];
-    a.fe64[row] = make_double4(tot[1], tot[2], tot[3], 0.0);
+    stv(a.fe64, DIM, row, make_double4(tot[1], tot[2], tot[3], 0.0));
 }
 
 // ---------------------------------------------------------------------------
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
     }
     if (!valid) return;
     const double4 ui = uv[row];
-    const double4 fe = a.fe64[row];
+    const double4 fe = ldv(a.fe64, DIM, row);
     double Fx = (sx + fe.x) * ui.w;
     double Fy = (sy + fe.y) * ui.w;
     double Fz = (sz + fe.z) * ui.w;
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
         Fz += fx4.z * r;
     }
     const double mass = sp.rho * ui.w;
-    double4 v = a.vel[row];
+    double4 v = ldv(a.vel, DIM, row);
     const double ax = (aux & 1u) ? 0.0 : Fx / mass;
     const double ay = (aux & 2u) ? 0.0 : Fy / mass;
     const double az = (aux & 4u) ? 0.0 : Fz / mass;
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
     u.y = u.y + sp.dt * v.y;
     u.z = u.z + sp.dt * v.z;
     a.uv[cur ^ 1][row] = u;
-    a.vel[row] = v;
+    stv(a.vel, DIM, row, v);
     const bool bad = !(isfinite(u.x) && isfinite(u.y) && isfinite(u.z));
     if (__ballot(bad) && lane == 0) atomicOr(&ctl->flags, PD_CTL_NONFINITE);
 }

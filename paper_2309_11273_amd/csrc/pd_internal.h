@@ -51,6 +51,31 @@ static_assert(sizeof(pd_ctl) % 8 == 0, "control block is cleared in 8-byte words
 #define PD_HD
 #endif
 
+#ifdef __HIPCC__
+#include <hip/hip_runtime.h>
+// Per-row vectors kept with the problem's dimension (velocity, the row
+// constants D_i and the carried force parts): a 3D row is four entries
+// (x, y, z, 0), a 2D row two (x, y), so 2D moves half the bytes.
+__device__ __forceinline__ double4 ldv(const double *p, int dim, int64_t r) {
+    if (dim == 3) return reinterpret_cast<const double4 *>(p)[r];
+    const double2 t = reinterpret_cast<const double2 *>(p)[r];
+    return make_double4(t.x, t.y, 0.0, 0.0);
+}
+__device__ __forceinline__ void stv(double *p, int dim, int64_t r, double4 v) {
+    if (dim == 3) reinterpret_cast<double4 *>(p)[r] = v;
+    else reinterpret_cast<double2 *>(p)[r] = make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ldvf(const float *p, int dim, int64_t r) {
+    if (dim == 3) return reinterpret_cast<const float4 *>(p)[r];
+    const float2 t = reinterpret_cast<const float2 *>(p)[r];
+    return make_float4(t.x, t.y, 0.0f, 0.0f);
+}
+__device__ __forceinline__ void stvf(float *p, int dim, int64_t r, float4 v) {
+    if (dim == 3) reinterpret_cast<float4 *>(p)[r] = v;
+    else reinterpret_cast<float2 *>(p)[r] = make_float2(v.x, v.y);
+}
+#endif
+
 // Bond word layout inside a 64-row slice whose words start at 'base' (a
 // multiple of 256): words come in groups of four per lane, so that lane
 // 'lane' reads words 4g..4g+3 of its row with one 16-byte load and the 64
