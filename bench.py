@@ -51,35 +51,39 @@ def make_workload(name):
     return W.workload(gen, **kw), desc
 
 
-def algorithmic_bytes(kernel: str, precision: str, nnz: int, n: int, n_loaded: int, tiled: bool) -> int:
+def algorithmic_bytes(kernel: str, precision: str, nnz: int, n: int, n_loaded: int, tiled: bool,
+                      dim: int = 3) -> int:
     """Bytes one launch must move between HBM and the chip (each array read
     or written once; neighbour data is served by the caches or LDS).
 
     Per directed bond: 1 bit of bond status (1/8 B), plus the 4 B bond word
     for the gather kernels; the LDS-staged tile kernels read no bond word
-    (the stencil position of a bond gives its neighbour).
+    (the stencil position of a bond gives its neighbour).  Per-row vectors
+    (velocity v, the FP32 row constant D, the carried force parts) are stored
+    with the dimension: w = 4 entries in 3D, 2 in 2D.
     Per node, gather kernels (pair force summed in pass 2):
       FP64 pass 1: u,V 32; aux 4; (theta/m, 1/m) 16 read + 8 write
-      FP64 pass 2: u,V 32; (theta/m, 1/m) 16; aux 4; v 32 + 32; u,V 32 write
+      FP64 pass 2: u,V 32; (theta/m, 1/m) 16; aux 4; v 8w + 8w; u,V 32 write
       FP32 pass 1: shadow 16; aux 4; float (theta/m, 1/m) 8 + 4
-      FP32 pass 2: shadow 16; float (theta/m, 1/m) 8; aux 4; D 32; u,V 32;
-                   v 32 + 32; u,V 32 write; next shadow 16 write
+      FP32 pass 2: shadow 16; float (theta/m, 1/m) 8; aux 4; D 8w; u,V 32;
+                   v 8w + 8w; u,V 32 write; next shadow 16 write
     Per node, tile kernels (deviatoric part of the pair force in pass 1):
-      FP64 pass 1: u,V 32; 1/m 8; aux 4; theta/m 8 write; force part 32 write
-      FP64 pass 2: theta/m 8; u,V 32; aux 4; force part 32; v 32 + 32;
+      FP64 pass 1: u,V 32; 1/m 8; aux 4; theta/m 8 write; force part 8w write
+      FP64 pass 2: theta/m 8; u,V 32; aux 4; force part 8w; v 8w + 8w;
                    u,V 32 write
-      FP32 pass 1: shadow 16; 1/m 4; aux 4; theta/m 4 write; (theta/m, V) 8
-                   write; force part 16 write
-      FP32 pass 2: (theta/m, V) 8; aux 4; D 32; force part 16; u,V 32;
-                   v 32 + 32; u,V 32 write; next shadow 16 write
+      FP32 pass 1: shadow 16; 1/m 4; aux 4; (theta/m, V) 8 write; force part
+                   4w write
+      FP32 pass 2: (theta/m, V) 8; aux 4; D 8w; force part 4w; u,V 32;
+                   v 8w + 8w; u,V 32 write; next shadow 16 write
     Loaded nodes read their external force (32 B) in pass 2."""
+    w = 4 if dim == 3 else 2
     bond = nnz * (0.125 if tiled else 4.125)
     if tiled:
-        node = {("fp64", "pass1"): 84, ("fp64", "pass2"): 172,
-                ("fp32", "pass1"): 52, ("fp32", "pass2"): 204}[(precision, kernel)]
+        node = {("fp64", "pass1"): 52 + 8 * w, ("fp64", "pass2"): 76 + 24 * w,
+                ("fp32", "pass1"): 32 + 4 * w, ("fp32", "pass2"): 92 + 28 * w}[(precision, kernel)]
     else:
-        node = {("fp64", "pass1"): 60, ("fp64", "pass2"): 148,
-                ("fp32", "pass1"): 32, ("fp32", "pass2"): 204}[(precision, kernel)]
+        node = {("fp64", "pass1"): 60, ("fp64", "pass2"): 84 + 16 * w,
+                ("fp32", "pass1"): 32, ("fp32", "pass2"): 108 + 24 * w}[(precision, kernel)]
     extra = 32 * n_loaded if kernel == "pass2" else 0
     return int(bond + node * n + extra)
 
@@ -127,7 +131,7 @@ def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
         kname = f"k_tpass{dom[-1]}_f64 (finite model)" if tiled else f"k_fin_{dom}"
     ms_dom = ms1 if dom == "pass1" else ms2
     sec = ms_dom * 1e-3
-    byt = algorithmic_bytes(dom, args.precision, nnz, n, n_loaded, tiled)
+    byt = algorithmic_bytes(dom, args.precision, nnz, n, n_loaded, tiled, int(s.fam.sizes.dim))
     fl = algorithmic_flops(dom, nnz, tiled)
     if args.extension == "finite" and tiled:
         # per directed bond, tile kernels: deformed bond 6, |Y|^2 5, square
