@@ -223,29 +223,30 @@ typedef struct pd_family_host {
 pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, int32_t ncuts,
                           pd_family_sizes *sizes, pd_family_host *bufs);
 
-/* Super-tiles of a 3D family of 4x4x4 tiles with stencil reach <= 3: the
- * tiles grouped 2 x 2 x 1 (same specimen, same tile layer), so that one
- * workgroup stages one halo box for four tiles (8 x 8 x 4 lattice points plus
- * the reach on every side) and each of its four waves sweeps the whole
- * stencil for its own tile.  Two-phase like pd_build_family (with
+/* Super-tiles of a family of 4x4x4 tiles (3D) or 8x8 tiles (2D) with
+ * stencil reach <= 3: the tiles grouped 2 x 2 (x 1) (same specimen, same
+ * tile layer), so that one workgroup stages one halo box for four tiles
+ * (8 x 8 x 4 or 16 x 16 lattice points plus the reach on every side) and
+ * each of its four waves sweeps the whole stencil for its own tile.  Two-phase like pd_build_family (with
  * st_tiles == NULL only *out is set).  Outputs [host]:
  *   st_tiles [4 n_st]   tile of quadrant q (x offset 4 (q & 1), y offset
  *                       4 (q >> 1)) of super-tile s at 4 s + q, -1 if none;
  *                       super-tiles in (specimen, z, y, x) order
  *   st_nbr  [48 n_st]   tile at tile offset (dx, dy, dz) in {-1..2}^2 x {-1..1}
  *                       from the super-tile's first tile, index
- *                       (dx + 1) + 4 (dy + 1) + 16 (dz + 1), -1 if none
+ *                       (dx + 1) + 4 (dy + 1) + 16 (dz + 1), -1 if none (2D:
+ *                       only dz = 0)
  *   st_pos  [n_pos]     the box points some stencil entry of some tile point
  *                       reaches, x fastest: (slot << 12) | (64 d + l), d the
  *                       st_nbr index of the point's tile and l its place in it,
- *                       slot = x + 16 y + 228 z in the box (pitches chosen so
- *                       that the 64 lanes of a tile reading the same offset hit
- *                       64 distinct LDS banks)
+ *                       slot = x + 16 y + 228 z in the 3D box, x + 40 y in the
+ *                       2D box (pitches chosen so that the lanes of a tile
+ *                       reading the same offset hit distinct LDS banks)
  *   st_ktab [128*8]     per stencil entry: M1/x, M2/x, x^2, x M1, x M2 as float,
  *                       the int32 offset of the neighbour in that box, M3/x,
  *                       x M3 as float (zero beyond n_stencil)
- * Errors: PD_ERR_ARG (NULL arguments), PD_ERR_UNSUPPORTED (not 3D, tiles
- * other than 4x4x4, or reach above 3). */
+ * Errors: PD_ERR_ARG (NULL arguments), PD_ERR_UNSUPPORTED (tiles other than
+ * 4x4x4 in 3D or 8x8 in 2D, or reach above 3). */
 typedef struct pd_st_sizes {
     int64_t n_st;            /* super-tiles                                        */
     int32_t n_pos;           /* reached box points                                 */
@@ -388,10 +389,11 @@ typedef struct pd_step_opts {
     int32_t kernel;      /* matrix-free kernels: 0 = LDS-staged tile kernels when the
                             family allows them (tile edges >= stencil reach; FP64 also
                             needs st->fe64), else gather kernels; 1 = gather kernels;
-                            2 = tile kernels, one tile per workgroup (error if not
-                            possible); 3 = FP32 super-tile kernels (four tiles per
-                            workgroup, pd_build_supertiles; error if not possible;
-                            the FP64 path then uses the tile kernels)               */
+                            2 = tile kernels, one tile per workgroup (3D) or per
+                            wave (2D) (error if not possible); 3 = FP32 super-tile
+                            kernels (four tiles per workgroup sharing one halo box,
+                            pd_build_supertiles; error if not possible; the FP64
+                            path then uses the tile kernels)                        */
     int32_t extension;   /* 0: linearized e = M.(u_j - u_i) along M (Eqs. 2.4, 2.7);
                             1: finite e = |x M + u_j - u_i| - x with the pair force
                             along the deformed bond (Eqs. 1.10, 1.13): PD_FP64,

@@ -465,7 +465,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
         pd_state_dev tmp = *st;
         if (!pdk::supertiles_supported(make_args(p, &tmp)))
             return fail(c, PD_ERR_UNSUPPORTED,
-                        "super-tile kernels need 3D 4x4x4 tiles, reach <= 3 and the tables of pd_build_supertiles");
+                        "super-tile kernels need 4x4x4 (3D) or 8x8 (2D) tiles, reach <= 3 and the tables of pd_build_supertiles");
     }
     if ((o.kernel == 2 || o.kernel == 3) && o.form == PD_MATRIX_FREE) {
         pd_state_dev tmp = *st;

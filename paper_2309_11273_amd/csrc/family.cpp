@@ -649,19 +649,25 @@ extern "C" pd_status pd_fac_pattern(const pd_family_sizes *sz, const pd_family_h
     return PD_OK;
 }
 
-// Super-tiles: 2 x 2 x 1 groups of 4x4x4 tiles sharing one halo box.  The
+// Super-tiles: 2 x 2 (x 1) groups of tiles sharing one halo box -- 4x4x4
+// tiles in 3D (box pitches 16 and 228), 8x8 tiles in 2D (x pitch 40).  The
 // tile coordinates follow from the tile origins: per specimen the smallest
 // origin is the tile grid's origin.
 extern "C" pd_status pd_build_supertiles(const pd_family_sizes *sz, const pd_family_host *fam, pd_st_sizes *out,
                                          int32_t *st_tiles, int32_t *st_nbr, int32_t *st_pos, uint32_t *st_ktab) {
     if (!sz || !fam || !out || !fam->tile_org || !fam->stencil || !fam->stencil_off) return PD_ERR_ARG;
-    if (sz->dim != 3 || sz->tile[0] != 4 || sz->tile[1] != 4 || sz->tile[2] != 4 || sz->reach < 1 ||
-        sz->reach > 3 || sz->n_stencil < 1 || sz->n_stencil > 124)
+    const int dim = sz->dim;
+    const bool ok3 = dim == 3 && sz->tile[0] == 4 && sz->tile[1] == 4 && sz->tile[2] == 4;
+    const bool ok2 = dim == 2 && sz->tile[0] == 8 && sz->tile[1] == 8 && sz->tile[2] == 1;
+    if (!(ok3 || ok2) || sz->reach < 1 || sz->reach > 3 || sz->n_stencil < 1 || sz->n_stencil > 124)
         return PD_ERR_UNSUPPORTED;
     const int64_t nt = sz->n_tiles;
     const int R = sz->reach;
     const int ns = sz->n_stencil;
-    const int P0 = 16, P1 = 228;  // box pitches; x, y extents 8 + 2R <= 14
+    const int T = sz->tile[0];              // tile edge in x and y (4 in 3D, 8 in 2D)
+    const int TZ = dim == 3 ? 4 : 1;
+    const int P0 = dim == 3 ? 16 : 40;     // box pitches (x extent 2T + 2R <= 22)
+    const int P1 = dim == 3 ? 228 : 0;
     // tile coordinates per specimen
     std::unordered_map<int32_t, std::array<int32_t, 3>> lo;
     for (int64_t t = 0; t < nt; t++) {
@@ -682,25 +688,25 @@ extern "C" pd_status pd_build_supertiles(const pd_family_sizes *sz, const pd_fam
     for (int64_t t = 0; t < nt; t++) {
         const int32_t sp = fam->tile_org[4 * t + 3];
         const auto &l = lo[sp];
-        int32_t tc[3];
-        for (int c = 0; c < 3; c++) tc[c] = (fam->tile_org[4 * t + c] - l[c]) / 4;
+        const int32_t tc[3] = {(fam->tile_org[4 * t] - l[0]) / T, (fam->tile_org[4 * t + 1] - l[1]) / T,
+                               (fam->tile_org[4 * t + 2] - l[2]) / TZ};
         tile_at[tkey(sp, tc[0], tc[1], tc[2])] = (int32_t)t;
         skeys.push_back(((uint64_t)sp << 48) | ((uint64_t)tc[2] << 32) | ((uint64_t)(tc[1] >> 1) << 16) |
                         (uint64_t)(tc[0] >> 1));
     }
     std::sort(skeys.begin(), skeys.end());
     skeys.erase(std::unique(skeys.begin(), skeys.end()), skeys.end());
-    // reached points of the box (8 + 2R) x (8 + 2R) x (4 + 2R)
-    const int e0 = 8 + 2 * R, e1 = 8 + 2 * R, e2 = 4 + 2 * R;
+    // reached points of the box (2T + 2R) x (2T + 2R) x (TZ + 2R in 3D)
+    const int e0 = 2 * T + 2 * R, e1 = 2 * T + 2 * R, e2 = dim == 3 ? TZ + 2 * R : 1;
     std::vector<uint8_t> reached((size_t)e0 * e1 * e2, 0);
     for (int q = 0; q < 4; q++)
         for (int l = 0; l < 64; l++)
             for (int s = -1; s < ns; s++) {
                 int32_t o[3] = {0, 0, 0};
                 if (s >= 0)
-                    for (int c = 0; c < 3; c++) o[c] = fam->stencil_off[3 * s + c];
-                const int bx = 4 * (q & 1) + (l & 3) + o[0] + R, by = 4 * (q >> 1) + ((l >> 2) & 3) + o[1] + R,
-                          bz = (l >> 4) + o[2] + R;
+                    for (int c = 0; c < dim; c++) o[c] = fam->stencil_off[3 * s + c];
+                const int bx = T * (q & 1) + (l % T) + o[0] + R, by = T * (q >> 1) + (l / T) % T + o[1] + R,
+                          bz = dim == 3 ? l / (T * T) + o[2] + R : 0;
                 if (bx < 0 || by < 0 || bz < 0 || bx >= e0 || by >= e1 || bz >= e2) return PD_ERR_UNSUPPORTED;
                 reached[bx + e0 * (by + e1 * bz)] = 1;
             }
@@ -723,21 +729,23 @@ extern "C" pd_status pd_build_supertiles(const pd_family_sizes *sz, const pd_fam
         for (int dz = 0; dz < 3; dz++)
             for (int dy = 0; dy < 4; dy++)
                 for (int dx = 0; dx < 4; dx++)
-                    st_nbr[48 * s + dx + 4 * dy + 16 * dz] = find(2 * sx - 1 + dx, 2 * sy - 1 + dy, z - 1 + dz);
+                    st_nbr[48 * s + dx + 4 * dy + 16 * dz] =
+                        (dim == 2 && dz != 1) ? -1 : find(2 * sx - 1 + dx, 2 * sy - 1 + dy, z - 1 + dz);
     }
     int32_t np = 0;
     for (int bz = 0; bz < e2; bz++)
         for (int by = 0; by < e1; by++)
             for (int bx = 0; bx < e0; bx++) {
                 if (!reached[bx + e0 * (by + e1 * bz)]) continue;
-                const int p[3] = {bx - R, by - R, bz - R};
+                const int p[3] = {bx - R, by - R, dim == 3 ? bz - R : 0};
+                const int Tc[3] = {T, T, TZ};
                 int d[3], l[3];
                 for (int c = 0; c < 3; c++) {
-                    d[c] = (p[c] + 4) / 4;  // tile offset + 1 (p >= -3)
-                    l[c] = p[c] - 4 * (d[c] - 1);
+                    d[c] = (p[c] + Tc[c]) / Tc[c];  // tile offset + 1 (p >= -R >= -T)
+                    l[c] = p[c] - Tc[c] * (d[c] - 1);
                 }
                 const int32_t slot = bx + P0 * by + P1 * bz;
-                st_pos[np++] = (slot << 12) | (64 * (d[0] + 4 * d[1] + 16 * d[2]) + l[0] + 4 * (l[1] + 4 * l[2]));
+                st_pos[np++] = (slot << 12) | (64 * (d[0] + 4 * d[1] + 16 * d[2]) + l[0] + T * (l[1] + T * l[2]));
             }
     auto fbits = [](double v) {
         const float f = (float)v;
@@ -755,7 +763,7 @@ extern "C" pd_status pd_build_supertiles(const pd_family_sizes *sz, const pd_fam
         k1[2] = fbits(S[3] * S[3]);
         k1[3] = fbits(S[3] * S[0]);
         k1[4] = fbits(S[3] * S[1]);
-        k1[5] = (uint32_t)(o[0] + P0 * o[1] + P1 * o[2]);
+        k1[5] = (uint32_t)(o[0] + P0 * o[1] + P1 * (dim == 3 ? o[2] : 0));
         k1[6] = fbits(S[2] / S[3]);
         k1[7] = fbits(S[3] * S[2]);
     }

@@ -61,12 +61,13 @@ namespace pdk {
 // from one address, which keeps the box of a one-wave tile small.
 template <int DIM, int TPW>
 struct Lay1 {
-    // super-tile box: 16 x 14 x 10 slots at pitches 16 and 228 (2280 slots)
-    static constexpr int S = TPW == 0 ? 2304 : (DIM == 3 ? 1472 : (TPW == 4 ? 336 : 1024));
+    // super-tile box: 3D 16 x 14 x 10 slots at pitches 16 and 228 (2280
+    // slots), 2D 40 x 22 (880)
+    static constexpr int S = TPW == 0 ? (DIM == 3 ? 2304 : 896) : (DIM == 3 ? 1472 : (TPW == 4 ? 336 : 1024));
     // box points staged per thread: 3D boxes of up to 1024 points (R <= 3),
-    // super-tile boxes up to 2048, 2D up to 256 per wave (TPW = 4) or 512
-    // per workgroup
-    static constexpr int MP = TPW == 0 ? 8 : (DIM == 3 ? 4 : (TPW == 4 ? 4 : 2));
+    // 3D super-tile boxes up to 2048, 2D up to 256 per wave (TPW = 4) or 512
+    // per workgroup (one tile per workgroup or a super-tile)
+    static constexpr int MP = TPW == 0 ? (DIM == 3 ? 8 : 2) : (DIM == 3 ? 4 : (TPW == 4 ? 4 : 2));
     static constexpr int BOX = DIM == 3 ? 5 * S * 4 : 2 * S * 8;
     static constexpr int SUMS = TPW == 1 ? PD_TILE_WAVES * 64 * (4 * 4 + 3 * 8) : 0;
     static constexpr int AREA = BOX > SUMS ? BOX : SUMS;
@@ -74,7 +75,7 @@ struct Lay1 {
     // super-tile, the shared reference point
     static constexpr int BYTES = AREA + (TPW == 0 ? 64 : 32) * 4;
     static_assert(DIM == 2 || (S % 64 == 0 && 4 * S * 4 / 256 <= 255), "array offsets fit the st64 encoding");
-    static_assert(TPW != 0 || (DIM == 3 && 228 * 10 <= S), "super-tile box fits the stride");
+    static_assert(TPW != 0 || (DIM == 3 ? 228 * 10 <= S : 40 * 22 <= S), "super-tile box fits the stride");
 };
 
 // access to the staged pass-1 box of Lay1
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         ctl->qs[cur ^ 1] = shadow_scale_t(ctl->umax_bits[cur]);
         ctl->umax_bits[cur ^ 1] = 0u;
     }
-    const int my = TPW == 0 ? own_slot_st(a.reach, sub, lane) : own_slot1<DIM>(a.tile, a.reach, B1, lane);
+    const int my = TPW == 0 ? own_slot_st<DIM>(a.reach, sub, lane) : own_slot1<DIM>(a.tile, a.reach, B1, lane);
     float aix, aiy, aiz;
     box.pos(my, aix, aiy, aiz);
     const float big_i = big_abs(aix) + big_abs(aiy) + big_abs(aiz);
@@ -589,7 +590,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     }
     tile_sync<TPW>();
     if (TPW == 0 && !valid) return;  // no later workgroup barrier in this mode
-    const int my = TPW == 0 ? own_slot_st(a.reach, sub, lane) : own_slot1<DIM>(a.tile, a.reach, B1, lane);
+    const int my = TPW == 0 ? own_slot_st<DIM>(a.reach, sub, lane) : own_slot1<DIM>(a.tile, a.reach, B1, lane);
     const float qi = DIM == 3 ? hb[my] : reinterpret_cast<const float2 *>(hb)[my].x;
     float fx = 0.f, fy = 0.f, fz = 0.f;
     {
@@ -847,29 +848,45 @@ bool supertiles_supported(const StepArgs &a) {
     if (!tiled_supported(a)) return false;  // the tile path's tables and limits
     if (!a.st_tiles || !a.st_nbr || !a.st_pos || !a.st_ktab || a.n_st < 1 || a.n_st >= (int64_t(1) << 31))
         return false;
-    if (a.dim != 3 || a.tile[0] != 4 || a.tile[1] != 4 || a.tile[2] != 4 || a.reach < 1 || a.reach > 3) return false;
-    if (a.st_n_pos < 1 || a.st_n_pos > Grp<3, 0>::CAP || a.st_n_pos > (8 + 2 * a.reach) * (8 + 2 * a.reach) * (4 + 2 * a.reach))
-        return false;
-    return Lay1<3, 0>::BYTES <= 64 * 1024 && Lay2<3, 0>::BYTES <= 64 * 1024;
+    if (a.reach < 1 || a.reach > 3) return false;
+    if (a.dim == 3) {
+        if (a.tile[0] != 4 || a.tile[1] != 4 || a.tile[2] != 4) return false;
+        if (a.st_n_pos < 1 || a.st_n_pos > Grp<3, 0>::CAP ||
+            a.st_n_pos > (8 + 2 * a.reach) * (8 + 2 * a.reach) * (4 + 2 * a.reach))
+            return false;
+        return Lay1<3, 0>::BYTES <= 64 * 1024 && Lay2<3, 0>::BYTES <= 64 * 1024;
+    }
+    if (a.tile[0] != 8 || a.tile[1] != 8 || a.tile[2] != 1) return false;
+    return a.st_n_pos >= 1 && a.st_n_pos <= Grp<2, 0>::CAP && a.st_n_pos <= (16 + 2 * a.reach) * (16 + 2 * a.reach);
 }
 
-hipError_t launch_spass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s) {
+template <int DIM>
+static hipError_t spass1(const StepArgs &a, int cur, bool brk, hipStream_t s) {
     const dim3 g((unsigned)a.n_st), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     const KEnt1 *kn = reinterpret_cast<const KEnt1 *>(a.st_ktab);
-    constexpr size_t lds = Lay1<3, 0>::BYTES;
-    if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true, 0>), g, b, lds, s, a, cur, kt, kn);
-    else hipLaunchKernelGGL((k_tpass1_f32<3, false, 0>), g, b, lds, s, a, cur, kt, kn);
+    constexpr size_t lds = Lay1<DIM, 0>::BYTES;
+    if (brk) hipLaunchKernelGGL((k_tpass1_f32<DIM, true, 0>), g, b, lds, s, a, cur, kt, kn);
+    else hipLaunchKernelGGL((k_tpass1_f32<DIM, false, 0>), g, b, lds, s, a, cur, kt, kn);
     return hipGetLastError();
 }
 
-hipError_t launch_spass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s) {
+template <int DIM>
+static hipError_t spass2(const StepArgs &a, int cur, bool update, hipStream_t s) {
     const dim3 g((unsigned)a.n_st), b(PD_TILE_THREADS);
     const KEnt1 *kn = reinterpret_cast<const KEnt1 *>(a.st_ktab);
-    constexpr size_t lds = Lay2<3, 0>::BYTES;
-    if (update) hipLaunchKernelGGL((k_tpass2_f32<3, true, 0>), g, b, lds, s, a, cur, kn);
-    else hipLaunchKernelGGL((k_tpass2_f32<3, false, 0>), g, b, lds, s, a, cur, kn);
+    constexpr size_t lds = Lay2<DIM, 0>::BYTES;
+    if (update) hipLaunchKernelGGL((k_tpass2_f32<DIM, true, 0>), g, b, lds, s, a, cur, kn);
+    else hipLaunchKernelGGL((k_tpass2_f32<DIM, false, 0>), g, b, lds, s, a, cur, kn);
     return hipGetLastError();
+}
+
+hipError_t launch_spass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s) {
+    return a.dim == 3 ? spass1<3>(a, cur, brk, s) : spass1<2>(a, cur, brk, s);
+}
+
+hipError_t launch_spass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s) {
+    return a.dim == 3 ? spass2<3>(a, cur, update, s) : spass2<2>(a, cur, update, s);
 }
 
 hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s) {

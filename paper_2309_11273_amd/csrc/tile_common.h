@@ -193,16 +193,16 @@ struct StageCap {
 //            their partial sums in LDS (3D: a long stencil, a large halo box);
 //   TPW = 4: every wave takes a whole tile of its own (2D: a short stencil,
 //            whose quarters would leave each wave too little work per box);
-//   TPW = 0: a super-tile, four 4x4x4 tiles side by side (2 x 2 x 1) that
-//            share one halo box staged by the whole workgroup; every wave
-//            sweeps the whole stencil for its own tile (3D).
+//   TPW = 0: a super-tile, four tiles side by side (2 x 2 (x 1); 4x4x4 in
+//            3D, 8x8 in 2D) that share one halo box staged by the whole
+//            workgroup; every wave sweeps the whole stencil for its own tile.
 // SPLIT waves share a tile; NT threads stage its box, MS slots each, so a box
 // holds at most NT * MS slots (TPW = 4: 256).
 template <int DIM, int TPW>
 struct Grp {
     static constexpr int SPLIT = TPW == 0 ? 1 : PD_TILE_WAVES / TPW;
     static constexpr int NT = TPW == 0 ? PD_TILE_THREADS : 64 * SPLIT;
-    static constexpr int MS = TPW == 0 ? 8 : (TPW == 1 ? StageCap<DIM>::value : 4);
+    static constexpr int MS = TPW == 0 ? (DIM == 3 ? 8 : 2) : (TPW == 1 ? StageCap<DIM>::value : 4);
     static constexpr int CAP = NT * MS;
 };
 
@@ -231,10 +231,15 @@ __device__ __forceinline__ int64_t first_st_tile(const StepArgs &a, int64_t st) 
     return 0;
 }
 
-// slot of lane l of quadrant q's tile in the super-tile box (pitches 16 and
-// 228, reach R on every side)
+// slot of lane l of quadrant q's tile in the super-tile box (reach R on
+// every side; pitches 16 and 228 in 3D, x pitch 40 in 2D)
+template <int DIM>
 __device__ __forceinline__ int own_slot_st(int R, int sub, int lane) {
-    return ((lane & 3) + 4 * (sub & 1) + R) + 16 * (((lane >> 2) & 3) + 4 * (sub >> 1) + R) + 228 * ((lane >> 4) + R);
+    if constexpr (DIM == 3)
+        return ((lane & 3) + 4 * (sub & 1) + R) + 16 * (((lane >> 2) & 3) + 4 * (sub >> 1) + R) +
+               228 * ((lane >> 4) + R);
+    else
+        return ((lane & 7) + 8 * (sub & 1) + R) + 40 * ((lane >> 3) + 8 * (sub >> 1) + R);
 }
 
 // tile of this wave; waves of the last workgroup past the last tile (TPW > 1)

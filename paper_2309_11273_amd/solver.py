@@ -122,7 +122,8 @@ class FamilyHost:
 
     def supertiles(self):
         """pd_build_supertiles: st_tiles, st_nbr, st_pos, st_ktab (None where the
-        family has no super-tiles: not 3D 4x4x4 tiles with reach <= 3)."""
+        family has no super-tiles: tiles other than 4x4x4 in 3D or 8x8 in 2D,
+        or reach above 3)."""
         self.st_tiles = self.st_nbr = self.st_pos = self.st_ktab = None
         self.n_st, self.st_n_pos = 0, 0
         L = A.load()

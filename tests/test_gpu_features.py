@@ -89,12 +89,14 @@ def test_graph_replay_equals_eager_all_paths(ctx, precision, form):
     assert np.array_equal(a.mask_host(), b.mask_host())
 
 
-@pytest.mark.parametrize("kernel", ["tiled", "gather", "super"])
+@pytest.mark.parametrize("kernel", ["tiled", "gather", "super", "super3d"])
 def test_fp32_split_calls_equal_one_call(ctx, kernel):
     """An FP32 trajectory is the same bits however its steps are split into
     calls (1 + 7 + 30 + 62 eager steps against 100 in one call), on a plate
-    that breaks bonds."""
-    if kernel == "super":  # 3D only: the cracking-free impact plate with its 16.5 m/s edge
+    that breaks bonds (super3d: the cracking-free impact plate with its
+    16.5 m/s edge)."""
+    if kernel == "super3d":
+        kernel = "super"
         w = W.impact3d(nx=36, ny=36, nz=9, dt=2.6e-7, steps=100)
     else:
         w = W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37, steps=100)
@@ -287,7 +289,7 @@ def test_autotune_picks_a_measured_candidate(ctx, tmp_path):
     cache = str(tmp_path / "tune.json")
     r = s.autotune("fp32", trial_steps=5, cache=cache)
     ms = [c["ms"] for c in r["candidates"]]
-    # tile kernels, super-tile kernels (3D 4x4x4 tiles), gather at 64/128/256
+    # tile kernels, super-tile kernels, gather at 64/128/256
     assert len(ms) == 5 and min(ms) == r["ms_per_step"]
     assert r["kernel"] in ("tiled", "super", "gather")
     # cached result is reused and the state was reset

@@ -152,8 +152,6 @@ def test_plate_full_size_fp64(ctx):
                                         ("plate_16x4", 200)])
 def test_fp32_recheck_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
-    if kernel == "super" and w.dim != 3:
-        pytest.skip("super-tiles are 3D")
     o = Oracle(w)
     s = solver(w, ctx)
     if kernel == "super" and s.fam.st_tiles is None:
@@ -192,10 +190,11 @@ def test_deterministic_and_block_invariant(ctx):
     for u, m in outs[1:]:
         assert np.array_equal(u, outs[0][0])
         assert np.array_equal(m, outs[0][1])
-    for prec, kern in (("fp64", "tiled"), ("fp32", "tiled"), ("fp32", "super")):
+    for prec, kern, wl in (("fp64", "tiled", w), ("fp32", "tiled", w), ("fp32", "super", w),
+                           ("fp32", "super", small_workloads()["plate_notched"])):
         runs = []
         for _ in range(2):
-            s = solver(w, ctx)
+            s = solver(wl, ctx)
             s.step(100, precision=prec, kernel=kern)
             runs.append((s.read()[0], s.mask_host()))
         assert np.array_equal(runs[0][0], runs[1][0]), (prec, kern)

@@ -574,13 +574,14 @@ def test_cleared_keys_and_status_index(lib, case):
         fam.cleared_keys(fam.mask, m2)
 
 
-@pytest.mark.parametrize("case", ["cantilever", "impact_small", "cylinder_small", "short_reach"])
+@pytest.mark.parametrize("case", ["cantilever", "impact_small", "cylinder_small", "short_reach", "plate", "batch3"])
 def test_supertile_box_addressing_matches_bond_words(lib, case):
-    """Super-tiles group the 4x4x4 tiles 2 x 2 x 1: every tile is in exactly
-    one quadrant of one super-tile, at its place; the shared box (pitches 16
-    and 228) receives, at slot(l) + soff[k] of lane l of quadrant q, exactly
-    the row the bond word of bond k names; the lanes of a quadrant hit 64
-    distinct LDS banks; the table holds M/x, x^2, x M of every entry."""
+    """Super-tiles group the tiles 2 x 2 (x 1) (4x4x4 tiles in 3D, 8x8 in
+    2D): every tile is in exactly one quadrant of one super-tile, at its
+    place; the shared box (pitches 16 and 228 in 3D, 40 in 2D) receives, at
+    slot(l) + soff[k] of lane l of quadrant q, exactly the row the bond word
+    of bond k names; the lanes of a quadrant hit 64 distinct LDS banks; the
+    table holds M/x, x^2, x M of every entry."""
     if case == "short_reach":
         w = W.impact3d(nx=24, ny=24, nz=8, dt=1e-7)
         w.delta = 2.015 * w.dx
@@ -589,7 +590,8 @@ def test_supertile_box_addressing_matches_bond_words(lib, case):
     f = _family(w)
     s = f.sizes
     R = int(s.reach)
-    assert f.st_tiles is not None and list(s.tile) == [4, 4, 4]
+    dim = int(s.dim)
+    assert f.st_tiles is not None and list(s.tile) == ([4, 4, 4] if dim == 3 else [8, 8, 1])
     nst = f.n_st
     st = f.st_tiles.reshape(nst, 4)
     assert np.array_equal(np.sort(st[st >= 0]), np.arange(int(s.n_tiles)))
@@ -599,10 +601,18 @@ def test_supertile_box_addressing_matches_bond_words(lib, case):
             t0 = st[sidx][st[sidx] >= 0][0]
             t = st[sidx, q]
             assert org[t, 3] == org[t0, 3] and org[t, 2] == org[t0, 2]
-    P0, P1 = 16, 228
+    if dim == 3:
+        P0, P1, nslot = 16, 228, 228 * (4 + 2 * R)
+
+        def own(q, l):
+            return ((l & 3) + 4 * (q & 1) + R) + P0 * (((l >> 2) & 3) + 4 * (q >> 1) + R) + P1 * ((l >> 4) + R)
+    else:
+        P0, P1, nslot = 40, 0, 40 * (16 + 2 * R)
+
+        def own(q, l):
+            return ((l & 7) + 8 * (q & 1) + R) + P0 * ((l >> 3) + 8 * (q >> 1) + R)
     for q in range(4):
-        lanes = [((l & 3) + 4 * (q & 1)) + P0 * (((l >> 2) & 3) + 4 * (q >> 1)) + P1 * (l >> 4) for l in range(64)]
-        assert len({v % 64 for v in lanes}) == 64
+        assert len({(own(q, l) - own(q, 0)) % 64 for l in range(64)}) == 64
     ns_ = int(s.n_stencil)
     off = f.stencil_off.reshape(-1, 3)
     kt = f.st_ktab.view(np.int32).reshape(128, 8)
@@ -613,11 +623,14 @@ def test_supertile_box_addressing_matches_bond_words(lib, case):
     assert np.array_equal(kf[:ns_, [0, 1, 2, 3, 4, 6, 7]], k1[:ns_, [0, 1, 2, 3, 4, 6, 7]])
     hp = f.st_pos.astype(np.int64)
     slots = hp >> 12
-    assert len(np.unique(slots)) == len(slots) and slots.max() < P1 * (4 + 2 * R)
+    assert len(np.unique(slots)) == len(slots) and slots.max() < nslot
+    assert f.st_n_pos <= (512 if dim == 2 else 2048)
     rng = np.random.default_rng(2)
     for sidx in rng.choice(nst, size=min(25, nst), replace=False):
         nb = f.st_nbr[48 * sidx: 48 * sidx + 48]
-        rows = np.full(P1 * (4 + 2 * R), -1, np.int64)
+        if dim == 2:
+            assert (nb[:16] == -1).all() and (nb[32:] == -1).all()
+        rows = np.full(nslot, -1, np.int64)
         nt = nb[(hp & 4095) >> 6]
         rows[slots] = np.where(nt >= 0, nt * 64 + (hp & 63), -1)
         for q in range(4):
@@ -626,7 +639,7 @@ def test_supertile_box_addressing_matches_bond_words(lib, case):
                 continue
             base = f.slice_ptr[t]
             for lane in range(64):
-                my = ((lane & 3) + 4 * (q & 1) + R) + P0 * (((lane >> 2) & 3) + 4 * (q >> 1) + R) + P1 * ((lane >> 4) + R)
+                my = own(q, lane)
                 assert rows[my] == t * 64 + lane
                 for k in range(ns_):
                     wd = f.words[base + (k // 4) * 256 + lane * 4 + (k % 4)]
@@ -634,6 +647,9 @@ def test_supertile_box_addressing_matches_bond_words(lib, case):
                         assert rows[my + soff[k]] == (wd >> 7)
 
 
-def test_supertiles_only_for_3d_4x4x4(lib):
-    f = _family(W.plate2d(nx=40, ny=20, dt=1e-7, notch_row=9, notch_tip=19.37))
+def test_supertiles_need_square_tiles(lib):
+    """A 2D family of 16x4 tiles has no super-tiles (its kernels are the tile
+    kernels)."""
+    f = _family(CASES["plate_16x4"]())
+    assert list(f.sizes.tile) == [16, 4, 1]
     assert f.st_tiles is None and f.n_st == 0
