@@ -190,6 +190,13 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     // its words once, before it rewrites that word, and no other wave reads it
     const cu64_t *mks = (const cu64_t *)mrow;
     const int64_t row = tile * 64 + lane;
+    // the loads that depend on the tile alone, requested together before any
+    // of them is waited for (unconditional, in-bounds indexes): the staging
+    // then waits for one memory round trip before its gathers
+    const int nbv = TPW == 0 ? a.st_nbr[48 * stid + min(gt, NNB - 1)] : a.tile_nbr[27 * tile + min(gt, NNB - 1)];
+    const uint32_t auxv = a.aux[row];
+    const int4 own = sh[row];
+    const float ri = qr[row].y;
     // box points of this thread; threads past the last point redo it (the
     // same value into the same slot)
     // (act[i]: some thread of this wave has a point in round i)
@@ -198,29 +205,30 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
 #pragma unroll
     for (int i = 0; i < MS; i++) {
         act[i] = (gt & ~63) + i * GR::NT < npts;
-        hp[i] = act[i] ? hpos[min(gt + i * GR::NT, npts - 1)] : 0;
+        hp[i] = hpos[min(gt + i * GR::NT, npts - 1)];
     }
-    if (gt < NNB) stn[gt] = TPW == 0 ? a.st_nbr[48 * stid + gt] : a.tile_nbr[27 * tile + gt];
+    if (gt < NNB) stn[gt] = nbv;
+    // the tile's bond range and the shadow scale arrive with the loads above
+    // (not requested later, next to their first use)
+    asm volatile("" ::"s"(base), "s"(L4), "s"(Q));
     const int G4 = L4 >> 2;
     const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
     const int g0 = kq * gper, g1 = min(G4, g0 + gper);
-    // this wave's first status words, requested before the staging
-    uint64_t mw[4];
-#pragma unroll
-    for (int c = 0; c < 4; c++) mw[c] = g0 < g1 ? mks[4 * g0 + c] : 0ull;
-    const pd_spec sp = a.spec[tile_specimen(a.aux[row])];
-    const float GQ = (float)(sp.G * Q);  // extension carried in units of Q
+    uint64_t mw[4];  // this wave's first status words (requested with the gathers)
+    const uint32_t spi = tile_specimen(auxv);
     // reference point: the shadow of the tile's centre lattice point, or of
     // its first node if the centre is padding (V = 0); zero if a sentinel
-    const int4 own = sh[row];
+    // (every component read, so that the row's record is one load)
     const uint64_t nodes = __ballot(own.w != 0);
     const int lc = (a.tile[0] >> 1) + a.tile[0] * ((a.tile[1] >> 1) + a.tile[1] * (a.tile[2] >> 1));
     const int lr = ((nodes >> lc) & 1ull) || !nodes ? lc : (int)__builtin_ctzll(nodes);
     const int r0 = __builtin_amdgcn_readlane(own.x, lr);
+    const int r1 = __builtin_amdgcn_readlane(own.y, lr);
+    const int r2 = DIM == 3 ? __builtin_amdgcn_readlane(own.z, lr) : 0;
     const bool rsent = r0 == PD_SENTINEL_T;
     int rx = rsent ? 0 : r0;
-    int ry = rsent ? 0 : __builtin_amdgcn_readlane(own.y, lr);
-    int rz = rsent ? 0 : __builtin_amdgcn_readlane(own.z, lr);
+    int ry = rsent ? 0 : r1;
+    int rz = rsent ? 0 : r2;
     int *rfl = stn + NNB;
     if constexpr (TPW == 0) {
         // one reference for the shared box: that of the first quadrant with a
@@ -233,12 +241,19 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         }
     }
     tile_sync<TPW>();
+    // every load issued so far has arrived (they were requested together):
+    // said explicitly, so that the gathers below, issued round by round, are
+    // not held up by waits the compiler would otherwise place for them
+    __builtin_amdgcn_s_waitcnt(0);
     if constexpr (TPW == 0) {
         rx = rfl[0];
         ry = rfl[1];
         rz = rfl[2];
     }
     bool sent = false;
+    // the specimen's constants, requested before the gathers (so that their
+    // wait does not include them)
+    const pd_spec sp = a.spec[spi];
     {
         uint32_t rw[MS];
 #pragma unroll
@@ -257,6 +272,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
             v[i] = sh[rw[i]];
             r[i] = qr[rw[i]].y;
         }
+        // the first status words of the sweep, requested once the gathers are
+        // in flight (scalar reads in flight would hold up every wait for LDS
+        // data before them)
+#pragma unroll
+        for (int c = 0; c < 4; c++) mw[c] = g0 < g1 ? mks[4 * g0 + c] : 0ull;
+        const float GQ = (float)(sp.G * Q);  // extension carried in units of Q
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             if (!act[i]) continue;
@@ -276,11 +297,11 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         ctl->qs[cur ^ 1] = shadow_scale_t(ctl->umax_bits[cur]);
         ctl->umax_bits[cur ^ 1] = 0u;
     }
+    const float GQ = (float)(sp.G * Q);  // extension carried in units of Q
     const int my = TPW == 0 ? own_slot_st<DIM>(a.reach, sub, lane) : own_slot1<DIM>(a.tile, a.reach, B1, lane);
     float aix, aiy, aiz;
     box.pos(my, aix, aiy, aiz);
     const float big_i = big_abs(aix) + big_abs(aiy) + big_abs(aiz);
-    const float ri = qr[row].y;
     const float rpi = GQ * ri;
     const double s0 = sp.s0;
     // breaking threshold in units of Q, widened by the float rounding of the test
@@ -834,7 +855,7 @@ bool tiled_supported(const StepArgs &a) {
     if (np < 1 || np > box_points(a)) return false;
     const int tpw = tiles_per_group(a.dim, box_points(a));
     const int cap = a.dim == 3 ? Grp<3, 1>::CAP : (tpw == 4 ? Grp<2, 4>::CAP : Grp<2, 1>::CAP);
-    if (ns > cap || np > cap) return false;
+    if (ns > cap || np > cap || np < 1) return false;
     int32_t B1[4];
     pd_tile_box1(a.tile, a.reach, a.dim, B1);
     if (B1[3] * B1[2] > pd_box1_stride(a.dim, box_points(a))) return false;

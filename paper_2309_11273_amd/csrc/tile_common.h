@@ -246,8 +246,9 @@ __device__ __forceinline__ int own_slot_st(int R, int sub, int lane) {
 // redo the last tile and must not write
 template <int TPW>
 __device__ __forceinline__ int64_t group_tile(int64_t n_tiles, int sub, bool &valid) {
-    const int64_t groups = (n_tiles + TPW - 1) / TPW;
-    const int64_t t = xcd_tile(blockIdx.x, groups) * TPW + sub;
+    constexpr int P = TPW > 0 ? TPW : 1;  // (TPW = 0 never reaches here)
+    const int64_t groups = (n_tiles + P - 1) / P;
+    const int64_t t = xcd_tile(blockIdx.x, groups) * P + sub;
     valid = t < n_tiles;
     return valid ? t : n_tiles - 1;
 }
