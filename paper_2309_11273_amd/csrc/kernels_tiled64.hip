@@ -45,6 +45,16 @@ struct Lay64 {
     static constexpr int BYTES = NA * S * 8 + 128 * 8 + 32 * 4;
 };
 // pass 1: G V/m, u_x, u_y, (u_z,) V;  pass 2: (K - G/3) theta/m, V
+// staging and stencil split of the double pass 1 with W waves per workgroup
+// (one tile per workgroup: the W waves share the tile's box and its stencil)
+template <int DIM, int TPW, int W>
+struct Grp64 {
+    using G = Grp<DIM, TPW>;
+    static constexpr int SPLIT = TPW == 1 ? W : G::SPLIT;
+    static constexpr int NT = TPW == 1 ? 64 * W : G::NT;
+    static constexpr int MS = TPW == 1 ? (G::CAP + NT - 1) / NT : G::MS;
+    static_assert(NT * MS >= G::CAP, "the staging covers the box capacity");
+};
 template <int DIM>
 struct NA1 {
     static constexpr int value = DIM == 3 ? 5 : 4;
@@ -81,11 +91,15 @@ __device__ __forceinline__ double rsqrt_refined(double s) {
 // ---------------------------------------------------------------------------
 // pass 1: breaking, dilatation, deviatoric pair force
 // ---------------------------------------------------------------------------
-template <int DIM, bool BREAK, int TPW, bool FIN = false>
-__global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int cur, const KEnt *__restrict__ kt,
-                                                                const double4 *__restrict__ sten) {
+// W waves per workgroup: with one tile per workgroup (TPW = 1) they split the
+// staging and the stencil between them (eight in 3D, where the five staged
+// double arrays hold a compute unit to three workgroups)
+template <int DIM, bool BREAK, int TPW, bool FIN = false, int W = PD_TILE_WAVES>
+__global__ __launch_bounds__(64 * W) void k_tpass1_f64(StepArgs a, int cur, const KEnt *__restrict__ kt,
+                                                       const double4 *__restrict__ sten) {
     extern __shared__ __align__(16) unsigned char smem[];
-    using GR = Grp<DIM, TPW>;
+    static_assert(TPW == 1 || W == PD_TILE_WAVES, "several tiles per workgroup take four waves");
+    using GR = Grp64<DIM, TPW, W>;
     constexpr int MS = GR::MS;
     constexpr int NA = NA1<DIM>::value;
     using LY = Lay64<DIM, TPW, NA>;
@@ -227,13 +241,13 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f64(StepArgs a, int 
         __syncthreads();  // every wave is done with the staged box: reuse it for the sums
         double *red = hA;
 #pragma unroll
-        for (int v = 0; v < 4; v++) red[(v * PD_TILE_WAVES + wv) * 64 + lane] = tot[v];
+        for (int v = 0; v < 4; v++) red[(v * W + wv) * 64 + lane] = tot[v];
         __syncthreads();
         if (wv != 0) return;
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            tot[v] = red[v * PD_TILE_WAVES * 64 + lane];
-            for (int q = 1; q < PD_TILE_WAVES; q++) tot[v] += red[(v * PD_TILE_WAVES + q) * 64 + lane];
+            tot[v] = red[v * W * 64 + lane];
+            for (int q = 1; q < W; q++) tot[v] += red[(v * W + q) * 64 + lane];
         }
     }
     if (!valid) return;
@@ -466,8 +480,9 @@ hipError_t launch_tpass1_f64(const StepArgs &a, int cur, bool brk, hipStream_t s
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     const double4 *sten = reinterpret_cast<const double4 *>(a.stencil);
     if (a.dim == 3) {
-        if (brk) hipLaunchKernelGGL((k_tpass1_f64<3, true, 1>), g, b, lds, s, a, cur, kt, sten);
-        else hipLaunchKernelGGL((k_tpass1_f64<3, false, 1>), g, b, lds, s, a, cur, kt, sten);
+        const dim3 b8(64 * 8);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f64<3, true, 1, false, 8>), g, b8, lds, s, a, cur, kt, sten);
+        else hipLaunchKernelGGL((k_tpass1_f64<3, false, 1, false, 8>), g, b8, lds, s, a, cur, kt, sten);
     } else if (tpw == 4) {
         if (brk) hipLaunchKernelGGL((k_tpass1_f64<2, true, 4>), g, b, lds, s, a, cur, kt, sten);
         else hipLaunchKernelGGL((k_tpass1_f64<2, false, 4>), g, b, lds, s, a, cur, kt, sten);
@@ -509,7 +524,11 @@ hipError_t launch_tpass1_f64_fin(const StepArgs &a, int cur, bool brk, hipStream
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     const double4 *sten = reinterpret_cast<const double4 *>(a.stencil);
 #define PD_FT1(D, B, T) hipLaunchKernelGGL((k_tpass1_f64<D, B, T, true>), g, b, lds, s, a, cur, kt, sten)
-    if (a.dim == 3) { if (brk) PD_FT1(3, true, 1); else PD_FT1(3, false, 1); }
+    if (a.dim == 3) {
+        const dim3 b8(64 * 8);
+        if (brk) hipLaunchKernelGGL((k_tpass1_f64<3, true, 1, true, 8>), g, b8, lds, s, a, cur, kt, sten);
+        else hipLaunchKernelGGL((k_tpass1_f64<3, false, 1, true, 8>), g, b8, lds, s, a, cur, kt, sten);
+    }
     else if (tpw == 4) { if (brk) PD_FT1(2, true, 4); else PD_FT1(2, false, 4); }
     else { if (brk) PD_FT1(2, true, 1); else PD_FT1(2, false, 1); }
 #undef PD_FT1
