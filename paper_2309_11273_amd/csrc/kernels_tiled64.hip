@@ -298,18 +298,22 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
     const int64_t row = tile * 64 + lane;
     const uint32_t aux = a.aux[row];
     const uint64_t *mrow = a.mask + (base >> 6);
+    // the loads that depend on the tile alone, requested together before any
+    // of them is waited for (unconditional, in-bounds indexes)
+    const int nbv = a.tile_nbr[27 * tile + min(gt, 26)];
     int hmv[MS];
 #pragma unroll
     for (int i = 0; i < MS; i++) {
         const int s = gt + i * GR::NT;
         hmv[i] = s < g.nslot ? a.halo_map[s] : -1;
     }
-    if (gt < 27) stn[gt] = a.tile_nbr[27 * tile + gt];
-    const uint64_t mw0 = gt < L4 ? mrow[gt] : 0ull;
-    const uint64_t mw1 = (TPW != 1 && gt + 64 < L4) ? mrow[gt + 64] : 0ull;
-    const pd_spec sp = a.spec[tile_specimen(aux)];
-    const double kp = sp.kp;
+    if (gt < 27) stn[gt] = nbv;
+    asm volatile("" ::"s"(base), "s"(L4));  // the bond range arrives with the loads above
+    const uint32_t spi = tile_specimen(aux);
     __syncthreads();
+    const pd_spec sp = a.spec[spi];
+    const double kp = sp.kp;
+    uint64_t mw0, mw1;
     {
         int64_t rw[MS];
         double q[MS];
@@ -323,6 +327,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
             q[i] = rw[i] >= 0 ? qr[rw[i]].x : 0.0;
             u[i] = rw[i] >= 0 ? uv[rw[i]] : make_double4(0.0, 0.0, 0.0, 0.0);
         }
+        // the tile's status words, requested with the gathers
+        mw0 = gt < L4 ? mrow[gt] : 0ull;
+        mw1 = (TPW != 1 && gt + 64 < L4) ? mrow[gt + 64] : 0ull;
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             const int s = gt + i * GR::NT;
