@@ -298,8 +298,9 @@ typedef struct pd_problem_dev {
     int32_t pad2;
 } pd_problem_dev;
 
-/* Device control block (step counter, diagnostics).  Size in bytes: */
-#define PD_CTL_BYTES 256
+/* Device control block (step counter, diagnostics, the shadow maxima of the
+ * FP32 path spread over 128 cache lines).  Size in bytes, 256-aligned: */
+#define PD_CTL_BYTES 16640
 
 /* Solver state, [device] arrays in internal row order. */
 typedef struct pd_state_dev {

@@ -17,7 +17,7 @@ STATUS = {0: "PD_OK", -1: "PD_ERR_ARG", -2: "PD_ERR_SIZE", -3: "PD_ERR_HIP", -4:
 PD_3D, PD_PLANE_STRESS, PD_PLANE_STRAIN = 0, 1, 2
 PD_FP64, PD_FP32_RECHECK = 0, 1
 PD_MATRIX_FREE, PD_BSR, PD_FACTORED = 0, 1, 2
-PD_CTL_BYTES = 256
+PD_CTL_BYTES = 16640
 
 
 class pd_body(C.Structure):

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -17,6 +19,9 @@
 #include "kernels.h"
 #include "pd.h"
 #include "pd_internal.h"
+
+// the control block without the shadow-maximum slots (what most reads need)
+static constexpr size_t kCtlHead = offsetof(pd_ctl, umax_slot);
 
 struct pd_ctx {
     int device = 0;
@@ -328,7 +333,7 @@ pd_status pd_tile_kernels_apply(const pd_problem_dev *p, const pd_state_dev *st,
 pd_status pd_get_step(pd_ctx *c, const pd_state_dev *st, int64_t *step) {
     if (!c || !st || !st->ctl || !step) return PD_ERR_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, kCtlHead, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     *step = c->host_ctl->s2;
     return PD_OK;
@@ -586,7 +591,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
             if (o.energy_check)
                 HIP_TRY(c, pdk::launch_energy(a, cur, o.extension != 0, c->part, nullptr, 0,
                                               reinterpret_cast<pd_ctl *>(st->ctl), c->stream));
-            HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, kCtlHead, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
             const pd_ctl *h = c->host_ctl;
             if (h->flags & PD_CTL_NONFINITE)
@@ -611,6 +616,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
         rep->nonfinite = (h->flags & PD_CTL_NONFINITE) ? 1 : 0;
         float um;
         unsigned int bits = h->umax_bits[cur];
+        for (int q = 0; q < PD_UMAX_SLOTS; q++) bits = std::max(bits, h->umax_slot[cur][q * PD_UMAX_STRIDE]);
         std::memcpy(&um, &bits, 4);
         rep->umax = (double)um;
         if (h->margin_key) {
@@ -1048,7 +1054,7 @@ pd_status pd_stable_dt(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, dou
         HIP_TRY(c, pdk::launch_pi_step(p->n_pad, p->dim, p->aux, p->spec, x,
                                        reinterpret_cast<const double4 *>(f_scratch), y, ctl, c->part, c->stream));
         if (it == iters - 1) {
-            HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, kCtlHead, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
             lam = c->host_ctl->red[0] / c->host_ctl->red[1];
         }

@@ -474,7 +474,9 @@ hipError_t launch_pass2_f64(const StepArgs &a, int cur, bool update, int block, 
 }
 
 hipError_t launch_state_init(const InitArgs &a, hipStream_t s) {
-    const int64_t nb = (a.n_pad + 255) / 256;
+    // one thread per row and at least one per word of the control block
+    const int64_t ctl_words = (int64_t)(sizeof(pd_ctl) / 8);
+    const int64_t nb = ((a.n_pad > ctl_words ? a.n_pad : ctl_words) + 255) / 256;
     hipLaunchKernelGGL(k_state_init, dim3((unsigned)nb), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -114,11 +114,10 @@ __device__ __forceinline__ void load_stencil_scaled(float4 *sst, const double *s
 // counter, same kind of set-up), so a trajectory does not depend on how its
 // steps are split across calls.  'force' redoes it regardless.
 __global__ void k_shadow_begin(pd_ctl *ctl, int k, int kind, int force) {
-    if (threadIdx.x == 0) {
-        const bool current = !force && ctl->sh_kind == kind && ctl->sh_cur == k && ctl->sh_step == ctl->s2;
-        ctl->sh_skip = current ? 1 : 0;
-        if (!current) ctl->umax_bits[k] = 0u;
-    }
+    // one wave (the maximum's slots are cleared lane by lane)
+    const bool current = !force && ctl->sh_kind == kind && ctl->sh_cur == k && ctl->sh_step == ctl->s2;
+    if (threadIdx.x == 0) ctl->sh_skip = current ? 1 : 0;
+    if (!current) umax_clear_wave(ctl, k, threadIdx.x & 63);
 }
 
 __global__ void k_shadow_invalidate(pd_ctl *ctl) {
@@ -218,10 +217,15 @@ __global__ __launch_bounds__(256) void k_pass1_f32(StepArgs a, int cur) {
     const int lane = threadIdx.x & 63;
     const int64_t slice = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (slice >= a.n_slices) return;
-    if (BREAK && blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->s1 = ctl->s2;
-        ctl->qs[cur ^ 1] = shadow_scale(ctl->umax_bits[cur]);
-        ctl->umax_bits[cur ^ 1] = 0u;
+    if (BREAK && blockIdx.x == 0 && threadIdx.x < 64) {
+        // the first wave: the next shadow's scale from this shadow's maximum
+        // (its word and the tile kernels' slots), the next maximum cleared
+        const unsigned int um = umax_wave(ctl, cur, lane);
+        umax_clear_wave(ctl, cur ^ 1, lane);
+        if (lane == 0) {
+            ctl->s1 = ctl->s2;
+            ctl->qs[cur ^ 1] = shadow_scale(um);
+        }
     }
     const int64_t row = slice * 64 + lane;
     const int64_t base = a.slice_ptr[slice];

@@ -292,10 +292,15 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     // a super-tile quadrant without a tile has nothing more to do (no later
     // workgroup barrier in this mode)
     if (TPW == 0 && !valid) return;
-    if (BREAK && valid && tile == 0 && (TPW == 1 ? gt == 0 : lane == 0)) {
-        ctl->s1 = ctl->s2;
-        ctl->qs[cur ^ 1] = shadow_scale_t(ctl->umax_bits[cur]);
-        ctl->umax_bits[cur ^ 1] = 0u;
+    if (BREAK && valid && tile == 0 && (TPW == 1 ? gt < 64 : true)) {
+        // one whole wave: the next shadow's scale from this shadow's maximum,
+        // and the next maximum cleared for pass 2
+        const unsigned int um = umax_wave(ctl, cur, lane);
+        umax_clear_wave(ctl, cur ^ 1, lane);
+        if (lane == 0) {
+            ctl->s1 = ctl->s2;
+            ctl->qs[cur ^ 1] = shadow_scale_t(um);
+        }
     }
     const float GQ = (float)(sp.G * Q);  // extension carried in units of Q
     const int my = TPW == 0 ? own_slot_st<DIM>(a.reach, sub, lane) : own_slot1<DIM>(a.tile, a.reach, B1, lane);
@@ -727,9 +732,9 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     if (!finite) m = 0.0f;
     m = __uint_as_float(__float_as_uint(m) + 1u);
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    // merge into the global maximum only when this tile exceeds what is there
-    if (lane == 0 && __float_as_uint(m) > __atomic_load_n(&ctl->umax_bits[cur ^ 1], __ATOMIC_RELAXED))
-        atomicMax(&ctl->umax_bits[cur ^ 1], __float_as_uint(m));
+    // into the slot of this tile's class: the slots spread the tiles' atomics
+    // over 64 lines, so no read of the running maximum has to filter them
+    if (lane == 0) atomicMax(&ctl->umax_slot[cur ^ 1][(tile % PD_UMAX_SLOTS) * PD_UMAX_STRIDE], __float_as_uint(m));
     if (__ballot(!finite) && lane == 0) atomicOr(&ctl->flags, PD_CTL_NONFINITE);
     if (__ballot(bad) && lane == 0) atomicOr(&ctl->flags, PD_CTL_FALLBACK);
 }

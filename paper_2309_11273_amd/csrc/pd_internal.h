@@ -1,6 +1,7 @@
 // Internal declarations shared by the host and device sources of libpd.
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 #include "pd.h"
@@ -9,6 +10,9 @@
 // pd_state_init).  Step counter: pass 1 of a step reads s2 and writes s1,
 // pass 2 reads s1 and writes s2 = s1 + 1, so no kernel writes a slot that
 // another wave of the same kernel reads.
+#define PD_UMAX_SLOTS 64
+#define PD_UMAX_STRIDE 32  // 4-byte words between slots (128 bytes)
+
 struct pd_ctl {
     int64_t s1;
     int64_t s2;
@@ -35,7 +39,13 @@ struct pd_ctl {
     // the total of the check before it, the step counter of the last check
     double en[4];
     unsigned long long pad1[6];
+    // max |u| of shadow buffer k as written by the tile kernels: one slot per
+    // tile class (tile mod PD_UMAX_SLOTS), each on its own 128-byte line, so
+    // that the tiles' atomics do not queue on one address.  The maximum of
+    // buffer k is that of umax_bits[k] and its slots.
+    unsigned int umax_slot[2][PD_UMAX_SLOTS * PD_UMAX_STRIDE];
 };
+static_assert(offsetof(pd_ctl, umax_slot) % 128 == 0, "slots on their own lines");
 static_assert(sizeof(pd_ctl) <= PD_CTL_BYTES, "control block too large");
 static_assert(sizeof(pd_ctl) % 8 == 0, "control block is cleared in 8-byte words");
 
@@ -53,6 +63,24 @@ static_assert(sizeof(pd_ctl) % 8 == 0, "control block is cleared in 8-byte words
 
 #ifdef __HIPCC__
 #include <hip/hip_runtime.h>
+
+static_assert(PD_UMAX_SLOTS == 64, "one slot per lane of a wave64");
+// Largest |u| bits of shadow buffer k: its word and its slots, read by one
+// whole wave (lane l reads slot l).
+__device__ __forceinline__ unsigned int umax_wave(const pd_ctl *ctl, int k, int lane) {
+    unsigned int m = ctl->umax_slot[k][lane * PD_UMAX_STRIDE];
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned int t = (unsigned int)__shfl_xor((int)m, o);
+        m = t > m ? t : m;
+    }
+    const unsigned int b = ctl->umax_bits[k];
+    return m > b ? m : b;
+}
+// Clears the word and the slots of shadow buffer k (one whole wave).
+__device__ __forceinline__ void umax_clear_wave(pd_ctl *ctl, int k, int lane) {
+    ctl->umax_slot[k][lane * PD_UMAX_STRIDE] = 0u;
+    if (lane == 0) ctl->umax_bits[k] = 0u;
+}
 // Per-row vectors kept with the problem's dimension (velocity, the row
 // constants D_i and the carried force parts): a 3D row is four entries
 // (x, y, z, 0), a 2D row two (x, y), so 2D moves half the bytes.
