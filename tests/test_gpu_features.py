@@ -129,6 +129,30 @@ def test_fp32_shadow_rebuilt_after_other_paths(ctx):
     assert np.array_equal(a.read()[0], b.read()[0])
 
 
+@pytest.mark.parametrize("order", [("tiled", "gather", "tiled"), ("gather", "tiled", "gather"),
+                                   ("super", "tiled", "super")])
+def test_fp32_kernel_kinds_in_turn(ctx, order):
+    """FP32 steps of the tile, super-tile and gather kernels in turn on one
+    state (the shadow rebuilt at every change of kind, its maximum kept in the
+    word and in the tile kernels' slots) follow the reference on a plate that
+    breaks bonds: rel-L2 <= 1e-4 and identical broken sets."""
+    w = W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37, steps=300)
+    s = solver(w, ctx)
+    if "super" in order and s.fam.st_tiles is None:
+        pytest.skip("no super-tiles for this family")
+    o = Oracle(w)
+    uo, vo = o.initial_state()
+    cut0 = int((o.rho() == 0).sum())  # notch cuts
+    for kern in order:
+        s.step(100, precision="fp32", kernel=kern)
+    o.run(300, uo, vo)
+    u, _ = s.read()
+    assert rel(u, uo) <= 1e-4
+    assert int((o.rho() == 0).sum()) > cut0  # bonds broke
+    assert np.array_equal(s.bond_status()[2], o.rho())
+    assert s.step_count() == 300
+
+
 def test_graph_cache_with_two_problems_on_one_context(ctx):
     """Captured step graphs are keyed on every launch parameter: problems of
     different shape and size stepped in turn on one context with graph
