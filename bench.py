@@ -435,9 +435,10 @@ def main():
     ap.add_argument("--form", default="mf", choices=["mf", "bsr", "fac"],
                     help="mf: matrix-free tile kernels; bsr: block-sparse K; fac: the paper's four "
                          "factored matrices (double values, so --precision fp64)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tiled", "super"],
-                    help="matrix-free kernels: auto (library default), gather (bond list), tiled (one tile "
-                         "per workgroup), super (FP32: four tiles per workgroup sharing one halo box)")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tiled", "super", "tiled1"],
+                    help="matrix-free kernels: auto (the library's tuner), gather (bond list), tiled (one tile "
+                         "per workgroup in 3D, per wave in 2D), super (FP32: four tiles per workgroup sharing "
+                         "one halo box), tiled1 (one tile per workgroup in 2D too)")
     ap.add_argument("--extension", default="linear", choices=["linear", "finite"],
                     help="finite: e = |x M + u_j - u_i| - x with the force along the deformed bond "
                          "(FP64 gather kernels)")
@@ -686,7 +687,7 @@ def main():
     }
     if tune is not None:
         out["config"]["kernel"] = args.kernel + (f" ({block} threads per block)" if args.kernel == "gather" else "")
-        names = {1: "gather", 2: "tiled", 3: "super"}
+        names = {1: "gather", 2: "tiled", 3: "super", 4: "tiled1"}
         out["autotune"] = {"pick": tune["kernel"], "block": tune["block"],
                            "candidates_ms_per_step": {f"{names.get(c['kernel'], c['kernel'])}"
                                                       f"{'/' + str(c['block']) if c['kernel'] == 1 else ''}":

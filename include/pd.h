@@ -394,7 +394,9 @@ typedef struct pd_step_opts {
                             wave (2D) (error if not possible); 3 = FP32 super-tile
                             kernels (four tiles per workgroup sharing one halo box,
                             pd_build_supertiles; error if not possible; the FP64
-                            path then uses the tile kernels)                        */
+                            path then uses the tile kernels); 4 = tile kernels with
+                            one tile per workgroup in 2D too (its four waves split
+                            the stencil; in 3D the same as 2)                       */
     int32_t extension;   /* 0: linearized e = M.(u_j - u_i) along M (Eqs. 2.4, 2.7);
                             1: finite e = |x M + u_j - u_i| - x with the pair force
                             along the deformed bond (Eqs. 1.10, 1.13): PD_FP64,

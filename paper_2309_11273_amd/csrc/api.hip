@@ -457,13 +457,15 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
         return fail(c, PD_ERR_ARG, "block must be 0, 64, 128 or 256");
     if (o.graph_chunk < 0 || o.check_every < 0) return fail(c, PD_ERR_ARG, "negative option");
     if (o.profile != 0 && o.profile != 1) return fail(c, PD_ERR_ARG, "profile must be 0 or 1");
-    if (o.kernel < 0 || o.kernel > 3) return fail(c, PD_ERR_ARG, "kernel must be 0, 1, 2 or 3");
+    if (o.kernel < 0 || o.kernel > 4) return fail(c, PD_ERR_ARG, "kernel must be 0 to 4");
     if (o.extension != 0 && o.extension != 1) return fail(c, PD_ERR_ARG, "extension must be 0 or 1");
     if (o.extension && (o.precision != PD_FP64 || o.form != PD_MATRIX_FREE))
         return fail(c, PD_ERR_UNSUPPORTED, "the finite extension runs with PD_FP64 and PD_MATRIX_FREE");
-    if (o.extension && o.kernel == 2) {
+    if (o.extension && (o.kernel == 2 || o.kernel == 4)) {
         pd_state_dev tmp = *st;
-        if (!pdk::tiled64_fin_supported(make_args(p, &tmp)))
+        pdk::StepArgs ta = make_args(p, &tmp);
+        ta.one_tile_per_group = o.kernel == 4;
+        if (!pdk::tiled64_fin_supported(ta))
             return fail(c, PD_ERR_UNSUPPORTED, "the finite model's tile kernels do not fit this family");
     }
     if (o.kernel == 3 && o.form == PD_MATRIX_FREE && o.precision == PD_FP32_RECHECK && !o.extension) {
@@ -472,9 +474,10 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
             return fail(c, PD_ERR_UNSUPPORTED,
                         "super-tile kernels need 4x4x4 (3D) or 8x8 (2D) tiles, reach <= 3 and the tables of pd_build_supertiles");
     }
-    if ((o.kernel == 2 || o.kernel == 3) && o.form == PD_MATRIX_FREE) {
+    if ((o.kernel == 2 || o.kernel == 3 || o.kernel == 4) && o.form == PD_MATRIX_FREE) {
         pd_state_dev tmp = *st;
-        const pdk::StepArgs ta = make_args(p, &tmp);
+        pdk::StepArgs ta = make_args(p, &tmp);
+        ta.one_tile_per_group = o.kernel == 4;
         if (o.precision == PD_FP32_RECHECK ? !pdk::tiled_supported(ta) : !pdk::tiled64_supported(ta))
             return fail(c, PD_ERR_UNSUPPORTED,
                         "tile kernels need tile edges >= the stencil reach (and qv32 for FP32, fe64 for FP64)");
@@ -511,6 +514,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
     const double growth = o.energy_growth > 0.0 ? o.energy_growth : 1e3;
     if (o.energy_check && (s = need_parts(c, p->n_pad)) != PD_OK) return s;
     pdk::StepArgs a = make_args(p, st);
+    a.one_tile_per_group = o.kernel == 4;
     int cur = st->cur;
     if (o.precision == PD_FP32_RECHECK && o.form == PD_MATRIX_FREE)
         HIP_TRY(c, pdk::launch_shadow_prep(a, cur, o.kernel != 1 && pdk::tiled_supported(a), false, c->stream));
@@ -929,6 +933,13 @@ pd_status pd_autotune(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st, int3
         }
         if (precision == PD_FP32_RECHECK && pdk::supertiles_supported(a)) {
             ck[nc] = 3;
+            cb[nc++] = 0;
+        }
+        // 2D: one tile per workgroup as well as one per wave
+        pdk::StepArgs a1 = a;
+        a1.one_tile_per_group = 1;
+        if (p->dim == 2 && (precision == PD_FP32_RECHECK ? pdk::tiled_supported(a1) : pdk::tiled64_supported(a1))) {
+            ck[nc] = 4;
             cb[nc++] = 0;
         }
     }

@@ -52,6 +52,8 @@ struct StepArgs {
     const uint32_t *st_ktab;
     int64_t n_st;
     int32_t st_n_pos;
+    // one tile per workgroup in 2D too (four waves splitting its stencil)
+    int32_t one_tile_per_group;
 };
 
 struct InitArgs {

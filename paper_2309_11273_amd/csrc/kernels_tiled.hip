@@ -858,7 +858,7 @@ bool tiled_supported(const StepArgs &a) {
     if (a.n_stencil > 124) return false;  // groups of four inside the 128-row table
     const int ns = box_slots(a), np = a.n_pos;
     if (np < 1 || np > box_points(a)) return false;
-    const int tpw = tiles_per_group(a.dim, box_points(a));
+    const int tpw = tiles_per_group(a, box_points(a));
     const int cap = a.dim == 3 ? Grp<3, 1>::CAP : (tpw == 4 ? Grp<2, 4>::CAP : Grp<2, 1>::CAP);
     if (ns > cap || np > cap || np < 1) return false;
     int32_t B1[4];
@@ -916,7 +916,7 @@ hipError_t launch_spass2_f32(const StepArgs &a, int cur, bool update, hipStream_
 }
 
 hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s) {
-    const int tpw = tiles_per_group(a.dim, box_points(a));
+    const int tpw = tiles_per_group(a, box_points(a));
     const size_t lds = tiled_lds(a, 1, tpw);
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
@@ -935,7 +935,7 @@ hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s
 }
 
 hipError_t launch_tpass2_f32(const StepArgs &a, int cur, bool update, hipStream_t s) {
-    const int tpw = tiles_per_group(a.dim, box_points(a));
+    const int tpw = tiles_per_group(a, box_points(a));
     const size_t lds = tiled_lds(a, 2, tpw);
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt1 *kn = reinterpret_cast<const KEnt1 *>(a.ktab + 1536);

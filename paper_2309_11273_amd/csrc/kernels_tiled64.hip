@@ -480,16 +480,16 @@ bool tiled64_supported(const StepArgs &a) {
     if (a.n_stencil > 124) return false;  // groups of four inside the 128-row table
     if (a.n_pad >= (int64_t(1) << 31)) return false;
     const int cap = a.dim == 3 ? Grp<3, 1>::CAP
-                               : (tiles_per_group(a.dim, box_slots64(a)) == 4 ? Grp<2, 4>::CAP : Grp<2, 1>::CAP);
+                               : (tiles_per_group(a, box_slots64(a)) == 4 ? Grp<2, 4>::CAP : Grp<2, 1>::CAP);
     if (box_slots64(a) > cap) return false;
-    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    const int tpw = tiles_per_group(a, box_slots64(a));
     // the partial sums of TPW = 1 reuse the staged arrays (2 of them in pass 2)
     if (tpw == 1 && 2 * (a.dim == 3 ? Grp<3, 1>::CAP : Grp<2, 1>::CAP) < 3 * PD_TILE_WAVES * 64) return false;
     return tiled64_lds(a.dim, 1, tpw) <= 64 * 1024 && tiled64_lds(a.dim, 2, tpw) <= 64 * 1024;
 }
 
 hipError_t launch_tpass1_f64(const StepArgs &a, int cur, bool brk, hipStream_t s) {
-    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    const int tpw = tiles_per_group(a, box_slots64(a));
     const size_t lds = tiled64_lds(a.dim, 1, tpw);
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
@@ -509,7 +509,7 @@ hipError_t launch_tpass1_f64(const StepArgs &a, int cur, bool brk, hipStream_t s
 }
 
 hipError_t launch_tpass2_f64(const StepArgs &a, int cur, bool update, hipStream_t s) {
-    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    const int tpw = tiles_per_group(a, box_slots64(a));
     const size_t lds = tiled64_lds(a.dim, 2, tpw);
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
@@ -529,11 +529,11 @@ hipError_t launch_tpass2_f64(const StepArgs &a, int cur, bool update, hipStream_
 
 bool tiled64_fin_supported(const StepArgs &a) {
     if (!tiled64_supported(a)) return false;
-    return tiled64_lds(a.dim, 3, tiles_per_group(a.dim, box_slots64(a))) <= 64 * 1024;
+    return tiled64_lds(a.dim, 3, tiles_per_group(a, box_slots64(a))) <= 64 * 1024;
 }
 
 hipError_t launch_tpass1_f64_fin(const StepArgs &a, int cur, bool brk, hipStream_t s) {
-    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    const int tpw = tiles_per_group(a, box_slots64(a));
     const size_t lds = tiled64_lds(a.dim, 1, tpw);
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
@@ -551,7 +551,7 @@ hipError_t launch_tpass1_f64_fin(const StepArgs &a, int cur, bool brk, hipStream
 }
 
 hipError_t launch_tpass2_f64_fin(const StepArgs &a, int cur, bool update, hipStream_t s) {
-    const int tpw = tiles_per_group(a.dim, box_slots64(a));
+    const int tpw = tiles_per_group(a, box_slots64(a));
     const size_t lds = tiled64_lds(a.dim, 3, tpw);
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);

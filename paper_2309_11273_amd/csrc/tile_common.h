@@ -254,7 +254,10 @@ __device__ __forceinline__ int64_t group_tile(int64_t n_tiles, int sub, bool &va
 }
 
 // workgroup tiling the launchers choose: whole tiles per wave in 2D when the
-// halo box (npoints points, unpadded) fits the per-wave staging capacity
-inline int tiles_per_group(int dim, int npoints) { return (dim == 2 && npoints <= Grp<2, 4>::CAP) ? 4 : 1; }
+// halo box (npoints points, unpadded) fits the per-wave staging capacity and
+// the caller did not ask for one tile per workgroup
+inline int tiles_per_group(const StepArgs &a, int npoints) {
+    return (a.dim == 2 && !a.one_tile_per_group && npoints <= Grp<2, 4>::CAP) ? 4 : 1;
+}
 
 }  // namespace pdk

@@ -429,7 +429,7 @@ class Solver:
         prec = {"fp64": A.PD_FP64, "fp32": A.PD_FP32_RECHECK}[precision]
         self.ctx.check("pd_autotune", A.load().pd_autotune(self.ctx.h, C.byref(self.P), C.byref(self.S), prec,
                                                              int(trial_steps), C.byref(r)))
-        res = dict(kernel={0: "auto", 1: "gather", 2: "tiled", 3: "super"}[r.kernel], block=int(r.block),
+        res = dict(kernel={0: "auto", 1: "gather", 2: "tiled", 3: "super", 4: "tiled1"}[r.kernel], block=int(r.block),
                    ms_per_step=r.ms_per_step,
                    candidates=[dict(kernel=int(r.cand_kernel[i]), block=int(r.cand_block[i]),
                                     ms=r.cand_ms[i]) for i in range(r.n_candidates)])
@@ -463,7 +463,7 @@ class Solver:
         o.form = {"mf": A.PD_MATRIX_FREE, "bsr": A.PD_BSR, "fac": A.PD_FACTORED}[form]
         o.graph_chunk, o.block, o.check_every = int(graph_chunk), int(block), int(check_every)
         o.profile = 1 if profile else 0
-        o.kernel = {"auto": 0, "gather": 1, "tiled": 2, "super": 3}[kernel]
+        o.kernel = {"auto": 0, "gather": 1, "tiled": 2, "super": 3, "tiled1": 4}[kernel]
         o.extension = {"linear": 0, "finite": 1}[extension]
         o.energy_check = 1 if energy_check else 0
         o.energy_growth = float(energy_growth)
@@ -673,7 +673,7 @@ class Solver:
         o.extension = {"linear": 0, "finite": 1}[extension]
         o.graph_chunk, o.check_every = int(graph_chunk), int(check_every)
         o.profile = 1 if profile else 0
-        o.kernel = {"auto": 0, "gather": 1, "tiled": 2, "super": 3}[kernel]
+        o.kernel = {"auto": 0, "gather": 1, "tiled": 2, "super": 3, "tiled1": 4}[kernel]
         rep = A.pd_step_report()
         self.ctx.check("pd_adr_step", A.load().pd_adr_step(self.ctx.h, C.byref(self.P), C.byref(self.S),
                                                              int(nsteps), C.byref(o), C.byref(self.R),

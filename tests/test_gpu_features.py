@@ -316,6 +316,12 @@ def test_autotune_picks_a_measured_candidate(ctx, tmp_path):
     # tile kernels, super-tile kernels, gather at 64/128/256
     assert len(ms) == 5 and min(ms) == r["ms_per_step"]
     assert r["kernel"] in ("tiled", "super", "gather")
+    # 2D: the tile kernels with one tile per wave and with one per workgroup
+    w2 = W.plate2d(nx=48, ny=24, dt=1.347e-7, sigma=12e6, notch_row=11, notch_tip=23.37, steps=50)
+    s2 = solver(w2, ctx)
+    r2 = s2.autotune("fp32", trial_steps=5)
+    assert sorted(c["kernel"] for c in r2["candidates"]) == [1, 1, 1, 2, 3, 4]
+    assert r2["kernel"] in ("tiled", "super", "gather", "tiled1")
     # cached result is reused and the state was reset
     assert s.autotune("fp32", trial_steps=5, cache=cache) == r
     assert s.step_count() == 0

@@ -107,12 +107,14 @@ def test_force_matches_reference(ctx, name):
     assert np.abs(th - tho).max() <= 1e-12 * np.abs(tho).max()
 
 
-@pytest.mark.parametrize("kernel", ["gather", "tiled"])
+@pytest.mark.parametrize("kernel", ["gather", "tiled", "tiled1"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("plane_strain", 100),
                                         ("impact", 200), ("impact_r2", 200), ("cylinder", 200), ("batch", 200),
                                         ("plate_wide", 200), ("plate_16x4", 200)])
 def test_fp64_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
+    if kernel == "tiled1" and w.dim != 2:
+        pytest.skip("one tile per workgroup is the 3D tile kernels' only mode")
     o = Oracle(w)
     s = solver(w, ctx)
     uo, vo = o.initial_state()
@@ -146,7 +148,7 @@ def test_plate_full_size_fp64(ctx):
         assert np.array_equal(s.bond_status()[2], o.rho())
 
 
-@pytest.mark.parametrize("kernel", ["gather", "tiled", "super"])
+@pytest.mark.parametrize("kernel", ["gather", "tiled", "super", "tiled1"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("impact", 200),
                                         ("impact_r2", 200), ("cylinder", 200), ("batch", 200), ("plate_wide", 200),
                                         ("plate_16x4", 200)])
@@ -156,6 +158,8 @@ def test_fp32_recheck_trajectory(ctx, name, steps, kernel):
     s = solver(w, ctx)
     if kernel == "super" and s.fam.st_tiles is None:
         pytest.skip("no super-tiles for this family (tile shape or reach)")
+    if kernel == "tiled1" and w.dim != 2:
+        pytest.skip("one tile per workgroup is the 3D tile kernels' only mode")
     uo, vo = o.initial_state()
     s.step(steps, precision="fp32", kernel=kernel)
     o.run(steps, uo, vo)
