@@ -60,7 +60,7 @@ def algorithmic_bytes(kernel: str, precision: str, nnz: int, n: int, n_loaded: i
     for the gather kernels; the LDS-staged tile kernels read no bond word
     (the stencil position of a bond gives its neighbour).  Per-row vectors
     (velocity v, the FP32 row constant D, the carried force parts) are stored
-    with the dimension: w = 4 entries in 3D, 2 in 2D.
+    with the dimension: w = 3 packed entries in 3D, 2 in 2D.
     Per node, gather kernels (pair force summed in pass 2):
       FP64 pass 1: u,V 32; aux 4; (theta/m, 1/m) 16 read + 8 write
       FP64 pass 2: u,V 32; (theta/m, 1/m) 16; aux 4; v 8w + 8w; u,V 32 write
@@ -76,7 +76,7 @@ def algorithmic_bytes(kernel: str, precision: str, nnz: int, n: int, n_loaded: i
       FP32 pass 2: (theta/m, V) 8; aux 4; D 8w; force part 4w; u,V 32;
                    v 8w + 8w; u,V 32 write; next shadow 16 write
     Loaded nodes read their external force (32 B) in pass 2."""
-    w = 4 if dim == 3 else 2
+    w = 3 if dim == 3 else 2
     bond = nnz * (0.125 if tiled else 4.125)
     if tiled:
         node = {("fp64", "pass1"): 52 + 8 * w, ("fp64", "pass2"): 76 + 24 * w,

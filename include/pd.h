@@ -305,9 +305,10 @@ typedef struct pd_problem_dev {
 /* Solver state, [device] arrays in internal row order. */
 typedef struct pd_state_dev {
     double *uv[2];      /* n_pad*4: (u_x, u_y, u_z, V) ping-pong                   */
-    double *vel;        /* n_pad*4 allocated: per row (v_x, v_y, v_z, 0) in 3D; in 2D
-                           (v_x, v_y) in the first n_pad*2 (the per-row vectors below
-                           marked "per row, by dim" follow the same rule)           */
+    double *vel;        /* n_pad*4 allocated: per row (v_x, v_y, v_z) packed in the
+                           first n_pad*3 in 3D, (v_x, v_y) in the first n_pad*2 in
+                           2D (the per-row vectors below marked "per row, by dim"
+                           follow the same rule)                                     */
     double *qr;         /* n_pad*2: (theta/m, 1/m)                                  */
     uint64_t *mask;     /* n_mask bond status bits (mutable: bonds break)           */
     int32_t *ush[2];    /* n_pad*4 fixed-point displacement shadow (FP32 path)      */

@@ -21,7 +21,7 @@ struct StepArgs {
     const uint32_t *aux;
     const double4 *fext;
     double4 *uv[2];
-    double *vel;        // per row: 3D double4 (v, 0), 2D double2 (ldv/stv)
+    double *vel;        // per row: 3D three packed doubles, 2D double2 (ldv/stv)
     double2 *qr;
     uint64_t *mask;
     pd_ctl *ctl;
@@ -31,7 +31,7 @@ struct StepArgs {
     int4 *ush[2];
     float2 *qr32;
     double *dsum;       // per row, as vel
-    float *fe32;        // per row: 3D float4, 2D float2 (ldvf/stvf)
+    float *fe32;        // per row: 3D three packed floats, 2D float2 (ldvf/stvf)
     double *fe64;       // per row, as vel
     float2 *qv32;
     // BSR path

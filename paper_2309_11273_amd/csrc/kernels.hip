@@ -3,7 +3,7 @@
 //
 // Layout (internal row order, 64-row slices, one wave64 per slice):
 //   uv[r]   double4 (u_x, u_y, u_z, V)       displacement and node volume
-//   vel[r]  double4 (v_x, v_y, v_z, 0)
+//   vel     per row (v_x, v_y, v_z) packed in 3D, (v_x, v_y) in 2D
 //   qr[r]   double2 (theta/m, 1/m)
 //   words   uint32 (j << 7 | stencil id), word k of all 64 rows of a slice
 //           stored contiguously: lanes read 256 consecutive bytes per k

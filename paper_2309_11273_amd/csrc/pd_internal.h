@@ -82,25 +82,44 @@ __device__ __forceinline__ void umax_clear_wave(pd_ctl *ctl, int k, int lane) {
     if (lane == 0) ctl->umax_bits[k] = 0u;
 }
 // Per-row vectors kept with the problem's dimension (velocity, the row
-// constants D_i and the carried force parts): a 3D row is four entries
-// (x, y, z, 0), a 2D row two (x, y), so 2D moves half the bytes.
+// constants D_i and the carried force parts): a 3D row is three packed
+// entries (x, y, z), a 2D row two (x, y), so no padding entry is moved.  The
+// wave's rows are consecutive, so its accesses cover one contiguous range.
 __device__ __forceinline__ double4 ldv(const double *p, int dim, int64_t r) {
-    if (dim == 3) return reinterpret_cast<const double4 *>(p)[r];
+    if (dim == 3) {
+        const double *q = p + 3 * r;
+        return make_double4(q[0], q[1], q[2], 0.0);
+    }
     const double2 t = reinterpret_cast<const double2 *>(p)[r];
     return make_double4(t.x, t.y, 0.0, 0.0);
 }
 __device__ __forceinline__ void stv(double *p, int dim, int64_t r, double4 v) {
-    if (dim == 3) reinterpret_cast<double4 *>(p)[r] = v;
-    else reinterpret_cast<double2 *>(p)[r] = make_double2(v.x, v.y);
+    if (dim == 3) {
+        double *q = p + 3 * r;
+        q[0] = v.x;
+        q[1] = v.y;
+        q[2] = v.z;
+    } else {
+        reinterpret_cast<double2 *>(p)[r] = make_double2(v.x, v.y);
+    }
 }
 __device__ __forceinline__ float4 ldvf(const float *p, int dim, int64_t r) {
-    if (dim == 3) return reinterpret_cast<const float4 *>(p)[r];
+    if (dim == 3) {
+        const float *q = p + 3 * r;
+        return make_float4(q[0], q[1], q[2], 0.0f);
+    }
     const float2 t = reinterpret_cast<const float2 *>(p)[r];
     return make_float4(t.x, t.y, 0.0f, 0.0f);
 }
 __device__ __forceinline__ void stvf(float *p, int dim, int64_t r, float4 v) {
-    if (dim == 3) reinterpret_cast<float4 *>(p)[r] = v;
-    else reinterpret_cast<float2 *>(p)[r] = make_float2(v.x, v.y);
+    if (dim == 3) {
+        float *q = p + 3 * r;
+        q[0] = v.x;
+        q[1] = v.y;
+        q[2] = v.z;
+    } else {
+        reinterpret_cast<float2 *>(p)[r] = make_float2(v.x, v.y);
+    }
 }
 #endif
 
