@@ -105,16 +105,20 @@ def algorithmic_flops(kernel: str, nnz: int, tiled: bool) -> int:
 
 def traffic_from_profiles(kernel_name: str, src_hash: str):
     """HBM bytes per launch measured with rocprofv3 counters (profiles/
-    traffic.json), or None if absent or taken on a different kernel source."""
+    traffic.json) as (FETCH_SIZE and WRITE_SIZE each scaled by a copy of
+    known size, the same reads counted by request size), each None if absent
+    or taken on a different kernel source.  The second is exact: FETCH_SIZE
+    counts a 128-byte read request as 64 bytes on gfx950, so the copy's
+    scale (2) overstates kernels that also issue 64-byte requests."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         t = json.load(f)
     e = t.get(kernel_name)
     if not e or e.get("source_sha") != src_hash:
-        return None
-    return e.get("bytes_per_launch")
+        return None, None
+    return e.get("bytes_per_launch"), e.get("bytes_per_launch_exact")
 
 
 def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
@@ -149,13 +153,13 @@ def roofline_entry(s, args, dom, ms1, ms2, nnz, n, n_loaded):
     gbs, tfs = byt / sec / 1e9, fl / sec / 1e12
     alu = fl / (peak_fl * 1e12) > byt / (HBM_PEAK_GBS * 1e9)
     from paper_2309_11273_amd.profsum import kernel_source_hash
-    traffic = None if args.extension == "finite" else \
+    traffic, traffic_exact = (None, None) if args.extension == "finite" else \
         traffic_from_profiles(f"{kname}@{args.workload}", kernel_source_hash(kname.split(" ")[0]))
     return {"bound": "alu" if alu else "hbm",
             "achieved": round(tfs if alu else gbs, 2), "peak": peak_fl if alu else HBM_PEAK_GBS,
             "unit": "TFLOP/s" if alu else "GB/s",
             "frac": round(tfs / peak_fl if alu else gbs / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "kernel": kname, "kernel_ms": round(ms_dom, 5),
+            "traffic": traffic, "traffic_exact": traffic_exact, "kernel": kname, "kernel_ms": round(ms_dom, 5),
             "algorithmic_bytes": byt, "algorithmic_flops": fl,
             "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "valu_tflops": round(tfs, 2), "valu_frac": round(tfs / peak_fl, 4),
@@ -175,14 +179,14 @@ def fac_bytes(kernel: str, dim: int, nnz: int, nb: int, n: int, n_loaded: int) -
                        E read; Theta written
       k_fac_force      F = K_theta Theta + K_e E and the update: per directed
                        bond 2 dim values, 2 columns; K_theta diagonal (8 dim
-                       per node), Theta and E read; per node u, v, aux
-                       (68 B) read, u and v (64 B) written; F_ext rows
+                       per node), Theta and E read; per node u,V (32 B), v
+                       (8 dim), aux (4 B) read, u,V and v written; F_ext rows
     """
     if kernel == "k_fac_extension":
         return nb * (16 * dim + 8 + 8 + 4 + 8) + nnz // 8 + 32 * n
     if kernel == "k_fac_dilatation":
         return nnz * 12 + 8 * nb + 8 * n
-    return nnz * (16 * dim + 8) + n * (8 * dim + 8 + 68 + 64) + 8 * nb + 32 * n_loaded
+    return nnz * (16 * dim + 8) + n * (8 * dim + 8 + (36 + 8 * dim) + (32 + 8 * dim)) + 8 * nb + 32 * n_loaded
 
 
 def fac_roofline(ms, dim, nnz, nb, n, n_loaded, workload):
@@ -192,9 +196,10 @@ def fac_roofline(ms, dim, nnz, nb, n, n_loaded, workload):
     byt = fac_bytes(kname, dim, nnz, nb, n, n_loaded)
     gbs = byt / (ms[kname] * 1e-3) / 1e9
     from paper_2309_11273_amd.profsum import kernel_source_hash
-    traffic = traffic_from_profiles(f"{kname}@{workload}", kernel_source_hash(kname))
+    traffic, traffic_exact = traffic_from_profiles(f"{kname}@{workload}", kernel_source_hash(kname))
     return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_exact": traffic_exact,
+            "kernel": kname,
             "kernel_ms": round(ms[kname], 5), "algorithmic_bytes": byt,
             "kernels_ms": {k: round(v, 5) for k, v in ms.items()},
             "kernels_gbs": {k: round(fac_bytes(k, dim, nnz, nb, n, n_loaded) / (v * 1e-3) / 1e9, 1)

@@ -11,6 +11,17 @@
       reads for a plain read-and-write kernel of N bytes each way launched
       in the same process; merged into the JSON file under
       "<kernel>@<workload>" with the hash of the kernel's sources
+  python -m paper_2309_11273_amd.profsum requests --csv CSV --workload NAME
+                                                  --copy-bytes N --out JSON
+      exact read bytes per launch from a run of the read-request counters by
+      size (TCC_EA0_RDREQ_32B_sum, _64B_sum, _128B_sum): 32, 64 and 128
+      bytes per request.  On gfx950 FETCH_SIZE counts a 128-byte request as
+      64 bytes (its 128-byte term, TCC_BUBBLE, reads zero), so the copy
+      reference's scale (2, all its reads are 128-byte requests) is exact
+      only for kernels that issue 128-byte requests alone.  Added to the
+      JSON entries taken on the same kernel source as "read_bytes_exact" and
+      "bytes_per_launch_exact" (with the WRITE_SIZE bytes, which count every
+      write request at its size)
 
 Nothing here touches the GPU.
 """
@@ -123,6 +134,33 @@ def traffic(fetch_csv: str, write_csv: str, copy_bytes: int, workload: str, out_
     return db
 
 
+REQ_COUNTERS = {"TCC_EA0_RDREQ_32B_sum": 32, "TCC_EA0_RDREQ_64B_sum": 64, "TCC_EA0_RDREQ_128B_sum": 128}
+
+
+def requests(req_csv: str, copy_bytes: int, workload: str, out_json: str) -> dict:
+    m = counter_means([req_csv])
+    exact = {k: sum(v[c] * b for c, b in REQ_COUNTERS.items()) for k, v in m.items()
+             if all(c in v for c in REQ_COUNTERS)}
+    ref = [k for k in exact if COPY_KERNEL_MARK in k]
+    if not ref:
+        raise SystemExit("no reference copy kernel in the request-size run")
+    ratio = exact[ref[0]] / copy_bytes
+    if abs(ratio - 1.0) > 0.01:
+        raise SystemExit(f"request-size bytes of the copy reference are {ratio:.4f} x its size")
+    db = json.load(open(out_json)) if os.path.exists(out_json) else {}
+    for k, rd in exact.items():
+        b = base_name(k)
+        e = db.get(f"{b}@{workload}")
+        if b not in KERNEL_SOURCES or not e or e.get("source_sha") != kernel_source_hash(b):
+            continue
+        e["read_bytes_exact"] = int(rd)
+        e["bytes_per_launch_exact"] = int(rd + e["write_bytes"])
+    with open(out_json, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return db
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="profsum")
     sp = ap.add_subparsers(dest="cmd", required=True)
@@ -138,13 +176,21 @@ def main(argv=None):
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--workload", required=True)
     c.add_argument("--out", required=True)
+    r = sp.add_parser("requests")
+    r.add_argument("--csv", required=True)
+    r.add_argument("--copy-bytes", type=int, required=True)
+    r.add_argument("--workload", required=True)
+    r.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         sys.stdout.write(stats_md(args.csv, args.command))
     elif args.cmd == "pmc":
         sys.stdout.write(pmc_md(args.csv, args.command))
-    else:
+    elif args.cmd == "traffic":
         json.dump(traffic(args.fetch, args.write, args.copy_bytes, args.workload, args.out), sys.stdout, indent=1)
+        sys.stdout.write("\n")
+    else:
+        json.dump(requests(args.csv, args.copy_bytes, args.workload, args.out), sys.stdout, indent=1)
         sys.stdout.write("\n")
 
 
