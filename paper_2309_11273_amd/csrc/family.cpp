@@ -41,6 +41,10 @@ double offset_length(double dx, const int32_t *o, double xi[3]) {
     return std::sqrt(s);
 }
 
+// Lattice offsets of the family, shortest first; every offset is followed by
+// its opposite (entry 2m+1 = -entry 2m, with exactly negated M), so that
+// the tile kernels can take a bond and its mirror together and entry 0 is
+// a shortest bond.
 std::vector<Stencil> make_stencil(int dim, double dx, double delta) {
     std::vector<Stencil> st;
     int R = (int)std::floor(delta / dx) + 1;
@@ -60,6 +64,22 @@ std::vector<Stencil> make_stencil(int dim, double dx, double delta) {
                 s.x = x;
                 st.push_back(s);
             }
+    // order: |o|^2, then the pair (represented by its lexicographically
+    // larger member), then the larger member first
+    auto n2 = [](const Stencil &a) {
+        return (int64_t)a.off[0] * a.off[0] + (int64_t)a.off[1] * a.off[1] + (int64_t)a.off[2] * a.off[2];
+    };
+    auto rep = [](const Stencil &a) {
+        const std::array<int32_t, 3> p{a.off[0], a.off[1], a.off[2]}, m{-a.off[0], -a.off[1], -a.off[2]};
+        return std::max(p, m);
+    };
+    std::sort(st.begin(), st.end(), [&](const Stencil &a, const Stencil &b) {
+        const int64_t na = n2(a), nb = n2(b);
+        if (na != nb) return na < nb;
+        const auto ra = rep(a), rb = rep(b);
+        if (ra != rb) return ra < rb;
+        return std::array<int32_t, 3>{a.off[0], a.off[1], a.off[2]} > std::array<int32_t, 3>{b.off[0], b.off[1], b.off[2]};
+    });
     return st;
 }
 

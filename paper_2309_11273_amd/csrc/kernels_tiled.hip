@@ -16,8 +16,11 @@
 //      box pitches are padded so that the 64 lanes of a tile, each reading
 //      the element at the same offset from its own point, hit 64 distinct
 //      LDS banks;
-//   2. every wave sweeps a quarter of the stencil for all 64 rows, four
-//      entries at a time: the neighbour of row l through entry k is point
+//   2. every wave sweeps a quarter of the stencil for all 64 rows (pass 1:
+//      every fourth group of four entries, so that each wave gets bonds of
+//      every length; pass 2: a contiguous quarter), four entries at a time,
+//      a bond and its mirror (the opposite offset, the next entry) summed as
+//      one term: the neighbour of row l through entry k is point
 //      slot(l) + soff[k], soff[k] the same for every lane, so one address
 //      per bond serves all arrays (their distance is a multiple of 256
 //      bytes: one ds_read2st64 per pair).  The entry's table row and bond-
@@ -71,8 +74,9 @@ struct Lay1 {
     static constexpr int BOX = DIM == 3 ? 5 * S * 4 : 2 * S * 8;
     static constexpr int SUMS = TPW == 1 ? PD_TILE_WAVES * 64 * (4 * 4 + 3 * 8) : 0;
     static constexpr int AREA = BOX > SUMS ? BOX : SUMS;
-    // then the neighbour tiles (27, or 48 for a super-tile) and, for a
-    // super-tile, the shared reference point
+    // then the neighbour tiles (27, or 48 for a super-tile), for a
+    // super-tile the shared reference point, and the box's largest staged
+    // magnitude (word 31, or 63 for a super-tile)
     static constexpr int BYTES = AREA + (TPW == 0 ? 64 : 32) * 4;
     static_assert(DIM == 2 || (S % 64 == 0 && 4 * S * 4 / 256 <= 255), "array offsets fit the st64 encoding");
     static_assert(TPW != 0 || (DIM == 3 ? 228 * 10 <= S : 40 * 22 <= S), "super-tile box fits the stride");
@@ -147,10 +151,12 @@ struct View1 {
 //     |e' x - e / Q| <= sqrt(3) + 2^-21 D + 2^-24 A,
 // D = sum_c |a_jc - a_ic|, A = the sum of the |a| at least 2^24 of both ends.
 // The screen passes every bond with e' >= thr_lo, thr_lo = s_c / Q minus
-// (sqrt(3) + 2^-21 * 3 * 2^31 + 2^-24 * 6 * 2^31) / x_min (|s| < 2^30: every
-// |a| and |a_j - a_i| is below 2^31), so no bond that can reach the critical
-// stretch escapes it; a screened bond whose e' x + 2^-20 D + 2^-23 A reaches
-// s_c x / Q - sqrt(3) is decided from the double state.
+// (sqrt(3) + 2^-21 * 6 a + 2^-24 * 6 a) / x_min, a the largest |a| staged
+// for a node point of the box (the last term only if a >= 2^24): every D of
+// the box's bonds is at most 6 a and every A at most 6 a, so no bond that
+// can reach the critical stretch escapes it; a screened bond whose
+// e' x + 2^-20 D + 2^-23 A reaches s_c x / Q - sqrt(3) is decided from the
+// double state.
 template <int DIM, bool BREAK, int TPW>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int cur,
                                                                 const KEnt *__restrict__ kt,
@@ -208,12 +214,18 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         hp[i] = hpos[min(gt + i * GR::NT, npts - 1)];
     }
     if (gt < NNB) stn[gt] = nbv;
+    // largest |a| of the staged box points (float bits), reduced in LDS
+    unsigned int *amw = reinterpret_cast<unsigned int *>(stn) + (TPW == 0 ? 63 : 31);
+    if (gt == 0) *amw = 0u;
     // the tile's bond range and the shadow scale arrive with the loads above
     // (not requested later, next to their first use)
     asm volatile("" ::"s"(base), "s"(L4), "s"(Q));
     const int G4 = L4 >> 2;
-    const int gper = (G4 + GR::SPLIT - 1) / GR::SPLIT;
-    const int g0 = kq * gper, g1 = min(G4, g0 + gper);
+    // this wave's groups of entries: kq, kq + SPLIT, ... (interleaved, so
+    // that every wave gets bonds of every length and direction, and the
+    // rechecks of a strained direction are shared among the waves)
+    constexpr int GS = GR::SPLIT;
+    const int g0 = kq;
     uint64_t mw[4];  // this wave's first status words (requested with the gathers)
     const uint32_t spi = tile_specimen(auxv);
     // reference point: the shadow of the tile's centre lattice point, or of
@@ -276,17 +288,22 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         // in flight (scalar reads in flight would hold up every wait for LDS
         // data before them)
 #pragma unroll
-        for (int c = 0; c < 4; c++) mw[c] = g0 < g1 ? mks[4 * g0 + c] : 0ull;
+        for (int c = 0; c < 4; c++) mw[c] = g0 < G4 ? mks[4 * g0 + c] : 0ull;
         const float GQ = (float)(sp.G * Q);  // extension carried in units of Q
+        float amx = 0.0f;  // largest |a| of this thread's node points (sentinels aside)
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             if (!act[i]) continue;
             const bool st = v[i].x == PD_SENTINEL_T;
             sent |= st;
             const float Vv = __int_as_float(v[i].w);
-            box.put(hp[i] >> HB, st ? __builtin_inff() : idiff(v[i].x, rx), idiff(v[i].y, ry),
-                    DIM == 3 ? idiff(v[i].z, rz) : 0.0f, Vv, GQ * r[i] * Vv);
+            const float ax = idiff(v[i].x, rx), ay = idiff(v[i].y, ry), az = DIM == 3 ? idiff(v[i].z, rz) : 0.0f;
+            // padding points (V = 0) end no bond
+            if (!st && Vv != 0.0f) amx = fmaxf(amx, fmaxf(fabsf(ax), fmaxf(fabsf(ay), fabsf(az))));
+            box.put(hp[i] >> HB, st ? __builtin_inff() : ax, ay, az, Vv, GQ * r[i] * Vv);
         }
+        const unsigned int wam = wave_max_bits(amx);
+        if (lane == 0) atomicMax(amw, wam);
     }
     const bool anysent = tile_sync_or<TPW>(sent);
     // a super-tile quadrant without a tile has nothing more to do (no later
@@ -312,9 +329,14 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     // breaking threshold in units of Q, widened by the float rounding of the test
     const double invQ = inv_pow2(Q);
     const float thrQ = (float)(s0 * invQ) * (1.0f - 1e-6f);
-    // screen on e': below thr_lo no bond can reach the threshold (entry 0 is
-    // the shortest bond of the stencil; 6200 > sqrt(3) + 3072 + 768)
-    const float thr_lo = thrQ * (1.0f - 9.5367432e-7f) - 6200.0f * kt[0].ix;
+    // screen on e': below thr_lo no bond of the box can reach the threshold.
+    // With a the largest staged |a| of a node point of the box, D <= 6 a
+    // and A <= 6 a (A only if a >= 2^24), so the band of every bond is at
+    // most (sqrt(3) + 2^-21 6 a + 2^-24 6 a) / x; entry 0 is a shortest
+    // bond of the stencil (the bound widened for its own float rounding)
+    const float am = __uint_as_float(*amw);
+    const float band = 1.7320509f + 2.8610229e-6f * am + (am >= 16777216.0f ? 3.5762787e-7f * am : 0.0f);
+    const float thr_lo = thrQ * (1.0f - 9.5367432e-7f) - (band * 1.001f + 1.0f) * kt[0].ix;
     float acc = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
     uint32_t nbroken = 0, nrecheck = 0, nfall = 0;
     double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
@@ -348,10 +370,15 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
             KEnt1 e[4];
             float ajx[4], ajy[4], ajz[4], vj[4], hj[4], evs[4];
 #pragma unroll
-            for (int c = 0; c < 4; c++) {
-                e[c] = kn[4 * gg + c];  // a 4 KiB table: scalar-cache hits
-                box.get(my + e[c].soff, ajx[c], ajy[c], ajz[c], vj[c], hj[c]);
-            }
+            for (int c = 0; c < 4; c++) e[c] = kn[4 * gg + c];  // a 4 KiB table: scalar-cache hits
+            // the mirror rows' x^2 and x M are not used; naming them keeps the
+            // four rows two whole 64-byte scalar loads, waited for once
+            // before the LDS reads (a partial row would be loaded piecewise,
+            // and a later wait would hold the LDS reads issued before it)
+            asm volatile("" ::"s"(e[1].x2), "s"(e[1].xm0), "s"(e[1].xm1), "s"(e[1].xm2), "s"(e[3].x2),
+                         "s"(e[3].xm0), "s"(e[3].xm1), "s"(e[3].xm2));
+#pragma unroll
+            for (int c = 0; c < 4; c++) box.get(my + e[c].soff, ajx[c], ajy[c], ajz[c], vj[c], hj[c]);
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 const float fdx = ajx[c] - aix, fdy = ajy[c] - aiy;
@@ -436,12 +463,16 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
                     }
                 }
             }
+            // entries c and c + 1 are a bond and its mirror (the opposite
+            // offset: the same x^2, x M negated), summed as one term
 #pragma unroll
-            for (int c = 0; c < 4; c++) {
-                const float evm = lane_bit(live[c]) ? evs[c] : 0.0f;  // broken bonds carry nothing
-                // dilatation: x V_j e = x^2 V_j e';  deviatoric force: G e (1/m_i + 1/m_j) V_j M
-                acc = fmaf(e[c].x2 * vj[c], evm, acc);
-                const float te = evm * fmaf(rpi, vj[c], hj[c]);
+            for (int c = 0; c < 4; c += 2) {
+                const float ea = lane_bit(live[c]) ? evs[c] : 0.0f;  // broken bonds carry nothing
+                const float eb = lane_bit(live[c + 1]) ? evs[c + 1] : 0.0f;
+                // dilatation: x V_j e = x^2 V_j e'
+                acc = fmaf(e[c].x2, fmaf(vj[c + 1], eb, vj[c] * ea), acc);
+                // deviatoric force: G e (1/m_i + 1/m_j) V_j M, with M of the mirror = -M
+                const float te = ea * fmaf(rpi, vj[c], hj[c]) - eb * fmaf(rpi, vj[c + 1], hj[c + 1]);
                 fx = fmaf(te, e[c].xm0, fx);
                 fy = fmaf(te, e[c].xm1, fy);
                 if (DIM == 3) fz = fmaf(te, e[c].xm2, fz);
@@ -454,9 +485,10 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         uint64_t ma[4], mb[4];
 #pragma unroll
         for (int c = 0; c < 4; c++) ma[c] = mw[c];
-        for (int gg = g0; gg < g1; gg += 2) {
-            group(chk, gg, ma, mb, min(gg + 1, g1 - 1));
-            if (gg + 1 < g1) group(chk, gg + 1, mb, ma, min(gg + 2, g1 - 1));
+        for (int gg = g0; gg < G4; gg += 2 * GS) {
+            const int g2 = gg + GS;  // the group after gg (if any: else gg's words again)
+            group(chk, gg, ma, mb, g2 < G4 ? g2 : gg);
+            if (g2 < G4) group(chk, g2, mb, ma, g2 + GS < G4 ? g2 + GS : g2);
         }
     };
     if (anysent) sweep(std::true_type{});
@@ -643,11 +675,14 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
                          "+v"(vj[2]), "+v"(vj[3])::"memory");
 #pragma unroll
             for (int c = 0; c < 4; c++) mn[c] = mks[4 * gn + c];
+            // entries c and c + 1 are a bond and its mirror (x M negated)
 #pragma unroll
-            for (int c = 0; c < 4; c++) {
+            for (int c = 0; c < 4; c += 2) {
                 // (K - G/3) (q_j - q_i) V_j, times x M from the table
-                float t = (qj[c] - qi) * vj[c];
-                t = lane_bit(mm[c]) ? t : 0.0f;
+                float ta = (qj[c] - qi) * vj[c], tb = (qj[c + 1] - qi) * vj[c + 1];
+                ta = lane_bit(mm[c]) ? ta : 0.0f;
+                tb = lane_bit(mm[c + 1]) ? tb : 0.0f;
+                const float t = ta - tb;
                 fx = fmaf(t, xm0[c], fx);
                 fy = fmaf(t, xm1[c], fy);
                 if (DIM == 3) fz = fmaf(t, xm2[c], fz);

@@ -89,6 +89,21 @@ __device__ __forceinline__ void margin_merge(float m, unsigned int *key) {
     if ((threadIdx.x & 63) == 0 && m < __builtin_inff()) atomicMax(key, ~__float_as_uint(m));
 }
 
+// Wave maximum of non-negative floats, as their bits (which order the same
+// way as int): a running maximum over lane shifts 1, 2, 4, 8 inside each
+// 16-lane row (DPP moves, no LDS traffic), then the four row maxima read
+// into scalars.  Called by every lane; the result is wave-uniform.
+__device__ __forceinline__ unsigned int wave_max_bits(float v) {
+    int b = (int)__float_as_uint(v);
+    b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x111, 0xf, 0xf, false));  // row_shr:1
+    b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x112, 0xf, 0xf, false));  // row_shr:2
+    b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x114, 0xf, 0xf, false));  // row_shr:4
+    b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x118, 0xf, 0xf, false));  // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(b, 15), r1 = __builtin_amdgcn_readlane(b, 31);
+    const int r2 = __builtin_amdgcn_readlane(b, 47), r3 = __builtin_amdgcn_readlane(b, 63);
+    return (unsigned int)max(max(r0, r1), max(r2, r3));
+}
+
 // lane's bit of a wave-uniform 64-bit word, used as the condition mask as is
 __device__ __forceinline__ bool lane_bit(uint64_t uniform_word) {
     return __builtin_amdgcn_inverse_ballot_w64(uniform_word);

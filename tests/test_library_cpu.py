@@ -85,6 +85,29 @@ def test_family_matches_reference(lib, case):
     assert np.all(np.diff(f.slice_ptr) % 64 == 0)
 
 
+@pytest.mark.parametrize("case", ["cantilever", "plate", "cylinder_small"])
+def test_stencil_order_shortest_first_in_mirror_pairs(lib, case):
+    """Stencil entries by length, each offset followed by its opposite with
+    exactly negated M and the same x (the tile kernels take a bond and its
+    mirror together and use entry 0 as a shortest bond)."""
+    w = CASES[case]()
+    f = _family(w)
+    ns = int(f.sizes.n_stencil)
+    off = f.stencil_off.reshape(-1, 3)[:ns].astype(np.int64)
+    sten = f.stencil.reshape(-1, 4)[:ns]
+    n2 = (off ** 2).sum(axis=1)
+    assert ns % 2 == 0 and np.all(np.diff(n2) >= 0)
+    assert np.array_equal(off[1::2], -off[0::2])
+    assert np.array_equal(sten[1::2, :3], -sten[0::2, :3])
+    assert np.array_equal(sten[1::2, 3], sten[0::2, 3])
+    assert sten[0, 3] == sten[:, 3].min()
+    # the single-precision table rows of a pair: M/x and x M negated, x^2 equal
+    kt1 = f.ktab[1536:1536 + 8 * ns].reshape(ns, 8).view(np.float32)
+    for c in (0, 1, 3, 4, 6, 7):
+        assert np.array_equal(kt1[1::2, c], -kt1[0::2, c]), c
+    assert np.array_equal(kt1[1::2, 2], kt1[0::2, 2])
+
+
 def _halo_rows(f, tile):
     """Emulation of the LDS-staged kernels' halo gather: global row of every
     slot of the (T0+2R)(T1+2R)(T2+2R) box around 'tile' (-1 = no tile).  In
