@@ -175,7 +175,8 @@ typedef struct pd_family_host {
     uint64_t *mask;       /* [n_mask] initial bond status, bit lane of word k of a
                              slice = status of bond k of row 64*slice + lane         */
     double *stencil;      /* [n_stencil*4] M1, M2, M3, x per bond offset (Eqs. 1.5, 1.13) */
-    int32_t *stencil_off; /* [n_stencil*3] lattice offset of each stencil entry      */
+    int32_t *stencil_off; /* [n_stencil*3] lattice offset of each stencil entry:
+                             shortest first, entry 2m+1 the opposite of entry 2m    */
     double *vol;          /* [n_pad] node volume (0 for padding)                     */
     double *inv_m;        /* [n_pad] 1 / m, m of Eq. 1.9 over the full family        */
     int32_t *spec;        /* [n_pad] specimen id (0 for padding)                     */
