@@ -185,7 +185,7 @@ __global__ __launch_bounds__(64 * W) void k_tpass1_f64(StepArgs a, int cur, cons
     double acc = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     uint32_t nbroken = 0;
     for (int gg = g0; gg < g1; gg++) {
-        double rv[4], ux[4], uy[4], uz[4], vj[4];
+        double rv[4], ux[4], uy[4], uz[4], vj[4], evk[4];
         double4 sd[4];
         uint64_t mm[4];
 #pragma unroll
@@ -233,14 +233,32 @@ __global__ __launch_bounds__(64 * W) void k_tpass1_f64(StepArgs a, int cur, cons
                     }
                 }
             }
-            const bool intact = lane_bit(live);
-            // dilatation: x V_j e;  deviatoric force: G e (1/m_i + 1/m_j) V_j
-            const double xv = sd[c].w * vj[c];
-            acc = fma(intact ? xv : 0.0, ev, acc);
-            const double te = intact ? ev * fma(rpi, vj[c], rv[c]) : 0.0;
-            fx = fma(te, n1, fx);
-            fy = fma(te, n2, fy);
-            if (DIM == 3) fz = fma(te, n3, fz);
+            if constexpr (FIN) {
+                const bool intact = lane_bit(live);
+                // dilatation: x V_j e;  deviatoric force: G e (1/m_i + 1/m_j) V_j
+                const double xv = sd[c].w * vj[c];
+                acc = fma(intact ? xv : 0.0, ev, acc);
+                const double te = intact ? ev * fma(rpi, vj[c], rv[c]) : 0.0;
+                fx = fma(te, n1, fx);
+                fy = fma(te, n2, fy);
+                if (DIM == 3) fz = fma(te, n3, fz);
+            } else {
+                evk[c] = lane_bit(live) ? ev : 0.0;  // broken bonds carry nothing
+            }
+        }
+        if constexpr (!FIN) {
+            // entries c and c + 1 are a bond and its mirror (the opposite
+            // offset: the same x, M negated), summed as one term
+#pragma unroll
+            for (int c = 0; c < 4; c += 2) {
+                // dilatation: x V_j e;  deviatoric force: G e (1/m_i + 1/m_j) V_j M
+                acc = fma(sd[c].w, fma(vj[c + 1], evk[c + 1], vj[c] * evk[c]), acc);
+                const double te =
+                    evk[c] * fma(rpi, vj[c], rv[c]) - evk[c + 1] * fma(rpi, vj[c + 1], rv[c + 1]);
+                fx = fma(te, sd[c].x, fx);
+                fy = fma(te, sd[c].y, fy);
+                if (DIM == 3) fz = fma(te, sd[c].z, fz);
+            }
         }
     }
     if (BREAK && valid && lane == 0 && nbroken) atomicAdd(&ctl->broken, (unsigned long long)nbroken);
@@ -377,6 +395,20 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f64(StepArgs a, int 
                 uj[c][2] = DIM == 3 ? hB[4 * S + slot] : 0.0;
             }
             mm[c] = uni64_t(smask[k]);
+        }
+        if constexpr (!FIN) {
+            // entries c and c + 1 are a bond and its mirror (the same x, M
+            // negated): (K - G/3) x [(q_i + q_j) V_j - (q_i + q_j') V_j'] M
+#pragma unroll
+            for (int c = 0; c < 4; c += 2) {
+                const double ta = lane_bit(mm[c]) ? (qi + qj[c]) * vj[c] : 0.0;
+                const double tb = lane_bit(mm[c + 1]) ? (qi + qj[c + 1]) * vj[c + 1] : 0.0;
+                const double t = (ta - tb) * sd[c].w;
+                fx = fma(t, sd[c].x, fx);
+                fy = fma(t, sd[c].y, fy);
+                if (DIM == 3) fz = fma(t, sd[c].z, fz);
+            }
+            continue;
         }
 #pragma unroll
         for (int c = 0; c < 4; c++) {
