@@ -654,9 +654,18 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass2_f32(StepArgs a, int 
     {
         auto group = [&](int gg, const uint64_t(&mm)[4], uint64_t(&mn)[4], int gn) {
             float xm0[4], xm1[4], xm2[4], qj[4], vj[4];
+            KEnt1 r[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) r[c] = kn[4 * gg + c];  // a 4 KiB table: scalar-cache hits
+            // every field named, so that the four rows come in two 64-byte
+            // scalar loads, waited for once before the LDS reads
+            asm volatile("" ::"s"(r[0].mx0), "s"(r[0].mx1), "s"(r[0].x2), "s"(r[0].mx2), "s"(r[1].mx0),
+                         "s"(r[1].mx1), "s"(r[1].x2), "s"(r[1].xm0), "s"(r[1].xm1), "s"(r[1].mx2), "s"(r[1].xm2),
+                         "s"(r[2].mx0), "s"(r[2].mx1), "s"(r[2].x2), "s"(r[2].mx2), "s"(r[3].mx0), "s"(r[3].mx1),
+                         "s"(r[3].x2), "s"(r[3].xm0), "s"(r[3].xm1), "s"(r[3].mx2), "s"(r[3].xm2));
 #pragma unroll
             for (int c = 0; c < 4; c++) {
-                const KEnt1 &e = kn[4 * gg + c];  // a 4 KiB table: scalar-cache hits
+                const KEnt1 &e = r[c];
                 xm0[c] = e.xm0;
                 xm1[c] = e.xm1;
                 xm2[c] = e.xm2;
