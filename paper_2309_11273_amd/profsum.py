@@ -11,6 +11,10 @@
       reads for a plain read-and-write kernel of N bytes each way launched
       in the same process; merged into the JSON file under
       "<kernel>@<workload>" with the hash of the kernel's sources
+  python -m paper_2309_11273_amd.profsum tail   TRACE_CSV --last N
+      average duration of the last N dispatches of every solver kernel in a
+      --kernel-trace run (the eager profiled steps that close a bench run,
+      which bench.py times with HIP events for the roofline's kernel_ms)
   python -m paper_2309_11273_amd.profsum requests --csv CSV --workload NAME
                                                   --copy-bytes N --out JSON
       exact read bytes per launch from a run of the read-request counters by
@@ -85,6 +89,19 @@ def stats_md(path: str, command: str) -> str:
         out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                    f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def tail_md(trace_csv: str, last: int) -> str:
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        k = short_name(r["Kernel_Name"])
+        if k.startswith("k_"):
+            per[k].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = ["| kernel | dispatches | last | average of the last (us) |", "|---|---|---|---|"]
+    for k in sorted(per, key=lambda k: -sum(d for _, d in per[k])):
+        d = [x[1] for x in sorted(per[k])[-last:]]
+        out.append(f"| `{k}` | {len(per[k])} | {len(d)} | {sum(d) / len(d) / 1e3:.2f} |")
     return "\n".join(out) + "\n"
 
 
@@ -176,6 +193,9 @@ def main(argv=None):
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--workload", required=True)
     c.add_argument("--out", required=True)
+    t = sp.add_parser("tail")
+    t.add_argument("csv")
+    t.add_argument("--last", type=int, required=True)
     r = sp.add_parser("requests")
     r.add_argument("--csv", required=True)
     r.add_argument("--copy-bytes", type=int, required=True)
@@ -186,6 +206,8 @@ def main(argv=None):
         sys.stdout.write(stats_md(args.csv, args.command))
     elif args.cmd == "pmc":
         sys.stdout.write(pmc_md(args.csv, args.command))
+    elif args.cmd == "tail":
+        sys.stdout.write(tail_md(args.csv, args.last))
     elif args.cmd == "traffic":
         json.dump(traffic(args.fetch, args.write, args.copy_bytes, args.workload, args.out), sys.stdout, indent=1)
         sys.stdout.write("\n")

@@ -64,3 +64,17 @@ def test_request_counts_must_reproduce_the_copy(tmp_path):
     _csv(tmp_path / "r.csv", _req_rows(COPY, 0, cb // 128, 0) + _req_rows(P1, 1, 1, 1))
     with pytest.raises(SystemExit):
         profsum.requests(str(tmp_path / "r.csv"), cb, "wl", str(tmp_path / "t.json"))
+
+
+def test_tail_averages_the_last_dispatches(tmp_path):
+    path = tmp_path / "trace.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        # out of time order on purpose: the last dispatches are the latest starts
+        for start, dur in ((300, 5000), (100, 1000), (200, 3000), (400, 7000)):
+            w.writerow({"Kernel_Name": P1, "Start_Timestamp": start, "End_Timestamp": start + dur})
+        w.writerow({"Kernel_Name": COPY, "Start_Timestamp": 0, "End_Timestamp": 99999})
+    md = profsum.tail_md(str(path), 2)
+    assert "| `k_tpass1_f32<3, true, 1>` | 4 | 2 | 6.00 |" in md
+    assert "MulFunctor" not in md
