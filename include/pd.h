@@ -163,6 +163,10 @@ typedef struct pd_family_sizes {
     int32_t n_box;      /* points of that box (tile + reach on every side) that
                            some stencil entry of some tile point reaches; see
                            pd_family_host.halo_pos                                 */
+    float vol_uniform;  /* the node volume as float when every node has the same
+                           one (then the FP32 tile kernels take it as a constant
+                           instead of staging it per point), else 0               */
+    int32_t pad_vu;
 } pd_family_sizes;
 
 /* Output arrays of pd_build_family, all [host], allocated by the caller
@@ -288,7 +292,11 @@ typedef struct pd_problem_dev {
     const int16_t *halo_map;    /* [device] n_halo, pd_family_host.halo_map        */
     const int32_t *halo_pos;    /* [device] n_box, pd_family_host.halo_pos         */
     int32_t n_pos;              /* pd_family_sizes.n_box                           */
-    int32_t pad1;
+    float vol_uniform;          /* pd_family_sizes.vol_uniform, or 0 (every kernel
+                                   reads the volumes); if nonzero it must equal the
+                                   float of every node's vol: the FP32 tile kernels
+                                   check the points they stage, and a mismatch fails
+                                   the next report or check of pd_step (PD_ERR_ARG) */
     /* super-tiles (pd_build_supertiles; NULL st_tiles: not used)                 */
     const int32_t *st_tiles;    /* [device] 4 n_st                                 */
     const int32_t *st_nbr;      /* [device] 48 n_st                                */

@@ -33,7 +33,8 @@ class pd_family_sizes(C.Structure):
     _fields_ = [("n", i64), ("n_pad", i64), ("n_slices", i64), ("n_words", i64), ("n_mask", i64),
                 ("nnz", i64), ("n_bonds", i64), ("n_cut", i64), ("n_stencil", i32), ("max_row", i32),
                 ("dim", i32), ("n_specimens", i32), ("n_tiles", i64), ("tile", i32 * 3),
-                ("words_per_row", i32), ("reach", i32), ("n_halo", i32), ("n_box", i32)]
+                ("words_per_row", i32), ("reach", i32), ("n_halo", i32), ("n_box", i32),
+                ("vol_uniform", C.c_float), ("pad_vu", i32)]
 
 
 class pd_family_host(C.Structure):
@@ -52,7 +53,7 @@ class pd_problem_dev(C.Structure):
                 ("n_specimens", i32), ("pad0", i32), ("slice_ptr", P), ("words", P), ("stencil", P),
                 ("vol", P), ("inv_m", P), ("lat4", P), ("spec", P), ("aux", P), ("fext", P),
                 ("ramp_steps", i64), ("stencil_off", P), ("tile_nbr", P), ("tile", i32 * 3), ("reach", i32),
-                ("ktab", P), ("halo_map", P), ("halo_pos", P), ("n_pos", i32), ("pad1", i32),
+                ("ktab", P), ("halo_map", P), ("halo_pos", P), ("n_pos", i32), ("vol_uniform", C.c_float),
                 ("st_tiles", P), ("st_nbr", P), ("st_pos", P), ("st_ktab", P), ("n_st", i64),
                 ("st_n_pos", i32), ("pad2", i32)]
 

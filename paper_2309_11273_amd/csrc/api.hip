@@ -122,6 +122,7 @@ pdk::StepArgs make_args(const pd_problem_dev *p, const pd_state_dev *st) {
     a.st_ktab = p->st_ktab;
     a.n_st = p->n_st;
     a.st_n_pos = p->st_n_pos;
+    a.vol_uniform = p->vol_uniform;
     return a;
 }
 
@@ -598,6 +599,8 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
             HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, kCtlHead, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
             const pd_ctl *h = c->host_ctl;
+            if (h->flags & PD_CTL_VOLUME)
+                return fail(c, PD_ERR_ARG, "vol_uniform does not match the node volumes");
             if (h->flags & PD_CTL_NONFINITE)
                 return fail(c, PD_ERR_UNSTABLE, "non-finite displacement before step %lld", (long long)h->s2);
             if (o.energy_check) {
@@ -614,6 +617,7 @@ static pd_status step_impl(pd_ctx *c, const pd_problem_dev *p, pd_state_dev *st,
         HIP_TRY(c, hipMemcpyAsync(c->host_ctl, st->ctl, sizeof(pd_ctl), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         const pd_ctl *h = c->host_ctl;
+        if (h->flags & PD_CTL_VOLUME) return fail(c, PD_ERR_ARG, "vol_uniform does not match the node volumes");
         rep->step = h->s2;
         rep->broken_total = (int64_t)h->broken;
         rep->rechecks = (int64_t)h->rechecks;

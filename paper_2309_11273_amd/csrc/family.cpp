@@ -387,6 +387,14 @@ extern "C" pd_status pd_build_family(const pd_body *body, const pd_cut *cuts, in
     for (int c = 0; c < 3; c++) sizes->tile[c] = T[c];
     sizes->words_per_row = L4;
     sizes->reach = reach;
+    // one volume for every node: the FP32 tile kernels then take it as a
+    // constant (compared as the float the shadow carries)
+    {
+        bool same = n > 0;
+        for (int64_t p = 1; p < n && same; p++) same = (float)body->vol[p] == (float)body->vol[0];
+        sizes->vol_uniform = same ? (float)body->vol[0] : 0.0f;
+        sizes->pad_vu = 0;
+    }
     {
         int32_t B[4];
         pd_tile_box(T, reach, dim, B);

@@ -54,6 +54,8 @@ struct StepArgs {
     int32_t st_n_pos;
     // one tile per workgroup in 2D too (four waves splitting its stencil)
     int32_t one_tile_per_group;
+    // every node's volume as float when they are all equal, else 0
+    float vol_uniform;
 };
 
 struct InitArgs {

@@ -59,10 +59,12 @@ namespace pdk {
 // r = 1/m) at the fixed stride S (pd_box1_stride); with TPW = 1 the partial
 // sums (4 floats and 3 doubles per thread) reuse it after the sweep; then the
 // 27 neighbour tiles.  3D: five float arrays, read per point with two
-// ds_read2st64 and one ds_read (array distances are multiples of 256 bytes);
-// 2D: two float2 arrays, (x, y) and (V, G Q r V), read with two 8-byte reads
-// from one address, which keeps the box of a one-wave tile small.
-template <int DIM, int TPW>
+// ds_read2st64 and one ds_read (array distances are multiples of 256 bytes),
+// or four when every node has the same volume (UV: V is then a constant, the
+// box a fifth smaller, and a compute unit holds six workgroups instead of
+// five); 2D: two float2 arrays, (x, y) and (V, G Q r V), read with two 8-byte
+// reads from one address, which keeps the box of a one-wave tile small.
+template <int DIM, int TPW, bool UV = false>
 struct Lay1 {
     // super-tile box: 3D 16 x 14 x 10 slots at pitches 16 and 228 (2280
     // slots), 2D 40 x 22 (880)
@@ -71,7 +73,7 @@ struct Lay1 {
     // 3D super-tile boxes up to 2048, 2D up to 256 per wave (TPW = 4) or 512
     // per workgroup (one tile per workgroup or a super-tile)
     static constexpr int MP = TPW == 0 ? (DIM == 3 ? 8 : 2) : (DIM == 3 ? 4 : (TPW == 4 ? 4 : 2));
-    static constexpr int BOX = DIM == 3 ? 5 * S * 4 : 2 * S * 8;
+    static constexpr int BOX = DIM == 3 ? (UV ? 4 : 5) * S * 4 : 2 * S * 8;
     static constexpr int SUMS = TPW == 1 ? PD_TILE_WAVES * 64 * (4 * 4 + 3 * 8) : 0;
     static constexpr int AREA = BOX > SUMS ? BOX : SUMS;
     // then the neighbour tiles (27, or 48 for a super-tile), for a
@@ -82,17 +84,22 @@ struct Lay1 {
     static_assert(TPW != 0 || (DIM == 3 ? 228 * 10 <= S : 40 * 22 <= S), "super-tile box fits the stride");
 };
 
-// access to the staged pass-1 box of Lay1
-template <int DIM, int S>
+// access to the staged pass-1 box of Lay1 (UV: no V array, V = Vu)
+template <int DIM, int S, bool UV = false>
 struct View1 {
     float *b;
+    float Vu;
     __device__ __forceinline__ void put(int slot, float x, float y, float z, float V, float h) const {
         if constexpr (DIM == 3) {
             b[slot] = x;
             b[S + slot] = y;
             b[2 * S + slot] = z;
-            b[3 * S + slot] = V;
-            b[4 * S + slot] = h;
+            if constexpr (UV) {
+                b[3 * S + slot] = h;
+            } else {
+                b[3 * S + slot] = V;
+                b[4 * S + slot] = h;
+            }
         } else {
             float2 *q = reinterpret_cast<float2 *>(b);
             q[slot] = make_float2(x, y);
@@ -114,8 +121,13 @@ struct View1 {
     __device__ __forceinline__ void get(int slot, float &x, float &y, float &z, float &V, float &h) const {
         if constexpr (DIM == 3) {
             pos(slot, x, y, z);
-            V = b[3 * S + slot];
-            h = b[4 * S + slot];
+            if constexpr (UV) {
+                V = Vu;
+                h = b[3 * S + slot];
+            } else {
+                V = b[3 * S + slot];
+                h = b[4 * S + slot];
+            }
         } else {
             const float2 *q = reinterpret_cast<const float2 *>(b);
             const float2 t = q[slot], u = q[S + slot];
@@ -157,13 +169,14 @@ struct View1 {
 // can reach the critical stretch escapes it; a screened bond whose
 // e' x + 2^-20 D + 2^-23 A reaches s_c x / Q - sqrt(3) is decided from the
 // double state.
-template <int DIM, bool BREAK, int TPW>
+template <int DIM, bool BREAK, int TPW, bool UV = false>
 __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int cur,
                                                                 const KEnt *__restrict__ kt,
                                                                 const KEnt1 *__restrict__ kn) {
     extern __shared__ __align__(16) unsigned char smem[];
+    static_assert(!UV || DIM == 3, "a constant volume is taken in 3D only");
     using GR = Grp<DIM, TPW>;
-    using LY = Lay1<DIM, TPW>;
+    using LY = Lay1<DIM, TPW, UV>;
     constexpr int S = LY::S;
     constexpr int MS = LY::MP;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -179,7 +192,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
     const int64_t base = a.slice_ptr[tile];
     const int L4 = (int)((a.slice_ptr[tile + 1] - base) >> 6);
     unsigned char *reg = smem + (TPW == 4 ? sub * LY::BYTES : 0);
-    const View1<DIM, S> box{reinterpret_cast<float *>(reg)};
+    const View1<DIM, S, UV> box{reinterpret_cast<float *>(reg), a.vol_uniform};
     int *stn = reinterpret_cast<int *>(reg + LY::AREA);
     int32_t B1[4];
     pd_tile_box1(a.tile, a.reach, DIM, B1);
@@ -291,6 +304,7 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
         for (int c = 0; c < 4; c++) mw[c] = g0 < G4 ? mks[4 * g0 + c] : 0ull;
         const float GQ = (float)(sp.G * Q);  // extension carried in units of Q
         float amx = 0.0f;  // largest |a| of this thread's node points (sentinels aside)
+        bool badv = false;  // UV: a staged node volume other than the constant
 #pragma unroll
         for (int i = 0; i < MS; i++) {
             if (!act[i]) continue;
@@ -300,10 +314,12 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
             const float ax = idiff(v[i].x, rx), ay = idiff(v[i].y, ry), az = DIM == 3 ? idiff(v[i].z, rz) : 0.0f;
             // padding points (V = 0) end no bond
             if (!st && Vv != 0.0f) amx = fmaxf(amx, fmaxf(fabsf(ax), fmaxf(fabsf(ay), fabsf(az))));
+            if (UV) badv |= Vv != 0.0f && Vv != box.Vu;
             box.put(hp[i] >> HB, st ? __builtin_inff() : ax, ay, az, Vv, GQ * r[i] * Vv);
         }
         const unsigned int wam = wave_max_bits(amx);
         if (lane == 0) atomicMax(amw, wam);
+        if (UV && __ballot(badv) && lane == 0) atomicOr(&ctl->flags, PD_CTL_VOLUME);
     }
     const bool anysent = tile_sync_or<TPW>(sent);
     // a super-tile quadrant without a tile has nothing more to do (no later
@@ -393,8 +409,13 @@ __global__ __launch_bounds__(PD_TILE_THREADS) void k_tpass1_f32(StepArgs a, int 
             // flight would hold up the wait for the LDS data (the empty asm
             // pins the strains and the staged values here and keeps the
             // scalar reads after them)
-            asm volatile("" : "+v"(evs[0]), "+v"(evs[1]), "+v"(evs[2]), "+v"(evs[3]), "+v"(vj[0]), "+v"(vj[1]),
-                         "+v"(vj[2]), "+v"(vj[3]), "+v"(hj[0]), "+v"(hj[1]), "+v"(hj[2]), "+v"(hj[3])::"memory");
+            if constexpr (UV) {  // (V a constant: not pinned, or it would be copied per entry)
+                asm volatile("" : "+v"(evs[0]), "+v"(evs[1]), "+v"(evs[2]), "+v"(evs[3]), "+v"(hj[0]), "+v"(hj[1]),
+                             "+v"(hj[2]), "+v"(hj[3])::"memory");
+            } else {
+                asm volatile("" : "+v"(evs[0]), "+v"(evs[1]), "+v"(evs[2]), "+v"(evs[3]), "+v"(vj[0]), "+v"(vj[1]),
+                             "+v"(vj[2]), "+v"(vj[3]), "+v"(hj[0]), "+v"(hj[1]), "+v"(hj[2]), "+v"(hj[3])::"memory");
+            }
 #pragma unroll
             for (int c = 0; c < 4; c++) mn[c] = mks[4 * gn + c];
             uint64_t live[4], fbm[4];
@@ -887,7 +908,8 @@ static_assert(Lay1<3, 1>::S == 1472 && Lay1<2, 4>::S == 336 && Lay1<2, 1>::S == 
               "pass-1 array strides follow pd_box1_stride");
 
 static size_t tiled_lds(const StepArgs &a, int pass, int tpw) {
-    if (pass == 1) return a.dim == 3 ? Lay1<3, 1>::BYTES : (tpw == 4 ? 4 * Lay1<2, 4>::BYTES : Lay1<2, 1>::BYTES);
+    if (pass == 1 && a.dim == 3) return a.vol_uniform > 0.0f ? Lay1<3, 1, true>::BYTES : Lay1<3, 1>::BYTES;
+    if (pass == 1) return tpw == 4 ? 4 * Lay1<2, 4>::BYTES : Lay1<2, 1>::BYTES;
     return a.dim == 3 ? Lay2<3, 1>::BYTES : (tpw == 4 ? 4 * Lay2<2, 4>::BYTES : Lay2<2, 1>::BYTES);
 }
 
@@ -935,6 +957,14 @@ static hipError_t spass1(const StepArgs &a, int cur, bool brk, hipStream_t s) {
     const dim3 g((unsigned)a.n_st), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     const KEnt1 *kn = reinterpret_cast<const KEnt1 *>(a.st_ktab);
+    if constexpr (DIM == 3) {
+        if (a.vol_uniform > 0.0f) {
+            constexpr size_t lds = Lay1<3, 0, true>::BYTES;
+            if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true, 0, true>), g, b, lds, s, a, cur, kt, kn);
+            else hipLaunchKernelGGL((k_tpass1_f32<3, false, 0, true>), g, b, lds, s, a, cur, kt, kn);
+            return hipGetLastError();
+        }
+    }
     constexpr size_t lds = Lay1<DIM, 0>::BYTES;
     if (brk) hipLaunchKernelGGL((k_tpass1_f32<DIM, true, 0>), g, b, lds, s, a, cur, kt, kn);
     else hipLaunchKernelGGL((k_tpass1_f32<DIM, false, 0>), g, b, lds, s, a, cur, kt, kn);
@@ -965,7 +995,10 @@ hipError_t launch_tpass1_f32(const StepArgs &a, int cur, bool brk, hipStream_t s
     const dim3 g((unsigned)((a.n_slices + tpw - 1) / tpw)), b(PD_TILE_THREADS);
     const KEnt *kt = reinterpret_cast<const KEnt *>(a.ktab);
     const KEnt1 *kn = reinterpret_cast<const KEnt1 *>(a.ktab + 1536);
-    if (a.dim == 3) {
+    if (a.dim == 3 && a.vol_uniform > 0.0f) {
+        if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true, 1, true>), g, b, lds, s, a, cur, kt, kn);
+        else hipLaunchKernelGGL((k_tpass1_f32<3, false, 1, true>), g, b, lds, s, a, cur, kt, kn);
+    } else if (a.dim == 3) {
         if (brk) hipLaunchKernelGGL((k_tpass1_f32<3, true, 1>), g, b, lds, s, a, cur, kt, kn);
         else hipLaunchKernelGGL((k_tpass1_f32<3, false, 1>), g, b, lds, s, a, cur, kt, kn);
     } else if (tpw == 4) {

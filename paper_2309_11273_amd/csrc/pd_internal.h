@@ -18,7 +18,8 @@ struct pd_ctl {
     int64_t s2;
     unsigned long long broken;    // directed bond-status bits cleared so far
     unsigned long long rechecks;  // FP64 rechecks made by the FP32 path
-    unsigned int flags;           // bit 0: non-finite state, bit 1: shadow fallback used
+    unsigned int flags;           // bit 0: non-finite state, bit 1: shadow fallback used,
+                                  // bit 2: a staged volume differs from vol_uniform
     unsigned int umax_bits[2];    // float bits of max |u| of shadow buffer k
     unsigned int margin_key;      // smallest |s - s_c| / s_c of a bond decided in double by
                                   // the FP32 path, stored as ~(float bits); 0 = none yet
@@ -51,6 +52,7 @@ static_assert(sizeof(pd_ctl) % 8 == 0, "control block is cleared in 8-byte words
 
 #define PD_CTL_NONFINITE 1u
 #define PD_CTL_FALLBACK 2u
+#define PD_CTL_VOLUME 4u  // a staged node volume differs from vol_uniform
 
 // Padding stencil id.
 #define PD_PAD_ID 127u

@@ -287,6 +287,7 @@ class Solver:
         self.halo_pos = t(self.fam.halo_pos)
         P.halo_pos = _tp(self.halo_pos)
         P.n_pos = int(s.n_box)
+        P.vol_uniform = float(s.vol_uniform)
         for c in range(3):
             P.tile[c] = int(s.tile[c])
         P.reach = int(s.reach)

@@ -53,8 +53,18 @@ def short_horizon_plate():
     return w
 
 
+def uneven_volume_impact():
+    """The reduced impact plate with node volumes spread by +-10 % (seeded):
+    the tile kernels then stage every node's volume instead of taking one
+    constant."""
+    w = W.impact3d(nx=36, ny=36, nz=9, dt=2.4e-7, steps=200)
+    w.vol = w.vol * (1.0 + 0.1 * np.random.default_rng(2309).uniform(-1.0, 1.0, w.n))
+    return w
+
+
 def small_workloads():
     return {
+        "impact_vol": uneven_volume_impact(),
         "impact_r2": short_horizon_plate(),
         # a 64 x 20 plate gets 16 x 4 tiles (unpadded pitches in the tile kernels)
         "plate_16x4": W.plate2d(nx=64, ny=20, dt=1.347e-7, sigma=2e6, notch_row=9, notch_tip=31.37, steps=200),
@@ -110,7 +120,7 @@ def test_force_matches_reference(ctx, name):
 @pytest.mark.parametrize("kernel", ["gather", "tiled", "tiled1"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("plane_strain", 100),
                                         ("impact", 200), ("impact_r2", 200), ("cylinder", 200), ("batch", 200),
-                                        ("plate_wide", 200), ("plate_16x4", 200)])
+                                        ("plate_wide", 200), ("plate_16x4", 200), ("impact_vol", 200)])
 def test_fp64_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
     if kernel == "tiled1" and w.dim != 2:
@@ -151,7 +161,7 @@ def test_plate_full_size_fp64(ctx):
 @pytest.mark.parametrize("kernel", ["gather", "tiled", "super", "tiled1"])
 @pytest.mark.parametrize("name,steps", [("cantilever", 2000), ("plate_notched", 300), ("impact", 200),
                                         ("impact_r2", 200), ("cylinder", 200), ("batch", 200), ("plate_wide", 200),
-                                        ("plate_16x4", 200)])
+                                        ("plate_16x4", 200), ("impact_vol", 200)])
 def test_fp32_recheck_trajectory(ctx, name, steps, kernel):
     w = small_workloads()[name]
     o = Oracle(w)

@@ -108,6 +108,17 @@ def test_stencil_order_shortest_first_in_mirror_pairs(lib, case):
     assert np.array_equal(kt1[1::2, 2], kt1[0::2, 2])
 
 
+def test_uniform_volume_flag(lib):
+    """The family reports one node volume (as float) when every node has it,
+    else 0, which keeps the FP32 tile kernels on the staged volumes."""
+    w = CASES["cylinder_small"]()
+    f = _family(w)
+    assert f.sizes.vol_uniform == np.float32(w.vol[0]) and f.sizes.vol_uniform > 0
+    w.vol = w.vol.copy()
+    w.vol[len(w.vol) // 2] *= 1.01
+    assert _family(w).sizes.vol_uniform == 0.0
+
+
 def _halo_rows(f, tile):
     """Emulation of the LDS-staged kernels' halo gather: global row of every
     slot of the (T0+2R)(T1+2R)(T2+2R) box around 'tile' (-1 = no tile).  In
